@@ -1,0 +1,335 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix (no GPU).
+
+Each test would fail for a plausible mistake in the oracle: a dropped term, a wrong
+sign or index, a transposed operand, a wrong scaling.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import sdp_inputs as si
+from oracle import usbs_oracle as orc
+
+
+# ---------------------------------------------------------------------------
+# Jacobi eigendecomposition vs closed-form Laplacian spectra
+# ---------------------------------------------------------------------------
+def _lap(n, i, j):
+    L = np.zeros((n, n))
+    for a, b in zip(i, j):
+        L[a, b] -= 1
+        L[b, a] -= 1
+        L[a, a] += 1
+        L[b, b] += 1
+    return L
+
+
+@pytest.mark.parametrize("n", [7, 16])
+def test_jacobi_complete_graph(n):
+    w, V = orc.jacobi_eigh(_lap(n, *si.complete_graph(n)))
+    assert np.allclose(w[:-1], n, atol=1e-12) and abs(w[-1]) < 1e-12
+    assert np.abs(V.T @ V - np.eye(n)).max() < 1e-13
+
+
+def test_jacobi_cycle_star_hypercube():
+    n = 13
+    w = orc.jacobi_eigh(_lap(n, *si.cycle_graph(n)))[0]
+    ref = np.sort(2 - 2 * np.cos(2 * np.pi * np.arange(n) / n))[::-1]
+    assert np.abs(w - ref).max() < 1e-12
+    w = orc.jacobi_eigh(_lap(9, *si.star_graph(9)))[0]
+    assert np.abs(w - np.array([9] + [1] * 7 + [0])).max() < 1e-12
+    d = 5
+    w = orc.jacobi_eigh(_lap(1 << d, *si.hypercube_graph(d)))[0]
+    ref = np.sort(np.concatenate([[2 * i] * math.comb(d, i) for i in range(d + 1)]))[::-1]
+    assert np.abs(w - ref).max() < 1e-12
+
+
+def test_jacobi_random_residual_and_order():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((40, 40))
+    A = A + A.T
+    w, V = orc.jacobi_eigh(A)
+    assert np.all(np.diff(w) <= 0)
+    assert np.abs(A @ V - V * w).max() < 1e-12 * np.abs(w).max()
+    assert np.abs(V.T @ V - np.eye(40)).max() < 1e-13
+    assert abs(w.sum() - np.trace(A)) < 1e-11
+
+
+# ---------------------------------------------------------------------------
+# svec, U, symmetric Kronecker product (App. B)
+# ---------------------------------------------------------------------------
+def test_svec_inner_product_and_U():
+    rng = np.random.default_rng(1)
+    k = 5
+    A = rng.standard_normal((k, k)); A = A + A.T
+    B = rng.standard_normal((k, k)); B = B + B.T
+    assert abs(orc.svec(A) @ orc.svec(B) - np.trace(A @ B)) < 1e-12
+    U = orc.svec_U(k)
+    vec = A.flatten(order="F")
+    assert np.abs(U @ vec - orc.svec(A)).max() < 1e-13
+    assert np.abs(U.T @ U @ vec - vec).max() < 1e-13
+    assert np.abs(U @ U.T - np.eye(k * (k + 1) // 2)).max() < 1e-14   # orthonormal rows
+    assert np.abs(orc.smat(orc.svec(A), k) - A).max() < 1e-14
+    # the printed n = 2 example
+    r = 1 / math.sqrt(2)
+    assert np.allclose(orc.svec_U(2), [[1, 0, 0, 0], [0, r, r, 0], [0, 0, 0, 1]])
+
+
+def test_skron_action():
+    rng = np.random.default_rng(2)
+    k = 4
+    G = rng.standard_normal((k, k)); G = G + G.T
+    H = rng.standard_normal((k, k)); H = H + H.T
+    A = rng.standard_normal((k, k)); A = A + A.T
+    lhs = orc.skron(G, H) @ orc.svec(A)
+    rhs = 0.5 * orc.svec(H @ A @ G.T + G @ A @ H.T)
+    assert np.abs(lhs - rhs).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# interior point methods (App. B.1, B.2)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ipm_linear_matches_extreme_points(seed):
+    """min g1's + eta g2 over {eta>=0, S PSD, eta + tr S <= 1} = min(0, g2, lambda_min(smat g1))."""
+    rng = np.random.default_rng(seed)
+    k = 4
+    G = rng.standard_normal((k, k)); G = G + G.T
+    g2 = rng.standard_normal()
+    val, S, eta = orc.ipm_linear(orc.svec(G), g2, k)
+    ref = min(0.0, g2, orc.jacobi_eigh(G)[0][-1])
+    assert abs(val - ref) < 1e-6
+
+
+def _kkt_check(qp, st, k):
+    F1, F2 = orc.qp_residuals(qp, st)
+    assert np.abs(F1).max() < 1e-6 and abs(F2) < 1e-6
+    assert orc.jacobi_eigh(st.S)[0][-1] > -1e-12 and orc.jacobi_eigh(st.T)[0][-1] > -1e-12
+    slack = 1 - np.trace(st.S) - st.eta
+    assert st.eta >= 0 and slack >= -1e-12 and st.zeta >= 0 and st.omega >= 0
+    gapc = np.sum(st.S * st.T) + st.eta * st.zeta + st.omega * slack
+    # stop rule mu < 1e-7 with mu = min(mu_prev, gamma gap / (2(k+2))), gamma >= 0.1
+    assert gapc < 20 * (k + 2) * 1e-7
+
+
+def _random_qp(k, rng, m=30):
+    d = k * (k + 1) // 2
+    Gm = rng.standard_normal((m, d))
+    Q11 = Gm.T @ Gm
+    zb = rng.standard_normal(m)
+    return orc.QPData(Q11=Q11, q12=Gm.T @ zb, q22=float(zb @ zb), h1=rng.standard_normal(d) * 3,
+                      h2=rng.standard_normal() * 3)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_ipm_qsdp_kkt(seed):
+    """The IPM output satisfies the KKT system of the dual barrier Lagrangian (App. B.2)."""
+    rng = np.random.default_rng(seed)
+    k = 4
+    qp = _random_qp(k, rng)
+    st = orc.ipm_qsdp(qp, k)
+    _kkt_check(qp, st, k)
+
+
+def test_ipm_qsdp_k1_bruteforce():
+    """k = 1: a convex quadratic over the triangle {s >= 0, eta >= 0, s + eta <= 1}; compare
+    with an exhaustive search over a fine grid refined around the best point."""
+    rng = np.random.default_rng(7)
+    for _ in range(3):
+        qp = _random_qp(1, rng, m=3)
+        st = orc.ipm_qsdp(qp, 1)
+        f = lambda s, e: 0.5 * qp.Q11[0, 0] * s * s + e * qp.q12[0] * s + 0.5 * qp.q22 * e * e \
+            + qp.h1[0] * s + qp.h2 * e
+        best, arg = np.inf, None
+        for s in np.linspace(0, 1, 401):
+            es = np.linspace(0, 1 - s, 401)
+            v = f(s, es)
+            i = int(np.argmin(v))
+            if v[i] < best:
+                best, arg = v[i], (s, es[i])
+        fi = f(st.S[0, 0], st.eta)
+        assert fi <= best + 20 * 3 * 1e-7    # duality gap bound of the stop rule (k = 1)
+        assert fi >= best - 1e-4   # the grid optimum is within grid resolution of the true one
+
+
+def test_ipm_warm_start_same_solution():
+    rng = np.random.default_rng(11)
+    k = 3
+    qp = _random_qp(k, rng)
+    st = orc.ipm_qsdp(qp, k)
+    qp2 = orc.QPData(qp.Q11, qp.q12, qp.q22, qp.h1 + 0.01 * rng.standard_normal(qp.h1.size), qp.h2)
+    cold = orc.ipm_qsdp(qp2, k)
+    warm = orc.ipm_qsdp(qp2, k, start=st)
+    # both stop within the duality-gap bound 20 (k+2) mu_stop of the optimum
+    assert abs(orc.qp_objective(qp2, cold.S, cold.eta) - orc.qp_objective(qp2, warm.S, warm.eta)) < 20 * (k + 2) * 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Nystrom sketch (Sec. 4, App. C.1)
+# ---------------------------------------------------------------------------
+def test_nystrom_exact_for_low_rank():
+    rng = np.random.default_rng(3)
+    n, r = 60, 10
+    F = rng.standard_normal((n, 6))
+    X = F @ F.T
+    Psi = si.test_matrix(n, r, seed=1).astype(float)
+    P = X @ Psi
+    assert np.abs(orc.nystrom_definition(P, Psi) - X).max() < 1e-9 * np.abs(X).max()
+    U, lam = orc.nystrom_stable(P, Psi)
+    assert np.abs((U * lam) @ U.T - X).max() < 1e-9 * np.abs(X).max()
+    assert np.abs(U.T @ U - np.eye(r)).max() < 1e-10
+
+
+def test_nystrom_error_bound_fact_c1():
+    """E ||X - Xhat||_* <= (1 + r'/(r - r' - 1)) ||X - [[X]]_r'||_* (Fact C.1), averaged over seeds."""
+    rng = np.random.default_rng(4)
+    n, r, rp = 50, 10, 4
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    ev = 0.6 ** np.arange(n)
+    X = (Q * ev) @ Q.T
+    tail = ev[rp:].sum()
+    errs = []
+    for s in range(30):
+        Psi = si.test_matrix(n, r, seed=100 + s).astype(float)
+        U, lam = orc.nystrom_stable(X @ Psi, Psi)
+        E = X - (U * lam) @ U.T
+        errs.append(np.abs(orc.jacobi_eigh(0.5 * (E + E.T))[0]).sum())
+    assert np.mean(errs) <= (1 + rp / (r - rp - 1)) * tail
+
+
+# ---------------------------------------------------------------------------
+# operators and scaling
+# ---------------------------------------------------------------------------
+def test_adjoint_identity_and_lowrank():
+    prob = si.cc_signed(30, avg_degree=4, seed=1)
+    rng = np.random.default_rng(5)
+    F = rng.standard_normal((prob.n, 3))
+    lam = rng.random(3)
+    X = (F * lam) @ F.T
+    y = rng.standard_normal(prob.m)
+    assert abs(orc.A_apply(prob, X) @ y - np.sum(X * orc.A_adjoint(prob, y))) < 1e-10
+    assert np.abs(orc.A_lowrank(prob, F, lam) - orc.A_apply(prob, X)).max() < 1e-12
+
+
+def test_scaling_units():
+    prob = si.maxcut_er(40, 0.2, seed=2)
+    sc = orc.scale_problem(prob)
+    assert abs(np.linalg.norm(sc.C) - 1) < 1e-12
+    assert abs(sc.b.sum() - 1) < 1e-12          # tr X* = 1 after scaling (diag X = 1/n)
+    assert np.allclose(orc.dense_C(prob), orc.dense_C(prob).T)
+
+
+def test_dual_bound_eigenvalue():
+    """For MaxCut y = (lambda_max(L)/4) 1 is dual feasible: p* <= (n/4) lambda_max(L); f(y) >= p*."""
+    prob = si.maxcut_er(30, 0.3, seed=3)
+    sc = orc.scale_problem(prob)
+    L4 = orc.dense_C(prob)
+    lmax = orc.jacobi_eigh(L4)[0][0]
+    y_orig = lmax * np.ones(prob.n)
+    f, _, _ = orc.penalized_dual(sc, y_orig / sc.sigma, 2.0, 1)
+    assert abs(orc.to_original(sc, f) - prob.n * lmax) < 1e-9 * prob.n * lmax
+
+
+# ---------------------------------------------------------------------------
+# full USBS runs against closed-form SDP values
+# ---------------------------------------------------------------------------
+def _solve(prob, eps=1e-3, rho=0.1, iters=800, kc=10, kp=1):
+    prm = orc.Params(rho=rho, eps_gap=eps, eps_infeas=eps, max_iters=iters, k_c=kc, k_p=kp)
+    psi = si.test_matrix(prob.n, 10, seed=0)
+    res = orc.usbs_solve(prob, prm, Psi=psi)
+    sc = orc.scale_problem(prob)
+    return res, sc
+
+
+def test_usbs_complete_graph():
+    """K_n: X = (n/(n-1))(I - J/n) and y = (n/4) 1 give p* = d* = n^2/4."""
+    n = 12
+    prob = si.maxcut_problem(n, *si.complete_graph(n), np.ones(n * (n - 1) // 2))
+    res, sc = _solve(prob)
+    assert res.converged
+    p = orc.to_original(sc, res.primal_obj)
+    f = orc.to_original(sc, res.f)
+    assert f >= n * n / 4 - 1e-9            # f(y) >= p* for every y
+    assert abs(p - n * n / 4) / (n * n / 4) < 5e-3
+    assert abs(f - n * n / 4) / (n * n / 4) < 5e-3
+
+
+def test_usbs_bipartite_and_odd_cycle():
+    """Even cycle: p* = |E|.  Odd cycle C_5: p* = (5/2)(1 + cos(pi/5)) = (25 + 5 sqrt 5)/8."""
+    for n, pstar in ((8, 8.0), (5, (25 + 5 * math.sqrt(5)) / 8)):
+        i, j = si.cycle_graph(n)
+        prob = si.maxcut_problem(n, i, j, np.ones(n))
+        res, sc = _solve(prob, kc=3, kp=1)
+        f = orc.to_original(sc, res.f)
+        p = orc.to_original(sc, res.primal_obj)
+        assert f >= pstar - 1e-9
+        assert abs(f - pstar) / pstar < 5e-3 and abs(p - pstar) / pstar < 5e-3, (n, p, f, pstar)
+
+
+def test_usbs_planted_signed_graph_and_invariants():
+    """Planted +-1 graph: p* = #positive edges.  Along the run: f(y_t) non-increasing, the model
+    is a minorant f^_t(y~) <= f(y~), tr X_{t+1} <= alpha, X_{t+1} PSD, tracked quantities equal
+    their dense recomputation."""
+    prob = si.maxcut_planted_pm1(40, 5.0, seed=1)
+    pstar = prob.meta["p_star"]
+    prm = orc.Params(rho=0.1, max_iters=300)
+    sc = orc.scale_problem(prob)
+    Psi = si.test_matrix(prob.n, 10, seed=0).astype(float)
+    st = orc.cold_start(sc, prm, Psi)
+    fprev = st.f
+    for t in range(300):
+        V, Xbar, tau = st.V.copy(), st.Xbar.copy(), st.tau
+        rec = orc.usbs_step(sc, prm, st, Psi)
+        assert rec["f"] <= fprev + 1e-15
+        fprev = rec["f"]
+        assert rec["fhat"] <= rec["f_cand"] + 1e-6
+        S, eta = st.ipm.S, st.ipm.eta
+        g = prm.alpha * eta / tau if tau > 0 else 0.0
+        X = g * Xbar + prm.alpha * V @ S @ V.T
+        assert np.trace(X) <= prm.alpha + 1e-9
+        assert orc.jacobi_eigh(X)[0][-1] > -1e-9
+        assert abs(np.trace(st.Xbar) - st.tau) < 1e-12
+        assert abs(np.sum(sc.C * st.Xbar) - st.cbar) < 1e-12
+        assert np.abs(orc.A_apply(prob, st.Xbar) - st.zbar).max() < 1e-12
+        assert np.abs(st.Xbar @ Psi - st.Pbar).max() < 1e-11
+        if rec["rel_gap"] <= 1e-3 and rec["rel_infeas"] <= 1e-3:
+            break
+    p = orc.to_original(sc, rec["primal"])
+    f = orc.to_original(sc, rec["f"])
+    assert f >= pstar - 1e-9
+    assert abs(p - pstar) / pstar < 5e-3 and abs(f - pstar) / pstar < 5e-3
+
+
+def test_usbs_bruteforce_cut_and_gw_bound():
+    """Tiny random graphs: cut* <= p_SDP <= f(y) and, for w >= 0, cut* >= 0.87856 p_SDP."""
+    for seed in range(2):
+        prob = si.maxcut_er(12, 0.4, seed=seed)
+        i, j, w = prob.meta["edges_i"], prob.meta["edges_j"], prob.meta["weights"]
+        cut = orc.brute_force_maxcut(prob.n, i, j, w)
+        res, sc = _solve(prob, kc=5, kp=1)
+        f = orc.to_original(sc, res.f)
+        p = orc.to_original(sc, res.primal_obj)
+        assert cut <= f + 1e-9
+        assert cut >= 0.87856 * p * (1 - 2e-3)
+
+
+def test_usbs_cc_closed_forms():
+    """Correlation clustering: W >= 0 gives X = J, p* = sum_ij W_ij.  Two planted clusters with
+    positive weights inside and negative weights across give X = blockdiag(J, J) (|X_ij| <= 1 and
+    X_ij >= 0 bound every term), p* = 2 x the within-cluster weight."""
+    rng = np.random.default_rng(3)
+    n = 16
+    i, j = si.random_edges(n, 40, rng)
+    w = 0.5 + rng.random(i.size)
+    side = np.arange(n) < n // 2
+    w2 = np.where(side[i] == side[j], w, -w)
+    for ww, pstar in ((w, 2 * w.sum()), (w2, 2 * w2[side[i] == side[j]].sum())):
+        prob = si.cc_problem(n, i, j, ww)
+        res, sc = _solve(prob, kc=3, kp=0, iters=600)
+        f = orc.to_original(sc, res.f)
+        p = orc.to_original(sc, res.primal_obj)
+        assert res.converged
+        assert f >= pstar - 1e-9
+        assert abs(p - pstar) / pstar < 1e-2 and abs(f - pstar) / pstar < 1e-2, (p, f, pstar)
+        assert np.all(res.y[prob.is_ineq.astype(bool)] >= 0)
