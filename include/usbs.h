@@ -1,0 +1,198 @@
+/*
+ * usbs.h -- C ABI of the MI355X (gfx950) implementation of Unified Spectral
+ * Bundling with Sketching (USBS), Angell & McCallum, arXiv 2312.11801.
+ *
+ * The library solves the SDP pair (P)/(D) of Sec. 2.1:
+ *     (P)  maximise <C, X>  s.t.  A_I' X = b_I',  A_I X <= b_I,  X PSD
+ *     (D)  minimise <b, y>  s.t.  C - A^* y NSD,  y_I >= 0
+ * by the proximal bundle iteration of Alg. 1 on the penalized dual
+ *     f(y) = alpha [lambda_max(C - A^* y)]_+ + <b, y>,  y_I >= 0   (Sec. 3, eq. pen-D)
+ * with the spectral bundle model of Sec. 3.1, the candidate of Sec. 3.2
+ * (eq. dual_update), the master QP of App. B.2 and the Nystrom sketch of
+ * Sec. 4 / App. C.  Every step runs on one GPU in hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   * Return value: 0 on success, USBS_NOT_CONVERGED (> 0) when a solve
+ *     stopped at its iteration or time limit (outputs are still filled), a
+ *     negative USBS_E_* code on error.  usbs_last_error() gives the message.
+ *   * Pointers are host pointers unless the name ends in _dev (device
+ *     memory of the GPU current at usbs_create, allocated by the caller).
+ *   * usbs_create deep-copies the problem; the caller may free its arrays
+ *     when it returns.  The handle owns all device memory it allocates and
+ *     usbs_free releases it.  A handle is used by one host thread at a time.
+ *   * Matrices handed over the boundary are row-major.
+ *   * All quantities of the step-level entry points (usbs_op_*, usbs_step_*)
+ *     are in the scaled units of App. E (eq. std_scaling): C_s = C/||C||_F,
+ *     b_s = b/trace, y_s = y/||C||_F; usbs_solve reports both unit systems.
+ */
+#ifndef USBS_H
+#define USBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define USBS_OK 0
+#define USBS_NOT_CONVERGED 1
+#define USBS_E_INVALID (-1) /* malformed problem or parameters              */
+#define USBS_E_NOMEM (-2)   /* device allocation failed (HBM budget)        */
+#define USBS_E_DEVICE (-3)  /* HIP runtime error                            */
+#define USBS_E_NUMERIC (-4) /* NaN/Inf in data or a failed inner solve      */
+#define USBS_E_STATE (-5)   /* call out of order (e.g. warm start on NULL)  */
+
+/* arithmetic of the sparse products and the sketch (Lanczos
+ * re-orthogonalisation, Ritz problems and the master QP are always FP64) */
+#define USBS_PREC_F64 0
+#define USBS_PREC_F32 1
+#define USBS_PREC_BF16 2
+
+/* units of the stopping metrics */
+#define USBS_UNITS_SCALED 0   /* the scaled problem of App. E (the paper's setting) */
+#define USBS_UNITS_ORIGINAL 1 /* the problem as handed in                           */
+
+typedef struct usbs_handle usbs_handle;
+
+/* The SDP instance (Sec. 2.1).
+ *   C: symmetric, CSR with both triangles and the diagonal (rowptr[n+1],
+ *      col[nnz], val[nnz]); columns within a row in any order.
+ *   A: triplets (a_row[t], a_i[t], a_j[t], a_v[t]) with a_i <= a_j, meaning
+ *      <A_k, X> = sum over the triplets of row k of v * X_ij.  Each off-diagonal
+ *      pair (i,j) may appear in at most one triplet.
+ *   b[m], is_ineq[m] (1 = row belongs to I, i.e. <A_k, X> <= b_k).
+ *   trace: tr(X*) (or the value the constraints fix, e.g. n for MaxCut),
+ *      used by the scaling of App. E.
+ *   psi:  n x r row-major Gaussian test matrix of the Nystrom sketch (Sec. 4),
+ *      or NULL to run without the sketch. */
+typedef struct usbs_problem {
+    int64_t n;
+    const int64_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    int64_t m;
+    int64_t n_triplets;
+    const int32_t *a_row;
+    const int32_t *a_i;
+    const int32_t *a_j;
+    const double *a_v;
+    const double *b;
+    const uint8_t *is_ineq;
+    double trace;
+    const float *psi;
+} usbs_problem;
+
+/* Parameters (defaults from usbs_default_params: the MaxCut settings of
+ * App. E.1: alpha 2, rho 0.01, beta 0.25, k_c 10, k_p 1, r 10). */
+typedef struct usbs_params {
+    double alpha, rho, beta;
+    int32_t k_c, k_p, r;
+    double eps_gap, eps_infeas; /* stop when both relative errors <= eps   */
+    int32_t units;              /* USBS_UNITS_*                            */
+    int32_t max_iters;
+    double time_limit;          /* seconds, <= 0 for none                  */
+    int32_t lanczos_steps;      /* block steps per restart cycle (b = 8)   */
+    int32_t lanczos_max_restarts;
+    double lanczos_tol;         /* residual / spectral-radius estimate      */
+    int32_t precision;          /* USBS_PREC_*                             */
+    uint64_t seed;              /* start block of the cold Lanczos solve   */
+    void *stream;               /* hipStream_t, NULL = default stream       */
+    int32_t verbose;
+} usbs_params;
+
+typedef struct usbs_result {
+    double primal_obj;        /* <C, X_T>, original units                         */
+    double dual_bound;        /* f(y_T), original units (>= p* when alpha >= 2 tr X*) */
+    double primal_obj_scaled; /* <C_s, X_T>                                       */
+    double f_scaled;          /* f(y_T) in scaled units                           */
+    double rel_gap;           /* |f - <C,X>| / (1 + |<C,X>|), units per params    */
+    double rel_infeas;        /* dist(A X, K) / (1 + ||b||), units per params     */
+    double lambda_max;        /* largest Ritz value of C_s - A^* y at the last candidate */
+    double sketch_primal_obj; /* <C, Xhat> of the Nystrom reconstruction (original units) */
+    double sketch_rel_infeas; /* dist(A Xhat, K)/(1+||b||) (units per params)     */
+    double seconds;
+    int64_t lanczos_matvecs;  /* columns multiplied by C - A^* y                  */
+    int32_t iters, descents, ipm_iters, status;
+} usbs_result;
+
+int usbs_default_params(usbs_params *prm);
+
+/* Validate, scale (App. E) and upload the problem; cold start of Alg. 1
+ * (y0 = 0, V0 = top-k eigenvectors of C_s, Xbar0 = 0). */
+int usbs_create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **out);
+
+/* Run Alg. 1 until both relative errors are <= eps or a limit is hit.
+ * y_out[m] (original units), U_out[n*r], lam_out[r] (rank-r Nystrom factors
+ * of Xbar, App. C.1, original units) may each be NULL. */
+int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, double *lam_out);
+
+/* Warm start (Sec. 5.1): replace the problem by a grown one whose first
+ * n_old vertices, first m_old constraint rows and their data are unchanged
+ * (appended vertices/rows only).  y, Xbar's tracked quantities and the
+ * sketch are padded with zeros and rescaled to the new scaling; V is padded
+ * with zero rows and re-orthonormalised.  The next usbs_solve continues. */
+int usbs_warm_start(usbs_handle *h, const usbs_problem *grown);
+
+void usbs_free(usbs_handle *h); /* NULL-safe */
+const char *usbs_last_error(const usbs_handle *h);
+
+/* ---------------------------------------------------------------------
+ * Step-level entry points: each runs one row of the hot path on device
+ * arrays, for parity testing and for callers that drive the iteration.
+ * ------------------------------------------------------------------- */
+
+/* Y_dev = (C_s - A^* y) X_dev for an n x nb block (nb in 1..16), row-major
+ * with leading dimensions ldx, ldy; y_dev (length m) sets the shift
+ * (Sec. 3, the operator whose lambda_max defines f). */
+int usbs_op_apply(usbs_handle *h, const double *y_dev, const double *X_dev, int32_t ldx,
+                  double *Y_dev, int32_t ldy, int32_t nb);
+
+/* Top eigenpairs of C_s - A^* y (the eigen step behind f(y), Sec. 3, by
+ * block Lanczos).  w (host, k values, descending), U_dev (n x 16 row-major,
+ * first k columns = eigenvectors), res (host, k residual norms) may be NULL;
+ * start_dev (n x 16) optional warm start.  Returns restarts used in *cycles. */
+int usbs_op_eigs(usbs_handle *h, const double *y_dev, int32_t k, const double *start_dev,
+                 double *w, double *U_dev, double *res, int32_t *cycles);
+
+/* (A(W diag(lam) W^T))_k for all rows k (App. C): out_dev[m];
+ * W_dev is n x q row-major (q <= 16), lam host [q]. */
+int usbs_op_lowrank_A(usbs_handle *h, const double *W_dev, int32_t q, const double *lam,
+                      double *out_dev);
+
+/* Sketch update of Sec. 4: P_dev <- g P_dev + W diag(lam) (W^T Psi), with
+ * W_dev n x q (q <= 16), P_dev n x r (FP64 here), the handle's Psi. */
+int usbs_op_sketch_update(usbs_handle *h, double g, const double *W_dev, int32_t q,
+                          const double *lam, double *P_dev);
+
+/* Master QP data (App. B.2, eq. compressed_subprob_2) for orthonormal
+ * V_dev (n x k, k <= 16), duals y_dev, w_dev = b - nu (m), zbar_dev (m),
+ * scalars tau, cbar.  Outputs (host): Q11 [d*d], q12 [d], q22, h1 [d], h2,
+ * d = k(k+1)/2, svec ordering of App. B (column-wise lower triangle). */
+int usbs_op_qp_data(usbs_handle *h, const double *V_dev, int32_t k, const double *y_dev,
+                    const double *w_dev, const double *zbar_dev, double tau, double cbar,
+                    double *Q11, double *q12, double *q22, double *h1, double *h2);
+
+/* Interior point solve of the master QP (App. B.2) on the device from host
+ * data (same layout as usbs_op_qp_data).  Outputs S [k*k], eta, and the
+ * Newton iteration count. */
+int usbs_op_ipm(usbs_handle *h, int32_t k, const double *Q11, const double *q12, double q22,
+                const double *h1, double h2, double *S, double *eta, int32_t *iters);
+
+/* Nystrom reconstruction (App. C.1, stable fixed-rank PSD method) of the
+ * sketch P_dev (n x r, FP64) with the handle's Psi: U_dev (n x r), lam (host r). */
+int usbs_op_nystrom(usbs_handle *h, const double *P_dev, double *U_dev, double *lam);
+
+/* Run t iterations of Alg. 1 (no stopping test) and copy out the state in
+ * scaled units: y (m), V (n x 16, first k columns), zbar (m), Pbar (n x r),
+ * scal[8] = {f, tau, cbar, primal, rel_gap, rel_infeas, lambda1, descents}.
+ * Any output may be NULL. */
+int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *zbar,
+                      double *Pbar, double *scal);
+
+/* Scaling factors of the handle's problem: sigma = ||C||_F, trace. */
+int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* USBS_H */

@@ -1,0 +1,108 @@
+// Launchers for the gfx950 kernels of the USBS hot path.  Every launcher
+// enqueues on the given stream and returns immediately; shapes are checked by
+// the caller (usbs.hip) before any launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace usbs {
+
+constexpr int kWG = 256;          // threads of every workgroup
+constexpr int kMaxK = 12;         // bundle width k = k_c + k_p handled by the device IPM
+constexpr int kMaxSvec = kMaxK * (kMaxK + 1) / 2;
+constexpr int kRitz = 16;         // Ritz vectors kept per Lanczos restart
+constexpr int kBlk = 8;           // Lanczos block width
+constexpr int kMaxSteps = 8;      // block steps per restart cycle
+constexpr int kMaxBasis = kRitz + kBlk * kMaxSteps;   // 80
+constexpr int kMaxRank = 16;      // sketch rank r
+
+// Scratch of the two-stage reductions: per-workgroup partial results plus a
+// completion counter; the last workgroup to finish reduces the partials in a
+// fixed order (deterministic) and resets the counter.
+struct RedScratch {
+    double *partials;
+    unsigned int *counter;
+    int max_blocks;
+    int max_elems;   // doubles per partial
+};
+
+// ---- sparse operator --------------------------------------------------
+// Y[i, c] = diag[i] * X[i, c] + scale * sum_e val[e] * X[col[e], c],  c < nb
+void spmm(hipStream_t s, int prec, int n, const int *rowptr, const int *col, const void *val,
+          double scale, const double *diag, const double *X, int ldx, double *Y, int ldy, int nb);
+// d[i] = cdiag[i] - sum over the diagonal triplets of vertex i of v * y[k]
+void diag_shift(hipStream_t s, int n, const int *dptr, const int *dk, const double *dv,
+                const double *cdiag, const double *y, double *d);
+// val[slot[t]] = (cbase[slot[t]] - hv[t] * y[k[t]]) / scale  (constrained off-diagonal slots)
+void offdiag_refresh(hipStream_t s, int prec, int nt, const int *slot, const int *k,
+                     const double *hv, const double *cbase, const double *y, double inv_scale,
+                     void *val);
+// copy base values into the compute-precision value array
+void convert_values(hipStream_t s, int prec, int nnz, const double *src, double inv_scale, void *dst);
+
+// ---- tall-skinny dense --------------------------------------------------
+// H[a*ldh + c] = beta*H + alpha * sum_i A[i*lda + a] * B[i*ldb + c]   (a < ca <= 80, c < cb <= 32,
+// ca * cb <= 1280)
+// post: 0 = store; 1 = Cholesky-QR factor (H must be square; writes R^{-1} into H and
+//       deflation flags into flags[0..ca) with the column offset flag_off)
+void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,
+               const double *B, int ldb, int cb, double *H, int ldh, double alpha, double beta,
+               int post = 0, int *flags = nullptr, const double *floor_ref = nullptr);
+void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,
+                 const float *B, int ldb, int cb, double *H, int ldh, double alpha);
+// C[i*ldc + c] = beta*C + alpha * sum_a A[i*lda + a] * H[a*ldh + c]   (c < cc <= 16, ca <= 80)
+void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
+               int cc, double *C, int ldc, double alpha, double beta);
+// same with a float32 destination (sketch storage)
+void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
+                 int cc, float *C, int ldc, double alpha, double beta);
+// C (n x cc, ldc) = A (n x cc, lda) (+ copy of float)
+void copy_cols(hipStream_t s, int n, const double *A, int lda, int cc, double *C, int ldc);
+void fill(hipStream_t s, size_t count, double v, double *p);
+// deterministic pseudo-random start block (counter hash, uniform in [-1, 1])
+void random_block(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ldc);
+
+// ---- small dense problems (one workgroup) --------------------------------
+// eigen-decomposition of the symmetric N x N matrix A (ld lda, N <= kMaxBasis):
+// w[0..N) descending, Y (N x ny, ldy) = first ny eigenvectors; entries of
+// 'dead' (length N, may be null) mark columns to push to the bottom.
+void small_eig(hipStream_t s, int N, const double *A, int lda, double *w, double *Y, int ldy,
+               int ny, const int *dead);
+
+// ---- Lanczos helpers ----------------------------------------------------
+// from R^T R (16 x 16) and Ritz values theta: residual norms res, convergence
+// flag (res_i <= tol * scale for i < kc), and Z (16 x 8) = top-8 right singular
+// directions scaled by 1/sigma, so that R Z has orthonormal columns.
+void lanczos_restart_prep(hipStream_t s, const double *RtR, const double *theta, int kc, double tol,
+                          double *res, int *flag, double *Z, double *scale_est);
+// T (ld) := 0 with diag(theta) in the leading 16 x 16 block; dead flags cleared
+void lanczos_reset_T(hipStream_t s, double *T, int ldt, int N, const double *theta, int *dead);
+// H = -diag(theta) (16 x 16)
+void neg_diag(hipStream_t s, const double *theta, int N, double *H);
+
+// ---- USBS small steps ----------------------------------------------------
+// Q11 partial sums and the G^T w products of the master QP (App. B.2).
+// out layout: [0, d*d) Q11 (unscaled sum g g^T), then G^T w_j for j < nw (d each)
+void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const int *ti,
+             const int *tj, const double *tv, const double *V, int ldv, int k, const double *const *w,
+             int nw, double *out, int do_q11);
+// z[k] = beta*z[k] + gamma*zb[k] + alpha * sum_t v_t V_i^T K V_j  (K k x k symmetric, device)
+void lowrank_A(hipStream_t s, int m, const int *kptr, const int *ti, const int *tj, const double *tv,
+               const double *V, int ldv, int k, const double *K, double alpha, const double *zb,
+               const double *gamma_dev, double gamma_host, double *z, double beta);
+// dot products / norms with a deterministic two-stage reduction:
+// out[j] = sum_i a_j[i] * b_j[i] for the given pairs (<= 8)
+void dots(hipStream_t s, const RedScratch &rs, int m, const double *const *a, const double *const *b,
+          int np, double *out);
+
+struct IpmArgs {
+    int k;
+    double tol_mu, tol_res;
+    int max_iter;
+    int warm;          // start from the state in 'state' instead of the default point
+};
+// interior point method of App. B.2 on one workgroup.  qp = [Q11 (d*d) | q12 (d) | q22 | h1 (d) | h2]
+// state = [S (k*k) | T (k*k) | eta | zeta | omega | iters | status]
+void ipm(hipStream_t s, const IpmArgs &a, const double *qp, double *state);
+
+}  // namespace usbs

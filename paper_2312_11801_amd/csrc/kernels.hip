@@ -1,0 +1,716 @@
+// gfx950 kernels of the USBS hot path: sparse shifted operator, tall-skinny
+// dense products for block Lanczos / sketch / low-rank constraint
+// evaluation, and one-workgroup solvers for the small dense problems
+// (Ritz eigenproblems, Cholesky-QR factors, the master-QP interior point method).
+//
+// Layout conventions: every n x c block is row-major (row i = c contiguous
+// values), so a gathered row of an 8-column block is one 64-byte segment and
+// a column slice of the Lanczos basis is addressed by (pointer + offset, ld).
+#include "kernels.h"
+#include "small_dense.h"
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace usbs {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    // round to nearest even
+    uint32_t u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    u = __float_as_uint(f);
+#else
+    memcpy(&u, &f, 4);
+#endif
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// SpMM with the shifted diagonal: L lanes per row, lane c owns column c.
+// The column index / value of a nonzero is read once per row group and
+// broadcast; the gathered X row segment is contiguous.
+// ---------------------------------------------------------------------------
+template <typename VT, typename ACC, int L>
+__global__ __launch_bounds__(kWG) void k_spmm(int n, const int *__restrict__ rowptr,
+                                              const int *__restrict__ col,
+                                              const VT *__restrict__ val, ACC scale,
+                                              const double *__restrict__ diag,
+                                              const double *__restrict__ X, int ldx,
+                                              double *__restrict__ Y, int ldy, int nb) {
+    const int i = blockIdx.x * (kWG / L) + threadIdx.x / L;
+    const int c = threadIdx.x % L;
+    if (i >= n) return;
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    const bool act = c < nb;
+    const int cc = act ? c : 0;
+    ACC acc0 = 0, acc1 = 0;
+    int e = e0;
+    for (; e + 1 < e1; e += 2) {
+        const int j0 = col[e], j1 = col[e + 1];
+        ACC v0, v1;
+        if constexpr (sizeof(VT) == 2) {
+            v0 = (ACC)bf16_to_f32(val[e]);
+            v1 = (ACC)bf16_to_f32(val[e + 1]);
+        } else {
+            v0 = (ACC)val[e];
+            v1 = (ACC)val[e + 1];
+        }
+        const ACC x0 = (ACC)X[(size_t)j0 * ldx + cc];
+        const ACC x1 = (ACC)X[(size_t)j1 * ldx + cc];
+        acc0 += v0 * x0;
+        acc1 += v1 * x1;
+    }
+    if (e < e1) {
+        const int j0 = col[e];
+        ACC v0;
+        if constexpr (sizeof(VT) == 2) v0 = (ACC)bf16_to_f32(val[e]);
+        else v0 = (ACC)val[e];
+        acc0 += v0 * (ACC)X[(size_t)j0 * ldx + cc];
+    }
+    if (act) {
+        const double xi = X[(size_t)i * ldx + c];
+        Y[(size_t)i * ldy + c] = diag[i] * xi + (double)(scale * (acc0 + acc1));
+    }
+}
+
+template <typename VT, typename ACC>
+static void spmm_t(hipStream_t s, int n, const int *rowptr, const int *col, const VT *val, ACC scale,
+                   const double *diag, const double *X, int ldx, double *Y, int ldy, int nb) {
+    if (n <= 0) return;
+    if (nb <= 8) {
+        hipLaunchKernelGGL((k_spmm<VT, ACC, 8>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, rowptr, col,
+                           val, scale, diag, X, ldx, Y, ldy, nb);
+    } else {
+        hipLaunchKernelGGL((k_spmm<VT, ACC, 16>), dim3(cdiv(n, kWG / 16)), dim3(kWG), 0, s, n, rowptr,
+                           col, val, scale, diag, X, ldx, Y, ldy, nb);
+    }
+}
+
+void spmm(hipStream_t s, int prec, int n, const int *rowptr, const int *col, const void *val,
+          double scale, const double *diag, const double *X, int ldx, double *Y, int ldy, int nb) {
+    if (prec == 0)
+        spmm_t<double, double>(s, n, rowptr, col, (const double *)val, scale, diag, X, ldx, Y, ldy, nb);
+    else if (prec == 1)
+        spmm_t<float, float>(s, n, rowptr, col, (const float *)val, (float)scale, diag, X, ldx, Y, ldy, nb);
+    else
+        spmm_t<uint16_t, float>(s, n, rowptr, col, (const uint16_t *)val, (float)scale, diag, X, ldx, Y,
+                                ldy, nb);
+}
+
+// ---------------------------------------------------------------------------
+// shift of the operator by A^* y
+// ---------------------------------------------------------------------------
+__global__ void k_diag_shift(int n, const int *__restrict__ dptr, const int *__restrict__ dk,
+                             const double *__restrict__ dv, const double *__restrict__ cdiag,
+                             const double *__restrict__ y, double *__restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double v = cdiag[i];
+    for (int e = dptr[i]; e < dptr[i + 1]; ++e) v -= dv[e] * y[dk[e]];
+    d[i] = v;
+}
+
+void diag_shift(hipStream_t s, int n, const int *dptr, const int *dk, const double *dv,
+                const double *cdiag, const double *y, double *d) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_diag_shift, dim3(cdiv(n, kWG)), dim3(kWG), 0, s, n, dptr, dk, dv, cdiag, y, d);
+}
+
+template <typename VT>
+__global__ void k_offdiag_refresh(int nt, const int *__restrict__ slot, const int *__restrict__ kk,
+                                  const double *__restrict__ hv, const double *__restrict__ cbase,
+                                  const double *__restrict__ y, double inv_scale, VT *__restrict__ val) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const int sl = slot[t];
+    const double v = (cbase[sl] - hv[t] * y[kk[t]]) * inv_scale;
+    if constexpr (sizeof(VT) == 2) val[sl] = f32_to_bf16((float)v);
+    else val[sl] = (VT)v;
+}
+
+void offdiag_refresh(hipStream_t s, int prec, int nt, const int *slot, const int *k, const double *hv,
+                     const double *cbase, const double *y, double inv_scale, void *val) {
+    if (nt <= 0) return;
+    dim3 g(cdiv(nt, kWG));
+    if (prec == 0)
+        hipLaunchKernelGGL(k_offdiag_refresh<double>, g, dim3(kWG), 0, s, nt, slot, k, hv, cbase, y,
+                           inv_scale, (double *)val);
+    else if (prec == 1)
+        hipLaunchKernelGGL(k_offdiag_refresh<float>, g, dim3(kWG), 0, s, nt, slot, k, hv, cbase, y,
+                           inv_scale, (float *)val);
+    else
+        hipLaunchKernelGGL(k_offdiag_refresh<uint16_t>, g, dim3(kWG), 0, s, nt, slot, k, hv, cbase, y,
+                           inv_scale, (uint16_t *)val);
+}
+
+template <typename VT>
+__global__ void k_convert(int nnz, const double *__restrict__ src, double inv_scale, VT *__restrict__ dst) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    const double v = src[e] * inv_scale;
+    if constexpr (sizeof(VT) == 2) dst[e] = f32_to_bf16((float)v);
+    else dst[e] = (VT)v;
+}
+
+void convert_values(hipStream_t s, int prec, int nnz, const double *src, double inv_scale, void *dst) {
+    if (nnz <= 0) return;
+    dim3 g(cdiv(nnz, kWG));
+    if (prec == 0)
+        hipLaunchKernelGGL(k_convert<double>, g, dim3(kWG), 0, s, nnz, src, inv_scale, (double *)dst);
+    else if (prec == 1)
+        hipLaunchKernelGGL(k_convert<float>, g, dim3(kWG), 0, s, nnz, src, inv_scale, (float *)dst);
+    else
+        hipLaunchKernelGGL(k_convert<uint16_t>, g, dim3(kWG), 0, s, nnz, src, inv_scale, (uint16_t *)dst);
+}
+
+// ---------------------------------------------------------------------------
+// H = beta*H + alpha*A^T B : two-stage deterministic reduction over rows.
+// Stage 1: each workgroup streams 32-row tiles of A and B through LDS and
+// accumulates its share of the (ca x cb) outputs in registers.
+// Stage 2: the last workgroup to finish sums the partials in block order.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 32;
+constexpr int kMaxCB = 32;
+constexpr int kMaxOut = kMaxBasis * 16;          // 1280 outputs (also >= 32 x 32)
+constexpr int kOutPerThread = (kMaxOut + kWG - 1) / kWG;
+
+template <typename TB, int POST>
+__global__ __launch_bounds__(kWG) void k_tn_reduce(int n, const double *__restrict__ A, int lda, int ca,
+                                                   const TB *__restrict__ B, int ldb, int cb, double *H,
+                                                   int ldh, double alpha, double beta, double *partials,
+                                                   unsigned int *counter, int *flags, const double *floor_ref) {
+    __shared__ double sA[kTile][kMaxBasis + 1];
+    __shared__ double sB[kTile][kMaxCB + 1];
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    const int nout = ca * cb;
+    double acc[kOutPerThread];
+#pragma unroll
+    for (int q = 0; q < kOutPerThread; ++q) acc[q] = 0.0;
+
+    for (long row0 = (long)blockIdx.x * kTile; row0 < n; row0 += (long)gridDim.x * kTile) {
+        for (int e = tid; e < kTile * ca; e += kWG) {
+            const int r = e / ca, a = e - r * ca;
+            const long i = row0 + r;
+            sA[r][a] = (i < n) ? A[i * lda + a] : 0.0;
+        }
+        for (int e = tid; e < kTile * cb; e += kWG) {
+            const int r = e / cb, c = e - r * cb;
+            const long i = row0 + r;
+            sB[r][c] = (i < n) ? (double)B[i * ldb + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kOutPerThread; ++q) {
+            const int o = tid + q * kWG;
+            if (o < nout) {
+                const int a = o / cb, c = o - a * cb;
+                double s = 0.0;
+#pragma unroll 8
+                for (int r = 0; r < kTile; ++r) s += sA[r][a] * sB[r][c];
+                acc[q] += s;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kOutPerThread; ++q) {
+        const int o = tid + q * kWG;
+        if (o < nout) partials[(size_t)blockIdx.x * nout + o] = acc[q];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) {
+        const unsigned int prev = atomicAdd(counter, 1u);
+        s_last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    __shared__ double sR[16 * 17];
+    for (int o = tid; o < nout; o += kWG) {
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) s += __builtin_nontemporal_load(&partials[(size_t)b * nout + o]);
+        const int a = o / cb, c = o - a * cb;
+        double v = alpha * s;
+        if (POST == 0) {
+            if (beta != 0.0) v += beta * H[a * ldh + c];
+            H[a * ldh + c] = v;
+        } else {
+            sR[a * 17 + c] = v;
+        }
+    }
+    if (tid == 0) *counter = 0u;
+    if (POST == 1) {
+        __syncthreads();
+        // Cholesky-QR factor: G = R^T R, write R^{-1} (upper) to H; a column whose
+        // pivot falls below max(1e-24 max diag, (1e-10 ref)^2) is deflated (zero
+        // column of R^{-1}): it lies in the span of the basis already.
+        double f2 = 0.0;
+        if (floor_ref) {
+            const double rf = 1e-10 * (*floor_ref);
+            f2 = rf * rf;
+        }
+        if (tid < 64) wave_cholqr(ca, sR, 17, H, ldh, flags, f2);
+    }
+}
+
+void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
+               int ldb, int cb, double *H, int ldh, double alpha, double beta, int post, int *flags,
+               const double *floor_ref) {
+    int blocks = cdiv(n, 4 * kTile);
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks < 1) blocks = 1;
+    if (post == 0)
+        hipLaunchKernelGGL((k_tn_reduce<double, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
+                           H, ldh, alpha, beta, rs.partials, rs.counter, flags, floor_ref);
+    else
+        hipLaunchKernelGGL((k_tn_reduce<double, 1>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
+                           H, ldh, alpha, beta, rs.partials, rs.counter, flags, floor_ref);
+}
+
+void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const float *B,
+                 int ldb, int cb, double *H, int ldh, double alpha) {
+    int blocks = cdiv(n, 4 * kTile);
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_tn_reduce<float, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, H,
+                       ldh, alpha, 0.0, rs.partials, rs.counter, (int *)nullptr, (const double *)nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// C = beta*C + alpha*A H : rows of A staged through LDS, H (ca x cc) in LDS,
+// L lanes per output row.
+// ---------------------------------------------------------------------------
+template <typename TC, int L>
+__global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restrict__ A, int lda, int ca,
+                                                   const double *__restrict__ H, int ldh, int cc,
+                                                   TC *__restrict__ C, int ldc, double alpha, double beta) {
+    constexpr int R = kWG / L;  // rows per workgroup
+    __shared__ double sH[kMaxBasis * 16];
+    __shared__ double sA[R][kMaxBasis + 1];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < ca * cc; e += kWG) {
+        const int a = e / cc, c = e - a * cc;
+        sH[e] = H[a * ldh + c];
+    }
+    const long row0 = (long)blockIdx.x * R;
+    for (int e = tid; e < R * ca; e += kWG) {
+        const int r = e / ca, a = e - r * ca;
+        const long i = row0 + r;
+        sA[r][a] = (i < n) ? A[i * lda + a] : 0.0;
+    }
+    __syncthreads();
+    const int r = tid / L, c = tid % L;
+    const long i = row0 + r;
+    if (i >= n || c >= cc) return;
+    double s = 0.0;
+    for (int a = 0; a < ca; ++a) s += sA[r][a] * sH[a * cc + c];
+    double v = alpha * s;
+    if (beta != 0.0) v += beta * (double)C[i * ldc + c];
+    C[i * ldc + c] = (TC)v;
+}
+
+template <typename TC>
+static void nn_update_t(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
+                        int cc, TC *C, int ldc, double alpha, double beta) {
+    if (n <= 0 || cc <= 0) return;
+    if (cc <= 4)
+        hipLaunchKernelGGL((k_nn_update<TC, 4>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, A, lda, ca, H, ldh,
+                           cc, C, ldc, alpha, beta);
+    else if (cc <= 8)
+        hipLaunchKernelGGL((k_nn_update<TC, 8>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, A, lda, ca, H, ldh,
+                           cc, C, ldc, alpha, beta);
+    else
+        hipLaunchKernelGGL((k_nn_update<TC, 16>), dim3(cdiv(n, kWG / 16)), dim3(kWG), 0, s, n, A, lda, ca, H,
+                           ldh, cc, C, ldc, alpha, beta);
+}
+
+void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
+               double *C, int ldc, double alpha, double beta) {
+    nn_update_t<double>(s, n, A, lda, ca, H, ldh, cc, C, ldc, alpha, beta);
+}
+void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
+                 float *C, int ldc, double alpha, double beta) {
+    nn_update_t<float>(s, n, A, lda, ca, H, ldh, cc, C, ldc, alpha, beta);
+}
+
+__global__ void k_copy_cols(int n, const double *__restrict__ A, int lda, int cc, double *__restrict__ C,
+                            int ldc) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * cc) return;
+    const long i = e / cc;
+    const int c = (int)(e - i * cc);
+    C[i * ldc + c] = A[i * lda + c];
+}
+void copy_cols(hipStream_t s, int n, const double *A, int lda, int cc, double *C, int ldc) {
+    if (n <= 0 || cc <= 0) return;
+    hipLaunchKernelGGL(k_copy_cols, dim3(cdiv((long)n * cc, kWG)), dim3(kWG), 0, s, n, A, lda, cc, C, ldc);
+}
+
+__global__ void k_fill(size_t count, double v, double *p) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = v;
+}
+void fill(hipStream_t s, size_t count, double v, double *p) {
+    if (count == 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(cdiv((long)count, kWG)), dim3(kWG), 0, s, count, v, p);
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    // splitmix64 finaliser
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__global__ void k_random_block(int n, int cc, uint64_t seed, double *C, int ldc) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * cc) return;
+    const long i = e / cc;
+    const int c = (int)(e - i * cc);
+    const uint64_t h = mix64(seed * 0x100000001B3ull + (uint64_t)e);
+    C[i * ldc + c] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+void random_block(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ldc) {
+    if (n <= 0 || cc <= 0) return;
+    hipLaunchKernelGGL(k_random_block, dim3(cdiv((long)n * cc, kWG)), dim3(kWG), 0, s, n, cc, seed, C, ldc);
+}
+
+// ---------------------------------------------------------------------------
+// small symmetric eigenproblem on one workgroup (parallel cyclic Jacobi)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_small_eig(int N, const double *__restrict__ A, int lda,
+                                                   double *__restrict__ w, double *__restrict__ Y, int ldy,
+                                                   int ny, const int *__restrict__ dead) {
+    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
+    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
+    __shared__ JacobiScratch js;
+    wg_load_sym(N, A, lda, dead, &sA[0][0], kMaxBasis + 1);
+    wg_jacobi(N, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
+    wg_sort_store(N, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, Y, ldy, ny, &js);
+}
+
+void small_eig(hipStream_t s, int N, const double *A, int lda, double *w, double *Y, int ldy, int ny,
+               const int *dead) {
+    hipLaunchKernelGGL(k_small_eig, dim3(1), dim3(kWG), 0, s, N, A, lda, w, Y, ldy, ny, dead);
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos restart: residual norms, convergence test and the compression of
+// the 16 Ritz residuals to the 8 dominant directions (next block).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__ RtR,
+                                                      const double *__restrict__ theta, int kc, double tol,
+                                                      double *__restrict__ res, int *__restrict__ flag,
+                                                      double *__restrict__ Z, double *__restrict__ scale_est) {
+    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
+    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
+    __shared__ JacobiScratch js;
+    __shared__ double wv[kRitz];
+    __shared__ double Yv[kRitz * kBlk];
+    const int tid = threadIdx.x;
+    if (tid < kRitz) res[tid] = sqrt(fmax(RtR[tid * kRitz + tid], 0.0));
+    wg_load_sym(kRitz, RtR, kRitz, nullptr, &sA[0][0], kMaxBasis + 1);
+    wg_jacobi(kRitz, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
+    wg_sort_store(kRitz, &sA[0][0], &sV[0][0], kMaxBasis + 1, wv, Yv, kBlk, kBlk, &js);
+    __syncthreads();
+    if (tid < kRitz * kBlk) {
+        const int c = tid % kBlk;
+        const double sg = sqrt(fmax(wv[c], 0.0));
+        const double ref = sqrt(fmax(wv[0], 0.0));
+        Z[tid] = (sg > 1e-150 && sg > 1e-14 * ref) ? Yv[tid] / sg : 0.0;
+    }
+    if (tid == 0) {
+        double sc = fmax(fabs(theta[0]), fabs(theta[kRitz - 1]));
+        if (scale_est) {
+            sc = fmax(sc, *scale_est);
+            *scale_est = sc;
+        }
+        int ok = 1;
+        for (int i = 0; i < kc; ++i) {
+            const double r = sqrt(fmax(RtR[i * kRitz + i], 0.0));
+            if (!(r <= tol * sc)) ok = 0;
+        }
+        *flag = ok;
+    }
+}
+
+void lanczos_restart_prep(hipStream_t s, const double *RtR, const double *theta, int kc, double tol,
+                          double *res, int *flag, double *Z, double *scale_est) {
+    hipLaunchKernelGGL(k_restart_prep, dim3(1), dim3(kWG), 0, s, RtR, theta, kc, tol, res, flag, Z, scale_est);
+}
+
+__global__ void k_reset_T(double *T, int ldt, int N, const double *theta, int *dead) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < N * ldt) {
+        const int a = e / ldt, c = e - a * ldt;
+        T[e] = (a == c && a < kRitz) ? theta[a] : 0.0;
+    }
+    if (e < N) dead[e] = 0;
+}
+void lanczos_reset_T(hipStream_t s, double *T, int ldt, int N, const double *theta, int *dead) {
+    hipLaunchKernelGGL(k_reset_T, dim3(cdiv((long)N * ldt, kWG)), dim3(kWG), 0, s, T, ldt, N, theta, dead);
+}
+
+__global__ void k_neg_diag(const double *theta, int N, double *H) {
+    const int e = threadIdx.x;
+    if (e < N * N) H[e] = (e / N == e % N) ? -theta[e / N] : 0.0;
+}
+void neg_diag(hipStream_t s, const double *theta, int N, double *H) {
+    hipLaunchKernelGGL(k_neg_diag, dim3(1), dim3(kWG), 0, s, theta, N, H);
+}
+
+// ---------------------------------------------------------------------------
+// constraint-side kernels of the bundle (App. B.2 and App. C)
+// ---------------------------------------------------------------------------
+// g_k = svec(V^T A_k V) for one constraint row k into g[0..d)
+__device__ __forceinline__ void svec_constraint(int k, const int *__restrict__ kptr, const int *__restrict__ ti,
+                                                const int *__restrict__ tj, const double *__restrict__ tv,
+                                                const double *__restrict__ V, int ldv, int kd, double *g) {
+    // g may live in LDS
+    const double r2 = 1.4142135623730951;
+    int d = kd * (kd + 1) / 2;
+    for (int p = 0; p < d; ++p) g[p] = 0.0;
+    for (int t = kptr[k]; t < kptr[k + 1]; ++t) {
+        const double *vi = V + (size_t)ti[t] * ldv;
+        const double *vj = V + (size_t)tj[t] * ldv;
+        const double v = tv[t];
+        int p = 0;
+        for (int b = 0; b < kd; ++b) {
+            const double vib = vi[b], vjb = vj[b];
+            for (int a = b; a < kd; ++a) {
+                if (a == b) g[p] += v * vi[a] * vjb;
+                else g[p] += v * r2 * 0.5 * (vi[a] * vjb + vib * vj[a]);
+                ++p;
+            }
+        }
+    }
+}
+
+// Q11 raw sum and G^T w_j.  Constraints are processed in batches of 64 staged
+// in LDS; each thread owns a fixed set of (P,Q) entries of the upper triangle.
+constexpr int kQB = 64;
+__global__ __launch_bounds__(kWG) void k_qp_gram(int m, const int *__restrict__ kptr, const int *__restrict__ ti,
+                                                 const int *__restrict__ tj, const double *__restrict__ tv,
+                                                 const double *__restrict__ V, int ldv, int kd, int do_q11,
+                                                 const double *w0, const double *w1, const double *w2,
+                                                 const double *w3, int nw, double *partials,
+                                                 unsigned int *counter, double *out) {
+    __shared__ double sg[kQB][kMaxSvec + 1];
+    __shared__ double sw[4][kQB];
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    const int d = kd * (kd + 1) / 2;
+    const int nupper = do_q11 ? d * (d + 1) / 2 : 0;
+    const int nout = nupper + nw * d;
+    constexpr int kPer = (kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec + kWG - 1) / kWG;
+    double acc[kPer];
+    int pP[kPer], pQ[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        acc[q] = 0.0;
+        const int o = tid + q * kWG;
+        pP[q] = -1;
+        pQ[q] = -1;
+        if (o < nupper) {
+            // o -> (P, Q) with P <= Q in row-major upper-triangle order
+            int P = 0, rem = o;
+            while (rem >= d - P) { rem -= d - P; ++P; }
+            pP[q] = P;
+            pQ[q] = P + rem;
+        } else if (o < nout) {
+            const int j = (o - nupper) / d;
+            pP[q] = -(j + 2);               // weight vector j
+            pQ[q] = (o - nupper) - j * d;   // svec entry
+        }
+    }
+    const double *ws[4] = {w0, w1, w2, w3};
+    for (long k0 = (long)blockIdx.x * kQB; k0 < m; k0 += (long)gridDim.x * kQB) {
+        if (tid < kQB) {
+            const long k = k0 + tid;
+            if (k < m) svec_constraint((int)k, kptr, ti, tj, tv, V, ldv, kd, &sg[tid][0]);
+            else for (int p = 0; p < d; ++p) sg[tid][p] = 0.0;
+            for (int j = 0; j < nw; ++j) sw[j][tid] = (k < m) ? ws[j][k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int P = pP[q], Q = pQ[q];
+            if (Q < 0) continue;
+            double s = 0.0;
+            if (P >= 0) {
+                for (int r = 0; r < kQB; ++r) s += sg[r][P] * sg[r][Q];
+            } else {
+                const int j = -P - 2;
+                for (int r = 0; r < kQB; ++r) s += sw[j][r] * sg[r][Q];
+            }
+            acc[q] += s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int o = tid + q * kWG;
+        if (o < nout) partials[(size_t)blockIdx.x * nout + o] = acc[q];
+    }
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int o = tid + q * kWG;
+        if (o >= nout) continue;
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) s += __builtin_nontemporal_load(&partials[(size_t)b * nout + o]);
+        const int P = pP[q], Q = pQ[q];
+        if (P >= 0) {
+            out[P * d + Q] = s;
+            out[Q * d + P] = s;
+        } else {
+            const int j = -P - 2;
+            out[d * d + j * d + Q] = s;
+        }
+    }
+    if (tid == 0) *counter = 0u;
+}
+
+void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const int *ti, const int *tj,
+             const double *tv, const double *V, int ldv, int k, const double *const *w, int nw, double *out,
+             int do_q11) {
+    int blocks = cdiv(m, 2 * kQB);
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks > 240) blocks = 240;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_qp_gram, dim3(blocks), dim3(kWG), 0, s, m, kptr, ti, tj, tv, V, ldv, k, do_q11,
+                       nw > 0 ? w[0] : nullptr, nw > 1 ? w[1] : nullptr, nw > 2 ? w[2] : nullptr,
+                       nw > 3 ? w[3] : nullptr, nw, rs.partials, rs.counter, out);
+}
+
+__global__ __launch_bounds__(kWG) void k_lowrank_A(int m, const int *__restrict__ kptr, const int *__restrict__ ti,
+                                                   const int *__restrict__ tj, const double *__restrict__ tv,
+                                                   const double *__restrict__ V, int ldv, int kd,
+                                                   const double *__restrict__ K, double alpha, const double *zb,
+                                                   const double *gamma_dev, double gamma_host, double *z,
+                                                   double beta) {
+    // zb and z may be the same array: each thread reads its entry before writing it
+    __shared__ double sK[16 * 16];
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+        const int a = e >> 4, b = e & 15;
+        sK[e] = (a < kd && b < kd) ? K[a * kd + b] : 0.0;
+    }
+    __syncthreads();
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    double acc = 0.0;
+    for (int t = kptr[k]; t < kptr[k + 1]; ++t) {
+        const double *vi = V + (size_t)ti[t] * ldv;
+        const double *vj = V + (size_t)tj[t] * ldv;
+        double xj[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) xj[b] = (b < kd) ? vj[b] : 0.0;
+        double q = 0.0;
+#pragma unroll 1
+        for (int a = 0; a < kd; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < 16; ++b) s += sK[a * 16 + b] * xj[b];
+            q += vi[a] * s;
+        }
+        acc += tv[t] * q;
+    }
+    double v = alpha * acc;
+    if (zb) v += (gamma_dev ? *gamma_dev : gamma_host) * zb[k];
+    if (beta != 0.0) v += beta * z[k];
+    z[k] = v;
+}
+
+void lowrank_A(hipStream_t s, int m, const int *kptr, const int *ti, const int *tj, const double *tv,
+               const double *V, int ldv, int k, const double *K, double alpha, const double *zb,
+               const double *gamma_dev, double gamma_host, double *z, double beta) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_lowrank_A, dim3(cdiv(m, kWG)), dim3(kWG), 0, s, m, kptr, ti, tj, tv, V, ldv, k, K, alpha,
+                       zb, gamma_dev, gamma_host, z, beta);
+}
+
+constexpr int kMaxDots = 8;
+__global__ __launch_bounds__(kWG) void k_dots(int m, const double *a0, const double *a1, const double *a2,
+                                              const double *a3, const double *a4, const double *a5,
+                                              const double *a6, const double *a7, const double *b0,
+                                              const double *b1, const double *b2, const double *b3,
+                                              const double *b4, const double *b5, const double *b6,
+                                              const double *b7, int np, double *partials,
+                                              unsigned int *counter, double *out) {
+    const double *as[kMaxDots] = {a0, a1, a2, a3, a4, a5, a6, a7};
+    const double *bs[kMaxDots] = {b0, b1, b2, b3, b4, b5, b6, b7};
+    __shared__ double red[kMaxDots][kWG];
+    __shared__ int s_last;
+    const int tid = threadIdx.x;
+    double acc[kMaxDots];
+    for (int j = 0; j < kMaxDots; ++j) acc[j] = 0.0;
+    for (long i = (long)blockIdx.x * kWG + tid; i < m; i += (long)gridDim.x * kWG)
+        for (int j = 0; j < np; ++j) acc[j] += as[j][i] * bs[j][i];
+    for (int j = 0; j < np; ++j) red[j][tid] = acc[j];
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (tid < st)
+            for (int j = 0; j < np; ++j) red[j][tid] += red[j][tid + st];
+        __syncthreads();
+    }
+    if (tid < np) partials[(size_t)blockIdx.x * np + tid] = red[tid][0];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (tid < np) {
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b) s += __builtin_nontemporal_load(&partials[(size_t)b * np + tid]);
+        out[tid] = s;
+    }
+    if (tid == 0) *counter = 0u;
+}
+
+void dots(hipStream_t s, const RedScratch &rs, int m, const double *const *a, const double *const *b, int np,
+          double *out) {
+    int blocks = cdiv(m, 4 * kWG);
+    if (blocks > 256) blocks = 256;
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks < 1) blocks = 1;
+    const double *A[kMaxDots] = {}, *B[kMaxDots] = {};
+    for (int j = 0; j < np && j < kMaxDots; ++j) {
+        A[j] = a[j];
+        B[j] = b[j];
+    }
+    hipLaunchKernelGGL(k_dots, dim3(blocks), dim3(kWG), 0, s, m, A[0], A[1], A[2], A[3], A[4], A[5], A[6], A[7],
+                       B[0], B[1], B[2], B[3], B[4], B[5], B[6], B[7], np, rs.partials, rs.counter, out);
+}
+
+// ---------------------------------------------------------------------------
+// interior point method for the master QP (App. B.2), one workgroup
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_ipm(IpmArgs a, const double *__restrict__ qp, double *state) {
+    __shared__ IpmShared sh;
+    wg_ipm(a, qp, state, &sh);
+}
+
+void ipm(hipStream_t s, const IpmArgs &a, const double *qp, double *state) {
+    hipLaunchKernelGGL(k_ipm, dim3(1), dim3(kWG), 0, s, a, qp, state);
+}
+
+}  // namespace usbs

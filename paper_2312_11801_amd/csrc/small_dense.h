@@ -1,0 +1,744 @@
+// Small dense linear algebra for one workgroup (256 threads) or one wavefront
+// (64 lanes) of gfx950, FP64, operating on LDS arrays:
+//   * parallel cyclic Jacobi (round-robin pairing) for symmetric eigenproblems
+//     up to kMaxBasis (the Rayleigh-Ritz problems of block Lanczos, the
+//     eigen-split of S in Sec. 3.1, the Nystrom core of App. C.1);
+//   * Cholesky factors for Cholesky-QR and the Newton systems of the master QP;
+//   * the interior point method of App. B.2 for the master QP.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+
+namespace usbs {
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+    if constexpr (TEAM == kWG) __syncthreads();
+    else wave_sync();
+}
+
+template <int TEAM, int MAXN>
+struct JacobiWork {
+    int p[MAXN / 2];
+    int q[MAXN / 2];
+    double c[MAXN / 2];
+    double s[MAXN / 2];
+    double red[TEAM];
+    double fro;
+    double off;
+    int rank[MAXN];
+};
+using JacobiScratch = JacobiWork<kWG, kMaxBasis>;
+
+// team-wide sum; every lane gets the result
+template <int TEAM, int MAXN>
+__device__ double team_sum(double v, JacobiWork<TEAM, MAXN> *js, int lane) {
+    js->red[lane] = v;
+    team_sync<TEAM>();
+    if (lane == 0) {
+        double s = 0.0;
+        for (int i = 0; i < TEAM; ++i) s += js->red[i];
+        js->off = s;
+    }
+    team_sync<TEAM>();
+    const double r = js->off;
+    team_sync<TEAM>();
+    return r;
+}
+
+// In-place Jacobi on the symmetric Np x Np LDS matrix A (Np even); V receives
+// the eigenvectors (columns) when WANTV.  On exit diag(A) holds the eigenvalues.
+template <int TEAM, int MAXN, bool WANTV>
+__device__ void jacobi_core(int Np, double *A, double *V, int ld, JacobiWork<TEAM, MAXN> *js, int lane,
+                            int max_sweeps, double tol) {
+    if (WANTV)
+        for (int e = lane; e < Np * Np; e += TEAM) {
+            const int r = e / Np, c = e - r * Np;
+            V[r * ld + c] = (r == c) ? 1.0 : 0.0;
+        }
+    double s = 0.0;
+    for (int e = lane; e < Np * Np; e += TEAM) {
+        const int r = e / Np, c = e - r * Np;
+        s += A[r * ld + c] * A[r * ld + c];
+    }
+    const double fro = sqrt(team_sum<TEAM, MAXN>(s, js, lane));
+    const int half = Np / 2;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+        s = 0.0;
+        for (int e = lane; e < Np * Np; e += TEAM) {
+            const int r = e / Np, c = e - r * Np;
+            if (r < c) s += A[r * ld + c] * A[r * ld + c];
+        }
+        const double off = team_sum<TEAM, MAXN>(s, js, lane);
+        if (fro == 0.0 || sqrt(2.0 * off) <= tol * fro) break;
+        for (int rd = 0; rd < Np - 1; ++rd) {
+            if (lane < half) {
+                const int ia = lane, ib = Np - 1 - lane;
+                const int pa = (ia == 0) ? 0 : ((ia - 1 + rd) % (Np - 1)) + 1;
+                const int pb = ((ib - 1 + rd) % (Np - 1)) + 1;
+                const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
+                const double apq = A[p * ld + q], app = A[p * ld + p], aqq = A[q * ld + q];
+                double cc = 1.0, ss = 0.0;
+                if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * fro) {
+                    const double th = (aqq - app) / (2.0 * apq);
+                    double t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
+                    if (th < 0.0) t = -t;
+                    cc = 1.0 / sqrt(t * t + 1.0);
+                    ss = t * cc;
+                }
+                js->p[lane] = p;
+                js->q[lane] = q;
+                js->c[lane] = cc;
+                js->s[lane] = ss;
+            }
+            team_sync<TEAM>();
+            for (int e = lane; e < half * Np; e += TEAM) {
+                const int pi = e / Np, k = e - pi * Np;
+                const double ss = js->s[pi];
+                if (ss == 0.0) continue;
+                const int p = js->p[pi], q = js->q[pi];
+                const double cc = js->c[pi];
+                const double ap = A[p * ld + k], aq = A[q * ld + k];
+                A[p * ld + k] = cc * ap - ss * aq;
+                A[q * ld + k] = ss * ap + cc * aq;
+            }
+            team_sync<TEAM>();
+            for (int e = lane; e < half * Np; e += TEAM) {
+                const int pi = e / Np, k = e - pi * Np;
+                const double ss = js->s[pi];
+                if (ss == 0.0) continue;
+                const int p = js->p[pi], q = js->q[pi];
+                const double cc = js->c[pi];
+                const double ap = A[k * ld + p], aq = A[k * ld + q];
+                A[k * ld + p] = cc * ap - ss * aq;
+                A[k * ld + q] = ss * ap + cc * aq;
+                if (WANTV) {
+                    const double vp = V[k * ld + p], vq = V[k * ld + q];
+                    V[k * ld + p] = cc * vp - ss * vq;
+                    V[k * ld + q] = ss * vp + cc * vq;
+                }
+            }
+            team_sync<TEAM>();
+        }
+    }
+}
+
+// Load the upper triangle of the N x N global matrix A (ld lda) as a symmetric
+// matrix into LDS, pad to an even size; rows flagged in 'dead' and the pad row
+// become decoupled with a diagonal below every eigenvalue.  Returns Np.
+__device__ __forceinline__ int wg_load_sym(int N, const double *A, int lda, const int *dead, double *sA, int ld) {
+    const int tid = threadIdx.x;
+    const int Np = N + (N & 1);
+    __shared__ double red[kWG];
+    __shared__ double fro2;
+    double s = 0.0;
+    for (int e = tid; e < Np * Np; e += kWG) {
+        const int r = e / Np, c = e - r * Np;
+        double v = 0.0;
+        if (r < N && c < N) {
+            const int lo = r < c ? r : c, hi = r < c ? c : r;
+            v = A[lo * lda + hi];
+            if (dead && (dead[r] || dead[c])) v = 0.0;
+        }
+        sA[r * ld + c] = v;
+        s += v * v;
+    }
+    red[tid] = s;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kWG; ++i) t += red[i];
+        fro2 = t;
+    }
+    __syncthreads();
+    const double sentinel = -(2.0 * sqrt(fro2) + 1.0);
+    for (int r = tid; r < Np; r += kWG) {
+        const bool isdead = (r >= N) || (dead && dead[r]);
+        if (isdead) sA[r * ld + r] = sentinel;
+    }
+    __syncthreads();
+    return Np;
+}
+
+__device__ __forceinline__ void wg_jacobi(int N, double *sA, double *sV, int ld, JacobiScratch *js) {
+    const int Np = N + (N & 1);
+    jacobi_core<kWG, kMaxBasis, true>(Np, sA, sV, ld, js, threadIdx.x, 40, 1e-15);
+}
+
+// sort descending (stable by index), w[0..N), Y[r*ldy + c] for r < N, c < ny
+__device__ __forceinline__ void wg_sort_store(int N, const double *sA, const double *sV, int ld, double *w,
+                                              double *Y, int ldy, int ny, JacobiScratch *js) {
+    const int tid = threadIdx.x;
+    const int Np = N + (N & 1);
+    for (int t = tid; t < Np; t += kWG) {
+        const double wt = sA[t * ld + t];
+        int rk = 0;
+        for (int j = 0; j < Np; ++j) {
+            const double wj = sA[j * ld + j];
+            rk += (wj > wt) || (wj == wt && j < t);
+        }
+        js->rank[t] = rk;
+    }
+    __syncthreads();
+    for (int t = tid; t < Np; t += kWG) {
+        const int rk = js->rank[t];
+        if (rk < N && w) w[rk] = sA[t * ld + t];
+    }
+    if (Y)
+        for (int e = tid; e < Np * N; e += kWG) {
+            const int t = e / N, r = e - t * N;
+            const int rk = js->rank[t];
+            if (rk < ny) Y[r * ldy + rk] = sV[r * ld + t];
+        }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky-QR factor (one thread-team = wavefront 0 of the calling workgroup).
+// G (nc x nc, LDS, ld) = W^T W.  Lower Cholesky with semidefinite deflation:
+// a pivot below max(1e-24 * max diag, floor2) marks the column dead and
+// zeroes it.  Writes R^{-1} = L^{-T} to H (global, ldh), dead columns zero.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_cholqr(int nc, double *G, int ld, double *H, int ldh, int *flags,
+                                            double floor2) {
+    const int lane = threadIdx.x & 63;
+    __shared__ int sdead[16];
+    __shared__ double sLi[16 * 17];
+    double md = 0.0;
+    for (int i = 0; i < nc; ++i) md = fmax(md, G[i * ld + i]);
+    const double thr = fmax(1e-24 * md, floor2);
+    if (lane < 16) sdead[lane] = 0;
+    wave_sync();
+    for (int j = 0; j < nc; ++j) {
+        if (lane == 0) {
+            const double piv = G[j * ld + j];
+            if (!(piv > thr)) {
+                sdead[j] = 1;
+                G[j * ld + j] = 1.0;
+            } else {
+                G[j * ld + j] = sqrt(piv);
+            }
+        }
+        wave_sync();
+        const double ljj = G[j * ld + j];
+        const int dj = sdead[j];
+        for (int i = j + 1 + lane; i < nc; i += 64) G[i * ld + j] = dj ? 0.0 : G[i * ld + j] / ljj;
+        wave_sync();
+        const int m = nc - j - 1;
+        for (int e = lane; e < m * m; e += 64) {
+            const int i = j + 1 + e / m, l = j + 1 + e % m;
+            if (l <= i) G[i * ld + l] -= G[i * ld + j] * G[l * ld + j];
+        }
+        wave_sync();
+    }
+    // L^{-1}: lane c solves L x = e_c
+    if (lane < nc) {
+        const int c = lane;
+        double x[16];
+        for (int i = 0; i < 16; ++i) x[i] = 0.0;
+        for (int i = c; i < nc; ++i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int l = c; l < i; ++l) v -= G[i * ld + l] * x[l];
+            x[i] = v / G[i * ld + i];
+        }
+        for (int i = 0; i < nc; ++i) sLi[i * 17 + c] = x[i];   // sLi[i][c] = L^{-1}[i][c]
+    }
+    wave_sync();
+    // H[a][c] = R^{-1}[a][c] = L^{-1}[c][a]; dead columns of R^{-1} are zero
+    for (int e = lane; e < nc * nc; e += 64) {
+        const int a = e / nc, c = e - a * nc;
+        H[a * ldh + c] = sdead[c] ? 0.0 : sLi[c * 17 + a];
+    }
+    if (flags && lane < nc && sdead[lane]) flags[lane] = 1;
+}
+
+// ---------------------------------------------------------------------------
+// wavefront-level helpers for the k x k matrices of the IPM (k <= 12)
+// ---------------------------------------------------------------------------
+// lower Cholesky in place (A = L L^T); returns false if not positive definite
+__device__ __forceinline__ bool wave_chol(int k, double *A, int ld) {
+    const int lane = threadIdx.x & 63;
+    __shared__ int bad[4];
+    const int w = (threadIdx.x >> 6) & 3;
+    if (lane == 0) bad[w] = 0;
+    wave_sync();
+    for (int j = 0; j < k; ++j) {
+        if (lane == 0) {
+            const double piv = A[j * ld + j];
+            if (!(piv > 0.0)) {
+                bad[w] = 1;
+                A[j * ld + j] = 1.0;
+            } else {
+                A[j * ld + j] = sqrt(piv);
+            }
+        }
+        wave_sync();
+        const double ljj = A[j * ld + j];
+        for (int i = j + 1 + lane; i < k; i += 64) A[i * ld + j] /= ljj;
+        wave_sync();
+        const int m = k - j - 1;
+        for (int e = lane; e < m * m; e += 64) {
+            const int i = j + 1 + e / m, l = j + 1 + e % m;
+            if (l <= i) A[i * ld + l] -= A[i * ld + j] * A[l * ld + j];
+        }
+        wave_sync();
+    }
+    // clear the strict upper triangle
+    for (int e = lane; e < k * k; e += 64) {
+        const int i = e / k, l = e - i * k;
+        if (l > i) A[i * ld + l] = 0.0;
+    }
+    wave_sync();
+    return bad[w] == 0;
+}
+
+// Li = L^{-1} (lower), lane c solves for column c
+__device__ __forceinline__ void wave_tri_inv(int k, const double *L, int ld, double *Li, int ldi) {
+    const int lane = threadIdx.x & 63;
+    if (lane < k) {
+        const int c = lane;
+        double x[kMaxK];
+        for (int i = 0; i < kMaxK; ++i) x[i] = 0.0;
+        for (int i = c; i < k; ++i) {
+            double v = (i == c) ? 1.0 : 0.0;
+            for (int l = c; l < i; ++l) v -= L[i * ld + l] * x[l];
+            x[i] = v / L[i * ld + i];
+        }
+        for (int i = 0; i < k; ++i) Li[i * ldi + c] = x[i];
+    }
+    wave_sync();
+}
+
+// X = Li D Li^T (D symmetric), via Y = Li D
+__device__ __forceinline__ void wave_congruence(int k, const double *Li, int ldi, const double *D, int ldd,
+                                                double *Y, double *X, int ldx) {
+    const int lane = threadIdx.x & 63;
+    for (int e = lane; e < k * k; e += 64) {
+        const int r = e / k, c = e - r * k;
+        double s = 0.0;
+        for (int a = 0; a <= r; ++a) s += Li[r * ldi + a] * D[a * ldd + c];
+        Y[r * ldx + c] = s;
+    }
+    wave_sync();
+    for (int e = lane; e < k * k; e += 64) {
+        const int r = e / k, c = e - r * k;
+        double s = 0.0;
+        for (int b = 0; b <= c; ++b) s += Y[r * ldx + b] * Li[c * ldi + b];
+        X[r * ldx + c] = s;
+    }
+    wave_sync();
+}
+
+// smallest eigenvalue of the symmetric k x k LDS matrix X (destroyed)
+__device__ __forceinline__ double wave_min_eig(int k, double *X, int ldx, JacobiWork<64, 16> *js) {
+    const int lane = threadIdx.x & 63;
+    const int Np = k + (k & 1);
+    if (k & 1) {
+        for (int e = lane; e < Np; e += 64) {
+            X[(Np - 1) * ldx + e] = 0.0;
+            X[e * ldx + (Np - 1)] = 0.0;
+        }
+        wave_sync();
+        if (lane == 0) X[(Np - 1) * ldx + (Np - 1)] = 0.0;
+        wave_sync();
+    }
+    jacobi_core<64, 16, false>(Np, X, nullptr, ldx, js, lane, 40, 1e-15);
+    double mn = 1e300;
+    for (int i = 0; i < k; ++i) mn = fmin(mn, X[i * ldx + i]);
+    wave_sync();
+    return mn;
+}
+
+// ---------------------------------------------------------------------------
+// Master QP (App. B.2, eq. compressed_subprob_2):
+//   min 1/2 s'Q11 s + eta q12's + 1/2 q22 eta^2 + h1's + h2 eta
+//   s.t. eta >= 0, S PSD, 1 - tr S - eta >= 0,      s = svec(S)
+// Primal-dual path following as in App. B.1/B.2: mu estimate with the factor
+// 1/2, step delta = min(1, 0.95 delta_max), mu <- min(mu, gamma * estimate),
+// stop when mu < tol_mu and the residuals F1, F2 are below tol_res.
+// Newton direction: Delta t, Delta zeta, Delta omega are eliminated, leaving
+// the symmetric positive definite bordered system in (Delta s, Delta eta)
+//   [Q11 + T(x)_s S^-1 + vv'/k1 ,  q12 + v/k1          ] [ds  ]   [-F1 + r4 - v r3/k1]
+//   [(q12 + v/k1)'             ,  q22 + zeta/eta + 1/k1] [deta] = [-F2 + r5 - r3/k1  ]
+// with k1 = (1 - tr S - eta)/omega, r3 = mu/omega + tr S + eta - 1,
+// r4 = mu svec(S^-1) - t, r5 = mu/eta - zeta, v = svec(I); eliminating deta as
+// well gives the paper's eq. delta_S_linear_system2 -- the same direction.
+// ---------------------------------------------------------------------------
+constexpr int kMaxD = kMaxSvec + 1;
+struct IpmShared {
+    double M[kMaxD * (kMaxD + 1)];
+    double S[kMaxK * kMaxK], T[kMaxK * kMaxK], Si[kMaxK * kMaxK];
+    double LS[kMaxK * kMaxK], LSi[kMaxK * kMaxK], LT[kMaxK * kMaxK], LTi[kMaxK * kMaxK];
+    double dS[kMaxK * kMaxK], dT[kMaxK * kMaxK];
+    double Y0[16 * 16], X0[16 * 16], Y1[16 * 16], X1[16 * 16];
+    double s[kMaxSvec], t[kMaxSvec], F1[kMaxSvec], q12[kMaxSvec], h1[kMaxSvec], svSi[kMaxSvec];
+    double rhs[kMaxD], dt[kMaxSvec];
+    int pi[kMaxSvec], pj[kMaxSvec];
+    double red[kWG];
+    JacobiWork<64, 16> js0, js1;
+    double eta, zeta, om, mu, slack, F2, maxres, kap1, r3, r5, q22, h2, dmaxS, dmaxT, deta, dzeta, dom, delta;
+    int okS, okT, okM, stop;
+};
+
+__device__ __forceinline__ double wg_reduce_sum(double v, IpmShared *sh) {
+    const int tid = threadIdx.x;
+    sh->red[tid] = v;
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (tid < st) sh->red[tid] += sh->red[tid + st];
+        __syncthreads();
+    }
+    const double r = sh->red[0];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double wg_reduce_max(double v, IpmShared *sh) {
+    const int tid = threadIdx.x;
+    sh->red[tid] = v;
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (tid < st) sh->red[tid] = fmax(sh->red[tid], sh->red[tid + st]);
+        __syncthreads();
+    }
+    const double r = sh->red[0];
+    __syncthreads();
+    return r;
+}
+
+// symmetric Kronecker product entry (G (x)_s H)_{PQ}, P=(i,j), Q=(k,l), i>=j, k>=l:
+// 1/2 s_P c_Q (H_ik G_jl + H_il G_jk + G_ik H_jl + G_il H_jk),
+// s_P = sqrt2 (i != j) or 1, c_Q = 1/sqrt2 (k != l) or 1/2.
+__device__ __forceinline__ double skron_entry(int i, int j, int k, int l, const double *G, const double *H, int ld) {
+    const double sP = (i != j) ? 1.4142135623730951 : 1.0;
+    const double cQ = (k != l) ? 0.7071067811865476 : 0.5;
+    return 0.5 * sP * cQ *
+           (H[i * ld + k] * G[j * ld + l] + H[i * ld + l] * G[j * ld + k] + G[i * ld + k] * H[j * ld + l] +
+            G[i * ld + l] * H[j * ld + k]);
+}
+
+__device__ void wg_ipm(const IpmArgs a, const double *__restrict__ qp, double *state, IpmShared *sh) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int k = a.k, d = k * (k + 1) / 2, D = d + 1, ldm = kMaxD + 1;
+    const double *Q11 = qp;
+    const double r2 = 1.4142135623730951;
+    // svec index tables and data
+    if (tid == 0) {
+        int p = 0;
+        for (int j = 0; j < k; ++j)
+            for (int i = j; i < k; ++i) {
+                sh->pi[p] = i;
+                sh->pj[p] = j;
+                ++p;
+            }
+    }
+    for (int p = tid; p < d; p += kWG) {
+        sh->q12[p] = qp[d * d + p];
+        sh->h1[p] = qp[d * d + d + 1 + p];
+    }
+    if (tid == 0) {
+        sh->q22 = qp[d * d + d];
+        sh->h2 = qp[d * d + d + 1 + d];
+    }
+    for (int e = tid; e < k * k; e += kWG) {
+        const int i = e / k, j = e - i * k;
+        if (a.warm) {
+            // previous solution pulled 10% towards the default interior point
+            sh->S[i * kMaxK + j] = 0.9 * state[e] + ((i == j) ? 0.1 / (2.0 * k) : 0.0);
+            sh->T[i * kMaxK + j] = 0.9 * state[k * k + e] + ((i == j) ? 0.1 : 0.0);
+        } else {
+            sh->S[i * kMaxK + j] = (i == j) ? 1.0 / (2.0 * k) : 0.0;
+            sh->T[i * kMaxK + j] = (i == j) ? 1.0 : 0.0;
+        }
+    }
+    if (tid == 0) {
+        if (a.warm) {
+            sh->eta = 0.9 * state[2 * k * k] + 0.1 * 0.25;
+            sh->zeta = 0.9 * state[2 * k * k + 1] + 0.1;
+            sh->om = 0.9 * state[2 * k * k + 2] + 0.1;
+        } else {
+            sh->eta = 0.25;
+            sh->zeta = 1.0;
+            sh->om = 1.0;
+        }
+        sh->stop = 0;
+    }
+    __syncthreads();
+    // initial mu = (<S,T> + eta zeta + omega slack) / (2(k+2))
+    {
+        double v = 0.0;
+        for (int e = tid; e < k * k; e += kWG) {
+            const int i = e / k, j = e - i * k;
+            v += sh->S[i * kMaxK + j] * sh->T[i * kMaxK + j];
+        }
+        const double st = wg_reduce_sum(v, sh);
+        if (tid == 0) {
+            double tr = 0.0;
+            for (int i = 0; i < k; ++i) tr += sh->S[i * kMaxK + i];
+            sh->slack = 1.0 - tr - sh->eta;
+            sh->mu = (st + sh->eta * sh->zeta + sh->om * sh->slack) / (2.0 * (k + 2));
+        }
+        __syncthreads();
+    }
+    int it = 0, status = 0;
+    for (;;) {
+        // s, t
+        for (int p = tid; p < d; p += kWG) {
+            const int i = sh->pi[p], j = sh->pj[p];
+            const double f = (i == j) ? 1.0 : r2;
+            sh->s[p] = f * sh->S[i * kMaxK + j];
+            sh->t[p] = f * sh->T[i * kMaxK + j];
+        }
+        __syncthreads();
+        // residuals F1 (d) and F2
+        double f2part = 0.0, mres = 0.0;
+        for (int p = tid; p < d; p += kWG) {
+            const double *row = Q11 + (size_t)p * d;
+            double v = 0.0;
+            for (int q = 0; q < d; ++q) v += row[q] * sh->s[q];
+            const double vI = (sh->pi[p] == sh->pj[p]) ? 1.0 : 0.0;
+            v += sh->eta * sh->q12[p] + sh->h1[p] - sh->t[p] + sh->om * vI;
+            sh->F1[p] = v;
+            mres = fmax(mres, fabs(v));
+            f2part += sh->q12[p] * sh->s[p];
+        }
+        const double qs = wg_reduce_sum(f2part, sh);
+        const double m1 = wg_reduce_max(mres, sh);
+        if (tid == 0) {
+            sh->F2 = qs + sh->eta * sh->q22 + sh->h2 - sh->zeta + sh->om;
+            sh->maxres = fmax(m1, fabs(sh->F2));
+            sh->stop = (sh->mu < a.tol_mu && sh->maxres < a.tol_res) || it >= a.max_iter;
+            if (!(sh->mu == sh->mu) || !(sh->maxres == sh->maxres)) sh->stop = 2;
+        }
+        __syncthreads();
+        if (sh->stop) {
+            if (sh->stop == 2) status = 2;
+            else if (it >= a.max_iter && !(sh->mu < a.tol_mu && sh->maxres < a.tol_res)) status = 1;
+            break;
+        }
+        // S^{-1} (wave 0), L_T (wave 1)
+        if (wave == 0) {
+            for (int e = lane; e < k * k; e += 64) {
+                const int i = e / k, j = e - i * k;
+                sh->LS[i * kMaxK + j] = sh->S[i * kMaxK + j];
+            }
+            wave_sync();
+            const bool ok = wave_chol(k, sh->LS, kMaxK);
+            if (lane == 0) sh->okS = ok;
+            wave_tri_inv(k, sh->LS, kMaxK, sh->LSi, kMaxK);
+            for (int e = lane; e < k * k; e += 64) {
+                const int i = e / k, j = e - i * k;
+                double v = 0.0;
+                const int lo = i > j ? i : j;
+                for (int l = lo; l < k; ++l) v += sh->LSi[l * kMaxK + i] * sh->LSi[l * kMaxK + j];
+                sh->Si[i * kMaxK + j] = v;
+            }
+        } else if (wave == 1) {
+            for (int e = lane; e < k * k; e += 64) {
+                const int i = e / k, j = e - i * k;
+                sh->LT[i * kMaxK + j] = sh->T[i * kMaxK + j];
+            }
+            wave_sync();
+            const bool ok = wave_chol(k, sh->LT, kMaxK);
+            if (lane == 0) sh->okT = ok;
+            wave_tri_inv(k, sh->LT, kMaxK, sh->LTi, kMaxK);
+        }
+        __syncthreads();
+        if (!sh->okS || !sh->okT) {
+            status = 2;
+            break;
+        }
+        for (int p = tid; p < d; p += kWG) {
+            const int i = sh->pi[p], j = sh->pj[p];
+            sh->svSi[p] = ((i == j) ? 1.0 : r2) * sh->Si[i * kMaxK + j];
+        }
+        if (tid == 0) {
+            double tr = 0.0;
+            for (int i = 0; i < k; ++i) tr += sh->S[i * kMaxK + i];
+            sh->slack = 1.0 - tr - sh->eta;
+            sh->kap1 = sh->slack / sh->om;
+            sh->r3 = sh->mu / sh->om + tr + sh->eta - 1.0;
+            sh->r5 = sh->mu / sh->eta - sh->zeta;
+        }
+        __syncthreads();
+        // bordered Newton matrix and right-hand side
+        const double ik1 = 1.0 / sh->kap1;
+        for (int e = tid; e < D * D; e += kWG) {
+            const int P = e / D, Q = e - P * D;
+            if (Q > P) continue;   // lower triangle only
+            double v;
+            if (P < d && Q < d) {
+                const int i = sh->pi[P], j = sh->pj[P], kk = sh->pi[Q], l = sh->pj[Q];
+                const double vP = (i == j) ? 1.0 : 0.0, vQ = (kk == l) ? 1.0 : 0.0;
+                v = Q11[(size_t)P * d + Q] + skron_entry(i, j, kk, l, sh->T, sh->Si, kMaxK) + vP * vQ * ik1;
+            } else if (P == d && Q < d) {
+                const double vQ = (sh->pi[Q] == sh->pj[Q]) ? 1.0 : 0.0;
+                v = sh->q12[Q] + vQ * ik1;
+            } else {
+                v = sh->q22 + sh->zeta / sh->eta + ik1;
+            }
+            sh->M[P * ldm + Q] = v;
+        }
+        for (int p = tid; p < D; p += kWG) {
+            if (p < d) {
+                const double vP = (sh->pi[p] == sh->pj[p]) ? 1.0 : 0.0;
+                const double r4 = sh->mu * sh->svSi[p] - sh->t[p];
+                sh->rhs[p] = -sh->F1[p] + r4 - vP * sh->r3 * ik1;
+            } else {
+                sh->rhs[p] = -sh->F2 + sh->r5 - sh->r3 * ik1;
+            }
+        }
+        if (tid == 0) sh->okM = 1;
+        __syncthreads();
+        // Cholesky of M (lower, right-looking)
+        for (int j = 0; j < D; ++j) {
+            if (tid == 0) {
+                const double piv = sh->M[j * ldm + j];
+                if (!(piv > 0.0)) {
+                    sh->okM = 0;
+                    sh->M[j * ldm + j] = 1.0;
+                } else {
+                    sh->M[j * ldm + j] = sqrt(piv);
+                }
+            }
+            __syncthreads();
+            const double ljj = sh->M[j * ldm + j];
+            for (int i = j + 1 + tid; i < D; i += kWG) sh->M[i * ldm + j] /= ljj;
+            __syncthreads();
+            const int m = D - j - 1;
+            for (int e = tid; e < m * m; e += kWG) {
+                const int i = j + 1 + e / m, l = j + 1 + e % m;
+                if (l <= i) sh->M[i * ldm + l] -= sh->M[i * ldm + j] * sh->M[l * ldm + j];
+            }
+            __syncthreads();
+        }
+        if (!sh->okM) {
+            status = 2;
+            break;
+        }
+        // solves on wavefront 0
+        if (wave == 0) {
+            for (int j = 0; j < D; ++j) {
+                if (lane == 0) sh->rhs[j] /= sh->M[j * ldm + j];
+                wave_sync();
+                const double xj = sh->rhs[j];
+                for (int i = j + 1 + lane; i < D; i += 64) sh->rhs[i] -= sh->M[i * ldm + j] * xj;
+                wave_sync();
+            }
+            for (int j = D - 1; j >= 0; --j) {
+                if (lane == 0) sh->rhs[j] /= sh->M[j * ldm + j];
+                wave_sync();
+                const double xj = sh->rhs[j];
+                for (int i = lane; i < j; i += 64) sh->rhs[i] -= sh->M[j * ldm + i] * xj;
+                wave_sync();
+            }
+        }
+        __syncthreads();
+        // back substitution of the eliminated unknowns
+        for (int p = tid; p < d; p += kWG) {
+            const int i = sh->pi[p], j = sh->pj[p];
+            double v = 0.0;
+            for (int q = 0; q < d; ++q) v += skron_entry(i, j, sh->pi[q], sh->pj[q], sh->T, sh->Si, kMaxK) * sh->rhs[q];
+            sh->dt[p] = sh->mu * sh->svSi[p] - sh->t[p] - v;
+        }
+        for (int e = tid; e < k * k; e += kWG) {
+            const int i = e / k, j = e - i * k;
+            const int lo = i > j ? j : i, hi = i > j ? i : j;
+            const int p = lo * k - lo * (lo - 1) / 2 + (hi - lo);
+            const double f = (i == j) ? 1.0 : (1.0 / r2);
+            sh->dS[i * kMaxK + j] = f * sh->rhs[p];
+        }
+        __syncthreads();
+        for (int e = tid; e < k * k; e += kWG) {
+            const int i = e / k, j = e - i * k;
+            const int lo = i > j ? j : i, hi = i > j ? i : j;
+            const int p = lo * k - lo * (lo - 1) / 2 + (hi - lo);
+            const double f = (i == j) ? 1.0 : (1.0 / r2);
+            sh->dT[i * kMaxK + j] = f * sh->dt[p];
+        }
+        if (tid == 0) {
+            double trd = 0.0;
+            for (int i = 0; i < k; ++i) trd += sh->rhs[(i * k - i * (i - 1) / 2)];
+            sh->deta = sh->rhs[d];
+            sh->dzeta = sh->r5 - (sh->zeta / sh->eta) * sh->deta;
+            sh->dom = (sh->r3 + trd + sh->deta) / sh->kap1;
+        }
+        __syncthreads();
+        // step lengths: lambda_min(L_S^{-1} dS L_S^{-T}) on wave 0, same for T on wave 1
+        if (wave == 0) {
+            wave_congruence(k, sh->LSi, kMaxK, sh->dS, kMaxK, sh->Y0, sh->X0, 16);
+            const double lm = wave_min_eig(k, sh->X0, 16, &sh->js0);
+            if (lane == 0) sh->dmaxS = (lm < 0.0) ? -1.0 / lm : 1e300;
+        } else if (wave == 1) {
+            wave_congruence(k, sh->LTi, kMaxK, sh->dT, kMaxK, sh->Y1, sh->X1, 16);
+            const double lm = wave_min_eig(k, sh->X1, 16, &sh->js1);
+            if (lane == 0) sh->dmaxT = (lm < 0.0) ? -1.0 / lm : 1e300;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double dm = fmin(sh->dmaxS, sh->dmaxT);
+            if (sh->deta < 0.0) dm = fmin(dm, -sh->eta / sh->deta);
+            if (sh->dzeta < 0.0) dm = fmin(dm, -sh->zeta / sh->dzeta);
+            if (sh->dom < 0.0) dm = fmin(dm, -sh->om / sh->dom);
+            double trd = 0.0;
+            for (int i = 0; i < k; ++i) trd += sh->dS[i * kMaxK + i];
+            const double dsl = -trd - sh->deta;
+            if (dsl < 0.0) dm = fmin(dm, -sh->slack / dsl);
+            sh->delta = fmin(1.0, 0.95 * dm);
+        }
+        __syncthreads();
+        const double dl = sh->delta;
+        for (int e = tid; e < k * k; e += kWG) {
+            const int i = e / k, j = e - i * k;
+            if (j < i) continue;
+            const double sv = sh->S[i * kMaxK + j] + dl * 0.5 * (sh->dS[i * kMaxK + j] + sh->dS[j * kMaxK + i]);
+            const double tv = sh->T[i * kMaxK + j] + dl * 0.5 * (sh->dT[i * kMaxK + j] + sh->dT[j * kMaxK + i]);
+            sh->S[i * kMaxK + j] = sv;
+            sh->S[j * kMaxK + i] = sv;
+            sh->T[i * kMaxK + j] = tv;
+            sh->T[j * kMaxK + i] = tv;
+        }
+        __syncthreads();
+        {
+            double v = 0.0;
+            for (int e = tid; e < k * k; e += kWG) {
+                const int i = e / k, j = e - i * k;
+                v += sh->S[i * kMaxK + j] * sh->T[i * kMaxK + j];
+            }
+            const double st = wg_reduce_sum(v, sh);
+            if (tid == 0) {
+                sh->eta += dl * sh->deta;
+                sh->zeta += dl * sh->dzeta;
+                sh->om += dl * sh->dom;
+                double tr = 0.0;
+                for (int i = 0; i < k; ++i) tr += sh->S[i * kMaxK + i];
+                sh->slack = 1.0 - tr - sh->eta;
+                const double gam = (dl <= 0.2) ? 1.0 : 0.5 - 0.4 * dl * dl;
+                const double est = (st + sh->eta * sh->zeta + sh->om * sh->slack) / (2.0 * (k + 2));
+                sh->mu = fmin(sh->mu, gam * est);
+            }
+            __syncthreads();
+        }
+        ++it;
+    }
+    __syncthreads();
+    for (int e = tid; e < k * k; e += kWG) {
+        const int i = e / k, j = e - i * k;
+        state[e] = sh->S[i * kMaxK + j];
+        state[k * k + e] = sh->T[i * kMaxK + j];
+    }
+    if (tid == 0) {
+        state[2 * k * k] = sh->eta;
+        state[2 * k * k + 1] = sh->zeta;
+        state[2 * k * k + 2] = sh->om;
+        state[2 * k * k + 3] = (double)it;
+        state[2 * k * k + 4] = (double)status;
+    }
+}
+
+}  // namespace usbs

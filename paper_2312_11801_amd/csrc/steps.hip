@@ -1,0 +1,386 @@
+// Small USBS-specific kernels: assembling the master QP from its reduced
+// pieces, the candidate iterate, the descent test, the model update and the
+// Nystrom core.  Each is a single workgroup or an elementwise map; scalars of
+// the iteration live in a device array so that consecutive kernels chain
+// without host round trips.
+#include "steps.h"
+#include "small_dense.h"
+
+namespace usbs {
+
+static inline int cdiv_(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// master QP coefficients (App. B.2, eq. compressed_subprob_2, normalised form)
+//   raw = [sum g g^T (d*d) | G^T zbar | G^T y | G^T b | G^T nu]
+// ---------------------------------------------------------------------------
+__global__ void k_qp_finalize(int k, const double *__restrict__ raw, const double *__restrict__ VCV,
+                              const double *__restrict__ sc, int has_nu, double *__restrict__ qp) {
+    const int d = k * (k + 1) / 2;
+    const double alpha = sc[SC_ALPHA], rho = sc[SC_RHO], tau = sc[SC_TAU];
+    const double a2r = alpha * alpha / rho;
+    const double *Gz = raw + d * d, *Gy = Gz + d, *Gb = Gy + d, *Gn = Gb + d;
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) qp[e] = a2r * raw[e];
+    for (int p = threadIdx.x; p < d; p += blockDim.x) {
+        // p -> (i, j), i >= j, column-wise lower triangle
+        int j = 0, rem = p;
+        while (rem >= k - j) { rem -= k - j; ++j; }
+        const int i = j + rem;
+        const double sv = (i == j ? 1.0 : 1.4142135623730951) * VCV[i * k + j];
+        const double gw = Gb[p] - (has_nu ? Gn[p] : 0.0);
+        qp[d * d + p] = (tau > 0.0) ? a2r / tau * Gz[p] : 0.0;               // q12
+        qp[d * d + d + 1 + p] = alpha * (Gy[p] - gw / rho - sv);             // h1
+    }
+    if (threadIdx.x == 0) {
+        const double zz = sc[SC_ZZ], yz = sc[SC_YZBAR], bz = sc[SC_BZ], nz = has_nu ? sc[SC_NUZ] : 0.0;
+        qp[d * d + d] = (tau > 0.0) ? a2r * zz / (tau * tau) : 0.0;                          // q22
+        qp[d * d + 2 * d + 1] = (tau > 0.0) ? alpha / tau * (yz - (bz - nz) / rho - sc[SC_CBAR]) : 0.0; // h2
+    }
+}
+
+void qp_finalize(hipStream_t s, int k, const double *raw, const double *VCV, const double *sc, int has_nu,
+                 double *qp) {
+    hipLaunchKernelGGL(k_qp_finalize, dim3(1), dim3(kWG), 0, s, k, raw, VCV, sc, has_nu, qp);
+}
+
+// g = alpha eta / tau, <C, X_{t+1}> = g cbar + alpha <V^T C V, S>
+__global__ void k_post_ipm(int k, const double *__restrict__ st, const double *__restrict__ VCV, double *sc) {
+    if (threadIdx.x != 0) return;
+    const double alpha = sc[SC_ALPHA], tau = sc[SC_TAU];
+    const double eta = st[2 * k * k];
+    const double g = (tau > 0.0) ? alpha * eta / tau : 0.0;
+    double vs = 0.0;
+    for (int e = 0; e < k * k; ++e) vs += VCV[e] * st[e];
+    sc[SC_ETA] = eta;
+    sc[SC_G] = g;
+    sc[SC_CX] = g * sc[SC_CBAR] + alpha * vs;
+    sc[SC_IPMIT] += st[2 * k * k + 3];
+    if (st[2 * k * k + 4] != 0.0) sc[SC_IPMSTATUS] = st[2 * k * k + 4];
+}
+void post_ipm(hipStream_t s, int k, const double *st, const double *VCV, double *sc) {
+    hipLaunchKernelGGL(k_post_ipm, dim3(1), dim3(64), 0, s, k, st, VCV, sc);
+}
+
+// alternating maximisation (eq. dual_slack_update): nu = proj_N(b - AX - rho y)
+__global__ void k_nu_update(int m, const double *__restrict__ b, const double *__restrict__ AX,
+                            const double *__restrict__ y, const double *__restrict__ ineq, double rho,
+                            double *__restrict__ nu, double *__restrict__ dnu) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const double v = (ineq[k] != 0.0) ? fmax(b[k] - AX[k] - rho * y[k], 0.0) : 0.0;
+    dnu[k] = v - nu[k];
+    nu[k] = v;
+}
+void nu_update(hipStream_t s, int m, const double *b, const double *AX, const double *y, const double *ineq,
+               double rho, double *nu, double *dnu) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_nu_update, dim3(cdiv_(m, kWG)), dim3(kWG), 0, s, m, b, AX, y, ineq, rho, nu, dnu);
+}
+
+// candidate (eq. dual_update, feasible form of Sec. 3.2) and the infeasibility vector
+__global__ void k_candidate(int m, const double *__restrict__ b, const double *__restrict__ AX,
+                            const double *__restrict__ y, const double *__restrict__ ineq, double rho,
+                            double *__restrict__ yc, double *__restrict__ e) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const double r = b[k] - AX[k];
+    double v = y[k] - r / rho;
+    if (ineq[k] != 0.0) {
+        v = fmax(v, 0.0);
+        e[k] = fmax(-r, 0.0);
+    } else {
+        e[k] = -r;
+    }
+    yc[k] = v;
+}
+void candidate(hipStream_t s, int m, const double *b, const double *AX, const double *y, const double *ineq,
+               double rho, double *yc, double *e) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_candidate, dim3(cdiv_(m, kWG)), dim3(kWG), 0, s, m, b, AX, y, ineq, rho, yc, e);
+}
+
+// lambda_max(V^T (C - A^* y~) V) with V^T A^* y~ V = smat(G^T y~)
+__global__ __launch_bounds__(kWG) void k_fhat_prep(int k, const double *__restrict__ VCV,
+                                                   const double *__restrict__ Gy, double *sc) {
+    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
+    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
+    __shared__ JacobiScratch js;
+    __shared__ double Mv[kMaxK * kMaxK];
+    __shared__ double w[kMaxK + 1];
+    const double r2 = 1.4142135623730951;
+    for (int e = threadIdx.x; e < k * k; e += kWG) {
+        const int i = e / k, j = e - i * k;
+        const int lo = i > j ? j : i, hi = i > j ? i : j;
+        const int p = lo * k - lo * (lo - 1) / 2 + (hi - lo);
+        Mv[e] = VCV[e] - ((i == j) ? Gy[p] : Gy[p] / r2);
+    }
+    __syncthreads();
+    wg_load_sym(k, Mv, k, nullptr, &sA[0][0], kMaxBasis + 1);
+    wg_jacobi(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
+    wg_sort_store(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, nullptr, 0, 0, &js);
+    if (threadIdx.x == 0) sc[SC_LAMV] = w[0];
+}
+void fhat_prep(hipStream_t s, int k, const double *VCV, const double *Gy, double *sc) {
+    hipLaunchKernelGGL(k_fhat_prep, dim3(1), dim3(kWG), 0, s, k, VCV, Gy, sc);
+}
+
+// descent test (Alg. 1), f, f^ and the relative errors (eq. relative_error_tol)
+__global__ void k_decide(const double *__restrict__ theta, double *sc) {
+    if (threadIdx.x != 0) return;
+    const double alpha = sc[SC_ALPHA], beta = sc[SC_BETA], tau = sc[SC_TAU];
+    const double by = sc[SC_BY];
+    const double lam1 = theta[0];
+    const double fc = alpha * fmax(lam1, 0.0) + by;
+    double best = fmax(0.0, sc[SC_LAMV]);
+    if (tau > 0.0) best = fmax(best, (sc[SC_CBAR] - sc[SC_YZ]) / tau);
+    const double fhat = alpha * best + by;
+    const double f = sc[SC_F];
+    const int desc = (beta * (f - fhat) <= f - fc) ? 1 : 0;
+    const double fn = desc ? fc : f;
+    sc[SC_FCAND] = fc;
+    sc[SC_FHAT] = fhat;
+    sc[SC_THETA1] = lam1;
+    sc[SC_DESC] = desc;
+    sc[SC_NDESC] += desc;
+    sc[SC_F] = fn;
+    const double cx = sc[SC_CX];
+    const double dist = sqrt(fmax(sc[SC_DIST2], 0.0));
+    if (sc[SC_UNITS] != 0.0) {
+        const double s = sc[SC_SIGMA] * sc[SC_TRACE];
+        const double fo = s * fn, co = s * cx;
+        sc[SC_GAP] = fabs(fo - co) / (1.0 + fabs(co));
+        sc[SC_INF] = sc[SC_TRACE] * dist / (1.0 + sc[SC_TRACE] * sc[SC_BNORM]);
+    } else {
+        sc[SC_GAP] = fabs(fn - cx) / (1.0 + fabs(cx));
+        sc[SC_INF] = dist / (1.0 + sc[SC_BNORM]);
+    }
+}
+void decide(hipStream_t s, const double *theta, double *sc) {
+    hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, theta, sc);
+}
+
+__global__ void k_cond_copy(int m, const double *__restrict__ flag, const double *__restrict__ src,
+                            double *__restrict__ dst) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m || *flag == 0.0) return;
+    dst[k] = src[k];
+}
+void cond_copy(hipStream_t s, int m, const double *flag, const double *src, double *dst) {
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_cond_copy, dim3(cdiv_(m, kWG)), dim3(kWG), 0, s, m, flag, src, dst);
+}
+
+// model update (eqs. model_update_eigendecomposition, x_bar_def; App. C tracking):
+// alpha S = Q diag(lam) Q^T (descending), Q_p = first k_p columns, Q_c = rest,
+// Kc = Q_c Lam_c Q_c^T, tau <- g tau + tr Lam_c, cbar <- g cbar + <Kc, V^T C V>,
+// Hsk = Kc (V^T Psi) (k x r) for the sketch.
+__global__ __launch_bounds__(kWG) void k_model_update(int k, int kp, int r, const double *__restrict__ st,
+                                                      const double *__restrict__ VCV,
+                                                      const double *__restrict__ VtPsi, double *sc,
+                                                      double *__restrict__ Kc, double *__restrict__ Qp,
+                                                      double *__restrict__ Hsk) {
+    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
+    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
+    __shared__ JacobiScratch js;
+    __shared__ double aS[kMaxK * kMaxK];
+    __shared__ double lam[kMaxK + 1];
+    __shared__ double Q[kMaxK * kMaxK];
+    __shared__ double sK[kMaxK * kMaxK];
+    const double alpha = sc[SC_ALPHA];
+    for (int e = threadIdx.x; e < k * k; e += kWG) aS[e] = alpha * st[e];
+    __syncthreads();
+    wg_load_sym(k, aS, k, nullptr, &sA[0][0], kMaxBasis + 1);
+    wg_jacobi(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
+    wg_sort_store(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, lam, Q, k, k, &js);
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += kWG) {
+        const int i = e / k, j = e - i * k;
+        double v = 0.0;
+        for (int c = kp; c < k; ++c) v += Q[i * k + c] * lam[c] * Q[j * k + c];
+        sK[e] = v;
+        Kc[e] = v;
+    }
+    for (int e = threadIdx.x; e < k * kp; e += kWG) {
+        const int i = e / kp, c = e - i * kp;
+        Qp[e] = Q[i * k + c];
+    }
+    __syncthreads();
+    if (Hsk)
+        for (int e = threadIdx.x; e < k * r; e += kWG) {
+            const int i = e / r, c = e - i * r;
+            double v = 0.0;
+            for (int a = 0; a < k; ++a) v += sK[i * k + a] * VtPsi[a * r + c];
+            Hsk[e] = v;
+        }
+    if (threadIdx.x == 0) {
+        const double g = sc[SC_G];
+        double trc = 0.0, kv = 0.0;
+        for (int c = kp; c < k; ++c) trc += lam[c];
+        for (int e = 0; e < k * k; ++e) kv += sK[e] * VCV[e];
+        sc[SC_TAU] = g * sc[SC_TAU] + trc;
+        sc[SC_CBAR] = g * sc[SC_CBAR] + kv;
+    }
+}
+void model_update(hipStream_t s, int k, int kp, int r, const double *st, const double *VCV, const double *VtPsi,
+                  double *sc, double *Kc, double *Qp, double *Hsk) {
+    hipLaunchKernelGGL(k_model_update, dim3(1), dim3(kWG), 0, s, k, kp, r, st, VCV, VtPsi, sc, Kc, Qp, Hsk);
+}
+
+// Vnew[:, kc + j] = Uritz[:, kc + j] where the orthogonalised V Q_p column died
+__global__ void k_fix_dead(int n, const int *__restrict__ flags, int kc, int kp, const double *__restrict__ U,
+                           int ldu, double *__restrict__ Vn, int ldv) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * kp) return;
+    const long i = e / kp;
+    const int j = (int)(e - i * kp);
+    if (flags[j]) Vn[i * ldv + kc + j] = U[i * ldu + kc + j];
+}
+void fix_dead(hipStream_t s, int n, const int *flags, int kc, int kp, const double *U, int ldu, double *Vn,
+              int ldv) {
+    if (n <= 0 || kp <= 0) return;
+    hipLaunchKernelGGL(k_fix_dead, dim3(cdiv_((long)n * kp, kWG)), dim3(kWG), 0, s, n, flags, kc, kp, U, ldu, Vn,
+                       ldv);
+}
+
+__global__ void k_add_small(int rows, int cols, const double *__restrict__ H, int ldh, double *__restrict__ T,
+                            int ldt) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * cols) return;
+    const int a = e / cols, c = e - a * cols;
+    T[a * ldt + c] += H[a * ldh + c];
+}
+void add_small(hipStream_t s, int rows, int cols, const double *H, int ldh, double *T, int ldt) {
+    hipLaunchKernelGGL(k_add_small, dim3(cdiv_(rows * cols, kWG)), dim3(kWG), 0, s, rows, cols, H, ldh, T, ldt);
+}
+
+__global__ void k_set_int(int *p, int count, int v) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = v;
+}
+void set_int(hipStream_t s, int *p, int count, int v) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_set_int, dim3(cdiv_(count, kWG)), dim3(kWG), 0, s, p, count, v);
+}
+
+// ---------------------------------------------------------------------------
+// Nystrom core (App. C.1; fixed-rank PSD approximation of Tropp, Yurtsever,
+// Udell & Cevher 2017): from the Gram of [P | Psi] (2r x 2r) compute
+//   nu = sqrt(n) eps(||P||_2), B = Psi^T (P + nu Psi) = L L^T,
+//   F = (P + nu Psi) L^{-T},  F^T F = Z Sigma^2 Z^T,  U = F Z Sigma^{-1},
+//   lam = max(Sigma^2 - nu, 0).
+// Output H (2r x r) with U = [P | Psi] H, and lam (r).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_nystrom_core(int n, int r, const double *__restrict__ Gm,
+                                                      double *__restrict__ H, double *__restrict__ lamo,
+                                                      int *status) {
+    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
+    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
+    __shared__ JacobiScratch js;
+    __shared__ double G[2 * kMaxRank * 2 * kMaxRank];
+    __shared__ double B[kMaxRank * kMaxRank], Li[kMaxRank * kMaxRank], PP[kMaxRank * kMaxRank];
+    __shared__ double FF[kMaxRank * kMaxRank], Z[kMaxRank * kMaxRank], w[kMaxRank + 1], tmp[kMaxRank * kMaxRank];
+    __shared__ double nu_s;
+    __shared__ int bad;
+    const int tid = threadIdx.x;
+    const int r2 = 2 * r;
+    for (int e = tid; e < r2 * r2; e += kWG) G[e] = Gm[e];
+    __syncthreads();
+    // ||P||_2^2 = lambda_max(P^T P)
+    for (int e = tid; e < r * r; e += kWG) PP[e] = G[(e / r) * r2 + (e % r)];
+    __syncthreads();
+    wg_load_sym(r, PP, r, nullptr, &sA[0][0], kMaxBasis + 1);
+    wg_jacobi(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
+    wg_sort_store(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, nullptr, 0, 0, &js);
+    if (tid == 0) {
+        const double nrm = sqrt(fmax(w[0], 0.0));
+        int ex;
+        frexp(nrm, &ex);                                 // nrm = f 2^ex, f in [0.5, 1)
+        const double eps = (nrm > 0.0) ? ldexp(1.0, ex - 53) : 0.0;   // spacing of doubles at nrm
+        nu_s = sqrt((double)n) * eps;
+        bad = 0;
+    }
+    __syncthreads();
+    const double nu = nu_s;
+    // PsiP = Psi^T P: rows r.. of G, cols 0..r ; PsiPsi = Psi^T Psi ; PP = P^T P
+    // B = Psi^T P + nu Psi^T Psi (symmetrised)
+    for (int e = tid; e < r * r; e += kWG) {
+        const int i = e / r, j = e - i * r;
+        const double bij = G[(r + i) * r2 + j] + nu * G[(r + i) * r2 + r + j];
+        const double bji = G[(r + j) * r2 + i] + nu * G[(r + j) * r2 + r + i];
+        B[i * kMaxRank + j] = 0.5 * (bij + bji);
+    }
+    __syncthreads();
+    if ((tid >> 6) == 0) {
+        const bool ok = wave_chol(r, B, kMaxRank);
+        if ((tid & 63) == 0 && !ok) bad = 1;
+        wave_tri_inv(r, B, kMaxRank, Li, kMaxRank);   // Li = L^{-1}
+    }
+    __syncthreads();
+    // Pn^T Pn = PP + nu (Psi^T P + P^T Psi) + nu^2 Psi^T Psi ; FF = Li (Pn^T Pn) Li^T
+    for (int e = tid; e < r * r; e += kWG) {
+        const int i = e / r, j = e - i * r;
+        tmp[e] = G[i * r2 + j] + nu * (G[(r + i) * r2 + j] + G[i * r2 + r + j]) + nu * nu * G[(r + i) * r2 + r + j];
+    }
+    __syncthreads();
+    for (int e = tid; e < r * r; e += kWG) {
+        const int i = e / r, j = e - i * r;
+        double v = 0.0;
+        for (int a = 0; a < r; ++a) v += Li[i * kMaxRank + a] * tmp[a * r + j];
+        PP[e] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < r * r; e += kWG) {
+        const int i = e / r, j = e - i * r;
+        double v = 0.0;
+        for (int a = 0; a < r; ++a) v += PP[i * r + a] * Li[j * kMaxRank + a];
+        FF[e] = v;
+    }
+    __syncthreads();
+    wg_load_sym(r, FF, r, nullptr, &sA[0][0], kMaxBasis + 1);
+    wg_jacobi(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
+    wg_sort_store(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, Z, r, r, &js);
+    __syncthreads();
+    // U = Pn Li^T Z Sigma^{-1}; Pn = [P | Psi] [I ; nu I]
+    // E = Li^T Z diag(1/sigma) (r x r)
+    for (int e = tid; e < r * r; e += kWG) {
+        const int i = e / r, c = e - i * r;
+        const double sg = sqrt(fmax(w[c], 0.0));
+        double v = 0.0;
+        for (int a = 0; a < r; ++a) v += Li[a * kMaxRank + i] * Z[a * r + c];
+        tmp[e] = (sg > 0.0) ? v / sg : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < r2 * r; e += kWG) {
+        const int a = e / r, c = e - a * r;
+        H[e] = (a < r) ? tmp[a * r + c] : nu * tmp[(a - r) * r + c];
+    }
+    for (int c = tid; c < r; c += kWG) lamo[c] = fmax(w[c] - nu, 0.0);
+    if (tid == 0 && status) *status = bad;
+}
+void nystrom_core(hipStream_t s, int n, int r, const double *Gm, double *H, double *lam, int *status) {
+    hipLaunchKernelGGL(k_nystrom_core, dim3(1), dim3(kWG), 0, s, n, r, Gm, H, lam, status);
+}
+
+__global__ void k_interleave(int n, int r, const double *__restrict__ P, const float *__restrict__ Psi,
+                             double *__restrict__ out) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * 2 * r) return;
+    const long i = e / (2 * r);
+    const int c = (int)(e - i * 2 * r);
+    out[e] = (c < r) ? P[i * r + c] : (double)Psi[i * r + (c - r)];
+}
+void interleave(hipStream_t s, int n, int r, const double *P, const float *Psi, double *out) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_interleave, dim3(cdiv_((long)n * 2 * r, kWG)), dim3(kWG), 0, s, n, r, P, Psi, out);
+}
+
+__global__ void k_psi_to_double(long count, const float *__restrict__ a, double *__restrict__ b) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) b[e] = (double)a[e];
+}
+void psi_to_double(hipStream_t s, long count, const float *a, double *b) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_psi_to_double, dim3(cdiv_(count, kWG)), dim3(kWG), 0, s, count, a, b);
+}
+
+}  // namespace usbs

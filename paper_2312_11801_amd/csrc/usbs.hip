@@ -1,0 +1,1091 @@
+// Host side of the USBS library: problem validation and scaling (App. E),
+// device memory, the block Lanczos eigen-solver and the iteration of Alg. 1,
+// all issued as kernels on one HIP stream.  Implements include/usbs.h.
+#include "../../include/usbs.h"
+#include "kernels.h"
+#include "steps.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <utility>
+#include <vector>
+
+using namespace usbs;
+
+namespace {
+
+struct DevError : std::runtime_error {
+    int code;
+    DevError(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                                      \
+    do {                                                                                               \
+        hipError_t e_ = (x);                                                                           \
+        if (e_ != hipSuccess)                                                                          \
+            throw DevError(e_ == hipErrorOutOfMemory ? USBS_E_NOMEM : USBS_E_DEVICE,                   \
+                           std::string(#x) + ": " + hipGetErrorString(e_));                            \
+    } while (0)
+
+template <typename T>
+T *dalloc(size_t count, std::vector<void *> &owned) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    HIPCHK(hipMalloc(&p, count * sizeof(T)));
+    owned.push_back(p);
+    return (T *)p;
+}
+
+// host copy of a problem (kept for warm starts)
+struct HostProblem {
+    int n = 0, m = 0;
+    std::vector<int64_t> rowptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<int32_t> a_row, a_i, a_j;
+    std::vector<double> a_v, b;
+    std::vector<uint8_t> ineq;
+    double trace = 0.0;
+    std::vector<float> psi;   // n * r (empty without sketch)
+};
+
+}  // namespace
+
+struct usbs_handle {
+    std::string err;
+    int dev = 0;
+    hipStream_t stream = nullptr;
+    usbs_params prm{};
+    HostProblem hp;
+    std::vector<void *> owned;   // device allocations of the current problem
+
+    int n = 0, m = 0, nnz = 0, k = 0, kc = 0, kp = 0, r = 0, prec = 0, steps = 8, ldb = 80;
+    bool sketch = false, has_offc = false, has_ineq = false;
+    double sigma = 1.0, trace = 1.0, val_scale = 1.0, bnorm = 0.0;
+
+    // operator (off-diagonal CSR, diagonal split out)
+    int *rowptr = nullptr, *col = nullptr;
+    void *val_cur = nullptr, *val_c = nullptr;   // compute precision: shifted / base
+    double *cbase = nullptr, *cdiag = nullptr, *dshift = nullptr;
+    int *dptr = nullptr, *dk = nullptr;
+    double *dv = nullptr;
+    int n_offt = 0;
+    int *off_slot = nullptr, *off_k = nullptr;
+    double *off_hv = nullptr;
+    int *kptr = nullptr, *ti = nullptr, *tj = nullptr;
+    double *tv = nullptr, *b = nullptr, *ineq = nullptr;
+    float *psi = nullptr;
+
+    // iteration state
+    double *y = nullptr, *yc = nullptr, *nu = nullptr, *dnu = nullptr, *zbar = nullptr, *AX = nullptr,
+           *evec = nullptr;
+    double *V = nullptr, *Vn = nullptr, *CV = nullptr, *Uritz = nullptr, *P = nullptr;
+    // Lanczos work
+    double *Bm = nullptr, *W = nullptr, *Wt = nullptr, *W2 = nullptr, *Ubuf = nullptr;
+    double *Tm = nullptr, *theta = nullptr, *Ysm = nullptr, *TUU = nullptr, *RtR = nullptr, *Zc = nullptr,
+           *Hred = nullptr, *Rinv = nullptr, *res = nullptr, *Hd = nullptr;
+    int *dead = nullptr, *flag = nullptr;
+    // QP / model
+    double *raw = nullptr, *qp = nullptr, *ipm = nullptr, *VCV = nullptr, *Gy = nullptr, *Kc = nullptr,
+           *Qp = nullptr, *Hsk = nullptr, *VtPsi = nullptr, *sc = nullptr, *small = nullptr, *Zp = nullptr,
+           *hz = nullptr, *Rz = nullptr;
+    int *zdead = nullptr;
+    RedScratch rs{};
+
+    int64_t matvecs = 0;
+    int iters = 0;
+    bool ready = false;
+};
+
+void nn_update_dev_beta(usbs_handle *h, const double *A, int lda, int ca, const double *H, int ldh, int cc, double *C,
+                        int ldc);
+
+namespace {
+
+void set_err(usbs_handle *h, const std::string &m) {
+    if (h) h->err = m;
+}
+
+// ---------------------------------------------------------------------------
+// validation and upload
+// ---------------------------------------------------------------------------
+HostProblem copy_problem(const usbs_problem *p, int r) {
+    if (!p) throw DevError(USBS_E_INVALID, "problem is NULL");
+    if (p->n < 2 || p->n > (int64_t)1 << 30) throw DevError(USBS_E_INVALID, "n out of range");
+    if (p->m < 1 || p->m > (int64_t)1 << 30) throw DevError(USBS_E_INVALID, "m out of range");
+    if (!p->rowptr || !p->col || !p->val || !p->b || !p->is_ineq)
+        throw DevError(USBS_E_INVALID, "NULL array in problem");
+    if (p->n_triplets < 1 || !p->a_row || !p->a_i || !p->a_j || !p->a_v)
+        throw DevError(USBS_E_INVALID, "constraint triplets missing");
+    if (!(p->trace > 0.0) || !std::isfinite(p->trace)) throw DevError(USBS_E_INVALID, "trace must be > 0");
+    HostProblem hp;
+    hp.n = (int)p->n;
+    hp.m = (int)p->m;
+    const int64_t nnz = p->rowptr[p->n];
+    if (p->rowptr[0] != 0 || nnz < 0 || nnz >= ((int64_t)1 << 31)) throw DevError(USBS_E_INVALID, "bad rowptr");
+    hp.rowptr.assign(p->rowptr, p->rowptr + p->n + 1);
+    for (int64_t i = 0; i < p->n; ++i)
+        if (hp.rowptr[i + 1] < hp.rowptr[i]) throw DevError(USBS_E_INVALID, "rowptr not monotone");
+    hp.col.assign(p->col, p->col + nnz);
+    hp.val.assign(p->val, p->val + nnz);
+    for (int64_t e = 0; e < nnz; ++e) {
+        if (hp.col[e] < 0 || hp.col[e] >= p->n) throw DevError(USBS_E_INVALID, "column index out of range");
+        if (!std::isfinite(hp.val[e])) throw DevError(USBS_E_NUMERIC, "non-finite value in C");
+    }
+    const int64_t nt = p->n_triplets;
+    hp.a_row.assign(p->a_row, p->a_row + nt);
+    hp.a_i.assign(p->a_i, p->a_i + nt);
+    hp.a_j.assign(p->a_j, p->a_j + nt);
+    hp.a_v.assign(p->a_v, p->a_v + nt);
+    for (int64_t t = 0; t < nt; ++t) {
+        if (hp.a_row[t] < 0 || hp.a_row[t] >= p->m || hp.a_i[t] < 0 || hp.a_j[t] >= p->n ||
+            hp.a_i[t] > hp.a_j[t])
+            throw DevError(USBS_E_INVALID, "constraint triplet out of range (need 0 <= i <= j < n)");
+        if (!std::isfinite(hp.a_v[t])) throw DevError(USBS_E_NUMERIC, "non-finite constraint coefficient");
+    }
+    hp.b.assign(p->b, p->b + p->m);
+    hp.ineq.assign(p->is_ineq, p->is_ineq + p->m);
+    for (int k = 0; k < hp.m; ++k)
+        if (!std::isfinite(hp.b[k])) throw DevError(USBS_E_NUMERIC, "non-finite b");
+    hp.trace = p->trace;
+    if (p->psi) {
+        hp.psi.assign(p->psi, p->psi + (size_t)p->n * r);
+        for (float v : hp.psi)
+            if (!std::isfinite(v)) throw DevError(USBS_E_NUMERIC, "non-finite test matrix");
+    }
+    // C symmetric (pattern and values)
+    {
+        std::vector<std::pair<int64_t, double>> tr;
+        tr.reserve(nnz);
+        std::vector<std::pair<int64_t, double>> fw;
+        fw.reserve(nnz);
+        for (int i = 0; i < hp.n; ++i)
+            for (int64_t e = hp.rowptr[i]; e < hp.rowptr[i + 1]; ++e) {
+                const int j = hp.col[e];
+                fw.push_back({(int64_t)i * hp.n + j, hp.val[e]});
+                tr.push_back({(int64_t)j * hp.n + i, hp.val[e]});
+            }
+        std::sort(fw.begin(), fw.end());
+        std::sort(tr.begin(), tr.end());
+        for (size_t e = 0; e < fw.size(); ++e) {
+            if (e > 0 && fw[e].first == fw[e - 1].first) throw DevError(USBS_E_INVALID, "duplicate entry in C");
+            if (fw[e].first != tr[e].first || std::fabs(fw[e].second - tr[e].second) >
+                                                  1e-12 * (1.0 + std::fabs(fw[e].second)))
+                throw DevError(USBS_E_INVALID, "C is not symmetric");
+        }
+    }
+    return hp;
+}
+
+void free_problem(usbs_handle *h) {
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    for (void *p : h->owned) (void)hipFree(p);
+    h->owned.clear();
+}
+
+void upload(usbs_handle *h) {
+    const HostProblem &hp = h->hp;
+    const int n = hp.n, m = hp.m;
+    h->n = n;
+    h->m = m;
+    std::vector<void *> &o = h->owned;
+    // scaling (App. E, eq. std_scaling)
+    double fro2 = 0.0;
+    for (double v : hp.val) fro2 += v * v;
+    h->sigma = fro2 > 0.0 ? std::sqrt(fro2) : 1.0;
+    h->trace = hp.trace;
+    double bn2 = 0.0;
+    for (double v : hp.b) bn2 += (v / hp.trace) * (v / hp.trace);
+    h->bnorm = std::sqrt(bn2);
+    h->has_ineq = false;
+    for (uint8_t v : hp.ineq) h->has_ineq |= (v != 0);
+
+    // off-diagonal pattern: C's off-diagonal entries plus the pairs that constraints touch
+    std::vector<double> cdiag(n, 0.0);
+    std::vector<std::vector<std::pair<int, double>>> rows(n);
+    for (int i = 0; i < n; ++i)
+        for (int64_t e = hp.rowptr[i]; e < hp.rowptr[i + 1]; ++e) {
+            const int j = hp.col[e];
+            if (j == i) cdiag[i] += hp.val[e] / h->sigma;
+            else rows[i].push_back({j, hp.val[e] / h->sigma});
+        }
+    // constraint triplets: diagonal ones per vertex, off-diagonal ones per slot
+    std::vector<std::vector<std::pair<int, double>>> dlist(n);
+    struct OffT { int i, j, k; double hv; };
+    std::vector<OffT> offt;
+    for (size_t t = 0; t < hp.a_row.size(); ++t) {
+        const int i = hp.a_i[t], j = hp.a_j[t], k = hp.a_row[t];
+        if (i == j) dlist[i].push_back({k, hp.a_v[t]});
+        else offt.push_back({i, j, k, 0.5 * hp.a_v[t]});
+    }
+    for (auto &ot : offt) {
+        bool f1 = false, f2 = false;
+        for (auto &pr : rows[ot.i]) f1 |= (pr.first == ot.j);
+        for (auto &pr : rows[ot.j]) f2 |= (pr.first == ot.i);
+        if (!f1) rows[ot.i].push_back({ot.j, 0.0});
+        if (!f2) rows[ot.j].push_back({ot.i, 0.0});
+    }
+    for (int i = 0; i < n; ++i) std::sort(rows[i].begin(), rows[i].end());
+    std::vector<int> rp(n + 1, 0);
+    for (int i = 0; i < n; ++i) rp[i + 1] = rp[i] + (int)rows[i].size();
+    const int nnz = rp[n];
+    h->nnz = nnz;
+    std::vector<int> colv(std::max(nnz, 1));
+    std::vector<double> cb(std::max(nnz, 1));
+    for (int i = 0; i < n; ++i)
+        for (size_t q = 0; q < rows[i].size(); ++q) {
+            colv[rp[i] + q] = rows[i][q].first;
+            cb[rp[i] + q] = rows[i][q].second;
+        }
+    auto slot_of = [&](int i, int j) -> int {
+        auto it = std::lower_bound(colv.begin() + rp[i], colv.begin() + rp[i + 1], j);
+        return (int)(it - colv.begin());
+    };
+    std::vector<int> osl, ok;
+    std::vector<double> ohv;
+    {
+        std::vector<int64_t> seen;
+        for (auto &ot : offt) seen.push_back((int64_t)ot.i * n + ot.j);
+        std::sort(seen.begin(), seen.end());
+        for (size_t q = 1; q < seen.size(); ++q)
+            if (seen[q] == seen[q - 1])
+                throw DevError(USBS_E_INVALID, "an off-diagonal pair appears in more than one constraint triplet");
+    }
+    for (auto &ot : offt) {
+        osl.push_back(slot_of(ot.i, ot.j));
+        ok.push_back(ot.k);
+        ohv.push_back(ot.hv);
+        osl.push_back(slot_of(ot.j, ot.i));
+        ok.push_back(ot.k);
+        ohv.push_back(ot.hv);
+    }
+    h->n_offt = (int)osl.size();
+    h->has_offc = h->n_offt > 0;
+    std::vector<int> dp(n + 1, 0), dkv;
+    std::vector<double> dvv;
+    for (int i = 0; i < n; ++i) {
+        for (auto &pr : dlist[i]) {
+            dkv.push_back(pr.first);
+            dvv.push_back(pr.second);
+        }
+        dp[i + 1] = (int)dkv.size();
+    }
+    // constraint rows as CSR over triplets
+    std::vector<int> kp(m + 1, 0);
+    for (int v : hp.a_row) kp[v + 1]++;
+    for (int k = 0; k < m; ++k) kp[k + 1] += kp[k];
+    std::vector<int> tiv(hp.a_row.size()), tjv(hp.a_row.size());
+    std::vector<double> tvv(hp.a_row.size());
+    {
+        std::vector<int> pos(kp.begin(), kp.end() - 1);
+        for (size_t t = 0; t < hp.a_row.size(); ++t) {
+            const int q = pos[hp.a_row[t]]++;
+            tiv[q] = hp.a_i[t];
+            tjv[q] = hp.a_j[t];
+            tvv[q] = hp.a_v[t];
+        }
+    }
+    // BF16 values carry a common factor so that equal magnitudes stay exact
+    double mx = 0.0;
+    for (int e = 0; e < nnz; ++e) mx = std::max(mx, std::fabs(cb[e]));
+    h->val_scale = (h->prec == USBS_PREC_BF16 && mx > 0.0) ? mx : 1.0;
+
+    hipStream_t s = h->stream;
+    h->rowptr = dalloc<int>(n + 1, o);
+    h->col = dalloc<int>(nnz, o);
+    h->cbase = dalloc<double>(nnz, o);
+    const size_t vsz = h->prec == 0 ? 8 : (h->prec == 1 ? 4 : 2);
+    h->val_cur = dalloc<char>(std::max(nnz, 1) * vsz, o);
+    h->val_c = h->has_offc ? (void *)dalloc<char>(std::max(nnz, 1) * vsz, o) : h->val_cur;
+    h->cdiag = dalloc<double>(n, o);
+    h->dshift = dalloc<double>(n, o);
+    h->dptr = dalloc<int>(n + 1, o);
+    h->dk = dalloc<int>(dkv.size(), o);
+    h->dv = dalloc<double>(dvv.size(), o);
+    h->off_slot = dalloc<int>(osl.size(), o);
+    h->off_k = dalloc<int>(ok.size(), o);
+    h->off_hv = dalloc<double>(ohv.size(), o);
+    h->kptr = dalloc<int>(m + 1, o);
+    h->ti = dalloc<int>(tiv.size(), o);
+    h->tj = dalloc<int>(tjv.size(), o);
+    h->tv = dalloc<double>(tvv.size(), o);
+    h->b = dalloc<double>(m, o);
+    h->ineq = dalloc<double>(m, o);
+    HIPCHK(hipMemcpyAsync(h->rowptr, rp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->col, colv.data(), nnz * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->cbase, cb.data(), nnz * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->cdiag, cdiag.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->dptr, dp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    if (!dkv.empty()) {
+        HIPCHK(hipMemcpyAsync(h->dk, dkv.data(), dkv.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->dv, dvv.data(), dvv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    if (!osl.empty()) {
+        HIPCHK(hipMemcpyAsync(h->off_slot, osl.data(), osl.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->off_k, ok.data(), ok.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->off_hv, ohv.data(), ohv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    HIPCHK(hipMemcpyAsync(h->kptr, kp.data(), (m + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->ti, tiv.data(), tiv.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->tj, tjv.data(), tjv.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->tv, tvv.data(), tvv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    std::vector<double> bs(m), inq(m);
+    for (int k = 0; k < m; ++k) {
+        bs[k] = hp.b[k] / hp.trace;
+        inq[k] = hp.ineq[k] ? 1.0 : 0.0;
+    }
+    HIPCHK(hipMemcpyAsync(h->b, bs.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(h->ineq, inq.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+    h->sketch = !hp.psi.empty();
+    if (h->sketch) {
+        h->psi = dalloc<float>((size_t)n * h->r, o);
+        HIPCHK(hipMemcpyAsync(h->psi, hp.psi.data(), (size_t)n * h->r * sizeof(float), hipMemcpyHostToDevice, s));
+    }
+    convert_values(s, h->prec, nnz, h->cbase, 1.0 / h->val_scale, h->val_cur);
+    if (h->has_offc) convert_values(s, h->prec, nnz, h->cbase, 1.0 / h->val_scale, h->val_c);
+
+    // state and work arrays
+    const int ldb = h->ldb;
+    h->y = dalloc<double>(m, o);
+    h->yc = dalloc<double>(m, o);
+    h->nu = dalloc<double>(m, o);
+    h->dnu = dalloc<double>(m, o);
+    h->zbar = dalloc<double>(m, o);
+    h->AX = dalloc<double>(m, o);
+    h->evec = dalloc<double>(m, o);
+    h->V = dalloc<double>((size_t)n * 16, o);
+    h->Vn = dalloc<double>((size_t)n * 16, o);
+    h->CV = dalloc<double>((size_t)n * 16, o);
+    h->Uritz = dalloc<double>((size_t)n * 16, o);
+    h->P = dalloc<double>((size_t)n * std::max(h->r, 1), o);
+    h->Bm = dalloc<double>((size_t)n * ldb, o);
+    h->W = dalloc<double>((size_t)n * 8, o);
+    h->Wt = dalloc<double>((size_t)n * 8, o);
+    h->W2 = dalloc<double>((size_t)n * 32, o);
+    h->Ubuf = dalloc<double>((size_t)n * 16, o);
+    h->Zp = dalloc<double>((size_t)n * 16, o);
+    h->Tm = dalloc<double>((size_t)ldb * ldb, o);
+    h->theta = dalloc<double>(ldb, o);
+    h->Ysm = dalloc<double>((size_t)ldb * 16, o);
+    h->TUU = dalloc<double>(256, o);
+    h->RtR = dalloc<double>(256, o);
+    h->Zc = dalloc<double>(128, o);
+    h->Hred = dalloc<double>((size_t)ldb * 16, o);
+    h->Rinv = dalloc<double>(256, o);
+    h->res = dalloc<double>(16, o);
+    h->Hd = dalloc<double>(256, o);
+    h->dead = dalloc<int>(ldb, o);
+    h->flag = dalloc<int>(16, o);
+    h->zdead = dalloc<int>(16, o);
+    const int d = kMaxSvec;
+    h->raw = dalloc<double>(d * d + 4 * d, o);
+    h->qp = dalloc<double>(d * d + 2 * d + 2, o);
+    h->ipm = dalloc<double>(2 * kMaxK * kMaxK + 8, o);
+    h->VCV = dalloc<double>(256, o);
+    h->Gy = dalloc<double>(d * d + 4 * d, o);
+    h->Kc = dalloc<double>(256, o);
+    h->Qp = dalloc<double>(256, o);
+    h->Hsk = dalloc<double>(16 * 32, o);
+    h->VtPsi = dalloc<double>(16 * 32, o);
+    h->hz = dalloc<double>(256, o);
+    h->Rz = dalloc<double>(256, o);
+    h->sc = dalloc<double>(SC_COUNT, o);
+    h->small = dalloc<double>(4096, o);
+    h->rs.max_blocks = 1024;
+    h->rs.max_elems = kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec;
+    if (h->rs.max_elems < kMaxBasis * 16) h->rs.max_elems = kMaxBasis * 16;
+    h->rs.partials = dalloc<double>((size_t)h->rs.max_blocks * h->rs.max_elems, o);
+    h->rs.counter = dalloc<unsigned int>(4, o);
+    HIPCHK(hipMemsetAsync(h->rs.counter, 0, 4 * sizeof(unsigned int), s));
+    HIPCHK(hipMemsetAsync(h->V, 0, (size_t)n * 16 * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(h->Vn, 0, (size_t)n * 16 * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(h->CV, 0, (size_t)n * 16 * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(h->P, 0, (size_t)n * std::max(h->r, 1) * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(h->nu, 0, m * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(h->Bm, 0, (size_t)n * ldb * sizeof(double), s));
+}
+
+// ---------------------------------------------------------------------------
+// operator pieces
+// ---------------------------------------------------------------------------
+void shift_operator(usbs_handle *h, const double *y) {
+    diag_shift(h->stream, h->n, h->dptr, h->dk, h->dv, h->cdiag, y, h->dshift);
+    if (h->has_offc)
+        offdiag_refresh(h->stream, h->prec, h->n_offt, h->off_slot, h->off_k, h->off_hv, h->cbase, y,
+                        1.0 / h->val_scale, h->val_cur);
+}
+
+void apply_op(usbs_handle *h, const double *X, int ldx, double *Y, int ldy, int nb) {
+    spmm(h->stream, h->prec, h->n, h->rowptr, h->col, h->val_cur, h->val_scale, h->dshift, X, ldx, Y, ldy, nb);
+    h->matvecs += nb;
+}
+
+void apply_C(usbs_handle *h, const double *X, int ldx, double *Y, int ldy, int nb) {
+    spmm(h->stream, h->prec, h->n, h->rowptr, h->col, h->val_c, h->val_scale, h->cdiag, X, ldx, Y, ldy, nb);
+}
+
+// Cholesky-QR twice of the n x nc block src (ld lds) into dst (ld ldd); deflated
+// columns are zero and flagged in flags[0..nc)
+void cholqr2(usbs_handle *h, const double *src, int lds, int nc, double *tmp, int ldt, double *dst, int ldd,
+             int *flags) {
+    hipStream_t s = h->stream;
+    tn_reduce(s, h->rs, h->n, src, lds, nc, src, lds, nc, h->Rinv, nc, 1.0, 0.0, 1, flags, h->sc + SC_SCALE);
+    nn_update(s, h->n, src, lds, nc, h->Rinv, nc, nc, tmp, ldt, 1.0, 0.0);
+    tn_reduce(s, h->rs, h->n, tmp, ldt, nc, tmp, ldt, nc, h->Rinv, nc, 1.0, 0.0, 1, flags, nullptr);
+    nn_update(s, h->n, tmp, ldt, nc, h->Rinv, nc, nc, dst, ldd, 1.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// block Lanczos with Rayleigh-Ritz restarts (the eigen step behind f(y),
+// Sec. 3 and App. E): start block of 16 vectors, block width 8, 'steps'
+// blocks per cycle, full FP64 re-orthogonalisation (two classical
+// Gram-Schmidt passes), Cholesky-QR2 for each new block.  On return
+// Uritz (n x 16) holds the Ritz vectors, theta[0..16) the Ritz values.
+// ---------------------------------------------------------------------------
+int lanczos(usbs_handle *h, const double *start, int kc, double tol, int maxr, bool orth_start) {
+    hipStream_t s = h->stream;
+    const int n = h->n, ldb = h->ldb, steps = h->steps;
+    if (start != h->Ubuf) copy_cols(s, n, start, 16, 16, h->Ubuf, 16);
+    if (orth_start) {
+        set_int(s, h->flag, 16, 0);
+        cholqr2(h, h->Ubuf, 16, 16, h->W2, 16, h->Ubuf, 16, h->flag);
+    }
+    int cyc = 0;
+    for (cyc = 0; cyc <= maxr; ++cyc) {
+        // explicit Rayleigh-Ritz on span(U) and residuals
+        apply_op(h, h->Ubuf, 16, h->W2, 16, 16);
+        tn_reduce(s, h->rs, n, h->Ubuf, 16, 16, h->W2, 16, 16, h->TUU, 16, 1.0, 0.0);
+        small_eig(s, 16, h->TUU, 16, h->theta, h->Ysm, 16, 16, nullptr);
+        nn_update(s, n, h->Ubuf, 16, 16, h->Ysm, 16, 16, h->Bm, ldb, 1.0, 0.0);
+        nn_update(s, n, h->W2, 16, 16, h->Ysm, 16, 16, h->Ubuf, 16, 1.0, 0.0);
+        neg_diag(s, h->theta, 16, h->Hd);
+        nn_update(s, n, h->Bm, ldb, 16, h->Hd, 16, 16, h->Ubuf, 16, 1.0, 1.0);
+        tn_reduce(s, h->rs, n, h->Ubuf, 16, 16, h->Ubuf, 16, 16, h->RtR, 16, 1.0, 0.0);
+        lanczos_restart_prep(s, h->RtR, h->theta, kc, tol, h->res, h->flag, h->Zc, h->sc + SC_SCALE);
+        int conv = 0;
+        HIPCHK(hipMemcpyAsync(&conv, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (conv || cyc == maxr) break;
+        // Krylov expansion from the dominant residual directions
+        lanczos_reset_T(s, h->Tm, ldb, ldb, h->theta, h->dead);
+        nn_update(s, n, h->Ubuf, 16, 16, h->Zc, 8, 8, h->W, 8, 1.0, 0.0);
+        for (int pass = 0; pass < 2; ++pass) {
+            tn_reduce(s, h->rs, n, h->Bm, ldb, 16, h->W, 8, 8, h->Hred, 8, 1.0, 0.0);
+            nn_update(s, n, h->Bm, ldb, 16, h->Hred, 8, 8, h->W, 8, -1.0, 1.0);
+        }
+        cholqr2(h, h->W, 8, 8, h->Wt, 8, h->Bm + 16, ldb, h->dead + 16);
+        for (int j = 0; j < steps; ++j) {
+            const int c0 = 16 + 8 * j, cols = c0 + 8;
+            apply_op(h, h->Bm + c0, ldb, h->W, 8, 8);
+            tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Tm + c0, ldb, 1.0, 0.0);
+            nn_update(s, n, h->Bm, ldb, cols, h->Tm + c0, ldb, 8, h->W, 8, -1.0, 1.0);
+            tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Hred, 8, 1.0, 0.0);
+            nn_update(s, n, h->Bm, ldb, cols, h->Hred, 8, 8, h->W, 8, -1.0, 1.0);
+            add_small(s, cols, 8, h->Hred, 8, h->Tm + c0, ldb);
+            if (j < steps - 1) cholqr2(h, h->W, 8, 8, h->Wt, 8, h->Bm + cols, ldb, h->dead + cols);
+        }
+        small_eig(s, ldb, h->Tm, ldb, h->theta, h->Ysm, 16, 16, h->dead);
+        nn_update(s, n, h->Bm, ldb, ldb, h->Ysm, 16, 16, h->Ubuf, 16, 1.0, 0.0);
+    }
+    copy_cols(s, n, h->Bm, ldb, 16, h->Uritz, 16);
+    return cyc;
+}
+
+// ---------------------------------------------------------------------------
+// one iteration of Alg. 1 (device work; one host synchronisation inside the
+// Lanczos restart test and one for the alternating maximisation)
+// ---------------------------------------------------------------------------
+void iterate(usbs_handle *h) {
+    hipStream_t s = h->stream;
+    const int n = h->n, m = h->m, k = h->k, kc = h->kc, kp = h->kp, r = h->r;
+    const int d = k * (k + 1) / 2;
+    const usbs_params &prm = h->prm;
+    // V^T C V
+    apply_C(h, h->V, 16, h->CV, 16, 16);
+    tn_reduce(s, h->rs, n, h->V, 16, k, h->CV, 16, k, h->VCV, k, 1.0, 0.0);
+    // reductions of the master QP: sum g g^T, G^T zbar, G^T y, G^T b
+    {
+        const double *ws[3] = {h->zbar, h->y, h->b};
+        qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 3, h->raw, 1);
+        const double *a[3] = {h->zbar, h->y, h->b}, *bb[3] = {h->zbar, h->zbar, h->zbar};
+        dots(s, h->rs, m, a, bb, 3, h->sc + SC_ZZ);
+    }
+    // alternating maximisation over (X, nu) (eqs. small_quad_sdp, dual_slack_update)
+    fill(s, m, 0.0, h->nu);
+    IpmArgs ia{k, 1e-7, 1e-7, 100, 0};
+    for (int pass = 0; pass < 50; ++pass) {
+        if (pass > 0) {
+            const double *ws[1] = {h->nu};
+            qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 1, h->Gy, 0);
+            // G^T nu lands after the d*d block of Gy; copy into raw's 4th vector slot
+            HIPCHK(hipMemcpyAsync(h->raw + d * d + 3 * d, h->Gy + d * d, d * sizeof(double),
+                                  hipMemcpyDeviceToDevice, s));
+            const double *a[1] = {h->nu}, *bb[1] = {h->zbar};
+            dots(s, h->rs, m, a, bb, 1, h->sc + SC_NUZ);
+        }
+        qp_finalize(s, k, h->raw, h->VCV, h->sc, pass > 0, h->qp);
+        ia.warm = pass > 0;
+        ipm(s, ia, h->qp, h->ipm);
+        post_ipm(s, k, h->ipm, h->VCV, h->sc);
+        // A X_{t+1} = g zbar + alpha A(V S V^T)
+        lowrank_A(s, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, h->ipm, prm.alpha, h->zbar, h->sc + SC_G, 0.0,
+                  h->AX, 0.0);
+        if (!h->has_ineq) break;
+        nu_update(s, m, h->b, h->AX, h->y, h->ineq, prm.rho, h->nu, h->dnu);
+        const double *a[1] = {h->dnu}, *bb[1] = {h->dnu};
+        dots(s, h->rs, m, a, bb, 1, h->sc + SC_DNU);
+        double dn = 0.0;
+        HIPCHK(hipMemcpyAsync(&dn, h->sc + SC_DNU, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (std::sqrt(dn) <= 1e-9) break;
+    }
+    // candidate (eq. dual_update) and primal infeasibility of X_{t+1}
+    candidate(s, m, h->b, h->AX, h->y, h->ineq, prm.rho, h->yc, h->evec);
+    {
+        const double *a[3] = {h->b, h->yc, h->evec}, *bb[3] = {h->yc, h->zbar, h->evec};
+        dots(s, h->rs, m, a, bb, 3, h->sc + SC_BY);   // SC_BY, SC_YZ, SC_DIST2 are consecutive
+        const double *ws[1] = {h->yc};
+        qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 1, h->Gy, 0);
+        fhat_prep(s, k, h->VCV, h->Gy + d * d, h->sc);
+    }
+    // eigen step at the candidate
+    shift_operator(h, h->yc);
+    lanczos(h, h->Uritz, kc, prm.lanczos_tol, prm.lanczos_max_restarts, false);
+    decide(s, h->theta, h->sc);
+    cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
+    // model update
+    if (h->sketch) tn_reduce_f(s, h->rs, n, h->V, 16, k, h->psi, r, r, h->VtPsi, r, 1.0);
+    model_update(s, k, kp, r, h->ipm, h->VCV, h->VtPsi, h->sc, h->Kc, h->Qp, h->sketch ? h->Hsk : nullptr);
+    lowrank_A(s, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, h->Kc, 1.0, h->zbar, h->sc + SC_G, 0.0, h->zbar,
+              0.0);
+    if (h->sketch) nn_update_dev_beta(h, h->V, 16, k, h->Hsk, r, r, h->P, r);
+    // V_{t+1} = orth([V Q_p, v_1..v_kc]) (eq. v_next_def)
+    copy_cols(s, n, h->Uritz, 16, kc, h->Vn, 16);
+    if (kp > 0) {
+        nn_update(s, n, h->V, 16, k, h->Qp, kp, kp, h->Zp, 16, 1.0, 0.0);
+        for (int pass = 0; pass < 2; ++pass) {
+            tn_reduce(s, h->rs, n, h->Uritz, 16, kc, h->Zp, 16, kp, h->hz, kp, 1.0, 0.0);
+            nn_update(s, n, h->Uritz, 16, kc, h->hz, kp, kp, h->Zp, 16, -1.0, 1.0);
+        }
+        set_int(s, h->zdead, 16, 0);
+        cholqr2(h, h->Zp, 16, kp, h->W2, 16, h->Vn + kc, 16, h->zdead);
+        fix_dead(s, n, h->zdead, kc, kp, h->Uritz, 16, h->Vn, 16);
+    }
+    std::swap(h->V, h->Vn);
+    h->iters++;
+}
+
+}  // namespace
+
+// nn_update with beta read from the device scalar g (sketch update of Sec. 4:
+// P <- g P + V (Kc V^T Psi)); implemented as scale-then-accumulate.
+namespace {
+__global__ void k_scale_dev(long count, const double *g, double *p) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] *= *g;
+}
+}  // namespace
+void nn_update_dev_beta(usbs_handle *h, const double *A, int lda, int ca, const double *H, int ldh, int cc, double *C,
+                        int ldc) {
+    const long count = (long)h->n * ldc;
+    hipLaunchKernelGGL(k_scale_dev, dim3((unsigned)((count + kWG - 1) / kWG)), dim3(kWG), 0, h->stream, count,
+                       h->sc + SC_G, C);
+    nn_update(h->stream, h->n, A, lda, ca, H, ldh, cc, C, ldc, 1.0, 1.0);
+}
+
+namespace {
+
+void init_scalars(usbs_handle *h) {
+    std::vector<double> sc(SC_COUNT, 0.0);
+    sc[SC_BNORM] = h->bnorm;
+    sc[SC_SIGMA] = h->sigma;
+    sc[SC_TRACE] = h->trace;
+    sc[SC_ALPHA] = h->prm.alpha;
+    sc[SC_RHO] = h->prm.rho;
+    sc[SC_BETA] = h->prm.beta;
+    sc[SC_UNITS] = h->prm.units;
+    HIPCHK(hipMemcpyAsync(h->sc, sc.data(), SC_COUNT * sizeof(double), hipMemcpyHostToDevice, h->stream));
+}
+
+// cold start (reading of Alg. 1's unspecified initialisation): y0 = 0,
+// V0 = top-k eigenvectors of C_s, Xbar0 = 0, f0 = f(y0)
+void cold_start(usbs_handle *h) {
+    hipStream_t s = h->stream;
+    HIPCHK(hipMemsetAsync(h->y, 0, h->m * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(h->zbar, 0, h->m * sizeof(double), s));
+    HIPCHK(hipMemsetAsync(h->P, 0, (size_t)h->n * std::max(h->r, 1) * sizeof(double), s));
+    init_scalars(h);
+    random_block(s, h->n, 16, h->prm.seed, h->Ubuf, 16);
+    shift_operator(h, h->y);
+    lanczos(h, h->Ubuf, h->k, h->prm.lanczos_tol, std::max(h->prm.lanczos_max_restarts, 20), true);
+    HIPCHK(hipMemsetAsync(h->V, 0, (size_t)h->n * 16 * sizeof(double), s));
+    copy_cols(s, h->n, h->Uritz, 16, h->k, h->V, 16);
+    // f(y0) = alpha [theta_1]_+ (b^T y0 = 0)
+    std::vector<double> th(1);
+    HIPCHK(hipMemcpyAsync(th.data(), h->theta, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double f0 = h->prm.alpha * std::max(th[0], 0.0);
+    HIPCHK(hipMemcpyAsync(h->sc + SC_F, &f0, sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+void check_params(const usbs_params *p) {
+    if (!p) throw DevError(USBS_E_INVALID, "params is NULL");
+    if (!(p->alpha > 0) || !(p->rho > 0) || !(p->beta > 0 && p->beta < 1))
+        throw DevError(USBS_E_INVALID, "need alpha > 0, rho > 0, 0 < beta < 1");
+    if (p->k_c < 1 || p->k_p < 0 || p->k_c + p->k_p > kMaxK)
+        throw DevError(USBS_E_INVALID, "need k_c >= 1, k_p >= 0, k_c + k_p <= 12");
+    if (p->k_c + p->k_p > kRitz - 2) throw DevError(USBS_E_INVALID, "k_c + k_p too large for the Ritz block");
+    if (p->r < 0 || p->r > kMaxRank) throw DevError(USBS_E_INVALID, "need 0 <= r <= 16");
+    if (p->lanczos_steps < 1 || p->lanczos_steps > kMaxSteps)
+        throw DevError(USBS_E_INVALID, "need 1 <= lanczos_steps <= 8");
+    if (p->lanczos_max_restarts < 0) throw DevError(USBS_E_INVALID, "lanczos_max_restarts < 0");
+    if (p->precision < 0 || p->precision > 2) throw DevError(USBS_E_INVALID, "unknown precision");
+    if (p->units != USBS_UNITS_SCALED && p->units != USBS_UNITS_ORIGINAL)
+        throw DevError(USBS_E_INVALID, "unknown units");
+}
+
+void configure(usbs_handle *h, const usbs_params *p) {
+    h->prm = *p;
+    h->kc = p->k_c;
+    h->kp = p->k_p;
+    h->k = p->k_c + p->k_p;
+    h->r = p->r;
+    h->prec = p->precision;
+    h->stream = (hipStream_t)p->stream;
+}
+
+void set_geometry(usbs_handle *h, int n) {
+    // the basis (16 + 8 s columns) must stay well inside R^n
+    int steps = h->prm.lanczos_steps;
+    while (steps > 1 && 2 * (16 + 8 * steps) > n) --steps;
+    if (2 * (16 + 8) > n) throw DevError(USBS_E_INVALID, "n too small for the block Lanczos basis (need n >= 48)");
+    h->steps = steps;
+    h->ldb = 16 + 8 * steps;
+}
+
+int fail(usbs_handle *h, const DevError &e) {
+    set_err(h, e.what());
+    return e.code;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int usbs_default_params(usbs_params *p) {
+    if (!p) return USBS_E_INVALID;
+    std::memset(p, 0, sizeof(*p));
+    p->alpha = 2.0;
+    p->rho = 0.01;
+    p->beta = 0.25;
+    p->k_c = 10;
+    p->k_p = 1;
+    p->r = 10;
+    p->eps_gap = 1e-3;
+    p->eps_infeas = 1e-3;
+    p->units = USBS_UNITS_SCALED;
+    p->max_iters = 1000;
+    p->time_limit = 0.0;
+    p->lanczos_steps = 8;
+    p->lanczos_max_restarts = 10;
+    p->lanczos_tol = 1e-6;
+    p->precision = USBS_PREC_F64;
+    p->seed = 0;
+    p->stream = nullptr;
+    p->verbose = 0;
+    return USBS_OK;
+}
+
+int usbs_create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **out) {
+    if (!out) return USBS_E_INVALID;
+    *out = nullptr;
+    usbs_handle *h = new usbs_handle();
+    try {
+        check_params(prm);
+        configure(h, prm);
+        HIPCHK(hipGetDevice(&h->dev));
+        h->hp = copy_problem(prob, h->r);
+        if (h->hp.psi.empty()) h->r = 0;
+        set_geometry(h, h->hp.n);
+        upload(h);
+        cold_start(h);
+        h->ready = true;
+    } catch (const DevError &e) {
+        *out = h;   // the handle carries the message; caller frees it
+        const int c = fail(h, e);
+        free_problem(h);
+        h->ready = false;
+        return c;
+    }
+    *out = h;
+    return USBS_OK;
+}
+
+int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, double *lam_out) {
+    if (!h || !h->ready) {
+        set_err(h, "handle not ready");
+        return USBS_E_STATE;
+    }
+    try {
+        const auto t0 = std::chrono::steady_clock::now();
+        const usbs_params &p = h->prm;
+        std::vector<double> sc(SC_COUNT);
+        int status = USBS_NOT_CONVERGED;
+        int it = 0;
+        for (it = 0; it < p.max_iters; ++it) {
+            iterate(h);
+            HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            if (!std::isfinite(sc[SC_F]) || !std::isfinite(sc[SC_CX]) || sc[SC_IPMSTATUS] == 2.0)
+                throw DevError(USBS_E_NUMERIC, "non-finite iterate or failed interior point solve");
+            if (p.verbose)
+                std::fprintf(stderr, "it %d f %.8e fc %.8e fhat %.8e desc %d gap %.3e inf %.3e cX %.8e mv %lld\n",
+                             h->iters, sc[SC_F], sc[SC_FCAND], sc[SC_FHAT], (int)sc[SC_DESC], sc[SC_GAP], sc[SC_INF],
+                             sc[SC_CX], (long long)h->matvecs);
+            if (sc[SC_GAP] <= p.eps_gap && sc[SC_INF] <= p.eps_infeas) {
+                status = USBS_OK;
+                ++it;
+                break;
+            }
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (p.time_limit > 0.0 && el > p.time_limit) {
+                ++it;
+                break;
+            }
+        }
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (res) {
+            std::memset(res, 0, sizeof(*res));
+            const double s = h->sigma * h->trace;
+            res->primal_obj_scaled = sc[SC_CX];
+            res->f_scaled = sc[SC_F];
+            res->primal_obj = s * sc[SC_CX];
+            res->dual_bound = s * sc[SC_F];
+            res->rel_gap = sc[SC_GAP];
+            res->rel_infeas = sc[SC_INF];
+            res->lambda_max = sc[SC_THETA1];
+            res->seconds = secs;
+            res->lanczos_matvecs = h->matvecs;
+            res->iters = it;
+            res->descents = (int)sc[SC_NDESC];
+            res->ipm_iters = (int)sc[SC_IPMIT];
+            res->status = status;
+        }
+        if (y_out) {
+            std::vector<double> yv(h->m);
+            HIPCHK(hipMemcpy(yv.data(), h->y, h->m * sizeof(double), hipMemcpyDeviceToHost));
+            for (int q = 0; q < h->m; ++q) y_out[q] = h->sigma * yv[q];
+        }
+        if ((U_out || lam_out || res) && h->sketch && h->r > 0) {
+            // Nystrom reconstruction of Xbar (App. C.1) and its certificate terms
+            const int n = h->n, r = h->r;
+            hipStream_t s = h->stream;
+            interleave(s, n, r, h->P, h->psi, h->W2);
+            tn_reduce(s, h->rs, n, h->W2, 2 * r, 2 * r, h->W2, 2 * r, 2 * r, h->small, 2 * r, 1.0, 0.0);
+            nystrom_core(s, n, r, h->small, h->small + 1024, h->small + 2048, h->flag);
+            nn_update(s, n, h->W2, 2 * r, 2 * r, h->small + 1024, r, r, h->Zp, 16, 1.0, 0.0);
+            std::vector<double> lam(r);
+            HIPCHK(hipMemcpyAsync(lam.data(), h->small + 2048, r * sizeof(double), hipMemcpyDeviceToHost, s));
+            // <C_s, Xhat> = sum_j lam_j u_j^T C_s u_j ; A(Xhat)
+            apply_C(h, h->Zp, 16, h->CV, 16, r);
+            tn_reduce(s, h->rs, n, h->Zp, 16, r, h->CV, 16, r, h->TUU, r, 1.0, 0.0);
+            std::vector<double> uc(r * r);
+            HIPCHK(hipMemcpyAsync(uc.data(), h->TUU, r * r * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double cx = 0.0;
+            for (int j = 0; j < r; ++j) cx += lam[j] * uc[j * r + j];
+            std::vector<double> K(r * r, 0.0);
+            for (int j = 0; j < r; ++j) K[j * r + j] = lam[j];
+            HIPCHK(hipMemcpyAsync(h->Kc, K.data(), r * r * sizeof(double), hipMemcpyHostToDevice, s));
+            lowrank_A(s, h->m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, r, h->Kc, 1.0, nullptr, nullptr, 0.0, h->AX,
+                      0.0);
+            std::vector<double> ax(h->m), bs(h->m);
+            HIPCHK(hipMemcpyAsync(ax.data(), h->AX, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(bs.data(), h->b, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            double d2 = 0.0;
+            for (int q = 0; q < h->m; ++q) {
+                const double e = h->hp.ineq[q] ? std::max(ax[q] - bs[q], 0.0) : ax[q] - bs[q];
+                d2 += e * e;
+            }
+            if (res) {
+                res->sketch_primal_obj = h->sigma * h->trace * cx;
+                res->sketch_rel_infeas = (p.units == USBS_UNITS_ORIGINAL)
+                                             ? h->trace * std::sqrt(d2) / (1.0 + h->trace * h->bnorm)
+                                             : std::sqrt(d2) / (1.0 + h->bnorm);
+            }
+            if (lam_out)
+                for (int j = 0; j < r; ++j) lam_out[j] = h->trace * lam[j];
+            if (U_out) {
+                std::vector<double> U((size_t)n * 16);
+                HIPCHK(hipMemcpy(U.data(), h->Zp, (size_t)n * 16 * sizeof(double), hipMemcpyDeviceToHost));
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < r; ++j) U_out[(size_t)i * r + j] = U[(size_t)i * 16 + j];
+            }
+        }
+        return status;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+void usbs_free(usbs_handle *h) {
+    if (!h) return;
+    free_problem(h);
+    delete h;
+}
+
+const char *usbs_last_error(const usbs_handle *h) { return h ? h->err.c_str() : "NULL handle"; }
+
+int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (sigma) *sigma = h->sigma;
+    if (trace) *trace = h->trace;
+    return USBS_OK;
+}
+
+int usbs_op_apply(usbs_handle *h, const double *y_dev, const double *X_dev, int32_t ldx, double *Y_dev, int32_t ldy,
+                  int32_t nb) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!y_dev || !X_dev || !Y_dev || nb < 1 || nb > 16 || ldx < nb || ldy < nb) {
+        set_err(h, "usbs_op_apply: bad arguments");
+        return USBS_E_INVALID;
+    }
+    try {
+        shift_operator(h, y_dev);
+        apply_op(h, X_dev, ldx, Y_dev, ldy, nb);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_op_eigs(usbs_handle *h, const double *y_dev, int32_t k, const double *start_dev, double *w, double *U_dev,
+                 double *res, int32_t *cycles) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!y_dev || k < 1 || k > 14) {
+        set_err(h, "usbs_op_eigs: need y_dev and 1 <= k <= 14");
+        return USBS_E_INVALID;
+    }
+    try {
+        hipStream_t s = h->stream;
+        shift_operator(h, y_dev);
+        if (start_dev) copy_cols(s, h->n, start_dev, 16, 16, h->Ubuf, 16);
+        else random_block(s, h->n, 16, h->prm.seed + 7, h->Ubuf, 16);
+        const int c = lanczos(h, h->Ubuf, k, h->prm.lanczos_tol, std::max(h->prm.lanczos_max_restarts, 30), true);
+        if (w) HIPCHK(hipMemcpyAsync(w, h->theta, k * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (res) HIPCHK(hipMemcpyAsync(res, h->res, k * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (U_dev) copy_cols(s, h->n, h->Uritz, 16, 16, U_dev, 16);
+        HIPCHK(hipStreamSynchronize(s));
+        if (cycles) *cycles = c;
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_op_lowrank_A(usbs_handle *h, const double *W_dev, int32_t q, const double *lam, double *out_dev) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!W_dev || !lam || !out_dev || q < 1 || q > 16) {
+        set_err(h, "usbs_op_lowrank_A: bad arguments");
+        return USBS_E_INVALID;
+    }
+    try {
+        std::vector<double> K(q * q, 0.0);
+        for (int j = 0; j < q; ++j) K[j * q + j] = lam[j];
+        HIPCHK(hipMemcpyAsync(h->Kc, K.data(), q * q * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        lowrank_A(h->stream, h->m, h->kptr, h->ti, h->tj, h->tv, W_dev, q, q, h->Kc, 1.0, nullptr, nullptr, 0.0,
+                  out_dev, 0.0);
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_op_sketch_update(usbs_handle *h, double g, const double *W_dev, int32_t q, const double *lam, double *P_dev) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!h->sketch) {
+        set_err(h, "usbs_op_sketch_update: problem has no test matrix");
+        return USBS_E_STATE;
+    }
+    if (!W_dev || !lam || !P_dev || q < 1 || q > 16) {
+        set_err(h, "usbs_op_sketch_update: bad arguments");
+        return USBS_E_INVALID;
+    }
+    try {
+        hipStream_t s = h->stream;
+        const int r = h->r;
+        tn_reduce_f(s, h->rs, h->n, W_dev, q, q, h->psi, r, r, h->VtPsi, r, 1.0);
+        std::vector<double> G(q * r);
+        HIPCHK(hipMemcpyAsync(G.data(), h->VtPsi, q * r * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int a = 0; a < q; ++a)
+            for (int c = 0; c < r; ++c) G[a * r + c] *= lam[a];
+        HIPCHK(hipMemcpyAsync(h->Hsk, G.data(), q * r * sizeof(double), hipMemcpyHostToDevice, s));
+        nn_update(s, h->n, W_dev, q, q, h->Hsk, r, r, P_dev, r, 1.0, g);
+        HIPCHK(hipStreamSynchronize(s));
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_op_qp_data(usbs_handle *h, const double *V_dev, int32_t k, const double *y_dev, const double *w_dev,
+                    const double *zbar_dev, double tau, double cbar, double *Q11, double *q12, double *q22,
+                    double *h1, double *h2) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!V_dev || !y_dev || !w_dev || !zbar_dev || k < 1 || k > kMaxK) {
+        set_err(h, "usbs_op_qp_data: bad arguments");
+        return USBS_E_INVALID;
+    }
+    try {
+        hipStream_t s = h->stream;
+        const int n = h->n, m = h->m, d = k * (k + 1) / 2;
+        copy_cols(s, n, V_dev, k, k, h->Zp, 16);
+        apply_C(h, h->Zp, 16, h->CV, 16, k);
+        tn_reduce(s, h->rs, n, h->Zp, 16, k, h->CV, 16, k, h->VCV, k, 1.0, 0.0);
+        const double *ws[3] = {zbar_dev, y_dev, w_dev};
+        qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, k, ws, 3, h->raw, 1);
+        const double *a[3] = {zbar_dev, y_dev, w_dev}, *bb[3] = {zbar_dev, zbar_dev, zbar_dev};
+        std::vector<double> sc(SC_COUNT, 0.0);
+        HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::vector<double> save = sc;
+        sc[SC_TAU] = tau;
+        sc[SC_CBAR] = cbar;
+        HIPCHK(hipMemcpyAsync(h->sc, sc.data(), SC_COUNT * sizeof(double), hipMemcpyHostToDevice, s));
+        dots(s, h->rs, m, a, bb, 3, h->sc + SC_ZZ);
+        qp_finalize(s, k, h->raw, h->VCV, h->sc, 0, h->qp);
+        std::vector<double> out(d * d + 2 * d + 2);
+        HIPCHK(hipMemcpyAsync(out.data(), h->qp, out.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(hipMemcpy(h->sc, save.data(), SC_COUNT * sizeof(double), hipMemcpyHostToDevice));
+        if (Q11) std::memcpy(Q11, out.data(), d * d * sizeof(double));
+        if (q12) std::memcpy(q12, out.data() + d * d, d * sizeof(double));
+        if (q22) *q22 = out[d * d + d];
+        if (h1) std::memcpy(h1, out.data() + d * d + d + 1, d * sizeof(double));
+        if (h2) *h2 = out[d * d + 2 * d + 1];
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_op_ipm(usbs_handle *h, int32_t k, const double *Q11, const double *q12, double q22, const double *h1,
+                double h2, double *S, double *eta, int32_t *iters) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (k < 1 || k > kMaxK || !Q11 || !q12 || !h1) {
+        set_err(h, "usbs_op_ipm: bad arguments");
+        return USBS_E_INVALID;
+    }
+    try {
+        hipStream_t s = h->stream;
+        const int d = k * (k + 1) / 2;
+        std::vector<double> qpv(d * d + 2 * d + 2);
+        std::memcpy(qpv.data(), Q11, d * d * sizeof(double));
+        std::memcpy(qpv.data() + d * d, q12, d * sizeof(double));
+        qpv[d * d + d] = q22;
+        std::memcpy(qpv.data() + d * d + d + 1, h1, d * sizeof(double));
+        qpv[d * d + 2 * d + 1] = h2;
+        HIPCHK(hipMemcpyAsync(h->qp, qpv.data(), qpv.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        IpmArgs ia{k, 1e-7, 1e-7, 100, 0};
+        ipm(s, ia, h->qp, h->ipm);
+        std::vector<double> st(2 * k * k + 5);
+        HIPCHK(hipMemcpyAsync(st.data(), h->ipm, st.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (S) std::memcpy(S, st.data(), k * k * sizeof(double));
+        if (eta) *eta = st[2 * k * k];
+        if (iters) *iters = (int)st[2 * k * k + 3];
+        if (st[2 * k * k + 4] == 2.0) {
+            set_err(h, "interior point method failed (numerical breakdown)");
+            return USBS_E_NUMERIC;
+        }
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_op_nystrom(usbs_handle *h, const double *P_dev, double *U_dev, double *lam) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!h->sketch || !P_dev || !U_dev) {
+        set_err(h, "usbs_op_nystrom: needs a test matrix and device arrays");
+        return USBS_E_INVALID;
+    }
+    try {
+        hipStream_t s = h->stream;
+        const int n = h->n, r = h->r;
+        interleave(s, n, r, P_dev, h->psi, h->W2);
+        tn_reduce(s, h->rs, n, h->W2, 2 * r, 2 * r, h->W2, 2 * r, 2 * r, h->small, 2 * r, 1.0, 0.0);
+        nystrom_core(s, n, r, h->small, h->small + 1024, h->small + 2048, h->flag);
+        nn_update(s, n, h->W2, 2 * r, 2 * r, h->small + 1024, r, r, U_dev, r, 1.0, 0.0);
+        int bad = 0;
+        if (lam) HIPCHK(hipMemcpyAsync(lam, h->small + 2048, r * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (bad) {
+            set_err(h, "Nystrom core matrix not positive definite");
+            return USBS_E_NUMERIC;
+        }
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *zbar, double *Pbar, double *scal) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (t < 0) return USBS_E_INVALID;
+    try {
+        for (int q = 0; q < t; ++q) iterate(h);
+        hipStream_t s = h->stream;
+        std::vector<double> sc(SC_COUNT);
+        HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (y) HIPCHK(hipMemcpyAsync(y, h->y, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (V) HIPCHK(hipMemcpyAsync(V, h->V, (size_t)h->n * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (zbar) HIPCHK(hipMemcpyAsync(zbar, h->zbar, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (Pbar && h->sketch)
+            HIPCHK(hipMemcpyAsync(Pbar, h->P, (size_t)h->n * h->r * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (scal) {
+            scal[0] = sc[SC_F];
+            scal[1] = sc[SC_TAU];
+            scal[2] = sc[SC_CBAR];
+            scal[3] = sc[SC_CX];
+            scal[4] = sc[SC_GAP];
+            scal[5] = sc[SC_INF];
+            scal[6] = sc[SC_THETA1];
+            scal[7] = sc[SC_NDESC];
+        }
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
+    if (!h || !h->ready) {
+        set_err(h, "usbs_warm_start: handle not ready");
+        return USBS_E_STATE;
+    }
+    (void)grown;
+    set_err(h, "usbs_warm_start: not implemented");
+    return USBS_E_STATE;
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+"""The C ABI library loads and exports every symbol include/usbs.h declares (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "usbs.h")).read()
+    return sorted(set(re.findall(r"\b(usbs_[a-z_A]+)\s*\(", src)))
+
+
+def test_header_matches_binding_list():
+    from paper_2312_11801_amd.native import EXPORTS
+    assert sorted(EXPORTS) == _declared()
+
+
+def test_library_exports_all_symbols():
+    from paper_2312_11801_amd.native import LIB_PATH
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("libusbs.so not built")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+def test_struct_layout_matches_header():
+    """Field order/types of the ctypes mirrors against the C structs (by parsing the header)."""
+    from paper_2312_11801_amd import native
+    src = open(os.path.join(ROOT, "include", "usbs.h")).read()
+    for cname, py in (("usbs_problem", native.UsbsProblem), ("usbs_params", native.UsbsParams),
+                      ("usbs_result", native.UsbsResult)):
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), src, re.S).group(1)
+        body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+        names = []
+        for decl in body.split(";"):
+            decl = decl.strip()
+            if not decl:
+                continue
+            parts = decl.replace("*", " ").split()
+            rest = " ".join(parts[1:]) if parts[0] != "const" else " ".join(parts[2:])
+            names += [x.strip() for x in rest.split(",")]
+        assert names == [f for f, _ in py._fields_], (cname, names)
+
+
+def test_default_params_call_is_host_only():
+    """usbs_default_params touches no device state and fills the App. E.1 defaults."""
+    from paper_2312_11801_amd.native import LIB_PATH, UsbsParams, load_library
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("libusbs.so not built")
+    lib = load_library()
+    p = UsbsParams()
+    assert lib.usbs_default_params(ctypes.byref(p)) == 0
+    assert (p.alpha, p.rho, p.beta, p.k_c, p.k_p, p.r) == (2.0, 0.01, 0.25, 10, 1, 10)

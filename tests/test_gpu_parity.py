@@ -1,0 +1,198 @@
+"""GPU parity: every row of the hot path through the C ABI against the FP64 CPU oracle.
+
+Inputs come from the seeded generators in sdp_inputs; expected values only from oracle/.
+Sizes span several workgroups/tiles and a ragged tail (n not a multiple of 8, 32 or 256).
+"""
+import numpy as np
+import pytest
+
+import sdp_inputs as si
+from oracle import usbs_oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a, torch):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _problems():
+    return {
+        "maxcut": si.maxcut_er(301, 0.05, seed=11),
+        "cc": si.cc_signed(257, avg_degree=8.0, seed=5),
+    }
+
+
+@pytest.mark.parametrize("kind", ["maxcut", "cc"])
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 2e-6), ("bf16", 2e-2)])
+def test_op_apply_parity(cuda, kind, prec, tol):
+    """(C_s - A^* y) X, the operator of the eigen step (Sec. 3, eq. pen-D)."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob = _problems()[kind]
+    rng = np.random.default_rng(1)
+    y = rng.standard_normal(prob.m) * 0.01
+    sc = orc.scale_problem(prob)
+    M = sc.C - orc.A_adjoint(prob, y)
+    s = Solver(prob, Params(precision=prec, k_c=3, k_p=0))
+    for nb in (8, 16, 5):
+        X = rng.standard_normal((prob.n, nb))
+        Y = torch.zeros((prob.n, nb), dtype=torch.float64, device="cuda")
+        s.op_apply(_dev(y, torch), _dev(X, torch), Y)
+        torch.cuda.synchronize()
+        ref = M @ X
+        err = np.abs(Y.cpu().numpy() - ref).max() / np.abs(ref).max()
+        exact_bf16 = prec == "bf16" and kind == "maxcut"   # unit-weight Laplacian: exact values
+        assert err <= (2e-6 if exact_bf16 else tol), (nb, err)
+    s.free()
+
+
+@pytest.mark.parametrize("kind", ["maxcut", "cc"])
+def test_eigs_parity(cuda, kind):
+    """Top-k Ritz values of block Lanczos vs the Jacobi spectrum: |theta_i - lambda_i| <=
+    1e-6 max(|lambda_i|, rho(M)), plus orthonormal Ritz vectors and small residuals."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob = _problems()[kind]
+    rng = np.random.default_rng(2)
+    y = rng.standard_normal(prob.m) * 0.005
+    sc = orc.scale_problem(prob)
+    M = sc.C - orc.A_adjoint(prob, y)
+    lam = orc.jacobi_eigh(M)[0]
+    rhoM = np.abs(lam).max()
+    s = Solver(prob, Params(k_c=3, k_p=0, lanczos_tol=1e-9))
+    U = torch.zeros((prob.n, 16), dtype=torch.float64, device="cuda")
+    k = 10
+    w, res, cyc = s.op_eigs(_dev(y, torch), k, U_dev=U)
+    Uh = U.cpu().numpy()[:, :k]
+    assert np.all(np.abs(w - lam[:k]) <= 1e-6 * np.maximum(np.abs(lam[:k]), rhoM)), (w, lam[:k])
+    assert np.abs(Uh.T @ Uh - np.eye(k)).max() <= 1e-10
+    R = M @ Uh - Uh * w[None, :]
+    assert np.linalg.norm(R, axis=0).max() <= 1e-6 * rhoM
+    s.free()
+
+
+def test_lowrank_A_parity(cuda):
+    """(A(W diag(lam) W^T))_k on both diagonal and edge rows (App. C)."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob = _problems()["cc"]
+    rng = np.random.default_rng(3)
+    q = 7
+    W = rng.standard_normal((prob.n, q))
+    lam = rng.random(q)
+    s = Solver(prob, Params(k_c=3, k_p=0))
+    out = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
+    s.op_lowrank_A(_dev(W, torch), lam, out)
+    ref = orc.A_lowrank(prob, W, lam)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-12 * (1 + np.abs(ref).max())
+    s.free()
+
+
+def test_sketch_update_parity(cuda):
+    """P <- g P + W Lam (W^T Psi) (Sec. 4)."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob = _problems()["maxcut"]
+    r = 10
+    psi = si.test_matrix(prob.n, r, seed=4)
+    rng = np.random.default_rng(4)
+    q = 10
+    W = rng.standard_normal((prob.n, q))
+    lam = rng.random(q)
+    P0 = rng.standard_normal((prob.n, r))
+    g = 0.37
+    s = Solver(prob, Params(k_c=3, k_p=0, r=r), psi=psi)
+    P = _dev(P0, torch)
+    s.op_sketch_update(g, _dev(W, torch), lam, P)
+    ref = g * P0 + W @ (lam[:, None] * (W.T @ psi.astype(np.float64)))
+    assert np.abs(P.cpu().numpy() - ref).max() <= 1e-11 * (1 + np.abs(ref).max())
+    s.free()
+
+
+@pytest.mark.parametrize("kind", ["maxcut", "cc"])
+def test_qp_data_and_ipm_parity(cuda, kind):
+    """Master QP coefficients (App. B.2) and its interior point solution."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob = _problems()[kind]
+    sc = orc.scale_problem(prob)
+    rng = np.random.default_rng(5)
+    k = 11 if kind == "maxcut" else 3
+    V = np.linalg.qr(rng.standard_normal((prob.n, k)))[0]
+    y = rng.standard_normal(prob.m) * 0.01
+    nu = np.where(prob.is_ineq.astype(bool), np.abs(rng.standard_normal(prob.m)) * 1e-3, 0.0)
+    w = sc.b - nu
+    Xb = rng.standard_normal((prob.n, 4))
+    Xbar = Xb @ Xb.T / prob.n
+    tau = float(np.trace(Xbar))
+    cbar = float(np.sum(sc.C * Xbar))
+    zbar = orc.A_apply(prob, Xbar)
+    Gk = orc.constraint_blocks(prob, V)
+    VCV = V.T @ sc.C @ V
+    ref = orc.qp_data(sc, V, Gk, VCV, y, w, zbar, cbar, tau, 2.0, 0.01)
+    s = Solver(prob, Params(k_c=k, k_p=0))
+    got = s.op_qp_data(_dev(V, torch), _dev(y, torch), _dev(w, torch), _dev(zbar, torch), tau, cbar)
+    for key in ("Q11", "q12", "h1"):
+        a, b = got[key], getattr(ref, key)
+        assert np.abs(a - b).max() <= 1e-10 * (1 + np.abs(b).max()), key
+    assert abs(got["q22"] - ref.q22) <= 1e-10 * (1 + abs(ref.q22))
+    assert abs(got["h2"] - ref.h2) <= 1e-10 * (1 + abs(ref.h2))
+    S, eta, it = s.op_ipm(k, ref.Q11, ref.q12, ref.q22, ref.h1, ref.h2)
+    st = orc.ipm_qsdp(ref, k)
+    assert abs(eta - st.eta) <= 1e-5 and np.abs(S - st.S).max() <= 1e-5, (eta, st.eta)
+    fo = orc.qp_objective(ref, st.S, st.eta)
+    fg = orc.qp_objective(ref, S, eta)
+    assert abs(fg - fo) <= 1e-6 * (1 + abs(fo))
+    s.free()
+
+
+def test_nystrom_parity(cuda):
+    """Stable Nystrom reconstruction (App. C.1): same rank-r approximation as the oracle."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob = _problems()["maxcut"]
+    r = 10
+    psi = si.test_matrix(prob.n, r, seed=6).astype(np.float64)
+    rng = np.random.default_rng(6)
+    F = rng.standard_normal((prob.n, 6)) * np.array([3, 2, 1, 0.5, 0.1, 0.01])
+    X = F @ F.T
+    P = X @ psi
+    s = Solver(prob, Params(k_c=3, k_p=0, r=r), psi=psi.astype(np.float32))
+    U = torch.zeros((prob.n, r), dtype=torch.float64, device="cuda")
+    lam = s.op_nystrom(_dev(P, torch), U)
+    Uh = U.cpu().numpy()
+    Xg = (Uh * lam[None, :]) @ Uh.T
+    Ur, lr = orc.nystrom_stable(P, psi)
+    Xr = (Ur * lr[None, :]) @ Ur.T
+    assert np.abs(Xg - Xr).max() <= 1e-8 * np.abs(Xr).max()
+    # rank 6 < r - 1: the reconstruction is exact
+    assert np.abs(Xg - X).max() <= 1e-7 * np.abs(X).max()
+    s.free()
+
+
+def test_solve_parity_small_maxcut(cuda):
+    """Full solve to the paper's 1e-3 criterion: the FP64 oracle recomputes the certificate
+    of the GPU result, and the GPU objective matches the oracle's own solve."""
+    from paper_2312_11801_amd import Params, Solver
+    prob = si.maxcut_er(120, 0.08, seed=7)
+    psi = si.test_matrix(prob.n, 10, seed=7)
+    s = Solver(prob, Params(rho=0.1, max_iters=600), psi=psi)
+    out = s.solve()
+    s.free()
+    print("gpu", {k: out[k] for k in ("iters", "primal_obj", "dual_bound", "rel_gap", "rel_infeas")})
+    assert out["converged"], out
+    sc = orc.scale_problem(prob)
+    y_s = out["y"] / sc.sigma
+    lam1 = orc.jacobi_eigh(sc.C - orc.A_adjoint(prob, y_s))[0][0]
+    f_ref = 2.0 * max(lam1, 0.0) + float(sc.b @ y_s)
+    assert abs(f_ref - out["f_scaled"]) <= 1e-7 * (1 + abs(f_ref))
+    gap = abs(f_ref - out["primal_obj_scaled"]) / (1 + abs(out["primal_obj_scaled"]))
+    assert gap <= 1e-3 + 1e-9
+    assert out["rel_infeas"] <= 1e-3
+    ref = orc.usbs_solve(prob, orc.Params(rho=0.1, max_iters=600), Psi=psi, keep_history=False)
+    assert ref.converged
+    p_ref_s = ref.primal_obj
+    print("oracle", ref.iters, orc.to_original(sc, p_ref_s))
+    assert abs(out["primal_obj_scaled"] - p_ref_s) / (1 + abs(p_ref_s)) <= 1e-3
+    assert abs(out["primal_obj"] - orc.to_original(sc, p_ref_s)) / abs(orc.to_original(sc, p_ref_s)) <= 5e-3
