@@ -93,7 +93,8 @@ typedef struct usbs_params {
     double time_limit;          /* seconds, <= 0 for none                  */
     int32_t lanczos_steps;      /* block steps per restart cycle (b = 8)   */
     int32_t lanczos_max_restarts;
-    double lanczos_tol;         /* residual / spectral-radius estimate      */
+    double lanczos_tol;         /* residual / spectral-radius estimate inside the iteration */
+    double lanczos_tol_final;   /* same, for f(y0) and the certified f(y_T) at convergence  */
     int32_t precision;          /* USBS_PREC_*                             */
     uint64_t seed;              /* start block of the cold Lanczos solve   */
     void *stream;               /* hipStream_t, NULL = default stream       */
@@ -188,6 +189,17 @@ int usbs_op_nystrom(usbs_handle *h, const double *P_dev, double *U_dev, double *
  * Any output may be NULL. */
 int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *zbar,
                       double *Pbar, double *scal);
+
+/* Live kernel timing (HIP events on the handle's stream) for one category at a time:
+ * flushes the pending events, returns the accumulated milliseconds and launch count of
+ * the category being timed (optionally resetting them), then times 'category' from now
+ * on (-1 = none).  Used by the benchmark for the roofline of the dominant kernel. */
+#define USBS_PROF_SPMM 0   /* (C - A^* y) X block products                    */
+#define USBS_PROF_REORTH 1 /* B^T W reductions of the block re-orthogonalisation */
+#define USBS_PROF_RITZ 2   /* projected (Rayleigh-Ritz) eigenproblem          */
+#define USBS_PROF_IPM 3    /* master-QP interior point solve                  */
+#define USBS_PROF_COUNT 4
+int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_total, int64_t *launches);
 
 /* Scaling factors of the handle's problem: sigma = ||C||_F, trace. */
 int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace);

@@ -16,14 +16,13 @@ constexpr int kMaxSteps = 8;      // block steps per restart cycle
 constexpr int kMaxBasis = kRitz + kBlk * kMaxSteps;   // 80
 constexpr int kMaxRank = 16;      // sketch rank r
 
-// Scratch of the two-stage reductions: per-workgroup partial results plus a
-// completion counter; the last workgroup to finish reduces the partials in a
-// fixed order (deterministic) and resets the counter.
+// Scratch of the two-stage reductions: one partial result per workgroup of the
+// first stage; a second kernel sums them in a fixed order (deterministic).
+constexpr int kRedMaxBlocks = 512;
 struct RedScratch {
-    double *partials;
-    unsigned int *counter;
+    double *partials;   // kRedMaxBlocks * max_elems
     int max_blocks;
-    int max_elems;   // doubles per partial
+    int max_elems;      // doubles per partial
 };
 
 // ---- sparse operator --------------------------------------------------
@@ -63,8 +62,8 @@ void fill(hipStream_t s, size_t count, double v, double *p);
 void random_block(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ldc);
 
 // ---- small dense problems (one workgroup) --------------------------------
-// eigen-decomposition of the symmetric N x N matrix A (ld lda, N <= kMaxBasis):
-// w[0..N) descending, Y (N x ny, ldy) = first ny eigenvectors; entries of
+// top eigenpairs of the symmetric N x N matrix A (upper triangle read, ld lda, N <= kMaxBasis):
+// w[0..min(N,16)) descending, Y (N x ny, ldy) = first ny <= 16 eigenvectors; entries of
 // 'dead' (length N, may be null) mark columns to push to the bottom.
 void small_eig(hipStream_t s, int N, const double *A, int lda, double *w, double *Y, int ldy,
                int ny, const int *dead);
@@ -73,16 +72,20 @@ void small_eig(hipStream_t s, int N, const double *A, int lda, double *w, double
 // from R^T R (16 x 16) and Ritz values theta: residual norms res, convergence
 // flag (res_i <= tol * scale for i < kc), and Z (16 x 8) = top-8 right singular
 // directions scaled by 1/sigma, so that R Z has orthonormal columns.
+// convergence: residual of Ritz pair 0 <= tol * scale and of pairs 1..kc-1 <= tol_rest * scale
 void lanczos_restart_prep(hipStream_t s, const double *RtR, const double *theta, int kc, double tol,
-                          double *res, int *flag, double *Z, double *scale_est);
+                          double tol_rest, double *res, int *flag, double *Z, double *scale_est);
 // T (ld) := 0 with diag(theta) in the leading 16 x 16 block; dead flags cleared
 void lanczos_reset_T(hipStream_t s, double *T, int ldt, int N, const double *theta, int *dead);
+// theta = diag(TUU), Y = I (N x N)
+void diag_theta(hipStream_t s, const double *TUU, int N, double *theta, double *Y);
 // H = -diag(theta) (16 x 16)
 void neg_diag(hipStream_t s, const double *theta, int N, double *H);
 
 // ---- USBS small steps ----------------------------------------------------
-// Q11 partial sums and the G^T w products of the master QP (App. B.2).
-// out layout: [0, d*d) Q11 (unscaled sum g g^T), then G^T w_j for j < nw (d each)
+// Q11 sums and the G^T w products of the master QP (App. B.2), g_k = svec(V^T A_k V).
+// out layout (d = k(k+1)/2): if do_q11, the upper triangle of sum_k g_k g_k^T row by row
+// (entry (P,Q), P <= Q, at P d - P(P-1)/2 + Q - P, d(d+1)/2 values); then G^T w_j, j < nw.
 void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const int *ti,
              const int *tj, const double *tv, const double *V, int ldv, int k, const double *const *w,
              int nw, double *out, int do_q11);

@@ -8,6 +8,7 @@
 // a column slice of the Lanczos basis is addressed by (pointer + offset, ld).
 #include "kernels.h"
 #include "small_dense.h"
+#include "syev.h"
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -35,6 +36,89 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
 }
 
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Second stage of every grid-wide reduction.  Stage-1 kernels write one partial
+// per workgroup (part[b * nout + o]) and exit; no workgroup waits for another,
+// so no device-scope fence (an L2 write-back/invalidate on this GPU) is issued
+// per workgroup.  This kernel sums the G partials of each output in block order
+// (deterministic): 4 waves split the partials, LDS combines them in fixed order.
+//   out[(o / cb) * ldo + (o % cb)] = alpha * sum_b part[b][o] (+ beta * old)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_red_finish(const double *__restrict__ part, int G, int nout,
+                                                    double *out, int cb, int ldo, double alpha, double beta) {
+    __shared__ double s4[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
+    const int per = (G + 3) / 4;
+    const int b0 = w * per, b1 = min(G, b0 + per);
+    double s = 0.0;
+    if (o < nout) {
+        double a0 = 0.0, a1 = 0.0;
+        int bb = b0;
+        for (; bb + 1 < b1; bb += 2) {
+            a0 += part[(size_t)bb * nout + o];
+            a1 += part[(size_t)(bb + 1) * nout + o];
+        }
+        if (bb < b1) a0 += part[(size_t)bb * nout + o];
+        s = a0 + a1;
+    }
+    s4[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && o < nout) {
+        const double t = alpha * (((s4[0][lane] + s4[1][lane]) + s4[2][lane]) + s4[3][lane]);
+        const int r = o / cb, c = o - r * cb;
+        double *dst = out + (size_t)r * ldo + c;
+        *dst = (beta != 0.0) ? t + beta * (*dst) : t;
+    }
+}
+
+static void red_finish(hipStream_t s, const double *part, int G, int nout, double *out, int cb, int ldo,
+                       double alpha, double beta) {
+    hipLaunchKernelGGL(k_red_finish, dim3(cdiv(nout, 64)), dim3(kWG), 0, s, part, G, nout, out, cb, ldo, alpha,
+                       beta);
+}
+
+// Cholesky-QR factor from the partial Gram matrices (one workgroup): G = sum of the
+// partials (nc x nc), then R^{-1} (upper) with deflation flags, see wave_cholqr.
+__global__ __launch_bounds__(kWG) void k_cholqr_finish(const double *__restrict__ part, int G, int nc,
+                                                       double *H, int ldh, int *flags, const double *floor_ref) {
+    __shared__ double sR[16 * 17];
+    __shared__ double s4[4][64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int nout = nc * nc;
+    const int per = (G + 3) / 4;
+    const int b0 = w * per, b1 = min(G, b0 + per);
+    for (int o0 = 0; o0 < nout; o0 += 64) {
+        const int o = o0 + lane;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        if (o < nout) {
+            int bb = b0;
+            for (; bb + 3 < b1; bb += 4) {
+                a0 += part[(size_t)bb * nout + o];
+                a1 += part[(size_t)(bb + 1) * nout + o];
+                a2 += part[(size_t)(bb + 2) * nout + o];
+                a3 += part[(size_t)(bb + 3) * nout + o];
+            }
+            for (; bb < b1; ++bb) a0 += part[(size_t)bb * nout + o];
+        }
+        s4[w][lane] = (a0 + a1) + (a2 + a3);
+        __syncthreads();
+        if (w == 0 && o < nout) {
+            const int a = o / nc, c = o - a * nc;
+            sR[a * 17 + c] = ((s4[0][lane] + s4[1][lane]) + s4[2][lane]) + s4[3][lane];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    double f2 = 0.0;
+    if (floor_ref) {
+        const double rf = 1e-10 * (*floor_ref);
+        f2 = rf * rf;
+    }
+    if (tid < 64) wave_cholqr(nc, sR, 17, H, ldh, flags, f2);
+}
 
 // ---------------------------------------------------------------------------
 // SpMM with the shifted diagonal: L lanes per row, lane c owns column c.
@@ -185,14 +269,12 @@ constexpr int kMaxCB = 32;
 constexpr int kMaxOut = kMaxBasis * 16;          // 1280 outputs (also >= 32 x 32)
 constexpr int kOutPerThread = (kMaxOut + kWG - 1) / kWG;
 
-template <typename TB, int POST>
+template <typename TB>
 __global__ __launch_bounds__(kWG) void k_tn_reduce(int n, const double *__restrict__ A, int lda, int ca,
-                                                   const TB *__restrict__ B, int ldb, int cb, double *H,
-                                                   int ldh, double alpha, double beta, double *partials,
-                                                   unsigned int *counter, int *flags, const double *floor_ref) {
+                                                   const TB *__restrict__ B, int ldb, int cb,
+                                                   double *__restrict__ partials) {
     __shared__ double sA[kTile][kMaxBasis + 1];
     __shared__ double sB[kTile][kMaxCB + 1];
-    __shared__ int s_last;
     const int tid = threadIdx.x;
     const int nout = ca * cb;
     double acc[kOutPerThread];
@@ -229,64 +311,29 @@ __global__ __launch_bounds__(kWG) void k_tn_reduce(int n, const double *__restri
         const int o = tid + q * kWG;
         if (o < nout) partials[(size_t)blockIdx.x * nout + o] = acc[q];
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned int prev = atomicAdd(counter, 1u);
-        s_last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    __shared__ double sR[16 * 17];
-    for (int o = tid; o < nout; o += kWG) {
-        double s = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) s += __builtin_nontemporal_load(&partials[(size_t)b * nout + o]);
-        const int a = o / cb, c = o - a * cb;
-        double v = alpha * s;
-        if (POST == 0) {
-            if (beta != 0.0) v += beta * H[a * ldh + c];
-            H[a * ldh + c] = v;
-        } else {
-            sR[a * 17 + c] = v;
-        }
-    }
-    if (tid == 0) *counter = 0u;
-    if (POST == 1) {
-        __syncthreads();
-        // Cholesky-QR factor: G = R^T R, write R^{-1} (upper) to H; a column whose
-        // pivot falls below max(1e-24 max diag, (1e-10 ref)^2) is deflated (zero
-        // column of R^{-1}): it lies in the span of the basis already.
-        double f2 = 0.0;
-        if (floor_ref) {
-            const double rf = 1e-10 * (*floor_ref);
-            f2 = rf * rf;
-        }
-        if (tid < 64) wave_cholqr(ca, sR, 17, H, ldh, flags, f2);
-    }
+}
+
+static int tn_blocks(const RedScratch &rs, int n) {
+    int blocks = cdiv(n, 4 * kTile);
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks < 1) blocks = 1;
+    return blocks;
 }
 
 void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
                int ldb, int cb, double *H, int ldh, double alpha, double beta, int post, int *flags,
                const double *floor_ref) {
-    int blocks = cdiv(n, 4 * kTile);
-    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
-    if (blocks < 1) blocks = 1;
-    if (post == 0)
-        hipLaunchKernelGGL((k_tn_reduce<double, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
-                           H, ldh, alpha, beta, rs.partials, rs.counter, flags, floor_ref);
-    else
-        hipLaunchKernelGGL((k_tn_reduce<double, 1>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
-                           H, ldh, alpha, beta, rs.partials, rs.counter, flags, floor_ref);
+    const int blocks = tn_blocks(rs, n);
+    hipLaunchKernelGGL((k_tn_reduce<double>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    if (post == 0) red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, beta);
+    else hipLaunchKernelGGL(k_cholqr_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, ca, H, ldh, flags, floor_ref);
 }
 
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const float *B,
                  int ldb, int cb, double *H, int ldh, double alpha) {
-    int blocks = cdiv(n, 4 * kTile);
-    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
-    if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL((k_tn_reduce<float, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, H,
-                       ldh, alpha, 0.0, rs.partials, rs.counter, (int *)nullptr, (const double *)nullptr);
+    const int blocks = tn_blocks(rs, n);
+    hipLaunchKernelGGL((k_tn_reduce<float>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -394,12 +441,10 @@ void random_block(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ld
 __global__ __launch_bounds__(kWG) void k_small_eig(int N, const double *__restrict__ A, int lda,
                                                    double *__restrict__ w, double *__restrict__ Y, int ldy,
                                                    int ny, const int *__restrict__ dead) {
-    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
-    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
-    __shared__ JacobiScratch js;
-    wg_load_sym(N, A, lda, dead, &sA[0][0], kMaxBasis + 1);
-    wg_jacobi(N, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
-    wg_sort_store(N, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, Y, ldy, ny, &js);
+    __shared__ SyevWork ws;
+    wg_syev_load(N, A, lda, dead, &ws);
+    const int nv = N < kSyevMaxV ? N : kSyevMaxV;
+    wg_syev_top(N, nv, ny < nv ? ny : nv, &ws, w, Y, ldy);
 }
 
 void small_eig(hipStream_t s, int N, const double *A, int lda, double *w, double *Y, int ldy, int ny,
@@ -413,19 +458,16 @@ void small_eig(hipStream_t s, int N, const double *A, int lda, double *w, double
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__ RtR,
                                                       const double *__restrict__ theta, int kc, double tol,
-                                                      double *__restrict__ res, int *__restrict__ flag,
-                                                      double *__restrict__ Z, double *__restrict__ scale_est) {
-    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
-    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
-    __shared__ JacobiScratch js;
+                                                      double tol_rest, double *__restrict__ res,
+                                                      int *__restrict__ flag, double *__restrict__ Z,
+                                                      double *__restrict__ scale_est) {
+    __shared__ SyevWork ws;
     __shared__ double wv[kRitz];
     __shared__ double Yv[kRitz * kBlk];
     const int tid = threadIdx.x;
     if (tid < kRitz) res[tid] = sqrt(fmax(RtR[tid * kRitz + tid], 0.0));
-    wg_load_sym(kRitz, RtR, kRitz, nullptr, &sA[0][0], kMaxBasis + 1);
-    wg_jacobi(kRitz, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
-    wg_sort_store(kRitz, &sA[0][0], &sV[0][0], kMaxBasis + 1, wv, Yv, kBlk, kBlk, &js);
-    __syncthreads();
+    wg_syev_load(kRitz, RtR, kRitz, nullptr, &ws);
+    wg_syev_top(kRitz, kBlk, kBlk, &ws, wv, Yv, kBlk);
     if (tid < kRitz * kBlk) {
         const int c = tid % kBlk;
         const double sg = sqrt(fmax(wv[c], 0.0));
@@ -438,18 +480,20 @@ __global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__
             sc = fmax(sc, *scale_est);
             *scale_est = sc;
         }
-        int ok = 1;
-        for (int i = 0; i < kc; ++i) {
+        // the top Ritz pair sets f(y): tight tolerance; the others only shape the bundle
+        int ok = sqrt(fmax(RtR[0], 0.0)) <= tol * sc;
+        for (int i = 1; i < kc; ++i) {
             const double r = sqrt(fmax(RtR[i * kRitz + i], 0.0));
-            if (!(r <= tol * sc)) ok = 0;
+            if (!(r <= tol_rest * sc)) ok = 0;
         }
         *flag = ok;
     }
 }
 
 void lanczos_restart_prep(hipStream_t s, const double *RtR, const double *theta, int kc, double tol,
-                          double *res, int *flag, double *Z, double *scale_est) {
-    hipLaunchKernelGGL(k_restart_prep, dim3(1), dim3(kWG), 0, s, RtR, theta, kc, tol, res, flag, Z, scale_est);
+                          double tol_rest, double *res, int *flag, double *Z, double *scale_est) {
+    hipLaunchKernelGGL(k_restart_prep, dim3(1), dim3(kWG), 0, s, RtR, theta, kc, tol, tol_rest, res, flag, Z,
+                       scale_est);
 }
 
 __global__ void k_reset_T(double *T, int ldt, int N, const double *theta, int *dead) {
@@ -462,6 +506,17 @@ __global__ void k_reset_T(double *T, int ldt, int N, const double *theta, int *d
 }
 void lanczos_reset_T(hipStream_t s, double *T, int ldt, int N, const double *theta, int *dead) {
     hipLaunchKernelGGL(k_reset_T, dim3(cdiv((long)N * ldt, kWG)), dim3(kWG), 0, s, T, ldt, N, theta, dead);
+}
+
+// Rayleigh quotient that is already diagonal (U = Ritz vectors of the previous cycle):
+// theta = diag(TUU), Y = I
+__global__ void k_diag_theta(const double *TUU, int N, double *theta, double *Y) {
+    const int e = threadIdx.x;
+    if (e < N * N) Y[e] = (e / N == e % N) ? 1.0 : 0.0;
+    if (e < N) theta[e] = TUU[e * N + e];
+}
+void diag_theta(hipStream_t s, const double *TUU, int N, double *theta, double *Y) {
+    hipLaunchKernelGGL(k_diag_theta, dim3(1), dim3(kWG), 0, s, TUU, N, theta, Y);
 }
 
 __global__ void k_neg_diag(const double *theta, int N, double *H) {
@@ -506,11 +561,9 @@ __global__ __launch_bounds__(kWG) void k_qp_gram(int m, const int *__restrict__ 
                                                  const int *__restrict__ tj, const double *__restrict__ tv,
                                                  const double *__restrict__ V, int ldv, int kd, int do_q11,
                                                  const double *w0, const double *w1, const double *w2,
-                                                 const double *w3, int nw, double *partials,
-                                                 unsigned int *counter, double *out) {
+                                                 const double *w3, int nw, double *partials) {
     __shared__ double sg[kQB][kMaxSvec + 1];
     __shared__ double sw[4][kQB];
-    __shared__ int s_last;
     const int tid = threadIdx.x;
     const int d = kd * (kd + 1) / 2;
     const int nupper = do_q11 ? d * (d + 1) / 2 : 0;
@@ -565,28 +618,6 @@ __global__ __launch_bounds__(kWG) void k_qp_gram(int m, const int *__restrict__ 
         const int o = tid + q * kWG;
         if (o < nout) partials[(size_t)blockIdx.x * nout + o] = acc[q];
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int o = tid + q * kWG;
-        if (o >= nout) continue;
-        double s = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) s += __builtin_nontemporal_load(&partials[(size_t)b * nout + o]);
-        const int P = pP[q], Q = pQ[q];
-        if (P >= 0) {
-            out[P * d + Q] = s;
-            out[Q * d + P] = s;
-        } else {
-            const int j = -P - 2;
-            out[d * d + j * d + Q] = s;
-        }
-    }
-    if (tid == 0) *counter = 0u;
 }
 
 void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const int *ti, const int *tj,
@@ -596,9 +627,12 @@ void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const 
     if (blocks > rs.max_blocks) blocks = rs.max_blocks;
     if (blocks > 240) blocks = 240;
     if (blocks < 1) blocks = 1;
+    const int d = k * (k + 1) / 2;
+    const int nout = (do_q11 ? d * (d + 1) / 2 : 0) + nw * d;
     hipLaunchKernelGGL(k_qp_gram, dim3(blocks), dim3(kWG), 0, s, m, kptr, ti, tj, tv, V, ldv, k, do_q11,
                        nw > 0 ? w[0] : nullptr, nw > 1 ? w[1] : nullptr, nw > 2 ? w[2] : nullptr,
-                       nw > 3 ? w[3] : nullptr, nw, rs.partials, rs.counter, out);
+                       nw > 3 ? w[3] : nullptr, nw, rs.partials);
+    red_finish(s, rs.partials, blocks, nout, out, nout, nout, 1.0, 0.0);
 }
 
 __global__ __launch_bounds__(kWG) void k_lowrank_A(int m, const int *__restrict__ kptr, const int *__restrict__ ti,
@@ -653,12 +687,10 @@ __global__ __launch_bounds__(kWG) void k_dots(int m, const double *a0, const dou
                                               const double *a6, const double *a7, const double *b0,
                                               const double *b1, const double *b2, const double *b3,
                                               const double *b4, const double *b5, const double *b6,
-                                              const double *b7, int np, double *partials,
-                                              unsigned int *counter, double *out) {
+                                              const double *b7, int np, double *partials) {
     const double *as[kMaxDots] = {a0, a1, a2, a3, a4, a5, a6, a7};
     const double *bs[kMaxDots] = {b0, b1, b2, b3, b4, b5, b6, b7};
     __shared__ double red[kMaxDots][kWG];
-    __shared__ int s_last;
     const int tid = threadIdx.x;
     double acc[kMaxDots];
     for (int j = 0; j < kMaxDots; ++j) acc[j] = 0.0;
@@ -672,18 +704,6 @@ __global__ __launch_bounds__(kWG) void k_dots(int m, const double *a0, const dou
         __syncthreads();
     }
     if (tid < np) partials[(size_t)blockIdx.x * np + tid] = red[tid][0];
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(counter, 1u) == gridDim.x - 1);
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (tid < np) {
-        double s = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b) s += __builtin_nontemporal_load(&partials[(size_t)b * np + tid]);
-        out[tid] = s;
-    }
-    if (tid == 0) *counter = 0u;
 }
 
 void dots(hipStream_t s, const RedScratch &rs, int m, const double *const *a, const double *const *b, int np,
@@ -698,7 +718,8 @@ void dots(hipStream_t s, const RedScratch &rs, int m, const double *const *a, co
         B[j] = b[j];
     }
     hipLaunchKernelGGL(k_dots, dim3(blocks), dim3(kWG), 0, s, m, A[0], A[1], A[2], A[3], A[4], A[5], A[6], A[7],
-                       B[0], B[1], B[2], B[3], B[4], B[5], B[6], B[7], np, rs.partials, rs.counter, out);
+                       B[0], B[1], B[2], B[3], B[4], B[5], B[6], B[7], np, rs.partials);
+    red_finish(s, rs.partials, blocks, np, out, np, np, 1.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------

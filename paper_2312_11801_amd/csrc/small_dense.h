@@ -32,21 +32,20 @@ struct JacobiWork {
     double fro;
     double off;
     int rank[MAXN];
+    int rotated;
 };
 using JacobiScratch = JacobiWork<kWG, kMaxBasis>;
 
-// team-wide sum; every lane gets the result
+// team-wide sum (tree in LDS); every lane gets the result
 template <int TEAM, int MAXN>
 __device__ double team_sum(double v, JacobiWork<TEAM, MAXN> *js, int lane) {
     js->red[lane] = v;
     team_sync<TEAM>();
-    if (lane == 0) {
-        double s = 0.0;
-        for (int i = 0; i < TEAM; ++i) s += js->red[i];
-        js->off = s;
+    for (int st = TEAM / 2; st > 0; st >>= 1) {
+        if (lane < st) js->red[lane] += js->red[lane + st];
+        team_sync<TEAM>();
     }
-    team_sync<TEAM>();
-    const double r = js->off;
+    const double r = js->red[0];
     team_sync<TEAM>();
     return r;
 }
@@ -68,14 +67,11 @@ __device__ void jacobi_core(int Np, double *A, double *V, int ld, JacobiWork<TEA
     }
     const double fro = sqrt(team_sum<TEAM, MAXN>(s, js, lane));
     const int half = Np / 2;
+    // a rotation is skipped when |a_pq| is below rounding of both diagonal entries (or of
+    // ||A||_F for zero diagonals); a sweep without any rotation ends the iteration
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-        s = 0.0;
-        for (int e = lane; e < Np * Np; e += TEAM) {
-            const int r = e / Np, c = e - r * Np;
-            if (r < c) s += A[r * ld + c] * A[r * ld + c];
-        }
-        const double off = team_sum<TEAM, MAXN>(s, js, lane);
-        if (fro == 0.0 || sqrt(2.0 * off) <= tol * fro) break;
+        if (lane == 0) js->rotated = 0;
+        team_sync<TEAM>();
         for (int rd = 0; rd < Np - 1; ++rd) {
             if (lane < half) {
                 const int ia = lane, ib = Np - 1 - lane;
@@ -84,12 +80,14 @@ __device__ void jacobi_core(int Np, double *A, double *V, int ld, JacobiWork<TEA
                 const int p = pa < pb ? pa : pb, q = pa < pb ? pb : pa;
                 const double apq = A[p * ld + q], app = A[p * ld + p], aqq = A[q * ld + q];
                 double cc = 1.0, ss = 0.0;
-                if (fabs(apq) > 1e-300 && fabs(apq) > 1e-18 * fro) {
+                const double thr = fmax(tol * fmax(fabs(app), fabs(aqq)), 1e-17 * fro);
+                if (fabs(apq) > thr && fabs(apq) > 1e-300) {
                     const double th = (aqq - app) / (2.0 * apq);
                     double t = 1.0 / (fabs(th) + sqrt(th * th + 1.0));
                     if (th < 0.0) t = -t;
                     cc = 1.0 / sqrt(t * t + 1.0);
                     ss = t * cc;
+                    js->rotated = 1;
                 }
                 js->p[lane] = p;
                 js->q[lane] = q;
@@ -125,6 +123,9 @@ __device__ void jacobi_core(int Np, double *A, double *V, int ld, JacobiWork<TEA
             }
             team_sync<TEAM>();
         }
+        const int any = js->rotated;
+        team_sync<TEAM>();
+        if (!any) break;
     }
 }
 
@@ -167,7 +168,7 @@ __device__ __forceinline__ int wg_load_sym(int N, const double *A, int lda, cons
 
 __device__ __forceinline__ void wg_jacobi(int N, double *sA, double *sV, int ld, JacobiScratch *js) {
     const int Np = N + (N & 1);
-    jacobi_core<kWG, kMaxBasis, true>(Np, sA, sV, ld, js, threadIdx.x, 40, 1e-15);
+    jacobi_core<kWG, kMaxBasis, true>(Np, sA, sV, ld, js, threadIdx.x, 30, 2e-16);
 }
 
 // sort descending (stable by index), w[0..N), Y[r*ldy + c] for r < N, c < ny
@@ -347,7 +348,7 @@ __device__ __forceinline__ double wave_min_eig(int k, double *X, int ldx, Jacobi
         if (lane == 0) X[(Np - 1) * ldx + (Np - 1)] = 0.0;
         wave_sync();
     }
-    jacobi_core<64, 16, false>(Np, X, nullptr, ldx, js, lane, 40, 1e-15);
+    jacobi_core<64, 16, false>(Np, X, nullptr, ldx, js, lane, 30, 2e-16);
     double mn = 1e300;
     for (int i = 0; i < k; ++i) mn = fmin(mn, X[i * ldx + i]);
     wave_sync();

@@ -5,6 +5,7 @@
 // without host round trips.
 #include "steps.h"
 #include "small_dense.h"
+#include "syev.h"
 
 namespace usbs {
 
@@ -12,15 +13,19 @@ static inline int cdiv_(long a, long b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
 // master QP coefficients (App. B.2, eq. compressed_subprob_2, normalised form)
-//   raw = [sum g g^T (d*d) | G^T zbar | G^T y | G^T b | G^T nu]
+//   raw = [upper triangle of sum g g^T | G^T zbar | G^T y | G^T b | G^T nu]
 // ---------------------------------------------------------------------------
 __global__ void k_qp_finalize(int k, const double *__restrict__ raw, const double *__restrict__ VCV,
                               const double *__restrict__ sc, int has_nu, double *__restrict__ qp) {
-    const int d = k * (k + 1) / 2;
+    const int d = k * (k + 1) / 2, nup = d * (d + 1) / 2;
     const double alpha = sc[SC_ALPHA], rho = sc[SC_RHO], tau = sc[SC_TAU];
     const double a2r = alpha * alpha / rho;
-    const double *Gz = raw + d * d, *Gy = Gz + d, *Gb = Gy + d, *Gn = Gb + d;
-    for (int e = threadIdx.x; e < d * d; e += blockDim.x) qp[e] = a2r * raw[e];
+    const double *Gz = raw + nup, *Gy = Gz + d, *Gb = Gy + d, *Gn = Gb + d;
+    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
+        const int P = e / d, Q = e - P * d;
+        const int lo = P < Q ? P : Q, hi = P < Q ? Q : P;
+        qp[e] = a2r * raw[lo * d - lo * (lo - 1) / 2 + (hi - lo)];
+    }
     for (int p = threadIdx.x; p < d; p += blockDim.x) {
         // p -> (i, j), i >= j, column-wise lower triangle
         int j = 0, rem = p;
@@ -102,9 +107,7 @@ void candidate(hipStream_t s, int m, const double *b, const double *AX, const do
 // lambda_max(V^T (C - A^* y~) V) with V^T A^* y~ V = smat(G^T y~)
 __global__ __launch_bounds__(kWG) void k_fhat_prep(int k, const double *__restrict__ VCV,
                                                    const double *__restrict__ Gy, double *sc) {
-    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
-    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
-    __shared__ JacobiScratch js;
+    __shared__ SyevWork ws;
     __shared__ double Mv[kMaxK * kMaxK];
     __shared__ double w[kMaxK + 1];
     const double r2 = 1.4142135623730951;
@@ -115,16 +118,31 @@ __global__ __launch_bounds__(kWG) void k_fhat_prep(int k, const double *__restri
         Mv[e] = VCV[e] - ((i == j) ? Gy[p] : Gy[p] / r2);
     }
     __syncthreads();
-    wg_load_sym(k, Mv, k, nullptr, &sA[0][0], kMaxBasis + 1);
-    wg_jacobi(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
-    wg_sort_store(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, nullptr, 0, 0, &js);
+    wg_syev_load(k, Mv, k, nullptr, &ws);
+    wg_syev_top(k, 1, 0, &ws, w, nullptr, 0);
     if (threadIdx.x == 0) sc[SC_LAMV] = w[0];
 }
 void fhat_prep(hipStream_t s, int k, const double *VCV, const double *Gy, double *sc) {
     hipLaunchKernelGGL(k_fhat_prep, dim3(1), dim3(kWG), 0, s, k, VCV, Gy, sc);
 }
 
-// descent test (Alg. 1), f, f^ and the relative errors (eq. relative_error_tol)
+// relative errors of eq. relative_error_tol (suboptimality through the upper bound of eq.
+// objective_subopt_upper_bound) in the units selected by SC_UNITS
+__device__ void set_metrics(double *sc, double fn) {
+    const double cx = sc[SC_CX];
+    const double dist = sqrt(fmax(sc[SC_DIST2], 0.0));
+    if (sc[SC_UNITS] != 0.0) {
+        const double s = sc[SC_SIGMA] * sc[SC_TRACE];
+        const double fo = s * fn, co = s * cx;
+        sc[SC_GAP] = fabs(fo - co) / (1.0 + fabs(co));
+        sc[SC_INF] = sc[SC_TRACE] * dist / (1.0 + sc[SC_TRACE] * sc[SC_BNORM]);
+    } else {
+        sc[SC_GAP] = fabs(fn - cx) / (1.0 + fabs(cx));
+        sc[SC_INF] = dist / (1.0 + sc[SC_BNORM]);
+    }
+}
+
+// descent test (Alg. 1), f, f^ and the relative errors
 __global__ void k_decide(const double *__restrict__ theta, double *sc) {
     if (threadIdx.x != 0) return;
     const double alpha = sc[SC_ALPHA], beta = sc[SC_BETA], tau = sc[SC_TAU];
@@ -143,20 +161,25 @@ __global__ void k_decide(const double *__restrict__ theta, double *sc) {
     sc[SC_DESC] = desc;
     sc[SC_NDESC] += desc;
     sc[SC_F] = fn;
-    const double cx = sc[SC_CX];
-    const double dist = sqrt(fmax(sc[SC_DIST2], 0.0));
-    if (sc[SC_UNITS] != 0.0) {
-        const double s = sc[SC_SIGMA] * sc[SC_TRACE];
-        const double fo = s * fn, co = s * cx;
-        sc[SC_GAP] = fabs(fo - co) / (1.0 + fabs(co));
-        sc[SC_INF] = sc[SC_TRACE] * dist / (1.0 + sc[SC_TRACE] * sc[SC_BNORM]);
-    } else {
-        sc[SC_GAP] = fabs(fn - cx) / (1.0 + fabs(cx));
-        sc[SC_INF] = dist / (1.0 + sc[SC_BNORM]);
-    }
+    set_metrics(sc, fn);
 }
 void decide(hipStream_t s, const double *theta, double *sc) {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, theta, sc);
+}
+
+// f(y_t) = alpha [theta_1]_+ + <b, y_t> from an accurate Ritz value (SC_BYT holds <b, y_t>)
+__global__ void k_refresh_f(const double *__restrict__ theta, double *sc) {
+    if (threadIdx.x != 0) return;
+    const double fn = sc[SC_ALPHA] * fmax(theta[0], 0.0) + sc[SC_BYT];
+    sc[SC_F] = fn;
+    sc[SC_THETA1] = theta[0];
+    set_metrics(sc, fn);
+}
+void recompute_f(hipStream_t s, const double *theta, const double *y, const double *b, int m, const RedScratch &rs,
+                 double *sc) {
+    const double *a[1] = {b}, *bb[1] = {y};
+    dots(s, rs, m, a, bb, 1, sc + SC_BYT);
+    hipLaunchKernelGGL(k_refresh_f, dim3(1), dim3(64), 0, s, theta, sc);
 }
 
 __global__ void k_cond_copy(int m, const double *__restrict__ flag, const double *__restrict__ src,
@@ -179,9 +202,7 @@ __global__ __launch_bounds__(kWG) void k_model_update(int k, int kp, int r, cons
                                                       const double *__restrict__ VtPsi, double *sc,
                                                       double *__restrict__ Kc, double *__restrict__ Qp,
                                                       double *__restrict__ Hsk) {
-    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
-    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
-    __shared__ JacobiScratch js;
+    __shared__ SyevWork ws;
     __shared__ double aS[kMaxK * kMaxK];
     __shared__ double lam[kMaxK + 1];
     __shared__ double Q[kMaxK * kMaxK];
@@ -189,9 +210,8 @@ __global__ __launch_bounds__(kWG) void k_model_update(int k, int kp, int r, cons
     const double alpha = sc[SC_ALPHA];
     for (int e = threadIdx.x; e < k * k; e += kWG) aS[e] = alpha * st[e];
     __syncthreads();
-    wg_load_sym(k, aS, k, nullptr, &sA[0][0], kMaxBasis + 1);
-    wg_jacobi(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
-    wg_sort_store(k, &sA[0][0], &sV[0][0], kMaxBasis + 1, lam, Q, k, k, &js);
+    wg_syev_load(k, aS, k, nullptr, &ws);
+    wg_syev_top(k, k, k, &ws, lam, Q, k);
     __syncthreads();
     for (int e = threadIdx.x; e < k * k; e += kWG) {
         const int i = e / k, j = e - i * k;
@@ -273,9 +293,7 @@ void set_int(hipStream_t s, int *p, int count, int v) {
 __global__ __launch_bounds__(kWG) void k_nystrom_core(int n, int r, const double *__restrict__ Gm,
                                                       double *__restrict__ H, double *__restrict__ lamo,
                                                       int *status) {
-    __shared__ double sA[kMaxBasis][kMaxBasis + 1];
-    __shared__ double sV[kMaxBasis][kMaxBasis + 1];
-    __shared__ JacobiScratch js;
+    __shared__ SyevWork ws;
     __shared__ double G[2 * kMaxRank * 2 * kMaxRank];
     __shared__ double B[kMaxRank * kMaxRank], Li[kMaxRank * kMaxRank], PP[kMaxRank * kMaxRank];
     __shared__ double FF[kMaxRank * kMaxRank], Z[kMaxRank * kMaxRank], w[kMaxRank + 1], tmp[kMaxRank * kMaxRank];
@@ -288,9 +306,8 @@ __global__ __launch_bounds__(kWG) void k_nystrom_core(int n, int r, const double
     // ||P||_2^2 = lambda_max(P^T P)
     for (int e = tid; e < r * r; e += kWG) PP[e] = G[(e / r) * r2 + (e % r)];
     __syncthreads();
-    wg_load_sym(r, PP, r, nullptr, &sA[0][0], kMaxBasis + 1);
-    wg_jacobi(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
-    wg_sort_store(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, nullptr, 0, 0, &js);
+    wg_syev_load(r, PP, r, nullptr, &ws);
+    wg_syev_top(r, 1, 0, &ws, w, nullptr, 0);
     if (tid == 0) {
         const double nrm = sqrt(fmax(w[0], 0.0));
         int ex;
@@ -336,9 +353,8 @@ __global__ __launch_bounds__(kWG) void k_nystrom_core(int n, int r, const double
         FF[e] = v;
     }
     __syncthreads();
-    wg_load_sym(r, FF, r, nullptr, &sA[0][0], kMaxBasis + 1);
-    wg_jacobi(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, &js);
-    wg_sort_store(r, &sA[0][0], &sV[0][0], kMaxBasis + 1, w, Z, r, r, &js);
+    wg_syev_load(r, FF, r, nullptr, &ws);
+    wg_syev_top(r, r, r, &ws, w, Z, r);
     __syncthreads();
     // U = Pn Li^T Z Sigma^{-1}; Pn = [P | Psi] [I ; nu I]
     // E = Li^T Z diag(1/sigma) (r x r)

@@ -1,0 +1,352 @@
+// Top eigenpairs of a small symmetric FP64 matrix (N <= kMaxBasis) on one
+// workgroup of 256 threads, for the Rayleigh-Ritz problems of the block
+// Lanczos solver and the other small eigenproblems of the iteration
+// (eigen-split of S, lambda_max(V^T M V), the Nystrom core).
+//
+//   1. Householder reduction to tridiagonal form, A = Q T Q^T, the reflectors
+//      kept in the strictly lower part of A (four barriers per column);
+//   2. eigenvalues of T by 16-section: 16 lanes share one eigenvalue and
+//      evaluate Sturm counts at 15 interior points of its bracket, which
+//      shrinks 16x per step (16 steps from the Gershgorin interval);
+//   3. eigenvectors of T by inverse iteration (one lane per eigenvector,
+//      Gaussian elimination with partial pivoting on T - lambda I);
+//   4. Cholesky-QR twice on the eigenvectors (vectors of a cluster become an
+//      orthonormal basis of its invariant subspace);
+//   5. back-transformation by the reflectors (16 lanes per vector, shuffles).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+#include "small_dense.h"
+
+namespace usbs {
+
+constexpr int kSyevMaxN = kMaxBasis;
+constexpr int kSyevMaxV = 16;
+
+struct SyevWork {
+    double A[kSyevMaxN][kSyevMaxN + 1];
+    double d[kSyevMaxN], e[kSyevMaxN], e2[kSyevMaxN], beta[kSyevMaxN];
+    double p[kSyevMaxN], w[kSyevMaxN];
+    double lam[kSyevMaxV];
+    double X[kSyevMaxV][kSyevMaxN + 1];
+    double U0[kSyevMaxV][kSyevMaxN], U1[kSyevMaxV][kSyevMaxN], U2[kSyevMaxV][kSyevMaxN];
+    double red[8];
+    double gl, gh;
+};
+
+__device__ __forceinline__ double wave_allsum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double group16_sum(double v) {
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
+    return v;
+}
+
+// number of eigenvalues of the tridiagonal (d, e) strictly below x
+__device__ __forceinline__ int sturm_count(int N, const double *d, const double *e2, double x, double pivmin) {
+    int c = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += (q < 0.0);
+    for (int i = 1; i < N; ++i) {
+        q = d[i] - x - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        c += (q < 0.0);
+    }
+    return c;
+}
+
+// A: the N x N matrix already in ws->A (symmetric, full).  Outputs the nv largest
+// eigenvalues (descending) into lam_out[0..nv) and the first ny <= nv eigenvectors
+// into Y[r * ldy + c] (r < N).  nv, ny <= 16.  All 256 threads must call.
+__device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out, double *Y, int ldy) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    // ---- 1. tridiagonalisation ----
+    for (int j = 0; j + 2 < N; ++j) {
+        const int m = N - j - 1;
+        if (wave == 0) {
+            const double x0 = (lane < m) ? ws->A[j + 1 + lane][j] : 0.0;
+            const double x1 = (lane + 64 < m) ? ws->A[j + 1 + lane + 64][j] : 0.0;
+            const double nx2 = wave_allsum(x0 * x0 + x1 * x1);
+            const double xf = ws->A[j + 1][j];
+            const double nx = sqrt(nx2);
+            double alpha = (xf >= 0.0) ? -nx : nx;
+            const double vv = nx2 - xf * xf + (xf - alpha) * (xf - alpha);
+            double b = (nx2 > 0.0 && vv > 0.0) ? 2.0 / vv : 0.0;
+            if (b == 0.0) alpha = xf;
+            if (lane == 0) {
+                ws->A[j + 1][j] = xf - alpha;   // v_0; the rest of v is x itself
+                ws->beta[j] = b;
+                ws->e[j] = alpha;
+                ws->d[j] = ws->A[j][j];
+            }
+        }
+        __syncthreads();
+        const double b = ws->beta[j];
+        if (b != 0.0) {
+            // p = b A22 v: 4 lanes per row, each over a quarter of the columns
+            {
+                const int q4 = tid & 3;
+                for (int r = tid >> 2; r < ((m + 63) & ~63); r += kWG / 4) {
+                    double s = 0.0;
+                    if (r < m) {
+                        const double *row = &ws->A[j + 1 + r][j + 1];
+#pragma unroll 4
+                        for (int q = q4; q < m; q += 4) s += row[q] * ws->A[j + 1 + q][j];
+                    }
+                    s += __shfl_xor(s, 1, 4);
+                    s += __shfl_xor(s, 2, 4);
+                    if (r < m && q4 == 0) ws->p[r] = b * s;
+                }
+            }
+            __syncthreads();
+            if (wave == 0) {
+                double pv = 0.0;
+                for (int t = lane; t < m; t += 64) pv += ws->p[t] * ws->A[j + 1 + t][j];
+                const double K = 0.5 * b * wave_allsum(pv);
+                for (int t = lane; t < m; t += 64) ws->w[t] = ws->p[t] - K * ws->A[j + 1 + t][j];
+            }
+            __syncthreads();
+            // A22 -= v w^T + w v^T on a 16 x 16 thread grid (no integer division)
+            {
+                const int tr = tid >> 4, tc = tid & 15;
+                for (int r = tr; r < m; r += 16) {
+                    const double vr = ws->A[j + 1 + r][j], wr = ws->w[r];
+                    double *row = &ws->A[j + 1 + r][j + 1];
+#pragma unroll 2
+                    for (int c = tc; c < m; c += 16) row[c] -= vr * ws->w[c] + wr * ws->A[j + 1 + c][j];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tid == 0) {
+        if (N >= 2) {
+            ws->d[N - 2] = ws->A[N - 2][N - 2];
+            ws->e[N - 2] = ws->A[N - 1][N - 2];
+            if (N >= 3) ws->beta[N - 2] = 0.0;
+        }
+        ws->d[N - 1] = ws->A[N - 1][N - 1];
+        double gl = 1e300, gh = -1e300, tn = 0.0;
+        for (int i = 0; i < N; ++i) {
+            const double r = (i > 0 ? fabs(ws->e[i - 1]) : 0.0) + (i + 1 < N ? fabs(ws->e[i]) : 0.0);
+            gl = fmin(gl, ws->d[i] - r);
+            gh = fmax(gh, ws->d[i] + r);
+            if (i + 1 < N) ws->e2[i] = ws->e[i] * ws->e[i];
+        }
+        tn = fmax(fabs(gl), fabs(gh));
+        // widen slightly so that the bracket certainly contains every eigenvalue
+        ws->gl = gl - 4e-16 * tn - 1e-300;
+        ws->gh = gh + 4e-16 * tn + 1e-300;
+        ws->red[0] = tn;
+    }
+    __syncthreads();
+    // ---- 2. eigenvalues by 16-section ----
+    {
+        const double tn = ws->red[0];
+        const double pivmin = fmax(1e-290, 1e-300 * tn * tn);
+        const int g = tid >> 4, l = tid & 15;   // group g handles the g-th largest eigenvalue
+        if (g < nv) {
+            const int kidx = N - 1 - g;        // ascending index of the target
+            double lo = ws->gl, hi = ws->gh;
+            for (int it = 0; it < 18; ++it) {
+                const double x = lo + (hi - lo) * (double)l * (1.0 / 16.0);
+                const int cnt = (l == 0) ? -1 : sturm_count(N, ws->d, ws->e2, x, pivmin);
+                // lanes with count <= kidx bound the eigenvalue from below, the others from above
+                double cand_lo = (l > 0 && cnt <= kidx) ? x : -1e308;
+                double cand_hi = (l > 0 && cnt > kidx) ? x : 1e308;
+#pragma unroll
+                for (int o = 8; o > 0; o >>= 1) {
+                    cand_lo = fmax(cand_lo, __shfl_xor(cand_lo, o, 16));
+                    cand_hi = fmin(cand_hi, __shfl_xor(cand_hi, o, 16));
+                }
+                if (cand_lo > -1e308) lo = cand_lo;
+                if (cand_hi < 1e308) hi = cand_hi;
+                if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + 1e-3 * 2.2e-16 * tn) break;
+            }
+            if (l == 0) ws->lam[g] = 0.5 * (lo + hi);
+        }
+    }
+    __syncthreads();
+    // ---- 3. inverse iteration: lane c < ny of each wave handles vector c (wave = c / 16 spread) ----
+    {
+        const int c = (tid & 3) * 4 + (tid >> 6);   // spread vectors over the 4 waves
+        const bool act = (tid & 63) < 4 && c < ny;
+        if (act) {
+            const double lam = ws->lam[c];
+            const double tn = ws->red[0];
+            const double tiny = fmax(1e-300, 2.2e-16 * tn);
+            double *x = ws->X[c];
+            uint32_t st = 0x9E3779B9u * (uint32_t)(c + 1);
+            for (int i = 0; i < N; ++i) {
+                st = st * 1664525u + 1013904223u;
+                x[i] = ((double)(st >> 8) * (1.0 / 16777216.0)) - 0.5;
+            }
+            for (int rep = 0; rep < 2; ++rep) {
+                // eliminate with partial pivoting; rows of U in U0/U1/U2, RHS in x
+                double c0 = ws->d[0] - lam, c1 = (N > 1) ? ws->e[0] : 0.0;
+                for (int i = 0; i + 1 < N; ++i) {
+                    const double ei = ws->e[i];
+                    const double an = ws->d[i + 1] - lam;
+                    const double en = (i + 2 < N) ? ws->e[i + 1] : 0.0;
+                    if (fabs(c0) >= fabs(ei)) {
+                        const double piv = (c0 == 0.0) ? tiny : c0;
+                        const double mlt = ei / piv;
+                        ws->U0[c][i] = piv;
+                        ws->U1[c][i] = c1;
+                        ws->U2[c][i] = 0.0;
+                        x[i + 1] -= mlt * x[i];
+                        c0 = an - mlt * c1;
+                        c1 = en;
+                    } else {
+                        const double mlt = c0 / ei;
+                        ws->U0[c][i] = ei;
+                        ws->U1[c][i] = an;
+                        ws->U2[c][i] = en;
+                        const double xi = x[i];
+                        x[i] = x[i + 1];
+                        x[i + 1] = xi - mlt * x[i];
+                        c0 = c1 - mlt * an;
+                        c1 = -mlt * en;
+                    }
+                }
+                ws->U0[c][N - 1] = (fabs(c0) < tiny) ? (c0 < 0.0 ? -tiny : tiny) : c0;
+                // back substitution
+                for (int i = N - 1; i >= 0; --i) {
+                    double v = x[i];
+                    if (i + 1 < N) v -= ws->U1[c][i] * x[i + 1];
+                    if (i + 2 < N) v -= ws->U2[c][i] * x[i + 2];
+                    const double u0 = (fabs(ws->U0[c][i]) < tiny) ? (ws->U0[c][i] < 0.0 ? -tiny : tiny) : ws->U0[c][i];
+                    x[i] = v / u0;
+                }
+                double s = 0.0, mx = 0.0;
+                for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(x[i]));
+                const double inv = (mx > 0.0) ? 1.0 / mx : 1.0;
+                for (int i = 0; i < N; ++i) {
+                    x[i] *= inv;
+                    s += x[i] * x[i];
+                }
+                const double nrm = 1.0 / sqrt(s);
+                for (int i = 0; i < N; ++i) x[i] *= nrm;
+            }
+        }
+    }
+    __syncthreads();
+    // ---- 4. orthonormalise the ny vectors: Cholesky-QR twice on all threads ----
+    for (int pass = 0; pass < 2 && ny > 1; ++pass) {
+        __shared__ double G[kSyevMaxV][kSyevMaxV + 1];
+        __shared__ double Li[kSyevMaxV][kSyevMaxV + 1];
+        {
+            const int b2 = tid >> 4, c = tid & 15;
+            if (b2 < ny && c < ny && c <= b2) {
+                double s = 0.0;
+                for (int i = 0; i < N; ++i) s += ws->X[b2][i] * ws->X[c][i];
+                G[b2][c] = s;
+                G[c][b2] = s;
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // lower Cholesky of G on lanes; a vanishing pivot zeroes that vector
+            for (int jj = 0; jj < ny; ++jj) {
+                if (lane == 0) {
+                    const double piv = G[jj][jj];
+                    G[jj][jj] = (piv > 1e-28) ? sqrt(piv) : 0.0;
+                }
+                wave_sync();
+                const double ljj = G[jj][jj];
+                for (int i = jj + 1 + lane; i < ny; i += 64) G[i][jj] = (ljj > 0.0) ? G[i][jj] / ljj : 0.0;
+                wave_sync();
+                const int mm = ny - jj - 1;
+                for (int e = lane; e < mm * mm; e += 64) {
+                    const int i = jj + 1 + e / mm, l = jj + 1 + e % mm;
+                    if (l <= i) G[i][l] -= G[i][jj] * G[l][jj];
+                }
+                wave_sync();
+            }
+            if (lane < ny) {
+                const int c = lane;
+                double x[kSyevMaxV];
+                for (int i = 0; i < kSyevMaxV; ++i) x[i] = 0.0;
+                for (int i = c; i < ny; ++i) {
+                    double v = (i == c) ? 1.0 : 0.0;
+                    for (int l = c; l < i; ++l) v -= G[i][l] * x[l];
+                    x[i] = (G[i][i] > 0.0) ? v / G[i][i] : 0.0;
+                }
+                for (int i = 0; i < ny; ++i) Li[i][c] = x[i];   // Li = L^{-1}
+            }
+        }
+        __syncthreads();
+        // X_new[c] = sum_b Li[c][b] X[b]  (rows of L^{-1} combine the old vectors)
+        double nv_[((kSyevMaxV * kSyevMaxN) + kWG - 1) / kWG];
+        int cnt = 0;
+        for (int q = tid; q < ny * N; q += kWG) {
+            const int c = q / N, i = q - c * N;
+            double v = 0.0;
+            for (int b2 = 0; b2 <= c; ++b2) v += Li[c][b2] * ws->X[b2][i];
+            nv_[cnt++] = v;
+        }
+        __syncthreads();
+        cnt = 0;
+        for (int q = tid; q < ny * N; q += kWG) {
+            const int c = q / N, i = q - c * N;
+            ws->X[c][i] = nv_[cnt++];
+        }
+        __syncthreads();
+    }
+    // ---- 5. back-transformation x <- H_0 ... H_{N-3} x, 16 lanes per vector ----
+    {
+        const int c = tid >> 4, l = tid & 15;
+        if (c < ny) {
+            double *x = ws->X[c];
+            for (int j = N - 3; j >= 0; --j) {
+                const double b = ws->beta[j];
+                if (b == 0.0) continue;
+                const int m = N - j - 1;
+                double s = 0.0;
+                for (int t = l; t < m; t += 16) s += ws->A[j + 1 + t][j] * x[j + 1 + t];
+                s = b * group16_sum(s);
+                for (int t = l; t < m; t += 16) x[j + 1 + t] -= s * ws->A[j + 1 + t][j];
+            }
+        }
+    }
+    __syncthreads();
+    for (int c = tid; c < nv; c += kWG) lam_out[c] = ws->lam[c];
+    if (Y)
+        for (int q = tid; q < N * ny; q += kWG) {
+            const int r = q / ny, c = q - r * ny;
+            Y[r * ldy + c] = ws->X[c][r];
+        }
+    __syncthreads();
+}
+
+// Load the upper triangle of the global N x N matrix (ld lda) as a full symmetric
+// matrix into ws->A; rows/columns flagged in dead become decoupled with a diagonal
+// below every eigenvalue (-(2 ||A||_F + 1)).
+__device__ void wg_syev_load(int N, const double *A, int lda, const int *dead, SyevWork *ws) {
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int q = tid; q < N * N; q += kWG) {
+        const int r = q / N, c = q - r * N;
+        const int lo = r < c ? r : c, hi = r < c ? c : r;
+        double v = A[lo * lda + hi];
+        if (dead && (dead[r] || dead[c])) v = 0.0;
+        ws->A[r][c] = v;
+        s += v * v;
+    }
+    s = wave_allsum(s);
+    if ((tid & 63) == 0) ws->red[1 + (tid >> 6)] = s;
+    __syncthreads();
+    if (dead) {
+        const double fro = sqrt(ws->red[1] + ws->red[2] + ws->red[3] + ws->red[4]);
+        for (int r = tid; r < N; r += kWG)
+            if (dead[r]) ws->A[r][r] = -(2.0 * fro + 1.0);
+    }
+    __syncthreads();
+}
+
+}  // namespace usbs

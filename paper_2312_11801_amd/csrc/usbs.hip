@@ -103,12 +103,48 @@ struct usbs_handle {
     int64_t matvecs = 0;
     int iters = 0;
     bool ready = false;
+
+    // live timing of one kernel category with HIP events (bench / roofline)
+    int prof_cat = -1;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    double prof_ms = 0.0;
+    int64_t prof_count = 0;
 };
 
 void nn_update_dev_beta(usbs_handle *h, const double *A, int lda, int ca, const double *H, int ldh, int cc, double *C,
                         int ldc);
 
 namespace {
+
+// RAII: records a start/stop event pair around the launches of the profiled category
+struct ProfScope {
+    usbs_handle *h;
+    int idx = -1;
+    ProfScope(usbs_handle *hh, int cat) : h(hh) {
+        if (h->prof_cat != cat) return;
+        if (h->ev_used + 2 > h->ev_pool.size()) return;
+        idx = (int)h->ev_used;
+        h->ev_used += 2;
+        (void)hipEventRecord(h->ev_pool[idx], h->stream);
+    }
+    ~ProfScope() {
+        if (idx >= 0) (void)hipEventRecord(h->ev_pool[idx + 1], h->stream);
+    }
+};
+
+void prof_flush(usbs_handle *h) {
+    if (h->ev_used == 0) return;
+    (void)hipEventSynchronize(h->ev_pool[h->ev_used - 1]);
+    for (size_t q = 0; q + 1 < h->ev_used; q += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, h->ev_pool[q], h->ev_pool[q + 1]) == hipSuccess) {
+            h->prof_ms += ms;
+            h->prof_count++;
+        }
+    }
+    h->ev_used = 0;
+}
 
 void set_err(usbs_handle *h, const std::string &m) {
     if (h) h->err = m;
@@ -400,12 +436,10 @@ void upload(usbs_handle *h) {
     h->Rz = dalloc<double>(256, o);
     h->sc = dalloc<double>(SC_COUNT, o);
     h->small = dalloc<double>(4096, o);
-    h->rs.max_blocks = 1024;
+    h->rs.max_blocks = kRedMaxBlocks;
     h->rs.max_elems = kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec;
     if (h->rs.max_elems < kMaxBasis * 16) h->rs.max_elems = kMaxBasis * 16;
     h->rs.partials = dalloc<double>((size_t)h->rs.max_blocks * h->rs.max_elems, o);
-    h->rs.counter = dalloc<unsigned int>(4, o);
-    HIPCHK(hipMemsetAsync(h->rs.counter, 0, 4 * sizeof(unsigned int), s));
     HIPCHK(hipMemsetAsync(h->V, 0, (size_t)n * 16 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(h->Vn, 0, (size_t)n * 16 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(h->CV, 0, (size_t)n * 16 * sizeof(double), s));
@@ -425,6 +459,8 @@ void shift_operator(usbs_handle *h, const double *y) {
 }
 
 void apply_op(usbs_handle *h, const double *X, int ldx, double *Y, int ldy, int nb) {
+    ProfScope ps(h, USBS_PROF_SPMM);
+    if (h->ev_used + 2 > h->ev_pool.size()) prof_flush(h);
     spmm(h->stream, h->prec, h->n, h->rowptr, h->col, h->val_cur, h->val_scale, h->dshift, X, ldx, Y, ldy, nb);
     h->matvecs += nb;
 }
@@ -451,7 +487,7 @@ void cholqr2(usbs_handle *h, const double *src, int lds, int nc, double *tmp, in
 // Gram-Schmidt passes), Cholesky-QR2 for each new block.  On return
 // Uritz (n x 16) holds the Ritz vectors, theta[0..16) the Ritz values.
 // ---------------------------------------------------------------------------
-int lanczos(usbs_handle *h, const double *start, int kc, double tol, int maxr, bool orth_start) {
+int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start) {
     hipStream_t s = h->stream;
     const int n = h->n, ldb = h->ldb, steps = h->steps;
     if (start != h->Ubuf) copy_cols(s, n, start, 16, 16, h->Ubuf, 16);
@@ -464,13 +500,17 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, int maxr, b
         // explicit Rayleigh-Ritz on span(U) and residuals
         apply_op(h, h->Ubuf, 16, h->W2, 16, 16);
         tn_reduce(s, h->rs, n, h->Ubuf, 16, 16, h->W2, 16, 16, h->TUU, 16, 1.0, 0.0);
-        small_eig(s, 16, h->TUU, 16, h->theta, h->Ysm, 16, 16, nullptr);
+        // after a cycle, U holds Ritz vectors of the explicit projection, so U^T M U is
+        // diagonal up to rounding; the 16 x 16 eigenproblem is needed for a new start
+        // block and for tight tolerances only
+        if (cyc == 0 || tol < 1e-7) small_eig(s, 16, h->TUU, 16, h->theta, h->Ysm, 16, 16, nullptr);
+        else diag_theta(s, h->TUU, 16, h->theta, h->Ysm);
         nn_update(s, n, h->Ubuf, 16, 16, h->Ysm, 16, 16, h->Bm, ldb, 1.0, 0.0);
         nn_update(s, n, h->W2, 16, 16, h->Ysm, 16, 16, h->Ubuf, 16, 1.0, 0.0);
         neg_diag(s, h->theta, 16, h->Hd);
         nn_update(s, n, h->Bm, ldb, 16, h->Hd, 16, 16, h->Ubuf, 16, 1.0, 1.0);
         tn_reduce(s, h->rs, n, h->Ubuf, 16, 16, h->Ubuf, 16, 16, h->RtR, 16, 1.0, 0.0);
-        lanczos_restart_prep(s, h->RtR, h->theta, kc, tol, h->res, h->flag, h->Zc, h->sc + SC_SCALE);
+        lanczos_restart_prep(s, h->RtR, h->theta, kc, tol, tol_rest, h->res, h->flag, h->Zc, h->sc + SC_SCALE);
         int conv = 0;
         HIPCHK(hipMemcpyAsync(&conv, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -486,14 +526,23 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, int maxr, b
         for (int j = 0; j < steps; ++j) {
             const int c0 = 16 + 8 * j, cols = c0 + 8;
             apply_op(h, h->Bm + c0, ldb, h->W, 8, 8);
-            tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Tm + c0, ldb, 1.0, 0.0);
+            {
+                ProfScope ps(h, USBS_PROF_REORTH);
+                tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Tm + c0, ldb, 1.0, 0.0);
+            }
             nn_update(s, n, h->Bm, ldb, cols, h->Tm + c0, ldb, 8, h->W, 8, -1.0, 1.0);
-            tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Hred, 8, 1.0, 0.0);
+            {
+                ProfScope ps(h, USBS_PROF_REORTH);
+                tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Hred, 8, 1.0, 0.0);
+            }
             nn_update(s, n, h->Bm, ldb, cols, h->Hred, 8, 8, h->W, 8, -1.0, 1.0);
             add_small(s, cols, 8, h->Hred, 8, h->Tm + c0, ldb);
             if (j < steps - 1) cholqr2(h, h->W, 8, 8, h->Wt, 8, h->Bm + cols, ldb, h->dead + cols);
         }
-        small_eig(s, ldb, h->Tm, ldb, h->theta, h->Ysm, 16, 16, h->dead);
+        {
+            ProfScope ps(h, USBS_PROF_RITZ);
+            small_eig(s, ldb, h->Tm, ldb, h->theta, h->Ysm, 16, 16, h->dead);
+        }
         nn_update(s, n, h->Bm, ldb, ldb, h->Ysm, 16, 16, h->Ubuf, 16, 1.0, 0.0);
     }
     copy_cols(s, n, h->Bm, ldb, 16, h->Uritz, 16);
@@ -527,14 +576,17 @@ void iterate(usbs_handle *h) {
             const double *ws[1] = {h->nu};
             qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 1, h->Gy, 0);
             // G^T nu lands after the d*d block of Gy; copy into raw's 4th vector slot
-            HIPCHK(hipMemcpyAsync(h->raw + d * d + 3 * d, h->Gy + d * d, d * sizeof(double),
+            HIPCHK(hipMemcpyAsync(h->raw + d * (d + 1) / 2 + 3 * d, h->Gy, d * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
             const double *a[1] = {h->nu}, *bb[1] = {h->zbar};
             dots(s, h->rs, m, a, bb, 1, h->sc + SC_NUZ);
         }
         qp_finalize(s, k, h->raw, h->VCV, h->sc, pass > 0, h->qp);
         ia.warm = pass > 0;
-        ipm(s, ia, h->qp, h->ipm);
+        {
+            ProfScope ps(h, USBS_PROF_IPM);
+            ipm(s, ia, h->qp, h->ipm);
+        }
         post_ipm(s, k, h->ipm, h->VCV, h->sc);
         // A X_{t+1} = g zbar + alpha A(V S V^T)
         lowrank_A(s, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, h->ipm, prm.alpha, h->zbar, h->sc + SC_G, 0.0,
@@ -555,11 +607,11 @@ void iterate(usbs_handle *h) {
         dots(s, h->rs, m, a, bb, 3, h->sc + SC_BY);   // SC_BY, SC_YZ, SC_DIST2 are consecutive
         const double *ws[1] = {h->yc};
         qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 1, h->Gy, 0);
-        fhat_prep(s, k, h->VCV, h->Gy + d * d, h->sc);
+        fhat_prep(s, k, h->VCV, h->Gy, h->sc);
     }
     // eigen step at the candidate
     shift_operator(h, h->yc);
-    lanczos(h, h->Uritz, kc, prm.lanczos_tol, prm.lanczos_max_restarts, false);
+    lanczos(h, h->Uritz, kc, prm.lanczos_tol, std::sqrt(prm.lanczos_tol), prm.lanczos_max_restarts, false);
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
     // model update
@@ -582,6 +634,15 @@ void iterate(usbs_handle *h) {
     }
     std::swap(h->V, h->Vn);
     h->iters++;
+}
+
+// accurate f(y_t): Lanczos on C - A^* y_t from the current Ritz vectors with a tight
+// tolerance; f and the relative gap are recomputed from it (the iterate is unchanged)
+void polish_dual(usbs_handle *h) {
+    hipStream_t s = h->stream;
+    shift_operator(h, h->y);
+    lanczos(h, h->Uritz, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, false);
+    recompute_f(s, h->theta, h->y, h->b, h->m, h->rs, h->sc);
 }
 
 }  // namespace
@@ -626,7 +687,8 @@ void cold_start(usbs_handle *h) {
     init_scalars(h);
     random_block(s, h->n, 16, h->prm.seed, h->Ubuf, 16);
     shift_operator(h, h->y);
-    lanczos(h, h->Ubuf, h->k, h->prm.lanczos_tol, std::max(h->prm.lanczos_max_restarts, 20), true);
+    lanczos(h, h->Ubuf, h->k, h->prm.lanczos_tol_final, std::sqrt(h->prm.lanczos_tol_final),
+            std::max(h->prm.lanczos_max_restarts, 30), true);
     HIPCHK(hipMemsetAsync(h->V, 0, (size_t)h->n * 16 * sizeof(double), s));
     copy_cols(s, h->n, h->Uritz, 16, h->k, h->V, 16);
     // f(y0) = alpha [theta_1]_+ (b^T y0 = 0)
@@ -649,6 +711,7 @@ void check_params(const usbs_params *p) {
     if (p->lanczos_steps < 1 || p->lanczos_steps > kMaxSteps)
         throw DevError(USBS_E_INVALID, "need 1 <= lanczos_steps <= 8");
     if (p->lanczos_max_restarts < 0) throw DevError(USBS_E_INVALID, "lanczos_max_restarts < 0");
+    if (!(p->lanczos_tol > 0) || !(p->lanczos_tol_final > 0)) throw DevError(USBS_E_INVALID, "Lanczos tolerances must be > 0");
     if (p->precision < 0 || p->precision > 2) throw DevError(USBS_E_INVALID, "unknown precision");
     if (p->units != USBS_UNITS_SCALED && p->units != USBS_UNITS_ORIGINAL)
         throw DevError(USBS_E_INVALID, "unknown units");
@@ -701,7 +764,8 @@ int usbs_default_params(usbs_params *p) {
     p->time_limit = 0.0;
     p->lanczos_steps = 8;
     p->lanczos_max_restarts = 10;
-    p->lanczos_tol = 1e-6;
+    p->lanczos_tol = 1e-4;
+    p->lanczos_tol_final = 1e-9;
     p->precision = USBS_PREC_F64;
     p->seed = 0;
     p->stream = nullptr;
@@ -756,9 +820,17 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
                              h->iters, sc[SC_F], sc[SC_FCAND], sc[SC_FHAT], (int)sc[SC_DESC], sc[SC_GAP], sc[SC_INF],
                              sc[SC_CX], (long long)h->matvecs);
             if (sc[SC_GAP] <= p.eps_gap && sc[SC_INF] <= p.eps_infeas) {
-                status = USBS_OK;
-                ++it;
-                break;
+                // certify: recompute lambda_max(C - A^* y_T) with a tight residual tolerance
+                // so that the reported f(y_T) is an accurate upper bound, then re-test
+                polish_dual(h);
+                HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost,
+                                      h->stream));
+                HIPCHK(hipStreamSynchronize(h->stream));
+                if (sc[SC_GAP] <= p.eps_gap && sc[SC_INF] <= p.eps_infeas) {
+                    status = USBS_OK;
+                    ++it;
+                    break;
+                }
             }
             const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             if (p.time_limit > 0.0 && el > p.time_limit) {
@@ -845,7 +917,33 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
 void usbs_free(usbs_handle *h) {
     if (!h) return;
     free_problem(h);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
+}
+
+int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_total, int64_t *launches) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (category < -1 || category >= USBS_PROF_COUNT) {
+        set_err(h, "usbs_profile: unknown category");
+        return USBS_E_INVALID;
+    }
+    try {
+        if (h->ev_pool.empty() && category >= 0) {
+            h->ev_pool.resize(8192);
+            for (auto &e : h->ev_pool) HIPCHK(hipEventCreate(&e));
+        }
+        prof_flush(h);
+        if (ms_total) *ms_total = h->prof_ms;
+        if (launches) *launches = h->prof_count;
+        if (reset) {
+            h->prof_ms = 0.0;
+            h->prof_count = 0;
+        }
+        h->prof_cat = category;
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
 }
 
 const char *usbs_last_error(const usbs_handle *h) { return h ? h->err.c_str() : "NULL handle"; }
@@ -886,7 +984,8 @@ int usbs_op_eigs(usbs_handle *h, const double *y_dev, int32_t k, const double *s
         shift_operator(h, y_dev);
         if (start_dev) copy_cols(s, h->n, start_dev, 16, 16, h->Ubuf, 16);
         else random_block(s, h->n, 16, h->prm.seed + 7, h->Ubuf, 16);
-        const int c = lanczos(h, h->Ubuf, k, h->prm.lanczos_tol, std::max(h->prm.lanczos_max_restarts, 30), true);
+        const int c = lanczos(h, h->Ubuf, k, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final,
+                              std::max(h->prm.lanczos_max_restarts, 30), true);
         if (w) HIPCHK(hipMemcpyAsync(w, h->theta, k * sizeof(double), hipMemcpyDeviceToHost, s));
         if (res) HIPCHK(hipMemcpyAsync(res, h->res, k * sizeof(double), hipMemcpyDeviceToHost, s));
         if (U_dev) copy_cols(s, h->n, h->Uritz, 16, 16, U_dev, 16);

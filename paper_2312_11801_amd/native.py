@@ -27,8 +27,9 @@ UNITS = {"scaled": 0, "original": 1}
 EXPORTS = [
     "usbs_default_params", "usbs_create", "usbs_solve", "usbs_warm_start", "usbs_free", "usbs_last_error",
     "usbs_op_apply", "usbs_op_eigs", "usbs_op_lowrank_A", "usbs_op_sketch_update", "usbs_op_qp_data",
-    "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling",
+    "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling", "usbs_profile",
 ]
+PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
 
 
 class UsbsProblem(ctypes.Structure):
@@ -47,6 +48,7 @@ class UsbsParams(ctypes.Structure):
         ("eps_gap", ctypes.c_double), ("eps_infeas", ctypes.c_double), ("units", ctypes.c_int32),
         ("max_iters", ctypes.c_int32), ("time_limit", ctypes.c_double), ("lanczos_steps", ctypes.c_int32),
         ("lanczos_max_restarts", ctypes.c_int32), ("lanczos_tol", ctypes.c_double),
+        ("lanczos_tol_final", ctypes.c_double),
         ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
         ("verbose", ctypes.c_int32),
     ]
@@ -96,6 +98,7 @@ def load_library(path: str | None = None):
         "usbs_op_nystrom": (ctypes.c_int, [vp, vp, vp, vp]),
         "usbs_step_iterate": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp]),
         "usbs_get_scaling": (ctypes.c_int, [vp, vp, vp]),
+        "usbs_profile": (ctypes.c_int, [vp, i32, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -134,7 +137,8 @@ class Params:
     time_limit: float = 0.0
     lanczos_steps: int = 8
     lanczos_max_restarts: int = 10
-    lanczos_tol: float = 1e-6
+    lanczos_tol: float = 1e-4
+    lanczos_tol_final: float = 1e-9
     precision: str = "f64"
     seed: int = 0
     verbose: int = 0
@@ -143,7 +147,7 @@ class Params:
         p = UsbsParams()
         load_library().usbs_default_params(ctypes.byref(p))
         for f in ("alpha", "rho", "beta", "k_c", "k_p", "r", "eps_gap", "eps_infeas", "max_iters", "time_limit",
-                  "lanczos_steps", "lanczos_max_restarts", "lanczos_tol", "seed", "verbose"):
+                  "lanczos_steps", "lanczos_max_restarts", "lanczos_tol", "lanczos_tol_final", "seed", "verbose"):
             setattr(p, f, getattr(self, f))
         p.units = UNITS[self.units]
         p.precision = PREC[self.precision]
@@ -282,6 +286,14 @@ class Solver:
                                                _ptr(P) if self.r else None, _ptr(scal)))
         keys = ["f", "tau", "cbar", "primal", "rel_gap", "rel_infeas", "lambda1", "descents"]
         return {"y": y, "V": V[:, :k], "zbar": zbar, "P": P[:, :self.r], **dict(zip(keys, scal))}
+
+    def profile(self, category: str | None, reset: bool = True):
+        """Return (ms, launches) timed so far for the current category and start timing
+        `category` (None stops timing)."""
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        cat = -1 if category is None else PROF[category]
+        self._check(self.lib.usbs_profile(self.h, cat, int(reset), ctypes.byref(ms), ctypes.byref(cnt)))
+        return ms.value, cnt.value
 
     def free(self) -> None:
         if self.h is not None:
