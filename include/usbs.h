@@ -111,9 +111,12 @@ typedef struct usbs_result {
     double lambda_max;        /* largest Ritz value of C_s - A^* y at the last candidate */
     double sketch_primal_obj; /* <C, Xhat> of the Nystrom reconstruction (original units) */
     double sketch_rel_infeas; /* dist(A Xhat, K)/(1+||b||) (units per params)     */
+    double rel_gap_scaled, rel_infeas_scaled;     /* the paper's metric on the scaled problem */
+    double rel_gap_original, rel_infeas_original; /* the same formulas in original units     */
     double seconds;
     int64_t lanczos_matvecs;  /* columns multiplied by C - A^* y                  */
     int32_t iters, descents, ipm_iters, status;
+    int32_t lanczos_unconverged; /* in-iteration eigen-solves that hit the restart limit */
 } usbs_result;
 
 int usbs_default_params(usbs_params *prm);

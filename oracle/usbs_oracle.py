@@ -603,6 +603,30 @@ def usbs_solve(prob, prm: Params | None = None, Psi: np.ndarray | None = None, s
                   descents=descents, converged=converged, state=st, history=hist)
 
 
+def warm_start(prob_new, prm: Params, sc_old: Scaled, st_old: State, Psi_old: np.ndarray,
+               Psi_new: np.ndarray):
+    """Warm start for a grown problem (Sec. 5.1: pad the old solution with zeros and rescale).
+    Reading: Xbar_0 is the rank-r Nystrom reconstruction of the old sketch (App. C.1), padded with
+    zero rows and rescaled to the new tr X*; y is padded with zeros and rescaled to the new ||C||_F;
+    V is padded and re-orthonormalised.  Returns (scaled problem, state)."""
+    sc = scale_problem(prob_new)
+    n0, n = sc_old.prob.n, prob_new.n
+    U, lam = nystrom_stable(st_old.Pbar, np.asarray(Psi_old, dtype=np.float64))
+    Up = np.zeros((n, U.shape[1]))
+    Up[:n0] = U
+    lam = lam * sc_old.tau_star / sc.tau_star
+    Xbar = (Up * lam[None, :]) @ Up.T
+    y = np.zeros(prob_new.m)
+    y[:sc_old.prob.m] = st_old.y * sc_old.sigma / sc.sigma
+    Vp = np.zeros((n, st_old.V.shape[1]))
+    Vp[:n0] = st_old.V
+    V = np.linalg.qr(Vp)[0]
+    f, _, _ = penalized_dual(sc, y, prm.alpha, 1)
+    st = State(y=y, f=f, V=V, Xbar=Xbar, tau=float(np.trace(Xbar)), cbar=float(np.sum(sc.C * Xbar)),
+               zbar=A_apply(prob_new, Xbar), Pbar=Xbar @ np.asarray(Psi_new, dtype=np.float64))
+    return sc, st
+
+
 def to_original(sc: Scaled, value: float) -> float:
     """Objective values in the units of the unscaled problem."""
     return sc.sigma * sc.tau_star * value
@@ -612,15 +636,64 @@ def to_original(sc: Scaled, value: float) -> float:
 # certificates for a result computed elsewhere
 # --------------------------------------------------------------------------
 
+def sparse_shifted(prob, y_scaled: np.ndarray):
+    """C_s - A^* y as a scipy CSR matrix (for n too large for dense storage)."""
+    import scipy.sparse as sp
+    n = prob.n
+    sigma = float(np.linalg.norm(prob.val)) or 1.0
+    rows = np.repeat(np.arange(n), np.diff(prob.rowptr))
+    M = sp.csr_matrix((prob.val / sigma, (rows, prob.col.astype(np.int64))), shape=(n, n))
+    c = y_scaled[prob.a_row] * prob.a_v
+    diag = prob.a_i == prob.a_j
+    off = ~diag
+    Ay = sp.coo_matrix((np.concatenate([c[diag], 0.5 * c[off], 0.5 * c[off]]),
+                        (np.concatenate([prob.a_i[diag], prob.a_i[off], prob.a_j[off]]),
+                         np.concatenate([prob.a_i[diag], prob.a_j[off], prob.a_i[off]]))), shape=(n, n))
+    return (M - Ay.tocsr()).tocsr()
+
+
+def lanczos_lambda_max(M, steps: int = 200, seed: int = 0):
+    """Largest eigenvalue of a symmetric (sparse or dense) matrix by plain single-vector
+    Lanczos with full re-orthogonalisation and the Jacobi eigenvalues of the tridiagonal
+    matrix; returns (theta_1, residual bound |beta_k y_k1|)."""
+    n = M.shape[0]
+    steps = min(steps, n)
+    rng = np.random.default_rng(seed)
+    Q = np.zeros((steps + 1, n))
+    q = rng.standard_normal(n)
+    Q[0] = q / np.linalg.norm(q)
+    alpha, beta = [], []
+    k = 0
+    for k in range(steps):
+        w = M @ Q[k]
+        a = float(Q[k] @ w)
+        w = w - Q[:k + 1].T @ (Q[:k + 1] @ w)
+        w = w - Q[:k + 1].T @ (Q[:k + 1] @ w)
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        beta.append(b)
+        if b < 1e-14 * max(1.0, abs(a)):
+            break
+        Q[k + 1] = w / b
+    m = len(alpha)
+    T = np.diag(alpha) + np.diag(beta[:m - 1], 1) + np.diag(beta[:m - 1], -1)
+    w, Y = jacobi_eigh(T)
+    return float(w[0]), float(abs(beta[m - 1] * Y[m - 1, 0]))
+
 def certificate(prob, y_scaled: np.ndarray, z_scaled: np.ndarray, cX_scaled: float,
                 alpha: float = 2.0, units: str = "scaled", lam_max: float | None = None):
     """Re-evaluate f(y) in FP64 (Jacobi) and the relative errors of a primal summary
     (z = A X, <C, X>) produced by another solver, all in scaled units."""
-    sc = scale_problem(prob)
+    sc = scale_problem(prob) if prob.n <= 3000 else None
     y = proj_Y(prob, np.asarray(y_scaled, dtype=np.float64))
+    if sc is None:
+        sigma = float(np.linalg.norm(prob.val)) or 1.0
+        sc = Scaled(prob=prob, C=None, b=prob.b / prob.trace, sigma=sigma, tau_star=float(prob.trace))
     if lam_max is None:
-        M = sc.C - A_adjoint(prob, y)
-        lam_max = jacobi_eigh(M)[0][0]
+        if sc.C is not None:
+            lam_max = jacobi_eigh(sc.C - A_adjoint(prob, y))[0][0]
+        else:
+            lam_max = lanczos_lambda_max(sparse_shifted(prob, y))[0]
     f = alpha * max(lam_max, 0.0) + float(sc.b @ y)
     gap, inf = metrics(sc, f, cX_scaled, np.asarray(z_scaled, dtype=np.float64), units)
     return {"f": f, "lambda_max": lam_max, "rel_gap": gap, "rel_infeas": inf}

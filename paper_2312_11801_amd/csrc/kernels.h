@@ -36,6 +36,9 @@ void diag_shift(hipStream_t s, int n, const int *dptr, const int *dk, const doub
 void offdiag_refresh(hipStream_t s, int prec, int nt, const int *slot, const int *k,
                      const double *hv, const double *cbase, const double *y, double inv_scale,
                      void *val);
+// Gershgorin bound max_i (|d_i| + scale sum_e |val_e|) of the shifted operator into *out
+void op_bound(hipStream_t s, const RedScratch &rs, int prec, int n, const int *rowptr, const void *val, double scale,
+              const double *d, double *out);
 // copy base values into the compute-precision value array
 void convert_values(hipStream_t s, int prec, int nnz, const double *src, double inv_scale, void *dst);
 

@@ -205,6 +205,58 @@ __global__ void k_diag_shift(int n, const int *__restrict__ dptr, const int *__r
     d[i] = v;
 }
 
+// Gershgorin bound of the shifted operator: out = max_i (|d_i| + scale * sum_e |val_e|)
+template <typename VT>
+__global__ __launch_bounds__(kWG) void k_op_bound(int n, const int *__restrict__ rowptr,
+                                                  const VT *__restrict__ val, double scale,
+                                                  const double *__restrict__ d, double *__restrict__ part) {
+    __shared__ double red[kWG];
+    double mx = 0.0;
+    for (long i = (long)blockIdx.x * kWG + threadIdx.x; i < n; i += (long)gridDim.x * kWG) {
+        double s = 0.0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+            if constexpr (sizeof(VT) == 2) s += fabs((double)bf16_to_f32(val[e]));
+            else s += fabs((double)val[e]);
+        }
+        mx = fmax(mx, fabs(d[i]) + fabs(scale) * s);
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_max_finish(const double *__restrict__ part, int G, double *out) {
+    __shared__ double red[kWG];
+    double mx = 0.0;
+    for (int b = threadIdx.x; b < G; b += kWG) mx = fmax(mx, part[b]);
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int st = kWG / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+void op_bound(hipStream_t s, const RedScratch &rs, int prec, int n, const int *rowptr, const void *val, double scale,
+              const double *d, double *out) {
+    int blocks = cdiv(n, 4 * kWG);
+    if (blocks > 256) blocks = 256;
+    if (blocks < 1) blocks = 1;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_op_bound<double>, dim3(blocks), dim3(kWG), 0, s, n, rowptr, (const double *)val, scale, d,
+                           rs.partials);
+    else if (prec == 1)
+        hipLaunchKernelGGL(k_op_bound<float>, dim3(blocks), dim3(kWG), 0, s, n, rowptr, (const float *)val, scale, d,
+                           rs.partials);
+    else
+        hipLaunchKernelGGL(k_op_bound<uint16_t>, dim3(blocks), dim3(kWG), 0, s, n, rowptr, (const uint16_t *)val,
+                           scale, d, rs.partials);
+    hipLaunchKernelGGL(k_max_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, out);
+}
+
 void diag_shift(hipStream_t s, int n, const int *dptr, const int *dk, const double *dv,
                 const double *cdiag, const double *y, double *d) {
     if (n <= 0) return;
@@ -475,11 +527,9 @@ __global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__
         Z[tid] = (sg > 1e-150 && sg > 1e-14 * ref) ? Yv[tid] / sg : 0.0;
     }
     if (tid == 0) {
+        // tolerances are relative to a Gershgorin bound of the current operator
         double sc = fmax(fabs(theta[0]), fabs(theta[kRitz - 1]));
-        if (scale_est) {
-            sc = fmax(sc, *scale_est);
-            *scale_est = sc;
-        }
+        if (scale_est) sc = fmax(sc, *scale_est);
         // the top Ritz pair sets f(y): tight tolerance; the others only shape the bundle
         int ok = sqrt(fmax(RtR[0], 0.0)) <= tol * sc;
         for (int i = 1; i < kc; ++i) {

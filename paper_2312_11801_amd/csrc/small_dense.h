@@ -373,6 +373,7 @@ __device__ __forceinline__ double wave_min_eig(int k, double *X, int ldx, Jacobi
 constexpr int kMaxD = kMaxSvec + 1;
 struct IpmShared {
     double M[kMaxD * (kMaxD + 1)];
+    double Q11[kMaxSvec * kMaxSvec];   // staged once per solve
     double S[kMaxK * kMaxK], T[kMaxK * kMaxK], Si[kMaxK * kMaxK];
     double LS[kMaxK * kMaxK], LSi[kMaxK * kMaxK], LT[kMaxK * kMaxK], LTi[kMaxK * kMaxK];
     double dS[kMaxK * kMaxK], dT[kMaxK * kMaxK];
@@ -426,7 +427,8 @@ __device__ void wg_ipm(const IpmArgs a, const double *__restrict__ qp, double *s
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int k = a.k, d = k * (k + 1) / 2, D = d + 1, ldm = kMaxD + 1;
-    const double *Q11 = qp;
+    for (int e = tid; e < d * d; e += kWG) sh->Q11[e] = qp[e];
+    const double *Q11 = sh->Q11;
     const double r2 = 1.4142135623730951;
     // svec index tables and data
     if (tid == 0) {
@@ -496,17 +498,26 @@ __device__ void wg_ipm(const IpmArgs a, const double *__restrict__ qp, double *s
             sh->t[p] = f * sh->T[i * kMaxK + j];
         }
         __syncthreads();
-        // residuals F1 (d) and F2
+        // residuals F1 (d) and F2: 4 lanes per row of Q11
         double f2part = 0.0, mres = 0.0;
-        for (int p = tid; p < d; p += kWG) {
-            const double *row = Q11 + (size_t)p * d;
-            double v = 0.0;
-            for (int q = 0; q < d; ++q) v += row[q] * sh->s[q];
-            const double vI = (sh->pi[p] == sh->pj[p]) ? 1.0 : 0.0;
-            v += sh->eta * sh->q12[p] + sh->h1[p] - sh->t[p] + sh->om * vI;
-            sh->F1[p] = v;
-            mres = fmax(mres, fabs(v));
-            f2part += sh->q12[p] * sh->s[p];
+        {
+            const int q4 = tid & 3;
+            for (int p = tid >> 2; p < ((d + 63) & ~63); p += kWG / 4) {
+                double v = 0.0;
+                if (p < d) {
+                    const double *row = Q11 + (size_t)p * d;
+                    for (int q = q4; q < d; q += 4) v += row[q] * sh->s[q];
+                }
+                v += __shfl_xor(v, 1, 4);
+                v += __shfl_xor(v, 2, 4);
+                if (p < d && q4 == 0) {
+                    const double vI = (sh->pi[p] == sh->pj[p]) ? 1.0 : 0.0;
+                    v += sh->eta * sh->q12[p] + sh->h1[p] - sh->t[p] + sh->om * vI;
+                    sh->F1[p] = v;
+                    mres = fmax(mres, fabs(v));
+                    f2part += sh->q12[p] * sh->s[p];
+                }
+            }
         }
         const double qs = wg_reduce_sum(f2part, sh);
         const double m1 = wg_reduce_max(mres, sh);

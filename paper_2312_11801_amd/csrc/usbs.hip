@@ -102,6 +102,8 @@ struct usbs_handle {
 
     int64_t matvecs = 0;
     int iters = 0;
+    int lz_unconverged = 0;   // in-iteration eigen-solves that hit the restart limit
+    bool last_conv = false;
     bool ready = false;
 
     // live timing of one kernel category with HIP events (bench / roofline)
@@ -456,6 +458,8 @@ void shift_operator(usbs_handle *h, const double *y) {
     if (h->has_offc)
         offdiag_refresh(h->stream, h->prec, h->n_offt, h->off_slot, h->off_k, h->off_hv, h->cbase, y,
                         1.0 / h->val_scale, h->val_cur);
+    // scale of the Lanczos tolerances and of the Cholesky-QR deflation floor
+    op_bound(h->stream, h->rs, h->prec, h->n, h->rowptr, h->val_cur, h->val_scale, h->dshift, h->sc + SC_SCALE);
 }
 
 void apply_op(usbs_handle *h, const double *X, int ldx, double *Y, int ldy, int nb) {
@@ -514,6 +518,7 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         int conv = 0;
         HIPCHK(hipMemcpyAsync(&conv, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
+        h->last_conv = conv != 0;
         if (conv || cyc == maxr) break;
         // Krylov expansion from the dominant residual directions
         lanczos_reset_T(s, h->Tm, ldb, ldb, h->theta, h->dead);
@@ -609,9 +614,14 @@ void iterate(usbs_handle *h) {
         qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 1, h->Gy, 0);
         fhat_prep(s, k, h->VCV, h->Gy, h->sc);
     }
-    // eigen step at the candidate
+    // eigen step at the candidate: the previous Ritz block with its last two columns
+    // replaced by fresh random directions (the new top eigenvector need not lie in it)
     shift_operator(h, h->yc);
-    lanczos(h, h->Uritz, kc, prm.lanczos_tol, std::sqrt(prm.lanczos_tol), prm.lanczos_max_restarts, false);
+    copy_cols(s, n, h->Uritz, 16, 14, h->Ubuf, 16);
+    random_block(s, n, 2, prm.seed + 7919ull * (uint64_t)(h->iters + 1), h->W, 8);
+    copy_cols(s, n, h->W, 8, 2, h->Ubuf + 14, 16);
+    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, std::sqrt(prm.lanczos_tol), prm.lanczos_max_restarts, true);
+    if (cyc >= prm.lanczos_max_restarts && !h->last_conv) h->lz_unconverged++;
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
     // model update
@@ -641,7 +651,11 @@ void iterate(usbs_handle *h) {
 void polish_dual(usbs_handle *h) {
     hipStream_t s = h->stream;
     shift_operator(h, h->y);
-    lanczos(h, h->Uritz, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, false);
+    // start: the 12 leading Ritz vectors of the last candidate plus 4 random directions
+    copy_cols(s, h->n, h->Uritz, 16, 12, h->Ubuf, 16);
+    random_block(s, h->n, 4, h->prm.seed + 1000003ull * (uint64_t)(h->iters + 1), h->W, 8);
+    copy_cols(s, h->n, h->W, 8, 4, h->Ubuf + 12, 16);
+    lanczos(h, h->Ubuf, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, true);
     recompute_f(s, h->theta, h->y, h->b, h->m, h->rs, h->sc);
 }
 
@@ -848,6 +862,14 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
             res->dual_bound = s * sc[SC_F];
             res->rel_gap = sc[SC_GAP];
             res->rel_infeas = sc[SC_INF];
+            {
+                const double s2 = h->sigma * h->trace, dist = std::sqrt(std::max(sc[SC_DIST2], 0.0));
+                res->rel_gap_scaled = std::fabs(sc[SC_F] - sc[SC_CX]) / (1.0 + std::fabs(sc[SC_CX]));
+                res->rel_infeas_scaled = dist / (1.0 + h->bnorm);
+                res->rel_gap_original = std::fabs(s2 * sc[SC_F] - s2 * sc[SC_CX]) / (1.0 + std::fabs(s2 * sc[SC_CX]));
+                res->rel_infeas_original = h->trace * dist / (1.0 + h->trace * h->bnorm);
+            }
+            res->lanczos_unconverged = h->lz_unconverged;
             res->lambda_max = sc[SC_THETA1];
             res->seconds = secs;
             res->lanczos_matvecs = h->matvecs;
@@ -1182,9 +1204,99 @@ int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
         set_err(h, "usbs_warm_start: handle not ready");
         return USBS_E_STATE;
     }
-    (void)grown;
-    set_err(h, "usbs_warm_start: not implemented");
-    return USBS_E_STATE;
+    try {
+        hipStream_t s = h->stream;
+        const int n0 = h->n, m0 = h->m, r = h->r, k = h->k;
+        HostProblem hp = copy_problem(grown, r);
+        if (hp.n < n0 || hp.m < m0)
+            throw DevError(USBS_E_INVALID, "usbs_warm_start: the grown problem must keep all vertices and rows");
+        if ((r > 0) != !hp.psi.empty())
+            throw DevError(USBS_E_INVALID, "usbs_warm_start: sketch presence must not change");
+        // ---- state of the old problem (scaled units) ----
+        const double sig0 = h->sigma, tr0 = h->trace;
+        std::vector<double> y0(m0), V0((size_t)n0 * 16), R0((size_t)n0 * 16), U0, lam0;
+        HIPCHK(hipMemcpyAsync(y0.data(), h->y, m0 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(V0.data(), h->V, (size_t)n0 * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(R0.data(), h->Uritz, (size_t)n0 * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (r > 0) {
+            // Nystrom reconstruction of Xbar (App. C.1): Xhat = U diag(lam) U^T
+            interleave(s, n0, r, h->P, h->psi, h->W2);
+            tn_reduce(s, h->rs, n0, h->W2, 2 * r, 2 * r, h->W2, 2 * r, 2 * r, h->small, 2 * r, 1.0, 0.0);
+            nystrom_core(s, n0, r, h->small, h->small + 1024, h->small + 2048, h->flag);
+            nn_update(s, n0, h->W2, 2 * r, 2 * r, h->small + 1024, r, r, h->Zp, 16, 1.0, 0.0);
+            U0.resize((size_t)n0 * 16);
+            lam0.resize(r);
+            HIPCHK(hipMemcpyAsync(U0.data(), h->Zp, (size_t)n0 * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(lam0.data(), h->small + 2048, r * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        // ---- the grown problem ----
+        free_problem(h);
+        h->ready = false;
+        h->hp = std::move(hp);
+        set_geometry(h, h->hp.n);
+        upload(h);
+        const int n = h->n, m = h->m;
+        init_scalars(h);
+        // y: pad with zeros; y_s = y / ||C||_F rescales by sigma_old / sigma_new
+        std::vector<double> y(m, 0.0);
+        for (int q = 0; q < m0; ++q) y[q] = y0[q] * sig0 / h->sigma;
+        HIPCHK(hipMemcpyAsync(h->y, y.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+        // V and the Ritz block: zero rows for the new vertices, re-orthonormalised
+        std::vector<double> Vp((size_t)n * 16, 0.0), Rp((size_t)n * 16, 0.0);
+        std::copy(V0.begin(), V0.end(), Vp.begin());
+        std::copy(R0.begin(), R0.end(), Rp.begin());
+        HIPCHK(hipMemcpyAsync(h->Zp, Vp.data(), (size_t)n * 16 * sizeof(double), hipMemcpyHostToDevice, s));
+        set_int(s, h->zdead, 16, 0);
+        cholqr2(h, h->Zp, 16, k, h->W2, 16, h->V, 16, h->zdead);
+        HIPCHK(hipMemcpyAsync(h->Ubuf, Rp.data(), (size_t)n * 16 * sizeof(double), hipMemcpyHostToDevice, s));
+        set_int(s, h->flag, 16, 0);
+        cholqr2(h, h->Ubuf, 16, 16, h->W2, 16, h->Uritz, 16, h->flag);
+        // Xbar0 = padded Xhat in the new scaling (X_s = X / trace)
+        double tau = 0.0, cbar = 0.0;
+        if (r > 0) {
+            std::vector<double> Up((size_t)n * 16, 0.0), K(r * r, 0.0);
+            std::copy(U0.begin(), U0.end(), Up.begin());
+            for (int j = 0; j < r; ++j) {
+                const double lj = lam0[j] * tr0 / h->trace;
+                K[j * r + j] = lj;
+                tau += lj;
+            }
+            HIPCHK(hipMemcpyAsync(h->Zp, Up.data(), (size_t)n * 16 * sizeof(double), hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(h->Kc, K.data(), r * r * sizeof(double), hipMemcpyHostToDevice, s));
+            // <C_s, Xhat> = sum_j lam_j u_j^T C_s u_j
+            apply_C(h, h->Zp, 16, h->CV, 16, r);
+            tn_reduce(s, h->rs, n, h->Zp, 16, r, h->CV, 16, r, h->TUU, r, 1.0, 0.0);
+            std::vector<double> uc(r * r);
+            HIPCHK(hipMemcpyAsync(uc.data(), h->TUU, r * r * sizeof(double), hipMemcpyDeviceToHost, s));
+            // zbar = A(Xhat); P = Xhat Psi = U (K (U^T Psi))
+            lowrank_A(s, m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, r, h->Kc, 1.0, nullptr, nullptr, 0.0, h->zbar,
+                      0.0);
+            tn_reduce_f(s, h->rs, n, h->Zp, 16, r, h->psi, r, r, h->VtPsi, r, 1.0);
+            HIPCHK(hipStreamSynchronize(s));
+            for (int j = 0; j < r; ++j) cbar += K[j * r + j] * uc[j * r + j];
+            std::vector<double> Ut(r * r);
+            HIPCHK(hipMemcpy(Ut.data(), h->VtPsi, r * r * sizeof(double), hipMemcpyDeviceToHost));
+            for (int j = 0; j < r; ++j)
+                for (int c = 0; c < r; ++c) Ut[j * r + c] *= K[j * r + j];
+            HIPCHK(hipMemcpyAsync(h->Hsk, Ut.data(), r * r * sizeof(double), hipMemcpyHostToDevice, s));
+            nn_update(s, n, h->Zp, 16, r, h->Hsk, r, r, h->P, r, 1.0, 0.0);
+        } else {
+            fill(s, m, 0.0, h->zbar);
+        }
+        const double tc[2] = {tau, cbar};
+        HIPCHK(hipMemcpyAsync(h->sc + SC_TAU, tc, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+        // f(y0) with a tight tolerance
+        shift_operator(h, h->y);
+        lanczos(h, h->Uritz, k, h->prm.lanczos_tol_final, std::sqrt(h->prm.lanczos_tol_final),
+                std::max(h->prm.lanczos_max_restarts, 30), false);
+        recompute_f(s, h->theta, h->y, h->b, m, h->rs, h->sc);
+        HIPCHK(hipStreamSynchronize(s));
+        h->ready = true;
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
 }
 
 }  // extern "C"

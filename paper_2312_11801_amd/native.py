@@ -60,8 +60,11 @@ class UsbsResult(ctypes.Structure):
         ("primal_obj_scaled", ctypes.c_double), ("f_scaled", ctypes.c_double),
         ("rel_gap", ctypes.c_double), ("rel_infeas", ctypes.c_double), ("lambda_max", ctypes.c_double),
         ("sketch_primal_obj", ctypes.c_double), ("sketch_rel_infeas", ctypes.c_double),
+        ("rel_gap_scaled", ctypes.c_double), ("rel_infeas_scaled", ctypes.c_double),
+        ("rel_gap_original", ctypes.c_double), ("rel_infeas_original", ctypes.c_double),
         ("seconds", ctypes.c_double), ("lanczos_matvecs", ctypes.c_int64), ("iters", ctypes.c_int32),
         ("descents", ctypes.c_int32), ("ipm_iters", ctypes.c_int32), ("status", ctypes.c_int32),
+        ("lanczos_unconverged", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

@@ -196,3 +196,38 @@ def test_solve_parity_small_maxcut(cuda):
     print("oracle", ref.iters, orc.to_original(sc, p_ref_s))
     assert abs(out["primal_obj_scaled"] - p_ref_s) / (1 + abs(p_ref_s)) <= 1e-3
     assert abs(out["primal_obj"] - orc.to_original(sc, p_ref_s)) / abs(orc.to_original(sc, p_ref_s)) <= 5e-3
+
+
+def test_warm_start_grown_maxcut(cuda):
+    """Warm start on a problem grown by 1% of vertices (Sec. 5.1): the GPU result after the
+    warm start is certified by the oracle and matches the oracle's cold solve of the grown
+    problem; the iteration count is reported against a cold GPU solve."""
+    from paper_2312_11801_amd import Params, Solver
+    rng = np.random.default_rng(9)
+    n0, n = 200, 202
+    i, j = si.erdos_renyi(n, 0.05, rng)
+    keep = (i < n0) & (j < n0)
+    base = si.maxcut_problem(n0, i[keep], j[keep], np.ones(int(keep.sum())))
+    grown = si.maxcut_problem(n, i, j, np.ones(i.size))
+    psi0, psi1 = si.test_matrix(n0, 10, seed=3), si.test_matrix(n, 10, seed=3)
+    prm = Params(rho=0.1, max_iters=800)
+    s = Solver(base, prm, psi=psi0)
+    out0 = s.solve()
+    assert out0["converged"]
+    s.warm_start(grown, psi=psi1)
+    warm = s.solve()
+    s.free()
+    c = Solver(grown, prm, psi=psi1)
+    cold = c.solve()
+    c.free()
+    print("warm iters", warm["iters"], "cold iters", cold["iters"])
+    assert warm["converged"] and cold["converged"]
+    sc = orc.scale_problem(grown)
+    y_s = warm["y"] / sc.sigma
+    lam1 = orc.jacobi_eigh(sc.C - orc.A_adjoint(grown, y_s))[0][0]
+    f_ref = 2.0 * max(lam1, 0.0) + float(sc.b @ y_s)
+    assert abs(f_ref - warm["f_scaled"]) <= 1e-7 * (1 + abs(f_ref))
+    ref = orc.usbs_solve(grown, orc.Params(rho=0.1, max_iters=800), Psi=psi1, keep_history=False)
+    p_ref = orc.to_original(sc, ref.primal_obj)
+    assert abs(warm["primal_obj_scaled"] - ref.primal_obj) / (1 + abs(ref.primal_obj)) <= 1e-3
+    assert abs(warm["primal_obj"] - p_ref) / abs(p_ref) <= 5e-3

@@ -333,3 +333,51 @@ def test_usbs_cc_closed_forms():
         assert f >= pstar - 1e-9
         assert abs(p - pstar) / pstar < 1e-2 and abs(f - pstar) / pstar < 1e-2, (p, f, pstar)
         assert np.all(res.y[prob.is_ineq.astype(bool)] >= 0)
+
+
+def test_oracle_warm_start_grown_problem():
+    """Warm start after adding 1% vertices (Sec. 5.1): the padded state is consistent (tracked
+    quantities equal the dense recomputation), and the warm solve converges to the cold value."""
+    import sdp_inputs as si2
+    rng = np.random.default_rng(8)
+    n0, n = 60, 61
+    i, j = si2.erdos_renyi(n, 0.15, rng)
+    keep = (i < n0) & (j < n0)
+    base = si2.maxcut_problem(n0, i[keep], j[keep], np.ones(int(keep.sum())))
+    grown = si2.maxcut_problem(n, i, j, np.ones(i.size))
+    psi0 = si2.test_matrix(n0, 10, seed=2).astype(float)
+    psi1 = si2.test_matrix(n, 10, seed=2).astype(float)
+    assert np.array_equal(psi1[:n0], psi0)
+    prm = orc.Params(rho=0.1, max_iters=600)
+    r0 = orc.usbs_solve(base, prm, Psi=psi0)
+    assert r0.converged
+    sc0 = orc.scale_problem(base)
+    sc1, st = orc.warm_start(grown, prm, sc0, r0.state, psi0, psi1)
+    assert abs(st.tau - np.trace(st.Xbar)) < 1e-12 and np.abs(st.Pbar - st.Xbar @ psi1).max() < 1e-12
+    assert np.abs(st.V.T @ st.V - np.eye(st.V.shape[1])).max() < 1e-12
+    warm = orc.usbs_solve(grown, prm, Psi=psi1, state=st)
+    cold = orc.usbs_solve(grown, prm, Psi=psi1)
+    assert warm.converged and cold.converged
+    pw, pc = orc.to_original(sc1, warm.primal_obj), orc.to_original(sc1, cold.primal_obj)
+    assert abs(pw - pc) / abs(pc) < 5e-3
+
+
+def test_oracle_lanczos_vs_jacobi_and_closed_form():
+    """The plain Lanczos of the certificate evaluator: equals Jacobi's lambda_max on small
+    problems; on large bipartite d-regular graphs lambda_max(L/4 - (d/2) I) = 0 exactly."""
+    prob = si.cc_signed(300, avg_degree=6, seed=3)
+    rng = np.random.default_rng(4)
+    y = rng.standard_normal(prob.m) * 0.01
+    sc = orc.scale_problem(prob)
+    ref = orc.jacobi_eigh(sc.C - orc.A_adjoint(prob, y))[0][0]
+    lam, res = orc.lanczos_lambda_max(orc.sparse_shifted(prob, y), steps=300)
+    assert abs(lam - ref) < 1e-10 * max(1, abs(ref))
+    big = si.maxcut_regular(20000, 4, seed=1, bipartite=True)
+    sigma = float(np.linalg.norm(big.val))
+    # L/4 of a bipartite d-regular graph has lambda_max = 2d/4 = d/2, so with y_s = (d/2)/sigma
+    # the shifted operator C_s - Diag(y_s) has lambda_max = 0 and f(y) = <b, y> = |E| = p*
+    y = np.full(big.n, (4 / 2) / sigma)
+    lam, res = orc.lanczos_lambda_max(orc.sparse_shifted(big, y), steps=150)
+    assert abs(lam) < 1e-6 / sigma and lam <= 1e-9
+    cert = orc.certificate(big, y, np.ones(big.n) / big.n, 2.0 * big.n / (sigma * big.n))
+    assert abs(cert["f"] * sigma * big.n - 2 * big.n) < 1e-6 * big.n
