@@ -117,6 +117,8 @@ typedef struct usbs_result {
     int64_t lanczos_matvecs;  /* columns multiplied by C - A^* y                  */
     int32_t iters, descents, ipm_iters, status;
     int32_t lanczos_unconverged; /* in-iteration eigen-solves that hit the restart limit */
+    int32_t stall_recoveries;    /* re-evaluations of f at the centre with the tight
+                                    eigen-solve after 25 consecutive null steps           */
 } usbs_result;
 
 int usbs_default_params(usbs_params *prm);

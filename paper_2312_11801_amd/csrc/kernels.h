@@ -84,6 +84,16 @@ void lanczos_reset_T(hipStream_t s, double *T, int ldt, int N, const double *the
 void diag_theta(hipStream_t s, const double *TUU, int N, double *theta, double *Y);
 // H = -diag(theta) (16 x 16)
 void neg_diag(hipStream_t s, const double *theta, int N, double *H);
+// decoupled rows (no off-diagonal entry in C - A^*(y) for any y): each carries the
+// exact eigenpair (d_i, e_i).  mask_rows zeroes rows idx[0..count) of X (nc columns);
+// iso_merge (one workgroup) merges the 16 largest d over those rows into the descending
+// coupled Ritz values theta / residuals res (both length 16, in place; have_coupled = 0
+// means there are none) and writes plan[q] = coupled column, -(row + 1) or 16 (empty);
+// gather_ritz builds U (n x 16) from the coupled Ritz vectors Uc (n x 16) and plan.
+void mask_rows(hipStream_t s, int count, const int *idx, double *X, int ldx, int nc);
+void iso_merge(hipStream_t s, int count, const int *idx, const double *d, int have_coupled, double *theta,
+               double *res, int *plan);
+void gather_ritz(hipStream_t s, int n, const double *Uc, const int *plan, double *U);
 
 // ---- USBS small steps ----------------------------------------------------
 // Q11 sums and the G^T w products of the master QP (App. B.2), g_k = svec(V^T A_k V).

@@ -785,3 +785,119 @@ void ipm(hipStream_t s, const IpmArgs &a, const double *qp, double *state) {
 }
 
 }  // namespace usbs
+
+namespace usbs {
+// ---------------------------------------------------------------------------
+// decoupled rows: C - A^*(y) restricted to them is diagonal for every y, so
+// each such row i carries the exact eigenpair (d_i, e_i).  The Krylov solver
+// works on the complementary (coupled) rows only; these kernels remove the
+// decoupled rows from a block and merge their eigenpairs into the Ritz set.
+// ---------------------------------------------------------------------------
+__global__ void k_mask_rows(int count, const int *__restrict__ idx, double *__restrict__ X, int ldx, int nc) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (long)count * nc) {
+        const int q = (int)(e / nc), c = (int)(e - (long)q * nc);
+        X[(size_t)idx[q] * ldx + c] = 0.0;
+    }
+}
+void mask_rows(hipStream_t s, int count, const int *idx, double *X, int ldx, int nc) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_mask_rows, dim3((unsigned)cdiv((long)count * nc, kWG)), dim3(kWG), 0, s, count, idx, X,
+                       ldx, nc);
+}
+
+// one workgroup: the 16 largest d_i over the decoupled rows (ties by row index) by
+// repeated arg-max, then a merge with the 16 descending coupled Ritz values.
+__global__ __launch_bounds__(kWG) void k_iso_merge(int count, const int *__restrict__ idx,
+                                                   const double *__restrict__ d, int have_coupled,
+                                                   double *__restrict__ theta, double *__restrict__ res,
+                                                   int *__restrict__ plan) {
+    __shared__ double bv[kWG];
+    __shared__ int bq[kWG];
+    __shared__ double iv[kRitz];
+    __shared__ int ii[kRitz];
+    const int tid = threadIdx.x;
+    const int want = count < kRitz ? count : kRitz;
+    for (int t = 0; t < want; ++t) {
+        double best = -INFINITY;
+        int bestq = -1;
+        for (int q = tid; q < count; q += kWG) {
+            bool taken = false;
+            for (int u = 0; u < t; ++u) taken |= (ii[u] == q);
+            const double v = d[idx[q]];
+            if (!taken && (bestq < 0 || v > best)) {
+                best = v;
+                bestq = q;
+            }
+        }
+        bv[tid] = best;
+        bq[tid] = bestq;
+        __syncthreads();
+        for (int o = kWG / 2; o > 0; o >>= 1) {
+            if (tid < o) {
+                const double v2 = bv[tid + o];
+                const int q2 = bq[tid + o];
+                if (q2 >= 0 && (bq[tid] < 0 || v2 > bv[tid] || (v2 == bv[tid] && q2 < bq[tid]))) {
+                    bv[tid] = v2;
+                    bq[tid] = q2;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            iv[t] = bv[0];
+            ii[t] = bq[0];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double th[kRitz], rr[kRitz];
+        int pl[kRitz];
+        int a = 0, b = 0;
+        const int nc = have_coupled ? kRitz : 0;
+        for (int q = 0; q < kRitz; ++q) {
+            const bool take_c = a < nc && (b >= want || theta[a] >= iv[b]);
+            if (take_c) {
+                th[q] = theta[a];
+                rr[q] = res[a];
+                pl[q] = a++;
+            } else if (b < want) {
+                th[q] = iv[b];
+                rr[q] = 0.0;
+                pl[q] = -(idx[ii[b]] + 1);
+                ++b;
+            } else {   // fewer than 16 eigenpairs in total: pad with empty columns
+                th[q] = -1e300;
+                rr[q] = 0.0;
+                pl[q] = kRitz;
+            }
+        }
+        for (int q = 0; q < kRitz; ++q) {
+            theta[q] = th[q];
+            res[q] = rr[q];
+            plan[q] = pl[q];
+        }
+    }
+}
+void iso_merge(hipStream_t s, int count, const int *idx, const double *d, int have_coupled, double *theta,
+               double *res, int *plan) {
+    hipLaunchKernelGGL(k_iso_merge, dim3(1), dim3(kWG), 0, s, count, idx, d, have_coupled, theta, res, plan);
+}
+
+// U[i, q] = Uc[i, plan[q]] (coupled Ritz vector), e_{-plan[q]-1} (decoupled row) or 0
+__global__ void k_gather_ritz(int n, const double *__restrict__ Uc, const int *__restrict__ plan,
+                              double *__restrict__ U) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (long)n * kRitz) {
+        const int i = (int)(e / kRitz), q = (int)(e - (long)i * kRitz);
+        const int p = plan[q];
+        double v = 0.0;
+        if (p >= 0 && p < kRitz) v = Uc[(size_t)i * kRitz + p];
+        else if (p < 0) v = (i == -p - 1) ? 1.0 : 0.0;
+        U[e] = v;
+    }
+}
+void gather_ritz(hipStream_t s, int n, const double *Uc, const int *plan, double *U) {
+    hipLaunchKernelGGL(k_gather_ritz, dim3((unsigned)cdiv((long)n * kRitz, kWG)), dim3(kWG), 0, s, n, Uc, plan, U);
+}
+}  // namespace usbs

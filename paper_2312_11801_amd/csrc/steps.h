@@ -53,7 +53,7 @@ void candidate(hipStream_t s, int m, const double *b, const double *AX, const do
 void fhat_prep(hipStream_t s, int k, const double *VCV, const double *Gy, double *sc);
 void decide(hipStream_t s, const double *theta, double *sc);
 void recompute_f(hipStream_t s, const double *theta, const double *y, const double *b, int m, const RedScratch &rs,
-                 double *sc);
+                 double *sc, int keep_max);
 void cond_copy(hipStream_t s, int m, const double *flag, const double *src, double *dst);
 void model_update(hipStream_t s, int k, int kp, int r, const double *st, const double *VCV, const double *VtPsi,
                   double *sc, double *Kc, double *Qp, double *Hsk);

@@ -167,19 +167,22 @@ void decide(hipStream_t s, const double *theta, double *sc) {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, theta, sc);
 }
 
-// f(y_t) = alpha [theta_1]_+ + <b, y_t> from an accurate Ritz value (SC_BYT holds <b, y_t>)
-__global__ void k_refresh_f(const double *__restrict__ theta, double *sc) {
+// f(y_t) = alpha [theta_1]_+ + <b, y_t> from an accurate Ritz value (SC_BYT holds <b, y_t>).
+// A Ritz value never exceeds lambda_max, so both the stored f and the new one are lower
+// bounds of f(y_t) when y_t is unchanged: keep_max then keeps the larger.
+__global__ void k_refresh_f(const double *__restrict__ theta, double *sc, int keep_max) {
     if (threadIdx.x != 0) return;
-    const double fn = sc[SC_ALPHA] * fmax(theta[0], 0.0) + sc[SC_BYT];
+    double fn = sc[SC_ALPHA] * fmax(theta[0], 0.0) + sc[SC_BYT];
+    if (keep_max) fn = fmax(fn, sc[SC_F]);
     sc[SC_F] = fn;
     sc[SC_THETA1] = theta[0];
     set_metrics(sc, fn);
 }
 void recompute_f(hipStream_t s, const double *theta, const double *y, const double *b, int m, const RedScratch &rs,
-                 double *sc) {
+                 double *sc, int keep_max) {
     const double *a[1] = {b}, *bb[1] = {y};
     dots(s, rs, m, a, bb, 1, sc + SC_BYT);
-    hipLaunchKernelGGL(k_refresh_f, dim3(1), dim3(64), 0, s, theta, sc);
+    hipLaunchKernelGGL(k_refresh_f, dim3(1), dim3(64), 0, s, theta, sc, keep_max);
 }
 
 __global__ void k_cond_copy(int m, const double *__restrict__ flag, const double *__restrict__ src,

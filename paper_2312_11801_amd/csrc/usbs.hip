@@ -88,6 +88,11 @@ struct usbs_handle {
     double *y = nullptr, *yc = nullptr, *nu = nullptr, *dnu = nullptr, *zbar = nullptr, *AX = nullptr,
            *evec = nullptr;
     double *V = nullptr, *Vn = nullptr, *CV = nullptr, *Uritz = nullptr, *P = nullptr;
+    // decoupled rows (exact eigenpairs (d_i, e_i)); Ucpl = Ritz vectors of the coupled
+    // rows (the Lanczos state; aliases Uritz when there are no decoupled rows)
+    int n_iso = 0;
+    int *iso_idx = nullptr, *plan = nullptr;
+    double *Ucpl = nullptr;
     // Lanczos work
     double *Bm = nullptr, *W = nullptr, *Wt = nullptr, *W2 = nullptr, *Ubuf = nullptr;
     double *Tm = nullptr, *theta = nullptr, *Ysm = nullptr, *TUU = nullptr, *RtR = nullptr, *Zc = nullptr,
@@ -103,6 +108,8 @@ struct usbs_handle {
     int64_t matvecs = 0;
     int iters = 0;
     int lz_unconverged = 0;   // in-iteration eigen-solves that hit the restart limit
+    int null_run = 0;         // consecutive null steps
+    int recoveries = 0;       // stall re-evaluations of f at the centre
     bool last_conv = false;
     bool ready = false;
 
@@ -265,6 +272,18 @@ void upload(usbs_handle *h) {
         if (i == j) dlist[i].push_back({k, hp.a_v[t]});
         else offt.push_back({i, j, k, 0.5 * hp.a_v[t]});
     }
+    // decoupled rows: no nonzero off-diagonal of C and no constraint touching an
+    // off-diagonal pair, so C - A^*(y) is diagonal on them for every y
+    std::vector<char> coupled(n, 0);
+    for (int i = 0; i < n; ++i)
+        for (auto &pr : rows[i]) coupled[i] |= (pr.second != 0.0);
+    for (auto &ot : offt) coupled[ot.i] = coupled[ot.j] = 1;
+    std::vector<int> iso;
+    for (int i = 0; i < n; ++i)
+        if (!coupled[i]) iso.push_back(i);
+    h->n_iso = (int)iso.size();
+    if (h->n_iso < n && n - h->n_iso < 2 * (16 + 8))
+        throw DevError(USBS_E_INVALID, "too few coupled rows for the block Lanczos basis (need 0 or >= 48)");
     for (auto &ot : offt) {
         bool f1 = false, f2 = false;
         for (auto &pr : rows[ot.i]) f1 |= (pr.first == ot.j);
@@ -404,6 +423,16 @@ void upload(usbs_handle *h) {
     h->Vn = dalloc<double>((size_t)n * 16, o);
     h->CV = dalloc<double>((size_t)n * 16, o);
     h->Uritz = dalloc<double>((size_t)n * 16, o);
+    h->plan = dalloc<int>(16, o);
+    if (h->n_iso > 0) {
+        h->iso_idx = dalloc<int>(h->n_iso, o);
+        HIPCHK(hipMemcpyAsync(h->iso_idx, iso.data(), h->n_iso * sizeof(int), hipMemcpyHostToDevice, s));
+        h->Ucpl = dalloc<double>((size_t)n * 16, o);
+        HIPCHK(hipMemsetAsync(h->Ucpl, 0, (size_t)n * 16 * sizeof(double), s));
+    } else {
+        h->iso_idx = nullptr;
+        h->Ucpl = h->Uritz;
+    }
     h->P = dalloc<double>((size_t)n * std::max(h->r, 1), o);
     h->Bm = dalloc<double>((size_t)n * ldb, o);
     h->W = dalloc<double>((size_t)n * 8, o);
@@ -490,11 +519,25 @@ void cholqr2(usbs_handle *h, const double *src, int lds, int nc, double *tmp, in
 // blocks per cycle, full FP64 re-orthogonalisation (two classical
 // Gram-Schmidt passes), Cholesky-QR2 for each new block.  On return
 // Uritz (n x 16) holds the Ritz vectors, theta[0..16) the Ritz values.
+// The iteration runs on the coupled rows only (start block masked, an invariant
+// subspace of the operator); the exact eigenpairs of the decoupled rows are
+// merged in at the end, and Ucpl keeps the coupled Ritz vectors for the next
+// start.
 // ---------------------------------------------------------------------------
 int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start) {
     hipStream_t s = h->stream;
     const int n = h->n, ldb = h->ldb, steps = h->steps;
     if (start != h->Ubuf) copy_cols(s, n, start, 16, 16, h->Ubuf, 16);
+    if (h->n_iso > 0) {
+        mask_rows(s, h->n_iso, h->iso_idx, h->Ubuf, 16, 16);
+        orth_start = true;
+        if (h->n_iso == n) {   // a diagonal operator: every eigenpair is exact
+            iso_merge(s, h->n_iso, h->iso_idx, h->dshift, 0, h->theta, h->res, h->plan);
+            gather_ritz(s, n, h->Ucpl, h->plan, h->Uritz);
+            h->last_conv = true;
+            return 0;
+        }
+    }
     if (orth_start) {
         set_int(s, h->flag, 16, 0);
         cholqr2(h, h->Ubuf, 16, 16, h->W2, 16, h->Ubuf, 16, h->flag);
@@ -507,7 +550,9 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         // after a cycle, U holds Ritz vectors of the explicit projection, so U^T M U is
         // diagonal up to rounding; the 16 x 16 eigenproblem is needed for a new start
         // block and for tight tolerances only
-        if (cyc == 0 || tol < 1e-7) small_eig(s, 16, h->TUU, 16, h->theta, h->Ysm, 16, 16, nullptr);
+        // (in the first cycle, columns deflated by the start orthonormalisation are flagged)
+        if (cyc == 0 || tol < 1e-7)
+            small_eig(s, 16, h->TUU, 16, h->theta, h->Ysm, 16, 16, (cyc == 0 && orth_start) ? h->flag : nullptr);
         else diag_theta(s, h->TUU, 16, h->theta, h->Ysm);
         nn_update(s, n, h->Ubuf, 16, 16, h->Ysm, 16, 16, h->Bm, ldb, 1.0, 0.0);
         nn_update(s, n, h->W2, 16, 16, h->Ysm, 16, 16, h->Ubuf, 16, 1.0, 0.0);
@@ -550,7 +595,11 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         }
         nn_update(s, n, h->Bm, ldb, ldb, h->Ysm, 16, 16, h->Ubuf, 16, 1.0, 0.0);
     }
-    copy_cols(s, n, h->Bm, ldb, 16, h->Uritz, 16);
+    copy_cols(s, n, h->Bm, ldb, 16, h->Ucpl, 16);
+    if (h->n_iso > 0) {
+        iso_merge(s, h->n_iso, h->iso_idx, h->dshift, 1, h->theta, h->res, h->plan);
+        gather_ritz(s, n, h->Ucpl, h->plan, h->Uritz);
+    }
     return cyc;
 }
 
@@ -558,6 +607,13 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
 // one iteration of Alg. 1 (device work; one host synchronisation inside the
 // Lanczos restart test and one for the alternating maximisation)
 // ---------------------------------------------------------------------------
+void polish_dual(usbs_handle *h);
+
+// consecutive null steps after which f at the centre is re-evaluated with the tight
+// eigen-solve (an inexact eigen-solve can under-estimate f at an accepted centre, after
+// which no candidate passes the descent test)
+constexpr int kStallWindow = 25;
+
 void iterate(usbs_handle *h) {
     hipStream_t s = h->stream;
     const int n = h->n, m = h->m, k = h->k, kc = h->kc, kp = h->kp, r = h->r;
@@ -617,7 +673,7 @@ void iterate(usbs_handle *h) {
     // eigen step at the candidate: the previous Ritz block with its last two columns
     // replaced by fresh random directions (the new top eigenvector need not lie in it)
     shift_operator(h, h->yc);
-    copy_cols(s, n, h->Uritz, 16, 14, h->Ubuf, 16);
+    copy_cols(s, n, h->Ucpl, 16, 14, h->Ubuf, 16);
     random_block(s, n, 2, prm.seed + 7919ull * (uint64_t)(h->iters + 1), h->W, 8);
     copy_cols(s, n, h->W, 8, 2, h->Ubuf + 14, 16);
     const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, std::sqrt(prm.lanczos_tol), prm.lanczos_max_restarts, true);
@@ -644,6 +700,15 @@ void iterate(usbs_handle *h) {
     }
     std::swap(h->V, h->Vn);
     h->iters++;
+    double desc = 0.0;
+    HIPCHK(hipMemcpyAsync(&desc, h->sc + SC_DESC, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    h->null_run = desc != 0.0 ? 0 : h->null_run + 1;
+    if (h->null_run >= kStallWindow) {
+        polish_dual(h);
+        h->null_run = 0;
+        h->recoveries++;
+    }
 }
 
 // accurate f(y_t): Lanczos on C - A^* y_t from the current Ritz vectors with a tight
@@ -652,11 +717,11 @@ void polish_dual(usbs_handle *h) {
     hipStream_t s = h->stream;
     shift_operator(h, h->y);
     // start: the 12 leading Ritz vectors of the last candidate plus 4 random directions
-    copy_cols(s, h->n, h->Uritz, 16, 12, h->Ubuf, 16);
+    copy_cols(s, h->n, h->Ucpl, 16, 12, h->Ubuf, 16);
     random_block(s, h->n, 4, h->prm.seed + 1000003ull * (uint64_t)(h->iters + 1), h->W, 8);
     copy_cols(s, h->n, h->W, 8, 4, h->Ubuf + 12, 16);
     lanczos(h, h->Ubuf, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, true);
-    recompute_f(s, h->theta, h->y, h->b, h->m, h->rs, h->sc);
+    recompute_f(s, h->theta, h->y, h->b, h->m, h->rs, h->sc, 1);
 }
 
 }  // namespace
@@ -852,6 +917,12 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
                 break;
             }
         }
+        if (status != USBS_OK) {
+            // stopped by a limit: report f(y_T) from the tight eigen-solve as well
+            polish_dual(h);
+            HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (res) {
             std::memset(res, 0, sizeof(*res));
@@ -870,6 +941,7 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
                 res->rel_infeas_original = h->trace * dist / (1.0 + h->trace * h->bnorm);
             }
             res->lanczos_unconverged = h->lz_unconverged;
+            res->stall_recoveries = h->recoveries;
             res->lambda_max = sc[SC_THETA1];
             res->seconds = secs;
             res->lanczos_matvecs = h->matvecs;
@@ -1290,7 +1362,7 @@ int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
         shift_operator(h, h->y);
         lanczos(h, h->Uritz, k, h->prm.lanczos_tol_final, std::sqrt(h->prm.lanczos_tol_final),
                 std::max(h->prm.lanczos_max_restarts, 30), false);
-        recompute_f(s, h->theta, h->y, h->b, m, h->rs, h->sc);
+        recompute_f(s, h->theta, h->y, h->b, m, h->rs, h->sc, 0);
         HIPCHK(hipStreamSynchronize(s));
         h->ready = true;
         return USBS_OK;

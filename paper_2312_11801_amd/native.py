@@ -64,7 +64,7 @@ class UsbsResult(ctypes.Structure):
         ("rel_gap_original", ctypes.c_double), ("rel_infeas_original", ctypes.c_double),
         ("seconds", ctypes.c_double), ("lanczos_matvecs", ctypes.c_int64), ("iters", ctypes.c_int32),
         ("descents", ctypes.c_int32), ("ipm_iters", ctypes.c_int32), ("status", ctypes.c_int32),
-        ("lanczos_unconverged", ctypes.c_int32),
+        ("lanczos_unconverged", ctypes.c_int32), ("stall_recoveries", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:

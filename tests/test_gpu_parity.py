@@ -72,6 +72,43 @@ def test_eigs_parity(cuda, kind):
     s.free()
 
 
+@pytest.mark.parametrize("case", ["lifted", "interleaved", "empty_graph"])
+def test_eigs_decoupled_rows(cuda, case):
+    """Isolated vertices give exact eigenpairs (d_i, e_i) that the Krylov iteration does
+    not see; the merged Ritz set must match the Jacobi spectrum of the whole matrix when an
+    isolated row holds the top eigenvalue, when isolated values interleave with coupled
+    ones, and when every row is isolated (empty graph)."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    rng = np.random.default_rng(21)
+    n, core = 300, 240
+    if case == "empty_graph":
+        prob = si.maxcut_problem(n, np.array([], dtype=np.int64), np.array([], dtype=np.int64), np.array([]))
+    else:
+        ei, ej = si.random_edges(core, 900, rng)
+        prob = si.maxcut_problem(n, ei, ej, rng.choice([-1.0, 1.0], size=ei.size))
+    sc = orc.scale_problem(prob)
+    y = rng.standard_normal(n) * 0.01
+    if case == "lifted":
+        y[core + 3] = -1.0
+    elif case == "interleaved":
+        lam_c = orc.jacobi_eigh(sc.C[:core, :core] - np.diag(y[:core]))[0]
+        y[core:core + 6] = -lam_c[[0, 2, 4, 6, 8, 30]] + 1e-9
+    M = sc.C - orc.A_adjoint(prob, y)
+    lam = orc.jacobi_eigh(M)[0]
+    rhoM = max(np.abs(lam).max(), 1e-300)
+    s = Solver(prob, Params(k_c=3, k_p=0, lanczos_tol=1e-9))
+    U = torch.zeros((n, 16), dtype=torch.float64, device="cuda")
+    k = 12
+    w, res, cyc = s.op_eigs(_dev(y, torch), k, U_dev=U)
+    Uh = U.cpu().numpy()[:, :k]
+    assert np.all(np.abs(w - lam[:k]) <= 1e-6 * np.maximum(np.abs(lam[:k]), rhoM)), (w, lam[:k])
+    assert np.abs(Uh.T @ Uh - np.eye(k)).max() <= 1e-10
+    R = M @ Uh - Uh * w[None, :]
+    assert np.linalg.norm(R, axis=0).max() <= 1e-6 * rhoM
+    s.free()
+
+
 def test_lowrank_A_parity(cuda):
     """(A(W diag(lam) W^T))_k on both diagonal and edge rows (App. C)."""
     import torch

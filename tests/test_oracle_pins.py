@@ -381,3 +381,31 @@ def test_oracle_lanczos_vs_jacobi_and_closed_form():
     assert abs(lam) < 1e-6 / sigma and lam <= 1e-9
     cert = orc.certificate(big, y, np.ones(big.n) / big.n, 2.0 * big.n / (sigma * big.n))
     assert abs(cert["f"] * sigma * big.n - 2 * big.n) < 1e-6 * big.n
+
+
+def test_decoupled_rows_direct_sum():
+    """Rows with no off-diagonal coupling (isolated vertices; a zero-weight edge that still
+    carries an X_ij >= 0 row is coupled) are found from the edge list independently, and
+    lambda_max of the direct sum equals numpy's dense eigvalsh, also when an isolated row
+    holds the top eigenvalue (a Krylov run from a generic start cannot see e_i there)."""
+    rng = np.random.default_rng(11)
+    n, core = 220, 160
+    ei, ej = si.random_edges(core, 500, rng)
+    w = rng.choice([-1.0, 1.0], size=ei.size)
+    mc = si.maxcut_problem(n, ei, ej, w)
+    deg = np.bincount(np.concatenate([ei, ej]), minlength=n)
+    assert np.array_equal(orc.decoupled_rows(mc), deg == 0)
+    sigma = float(np.linalg.norm(mc.val))
+    for lift in (0.0, 5.0):
+        y = rng.standard_normal(n) * 0.01 / sigma
+        y[core + 7] = -lift / sigma          # d_i = -y_i: the top eigenvalue when lifted
+        dense = np.linalg.eigvalsh(orc.sparse_shifted(mc, y).toarray())[-1]
+        assert abs(orc.lambda_max_sparse(mc, y) - dense) <= 1e-10 * max(1.0, abs(dense))
+        c1 = orc.certificate(mc, y, np.zeros(n), 0.0, dense=True)
+        c2 = orc.certificate(mc, y, np.zeros(n), 0.0, dense=False)
+        assert abs(c1["f"] - c2["f"]) <= 1e-10 * max(1.0, abs(c1["f"]))
+    # correlation clustering: an edge of weight 0 keeps its endpoints coupled via X_ij >= 0
+    ci, cj = np.array([0, 2, 3]), np.array([1, 5, 4])
+    cc = si.cc_problem(8, ci, cj, np.array([1.0, 0.0, -1.0]))
+    iso = orc.decoupled_rows(cc)
+    assert np.array_equal(np.flatnonzero(iso), [6, 7])
