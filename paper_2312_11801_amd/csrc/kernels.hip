@@ -54,14 +54,14 @@ __global__ __launch_bounds__(kWG) void k_red_finish(const double *__restrict__ p
     const int b0 = w * per, b1 = min(G, b0 + per);
     double s = 0.0;
     if (o < nout) {
-        double a0 = 0.0, a1 = 0.0;
-        int bb = b0;
-        for (; bb + 1 < b1; bb += 2) {
-            a0 += part[(size_t)bb * nout + o];
-            a1 += part[(size_t)(bb + 1) * nout + o];
+        // sixteen independent loads in flight per lane
+        for (int bb = b0; bb < b1; bb += 16) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = (bb + q < b1) ? part[(size_t)(bb + q) * nout + o] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) s += v[q];
         }
-        if (bb < b1) a0 += part[(size_t)bb * nout + o];
-        s = a0 + a1;
     }
     s4[w][lane] = s;
     __syncthreads();
@@ -84,30 +84,37 @@ static void red_finish(hipStream_t s, const double *part, int G, int nout, doubl
 __global__ __launch_bounds__(kWG) void k_cholqr_finish(const double *__restrict__ part, int G, int nc,
                                                        double *H, int ldh, int *flags, const double *floor_ref) {
     __shared__ double sR[16 * 17];
-    __shared__ double s4[4][64];
+    __shared__ double sp[kWG];
     const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
     const int nout = nc * nc;
-    const int per = (G + 3) / 4;
-    const int b0 = w * per, b1 = min(G, b0 + per);
-    for (int o0 = 0; o0 < nout; o0 += 64) {
-        const int o = o0 + lane;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        if (o < nout) {
-            int bb = b0;
-            for (; bb + 3 < b1; bb += 4) {
-                a0 += part[(size_t)bb * nout + o];
-                a1 += part[(size_t)(bb + 1) * nout + o];
-                a2 += part[(size_t)(bb + 2) * nout + o];
-                a3 += part[(size_t)(bb + 3) * nout + o];
+    // thread (sl, o) sums partials sl, sl + S, ... of output o; sixteen loads in flight
+    // per thread, then the S slices are added in a fixed order (deterministic)
+    const int S = nout >= kWG ? 1 : kWG / nout;
+    for (int o0 = 0; o0 < nout; o0 += kWG / S) {
+        const int o = o0 + tid % (kWG / S), sl = tid / (kWG / S);
+        double acc = 0.0;
+        if (o < nout && sl < S) {
+            for (int b0 = sl; b0 < G; b0 += 16 * S) {
+                double v[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int b = b0 + q * S;
+                    v[q] = (b < G) ? part[(size_t)b * nout + o] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < 16; ++q) acc += v[q];
             }
-            for (; bb < b1; ++bb) a0 += part[(size_t)bb * nout + o];
         }
-        s4[w][lane] = (a0 + a1) + (a2 + a3);
+        sp[tid] = acc;
         __syncthreads();
-        if (w == 0 && o < nout) {
-            const int a = o / nc, c = o - a * nc;
-            sR[a * 17 + c] = ((s4[0][lane] + s4[1][lane]) + s4[2][lane]) + s4[3][lane];
+        if (tid < kWG / S) {
+            const int oo = o0 + tid;
+            if (oo < nout) {
+                double t = 0.0;
+                for (int q = 0; q < S; ++q) t += sp[q * (kWG / S) + tid];
+                const int a = oo / nc, c = oo - a * nc;
+                sR[a * 17 + c] = t;
+            }
         }
         __syncthreads();
     }
@@ -513,18 +520,41 @@ __global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__
                                                       double tol_rest, double *__restrict__ res,
                                                       int *__restrict__ flag, double *__restrict__ Z,
                                                       double *__restrict__ scale_est) {
-    __shared__ SyevWork ws;
-    __shared__ double wv[kRitz];
-    __shared__ double Yv[kRitz * kBlk];
+    // eigenvectors of the 16 x 16 Gram matrix R^T R by cyclic Jacobi on wavefront 0
+    __shared__ double sA[kRitz * kRitz], sV[kRitz * kRitz];
+    __shared__ JacobiWork<64, kRitz> js;
+    __shared__ int rank[kRitz];
     const int tid = threadIdx.x;
     if (tid < kRitz) res[tid] = sqrt(fmax(RtR[tid * kRitz + tid], 0.0));
-    wg_syev_load(kRitz, RtR, kRitz, nullptr, &ws);
-    wg_syev_top(kRitz, kBlk, kBlk, &ws, wv, Yv, kBlk);
-    if (tid < kRitz * kBlk) {
-        const int c = tid % kBlk;
-        const double sg = sqrt(fmax(wv[c], 0.0));
-        const double ref = sqrt(fmax(wv[0], 0.0));
-        Z[tid] = (sg > 1e-150 && sg > 1e-14 * ref) ? Yv[tid] / sg : 0.0;
+    if (tid >= 64) return;
+    for (int e = tid; e < kRitz * kRitz; e += 64) {
+        const int r = e / kRitz, c = e - r * kRitz;
+        sA[e] = RtR[(r < c ? r : c) * kRitz + (r < c ? c : r)];
+    }
+    wave_sync();
+    jacobi_core<64, kRitz, true>(kRitz, sA, sV, kRitz, &js, tid, 30, 2e-16);
+    if (tid < kRitz) {
+        const double wt = sA[tid * kRitz + tid];
+        int rk = 0;
+        for (int j = 0; j < kRitz; ++j) {
+            const double wj = sA[j * kRitz + j];
+            rk += (wj > wt) || (wj == wt && j < tid);
+        }
+        rank[tid] = rk;
+    }
+    wave_sync();
+    // Z[:, rank] = v / sigma for the 8 dominant directions (R Z orthonormal)
+    double top = 0.0;
+    for (int t = 0; t < kRitz; ++t)
+        if (rank[t] == 0) top = sA[t * kRitz + t];
+    const double ref = sqrt(fmax(top, 0.0));
+    for (int e = tid; e < kRitz * kRitz; e += 64) {
+        const int r = e / kRitz, t = e - r * kRitz;
+        const int rk = rank[t];
+        if (rk < kBlk) {
+            const double sg = sqrt(fmax(sA[t * kRitz + t], 0.0));
+            Z[r * kBlk + rk] = (sg > 1e-150 && sg > 1e-14 * ref) ? sV[r * kRitz + t] / sg : 0.0;
+        }
     }
     if (tid == 0) {
         // tolerances are relative to a Gershgorin bound of the current operator

@@ -11,6 +11,58 @@
 
 namespace usbs {
 
+// ---------------------------------------------------------------------------
+// wavefront reductions on DPP lane permutations (VALU, no LDS round trip).
+// Within a row of 16 lanes: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror; each step combines two lanes symmetrically, so
+// every lane of a row ends with the bitwise-identical result.  The four row
+// results of a wavefront are read with readlane and combined in a fixed order.
+// All lanes of the rows involved must be active.
+// ---------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double lane_read(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    return v;
+}
+__device__ __forceinline__ double row16_sum(double v) {
+    v = quad_sum(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    return v;
+}
+__device__ __forceinline__ double row16_max(double v) {
+    v = fmax(v, dpp_f64<0xB1>(v));
+    v = fmax(v, dpp_f64<0x4E>(v));
+    v = fmax(v, dpp_f64<0x141>(v));
+    v = fmax(v, dpp_f64<0x140>(v));
+    return v;
+}
+__device__ __forceinline__ double row16_min(double v) {
+    v = fmin(v, dpp_f64<0xB1>(v));
+    v = fmin(v, dpp_f64<0x4E>(v));
+    v = fmin(v, dpp_f64<0x141>(v));
+    v = fmin(v, dpp_f64<0x140>(v));
+    return v;
+}
+// sum over the 64 lanes; every lane receives the same value
+__device__ __forceinline__ double wave_allsum(double v) {
+    v = row16_sum(v);
+    return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -38,7 +90,7 @@ using JacobiScratch = JacobiWork<kWG, kMaxBasis>;
 
 // team-wide sum (tree in LDS); every lane gets the result
 template <int TEAM, int MAXN>
-__device__ double team_sum(double v, JacobiWork<TEAM, MAXN> *js, int lane) {
+__device__ __forceinline__ double team_sum(double v, JacobiWork<TEAM, MAXN> *js, int lane) {
     js->red[lane] = v;
     team_sync<TEAM>();
     for (int st = TEAM / 2; st > 0; st >>= 1) {
@@ -53,7 +105,7 @@ __device__ double team_sum(double v, JacobiWork<TEAM, MAXN> *js, int lane) {
 // In-place Jacobi on the symmetric Np x Np LDS matrix A (Np even); V receives
 // the eigenvectors (columns) when WANTV.  On exit diag(A) holds the eigenvalues.
 template <int TEAM, int MAXN, bool WANTV>
-__device__ void jacobi_core(int Np, double *A, double *V, int ld, JacobiWork<TEAM, MAXN> *js, int lane,
+__device__ __forceinline__ void jacobi_core(int Np, double *A, double *V, int ld, JacobiWork<TEAM, MAXN> *js, int lane,
                             int max_sweeps, double tol) {
     if (WANTV)
         for (int e = lane; e < Np * Np; e += TEAM) {
@@ -387,27 +439,24 @@ struct IpmShared {
     int okS, okT, okM, stop;
 };
 
+// workgroup-wide sum / max: DPP within each wavefront, then the four wave results in a
+// fixed order (every thread receives the same value; all 256 threads must call)
 __device__ __forceinline__ double wg_reduce_sum(double v, IpmShared *sh) {
     const int tid = threadIdx.x;
-    sh->red[tid] = v;
+    v = wave_allsum(v);
+    if ((tid & 63) == 0) sh->red[tid >> 6] = v;
     __syncthreads();
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-        if (tid < st) sh->red[tid] += sh->red[tid + st];
-        __syncthreads();
-    }
-    const double r = sh->red[0];
+    const double r = (sh->red[0] + sh->red[1]) + (sh->red[2] + sh->red[3]);
     __syncthreads();
     return r;
 }
 __device__ __forceinline__ double wg_reduce_max(double v, IpmShared *sh) {
     const int tid = threadIdx.x;
-    sh->red[tid] = v;
+    v = row16_max(v);
+    v = fmax(fmax(lane_read(v, 0), lane_read(v, 16)), fmax(lane_read(v, 32), lane_read(v, 48)));
+    if ((tid & 63) == 0) sh->red[tid >> 6] = v;
     __syncthreads();
-    for (int st = kWG / 2; st > 0; st >>= 1) {
-        if (tid < st) sh->red[tid] = fmax(sh->red[tid], sh->red[tid + st]);
-        __syncthreads();
-    }
-    const double r = sh->red[0];
+    const double r = fmax(fmax(sh->red[0], sh->red[1]), fmax(sh->red[2], sh->red[3]));
     __syncthreads();
     return r;
 }
@@ -423,7 +472,7 @@ __device__ __forceinline__ double skron_entry(int i, int j, int k, int l, const 
             G[i * ld + l] * H[j * ld + k]);
 }
 
-__device__ void wg_ipm(const IpmArgs a, const double *__restrict__ qp, double *state, IpmShared *sh) {
+__device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict__ qp, double *state, IpmShared *sh) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int k = a.k, d = k * (k + 1) / 2, D = d + 1, ldm = kMaxD + 1;
@@ -508,8 +557,7 @@ __device__ void wg_ipm(const IpmArgs a, const double *__restrict__ qp, double *s
                     const double *row = Q11 + (size_t)p * d;
                     for (int q = q4; q < d; q += 4) v += row[q] * sh->s[q];
                 }
-                v += __shfl_xor(v, 1, 4);
-                v += __shfl_xor(v, 2, 4);
+                v = quad_sum(v);
                 if (p < d && q4 == 0) {
                     const double vI = (sh->pi[p] == sh->pj[p]) ? 1.0 : 0.0;
                     v += sh->eta * sh->q12[p] + sh->h1[p] - sh->t[p] + sh->om * vI;

@@ -26,7 +26,8 @@ constexpr int kSyevMaxV = 16;
 struct SyevWork {
     double A[kSyevMaxN][kSyevMaxN + 1];
     double d[kSyevMaxN], e[kSyevMaxN], e2[kSyevMaxN], beta[kSyevMaxN];
-    double p[kSyevMaxN], w[kSyevMaxN];
+    double p[kSyevMaxN];
+    double vw[4][kSyevMaxN];   // per-wave copy of the current Householder vector
     double lam[kSyevMaxV];
     double X[kSyevMaxV][kSyevMaxN + 1];
     double U0[kSyevMaxV][kSyevMaxN], U1[kSyevMaxV][kSyevMaxN], U2[kSyevMaxV][kSyevMaxN];
@@ -34,16 +35,7 @@ struct SyevWork {
     double gl, gh;
 };
 
-__device__ __forceinline__ double wave_allsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double group16_sum(double v) {
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) v += __shfl_xor(v, o, 16);
-    return v;
-}
+__device__ __forceinline__ double group16_sum(double v) { return row16_sum(v); }
 
 // number of eigenvalues of the tridiagonal (d, e) strictly below x
 __device__ __forceinline__ int sturm_count(int N, const double *d, const double *e2, double x, double pivmin) {
@@ -51,6 +43,7 @@ __device__ __forceinline__ int sturm_count(int N, const double *d, const double 
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     c += (q < 0.0);
+#pragma unroll 8
     for (int i = 1; i < N; ++i) {
         q = d[i] - x - e2[i - 1] / q;
         if (fabs(q) < pivmin) q = -pivmin;
@@ -62,31 +55,30 @@ __device__ __forceinline__ int sturm_count(int N, const double *d, const double 
 // A: the N x N matrix already in ws->A (symmetric, full).  Outputs the nv largest
 // eigenvalues (descending) into lam_out[0..nv) and the first ny <= nv eigenvectors
 // into Y[r * ldy + c] (r < N).  nv, ny <= 16.  All 256 threads must call.
-__device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out, double *Y, int ldy) {
+__device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out, double *Y, int ldy) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     // ---- 1. tridiagonalisation ----
+    // Column j: every wave forms the reflector from column j itself (identical
+    // arithmetic, so all waves hold the same v) into its own LDS row vw[wave]; the
+    // rows of p = b A22 v are split over the workgroup; after one barrier every wave
+    // forms K = (b/2) p^T v and updates its rows of A22 -= v w^T + w v^T with
+    // w = p - K v.  Two barriers per column.
     for (int j = 0; j + 2 < N; ++j) {
         const int m = N - j - 1;
-        if (wave == 0) {
-            const double x0 = (lane < m) ? ws->A[j + 1 + lane][j] : 0.0;
-            const double x1 = (lane + 64 < m) ? ws->A[j + 1 + lane + 64][j] : 0.0;
-            const double nx2 = wave_allsum(x0 * x0 + x1 * x1);
-            const double xf = ws->A[j + 1][j];
-            const double nx = sqrt(nx2);
-            double alpha = (xf >= 0.0) ? -nx : nx;
-            const double vv = nx2 - xf * xf + (xf - alpha) * (xf - alpha);
-            double b = (nx2 > 0.0 && vv > 0.0) ? 2.0 / vv : 0.0;
-            if (b == 0.0) alpha = xf;
-            if (lane == 0) {
-                ws->A[j + 1][j] = xf - alpha;   // v_0; the rest of v is x itself
-                ws->beta[j] = b;
-                ws->e[j] = alpha;
-                ws->d[j] = ws->A[j][j];
-            }
-        }
-        __syncthreads();
-        const double b = ws->beta[j];
+        double *vv = ws->vw[wave];
+        const double x0 = (lane < m) ? ws->A[j + 1 + lane][j] : 0.0;
+        const double x1 = (lane + 64 < m) ? ws->A[j + 1 + lane + 64][j] : 0.0;
+        const double nx2 = wave_allsum(x0 * x0 + x1 * x1);
+        const double xf = ws->A[j + 1][j];
+        const double nx = sqrt(nx2);
+        double alpha = (xf >= 0.0) ? -nx : nx;
+        const double vn2 = nx2 - xf * xf + (xf - alpha) * (xf - alpha);
+        const double b = (nx2 > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+        if (b == 0.0) alpha = xf;
+        if (lane < m) vv[lane] = (lane == 0) ? xf - alpha : x0;
+        if (lane + 64 < m) vv[lane + 64] = x1;
+        wave_sync();
         if (b != 0.0) {
             // p = b A22 v: 4 lanes per row, each over a quarter of the columns
             {
@@ -96,33 +88,44 @@ __device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out
                     if (r < m) {
                         const double *row = &ws->A[j + 1 + r][j + 1];
 #pragma unroll 4
-                        for (int q = q4; q < m; q += 4) s += row[q] * ws->A[j + 1 + q][j];
+                        for (int q = q4; q < m; q += 4) s += row[q] * vv[q];
                     }
-                    s += __shfl_xor(s, 1, 4);
-                    s += __shfl_xor(s, 2, 4);
+                    s = quad_sum(s);
                     if (r < m && q4 == 0) ws->p[r] = b * s;
                 }
             }
             __syncthreads();
-            if (wave == 0) {
-                double pv = 0.0;
-                for (int t = lane; t < m; t += 64) pv += ws->p[t] * ws->A[j + 1 + t][j];
-                const double K = 0.5 * b * wave_allsum(pv);
-                for (int t = lane; t < m; t += 64) ws->w[t] = ws->p[t] - K * ws->A[j + 1 + t][j];
+            double pv = 0.0;
+            for (int t = lane; t < m; t += 64) pv += ws->p[t] * vv[t];
+            const double K = 0.5 * b * wave_allsum(pv);
+            // A22 -= v w^T + w v^T on a 16 x 16 thread grid; the thread's columns of v and
+            // w are held in registers
+            const int tr = tid >> 4, tc = tid & 15;
+            double vc[kSyevMaxN / 16], wc[kSyevMaxN / 16];
+#pragma unroll
+            for (int q = 0; q < kSyevMaxN / 16; ++q) {
+                const int c = tc + 16 * q;
+                vc[q] = (c < m) ? vv[c] : 0.0;
+                wc[q] = (c < m) ? ws->p[c] - K * vc[q] : 0.0;
             }
-            __syncthreads();
-            // A22 -= v w^T + w v^T on a 16 x 16 thread grid (no integer division)
-            {
-                const int tr = tid >> 4, tc = tid & 15;
-                for (int r = tr; r < m; r += 16) {
-                    const double vr = ws->A[j + 1 + r][j], wr = ws->w[r];
-                    double *row = &ws->A[j + 1 + r][j + 1];
-#pragma unroll 2
-                    for (int c = tc; c < m; c += 16) row[c] -= vr * ws->w[c] + wr * ws->A[j + 1 + c][j];
+            for (int r = tr; r < m; r += 16) {
+                const double vr = vv[r], wr = ws->p[r] - K * vv[r];
+                double *row = &ws->A[j + 1 + r][j + 1];
+#pragma unroll
+                for (int q = 0; q < kSyevMaxN / 16; ++q) {
+                    const int c = tc + 16 * q;
+                    if (c < m) row[c] -= vr * wc[q] + wr * vc[q];
                 }
             }
-            __syncthreads();
         }
+        // column j has been read by every wave (before the barrier above, or it is zero)
+        if (tid == 0) {
+            ws->A[j + 1][j] = vv[0];   // v_0; the rest of v is the column itself
+            ws->beta[j] = b;
+            ws->e[j] = alpha;
+            ws->d[j] = ws->A[j][j];
+        }
+        __syncthreads();
     }
     if (tid == 0) {
         if (N >= 2) {
@@ -159,11 +162,8 @@ __device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out
                 // lanes with count <= kidx bound the eigenvalue from below, the others from above
                 double cand_lo = (l > 0 && cnt <= kidx) ? x : -1e308;
                 double cand_hi = (l > 0 && cnt > kidx) ? x : 1e308;
-#pragma unroll
-                for (int o = 8; o > 0; o >>= 1) {
-                    cand_lo = fmax(cand_lo, __shfl_xor(cand_lo, o, 16));
-                    cand_hi = fmin(cand_hi, __shfl_xor(cand_hi, o, 16));
-                }
+                cand_lo = row16_max(cand_lo);
+                cand_hi = row16_min(cand_hi);
                 if (cand_lo > -1e308) lo = cand_lo;
                 if (cand_hi < 1e308) hi = cand_hi;
                 if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + 1e-3 * 2.2e-16 * tn) break;
@@ -173,6 +173,8 @@ __device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out
     }
     __syncthreads();
     // ---- 3. inverse iteration: lane c < ny of each wave handles vector c (wave = c / 16 spread) ----
+    // The running right-hand side entries are carried in registers; LDS holds the
+    // final entries and the rows of U only (no store-to-load chains).
     {
         const int c = (tid & 3) * 4 + (tid >> 6);   // spread vectors over the 4 waves
         const bool act = (tid & 63) < 4 && c < ny;
@@ -187,59 +189,71 @@ __device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out
                 x[i] = ((double)(st >> 8) * (1.0 / 16777216.0)) - 0.5;
             }
             for (int rep = 0; rep < 2; ++rep) {
-                // eliminate with partial pivoting; rows of U in U0/U1/U2, RHS in x
+                // eliminate T - lambda I with partial pivoting; rows of U in U0/U1/U2.
+                // Branch-free (the four lanes of a wave follow different vectors) with the
+                // next row's entries loaded one step ahead.
                 double c0 = ws->d[0] - lam, c1 = (N > 1) ? ws->e[0] : 0.0;
+                double xc = x[0];
+                double ei = (N > 1) ? ws->e[0] : 0.0, dn = (N > 1) ? ws->d[1] : 0.0;
+                double en = (N > 2) ? ws->e[1] : 0.0, xn = (N > 1) ? x[1] : 0.0;
                 for (int i = 0; i + 1 < N; ++i) {
-                    const double ei = ws->e[i];
-                    const double an = ws->d[i + 1] - lam;
-                    const double en = (i + 2 < N) ? ws->e[i + 1] : 0.0;
-                    if (fabs(c0) >= fabs(ei)) {
-                        const double piv = (c0 == 0.0) ? tiny : c0;
-                        const double mlt = ei / piv;
-                        ws->U0[c][i] = piv;
-                        ws->U1[c][i] = c1;
-                        ws->U2[c][i] = 0.0;
-                        x[i + 1] -= mlt * x[i];
-                        c0 = an - mlt * c1;
-                        c1 = en;
-                    } else {
-                        const double mlt = c0 / ei;
-                        ws->U0[c][i] = ei;
-                        ws->U1[c][i] = an;
-                        ws->U2[c][i] = en;
-                        const double xi = x[i];
-                        x[i] = x[i + 1];
-                        x[i + 1] = xi - mlt * x[i];
-                        c0 = c1 - mlt * an;
-                        c1 = -mlt * en;
-                    }
+                    // prefetch row i + 2
+                    const double ei2 = (i + 2 < N) ? ws->e[i + 1] : 0.0;
+                    const double dn2 = (i + 2 < N) ? ws->d[i + 2] : 0.0;
+                    const double en2 = (i + 3 < N) ? ws->e[i + 2] : 0.0;
+                    const double xn2 = (i + 2 < N) ? x[i + 2] : 0.0;
+                    const double an = dn - lam;
+                    const bool keep = fabs(c0) >= fabs(ei);
+                    const double piv = (c0 == 0.0) ? tiny : c0;
+                    const double mlt = keep ? ei / piv : c0 / ei;
+                    ws->U0[c][i] = keep ? piv : ei;
+                    ws->U1[c][i] = keep ? c1 : an;
+                    ws->U2[c][i] = keep ? 0.0 : en;
+                    x[i] = keep ? xc : xn;
+                    const double xnew = keep ? xn - mlt * xc : xc - mlt * xn;
+                    const double c0n = keep ? an - mlt * c1 : c1 - mlt * an;
+                    const double c1n = keep ? en : -mlt * en;
+                    xc = xnew;
+                    c0 = c0n;
+                    c1 = c1n;
+                    ei = ei2;
+                    dn = dn2;
+                    en = en2;
+                    xn = xn2;
                 }
+                x[N - 1] = xc;
                 ws->U0[c][N - 1] = (fabs(c0) < tiny) ? (c0 < 0.0 ? -tiny : tiny) : c0;
-                // back substitution
+                // back substitution with x_{i+1}, x_{i+2} carried; track max |x_i|
+                double x1 = 0.0, x2 = 0.0, mx = 0.0;
                 for (int i = N - 1; i >= 0; --i) {
                     double v = x[i];
-                    if (i + 1 < N) v -= ws->U1[c][i] * x[i + 1];
-                    if (i + 2 < N) v -= ws->U2[c][i] * x[i + 2];
-                    const double u0 = (fabs(ws->U0[c][i]) < tiny) ? (ws->U0[c][i] < 0.0 ? -tiny : tiny) : ws->U0[c][i];
-                    x[i] = v / u0;
+                    if (i + 1 < N) v -= ws->U1[c][i] * x1;
+                    if (i + 2 < N) v -= ws->U2[c][i] * x2;
+                    const double u = ws->U0[c][i];
+                    const double u0 = (fabs(u) < tiny) ? (u < 0.0 ? -tiny : tiny) : u;
+                    const double xi = v / u0;
+                    x[i] = xi;
+                    mx = fmax(mx, fabs(xi));
+                    x2 = x1;
+                    x1 = xi;
                 }
-                double s = 0.0, mx = 0.0;
-                for (int i = 0; i < N; ++i) mx = fmax(mx, fabs(x[i]));
                 const double inv = (mx > 0.0) ? 1.0 / mx : 1.0;
+                double s = 0.0;
                 for (int i = 0; i < N; ++i) {
-                    x[i] *= inv;
-                    s += x[i] * x[i];
+                    const double t = x[i] * inv;
+                    s += t * t;
                 }
-                const double nrm = 1.0 / sqrt(s);
-                for (int i = 0; i < N; ++i) x[i] *= nrm;
+                const double sc = inv / sqrt(s);
+                for (int i = 0; i < N; ++i) x[i] *= sc;
             }
         }
     }
     __syncthreads();
     // ---- 4. orthonormalise the ny vectors: Cholesky-QR twice on all threads ----
+    // G = X X^T (ny x ny), G = L L^T, X <- L^{-1} X by forward substitution along each
+    // position i (one thread per position, in place)
     for (int pass = 0; pass < 2 && ny > 1; ++pass) {
         __shared__ double G[kSyevMaxV][kSyevMaxV + 1];
-        __shared__ double Li[kSyevMaxV][kSyevMaxV + 1];
         {
             const int b2 = tid >> 4, c = tid & 15;
             if (b2 < ny && c < ny && c <= b2) {
@@ -268,33 +282,15 @@ __device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out
                 }
                 wave_sync();
             }
-            if (lane < ny) {
-                const int c = lane;
-                double x[kSyevMaxV];
-                for (int i = 0; i < kSyevMaxV; ++i) x[i] = 0.0;
-                for (int i = c; i < ny; ++i) {
-                    double v = (i == c) ? 1.0 : 0.0;
-                    for (int l = c; l < i; ++l) v -= G[i][l] * x[l];
-                    x[i] = (G[i][i] > 0.0) ? v / G[i][i] : 0.0;
-                }
-                for (int i = 0; i < ny; ++i) Li[i][c] = x[i];   // Li = L^{-1}
+        }
+        __syncthreads();
+        if (tid < N) {
+            for (int b2 = 0; b2 < ny; ++b2) {
+                double v = ws->X[b2][tid];
+                for (int l = 0; l < b2; ++l) v -= G[b2][l] * ws->X[l][tid];
+                const double g = G[b2][b2];
+                ws->X[b2][tid] = (g > 0.0) ? v / g : 0.0;
             }
-        }
-        __syncthreads();
-        // X_new[c] = sum_b Li[c][b] X[b]  (rows of L^{-1} combine the old vectors)
-        double nv_[((kSyevMaxV * kSyevMaxN) + kWG - 1) / kWG];
-        int cnt = 0;
-        for (int q = tid; q < ny * N; q += kWG) {
-            const int c = q / N, i = q - c * N;
-            double v = 0.0;
-            for (int b2 = 0; b2 <= c; ++b2) v += Li[c][b2] * ws->X[b2][i];
-            nv_[cnt++] = v;
-        }
-        __syncthreads();
-        cnt = 0;
-        for (int q = tid; q < ny * N; q += kWG) {
-            const int c = q / N, i = q - c * N;
-            ws->X[c][i] = nv_[cnt++];
         }
         __syncthreads();
     }
@@ -327,7 +323,7 @@ __device__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws, double *lam_out
 // Load the upper triangle of the global N x N matrix (ld lda) as a full symmetric
 // matrix into ws->A; rows/columns flagged in dead become decoupled with a diagonal
 // below every eigenvalue (-(2 ||A||_F + 1)).
-__device__ void wg_syev_load(int N, const double *A, int lda, const int *dead, SyevWork *ws) {
+__device__ __forceinline__ void wg_syev_load(int N, const double *A, int lda, const int *dead, SyevWork *ws) {
     const int tid = threadIdx.x;
     double s = 0.0;
     for (int q = tid; q < N * N; q += kWG) {
