@@ -105,16 +105,23 @@ def main() -> int:
     # ---- throughput: K timed iterations of Alg. 1 ----
     s = Solver(prob, prm, psi=psi, stream=stream)
     s.step_iterate(args.warmup, 11)
-    s.profile("reorth", reset=True)       # time the dominant kernel live (HIP events)
+    s.profile("reorth", reset=True)       # time the roofline kernel live (HIP events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = s.step_iterate(args.steps, 11)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     reorth_ms, reorth_launches = s.profile("spmm", reset=True)
-    # one more timed stretch for the SpMM figure (secondary)
-    s.step_iterate(max(2, args.steps // 4), 11)
-    spmm_ms, spmm_launches = s.profile(None, reset=True)
+    # two more short stretches for secondary figures: the SpMM and the Ritz eigenproblem
+    extra = max(2, args.steps // 4)
+    s.step_iterate(extra, 11)
+    spmm_ms, spmm_launches = s.profile("ritz", reset=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    s.step_iterate(extra, 11)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    ritz_ms, ritz_launches = s.profile(None, reset=True)
     s.free()
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -131,7 +138,8 @@ def main() -> int:
                "rel_gap": out["rel_gap"], "rel_infeas": out["rel_infeas"], "primal_obj": out["primal_obj"],
                "dual_bound": out["dual_bound"], "lanczos_matvecs": out["lanczos_matvecs"]}
 
-    # ---- roofline of the dominant kernel (re-orthogonalisation reductions) ----
+    # ---- roofline of the dominant bandwidth kernel (first stage of the re-orthogonalisation
+    # reductions, k_tn_reduce<double, 1>) ----
     # algorithmic bytes per launch averaged over the basis widths of a restart cycle
     # (block j of 8 reduces against 16 + 8 (j + 1) columns, j = 0..7)
     widths = [16 + 8 * (j + 1) for j in range(8)]
@@ -158,7 +166,7 @@ def main() -> int:
                    "rho": args.rho, "k_c": 10, "k_p": 1, "lanczos_steps": 8, "precision": args.precision},
         "time_to_gap": ttg,
         "roofline": {
-            "bound": "hbm", "kernel": "k_tn_reduce (B^T W of the block re-orthogonalisation)",
+            "bound": "hbm", "kernel": "k_tn_reduce<double, 1> (first stage of B^T W in the Krylov re-orthogonalisation)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
             "avg_launch_us": avg_reorth_s * 1e6, "launches": reorth_launches,
@@ -166,6 +174,11 @@ def main() -> int:
         },
         "spmm": {"avg_launch_us": avg_spmm_s * 1e6, "achieved_GBs": spmm_gbs, "launches": spmm_launches,
                  "bytes_per_launch": spmm_bytes(n, nnz_off, 8, val_bytes)},
+        # the largest single share of kernel time: the one-workgroup Rayleigh-Ritz eigensolver
+        # (latency-bound: one CU, a few hundred dependent Householder / bisection steps)
+        "ritz": {"kernel": "k_small_eig (80 x 80 projected eigenproblem)",
+                 "avg_launch_us": 1e3 * ritz_ms / max(ritz_launches, 1), "launches": ritz_launches,
+                 "share_of_step_time": (ritz_ms / 1e3) / max(t3 - t2, 1e-12)},
         "final_state": {"f": st["f"], "rel_gap": st["rel_gap"], "rel_infeas": st["rel_infeas"]},
     }
     if not args.no_cpu:

@@ -200,7 +200,7 @@ int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *z
  * the category being timed (optionally resetting them), then times 'category' from now
  * on (-1 = none).  Used by the benchmark for the roofline of the dominant kernel. */
 #define USBS_PROF_SPMM 0   /* (C - A^* y) X block products                    */
-#define USBS_PROF_REORTH 1 /* B^T W reductions of the block re-orthogonalisation */
+#define USBS_PROF_REORTH 1 /* first stage of the B^T W reductions of the Krylov block re-orthogonalisation (kernel k_tn_reduce<double, 1>; the finisher is not included) */
 #define USBS_PROF_RITZ 2   /* projected (Rayleigh-Ritz) eigenproblem          */
 #define USBS_PROF_IPM 3    /* master-QP interior point solve                  */
 #define USBS_PROF_COUNT 4
@@ -208,6 +208,63 @@ int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_tot
 
 /* Scaling factors of the handle's problem: sigma = ||C||_F, trace. */
 int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace);
+
+/* Upper bound of the device memory (bytes) that usbs_create allocates for this
+ * problem and these parameters (used by the server's admission test); < 0 on
+ * malformed input. */
+int64_t usbs_footprint_bytes(const usbs_problem *prob, const usbs_params *prm);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching on one GPU.
+ *
+ * A request is one SDP instance, optionally with a grown version of it (more
+ * vertices / rows appended, as in the incremental setting of Sec. 5.1) that is
+ * warm-started (usbs_warm_start) from the first solve's resident state.  The
+ * server owns `slots` worker threads, each with its own non-blocking HIP stream
+ * of default priority.  A free slot admits the first queued request (arrival
+ * order) whose usbs_footprint_bytes fits in the remaining HBM budget, so work
+ * of several instances overlaps on the device and new arrivals join as slots
+ * and memory free up.  Results do not depend on the mix: each request's
+ * computation reads only its own data and every kernel is deterministic.
+ * Times are seconds since usbs_server_create.
+ * ------------------------------------------------------------------------ */
+typedef struct usbs_server usbs_server;
+
+typedef struct usbs_server_config {
+    int32_t slots;            /* instances on the device at once, 1..64                */
+    int64_t hbm_budget_bytes; /* admission limit on summed footprints; <= 0: 90% of the
+                                 free device memory at creation                      */
+    usbs_params params;       /* parameters of every solve (the stream field is ignored) */
+} usbs_server_config;
+
+typedef struct usbs_served_result {
+    usbs_result base;         /* the solve of the submitted instance                 */
+    usbs_result grown;        /* the warm-started solve of the grown instance         */
+    int32_t status_base, status_grown, has_grown, slot;
+    int64_t footprint_bytes;
+    double t_submit, t_admit, t_base_done, t_done;
+} usbs_served_result;
+
+typedef struct usbs_server_stats {
+    int64_t queued, running, peak_running, completed;
+    int64_t budget_bytes, used_bytes, peak_used_bytes;
+    double seconds;
+} usbs_server_stats;
+
+/* Start the worker threads on the current device. */
+int usbs_server_create(const usbs_server_config *cfg, usbs_server **out);
+/* Queue a request (deep copy of both problems; grown may be NULL).  Returns
+ * USBS_E_NOMEM if its footprint exceeds the whole budget. */
+int usbs_server_submit(usbs_server *sv, const usbs_problem *prob, const usbs_problem *grown,
+                       int64_t *request_id);
+/* Block until the request is done and return its results (once per request).
+ * The return value is the first negative status of its solves, else USBS_OK
+ * (per-solve statuses, including USBS_NOT_CONVERGED, are in *out). */
+int usbs_server_wait(usbs_server *sv, int64_t request_id, usbs_served_result *out);
+int usbs_server_get_stats(usbs_server *sv, usbs_server_stats *out);
+const char *usbs_server_last_error(const usbs_server *sv);
+/* Finish every queued and running request, stop the workers, release the server. */
+void usbs_server_free(usbs_server *sv);
 
 #ifdef __cplusplus
 }

@@ -50,6 +50,12 @@ void convert_values(hipStream_t s, int prec, int nnz, const double *src, double 
 void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,
                const double *B, int ldb, int cb, double *H, int ldh, double alpha, double beta,
                int post = 0, int *flags = nullptr, const double *floor_ref = nullptr);
+// the same product for the Krylov re-orthogonalisation, split into its first stage
+// (per-workgroup partials; returns the number of partials) and the finisher.  With
+// both events given, they record the first stage's own start and end (timing).
+int reorth_partials(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
+                    int ldb, int cb, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int cb, double *H, int ldh);
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,
                  const float *B, int ldb, int cb, double *H, int ldh, double alpha);
 // C[i*ldc + c] = beta*C + alpha * sum_a A[i*lda + a] * H[a*ldh + c]   (c < cc <= 16, ca <= 80)

@@ -11,6 +11,7 @@
 #include "syev.h"
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 namespace usbs {
@@ -328,7 +329,9 @@ constexpr int kMaxCB = 32;
 constexpr int kMaxOut = kMaxBasis * 16;          // 1280 outputs (also >= 32 x 32)
 constexpr int kOutPerThread = (kMaxOut + kWG - 1) / kWG;
 
-template <typename TB>
+// TAG only names the instantiation: 1 = the Krylov re-orthogonalisation (its own
+// symbol, so that profilers report those launches separately)
+template <typename TB, int TAG>
 __global__ __launch_bounds__(kWG) void k_tn_reduce(int n, const double *__restrict__ A, int lda, int ca,
                                                    const TB *__restrict__ B, int ldb, int cb,
                                                    double *__restrict__ partials) {
@@ -383,15 +386,30 @@ void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int 
                int ldb, int cb, double *H, int ldh, double alpha, double beta, int post, int *flags,
                const double *floor_ref) {
     const int blocks = tn_blocks(rs, n);
-    hipLaunchKernelGGL((k_tn_reduce<double>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    hipLaunchKernelGGL((k_tn_reduce<double, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
     if (post == 0) red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, beta);
     else hipLaunchKernelGGL(k_cholqr_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, ca, H, ldh, flags, floor_ref);
+}
+
+int reorth_partials(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
+                    int ldb, int cb, hipEvent_t ev_start, hipEvent_t ev_stop) {
+    const int blocks = tn_blocks(rs, n);
+    if (ev_start && ev_stop)   // events carry this dispatch's own start / end time
+        hipExtLaunchKernelGGL((k_tn_reduce<double, 1>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A,
+                              lda, ca, B, ldb, cb, rs.partials);
+    else
+        hipLaunchKernelGGL((k_tn_reduce<double, 1>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
+                           rs.partials);
+    return blocks;
+}
+void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int cb, double *H, int ldh) {
+    red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, 1.0, 0.0);
 }
 
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const float *B,
                  int ldb, int cb, double *H, int ldh, double alpha) {
     const int blocks = tn_blocks(rs, n);
-    hipLaunchKernelGGL((k_tn_reduce<float>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    hipLaunchKernelGGL((k_tn_reduce<float, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
     red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, 0.0);
 }
 

@@ -142,6 +142,18 @@ struct ProfScope {
     }
 };
 
+// event pair for a launch that records its own start / end (hipExtLaunchKernelGGL)
+struct ProfPair {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ProfPair(usbs_handle *h, int cat) {
+        if (h->prof_cat != cat) return;
+        if (h->ev_used + 2 > h->ev_pool.size()) return;
+        e0 = h->ev_pool[h->ev_used];
+        e1 = h->ev_pool[h->ev_used + 1];
+        h->ev_used += 2;
+    }
+};
+
 void prof_flush(usbs_handle *h) {
     if (h->ev_used == 0) return;
     (void)hipEventSynchronize(h->ev_pool[h->ev_used - 1]);
@@ -576,15 +588,20 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         for (int j = 0; j < steps; ++j) {
             const int c0 = 16 + 8 * j, cols = c0 + 8;
             apply_op(h, h->Bm + c0, ldb, h->W, 8, 8);
+            int g;
             {
-                ProfScope ps(h, USBS_PROF_REORTH);
-                tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Tm + c0, ldb, 1.0, 0.0);
+                if (h->ev_used + 2 > h->ev_pool.size()) prof_flush(h);
+                ProfPair pp(h, USBS_PROF_REORTH);
+                g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, pp.e0, pp.e1);
             }
+            reorth_finish(s, h->rs, g, cols, 8, h->Tm + c0, ldb);
             nn_update(s, n, h->Bm, ldb, cols, h->Tm + c0, ldb, 8, h->W, 8, -1.0, 1.0);
             {
-                ProfScope ps(h, USBS_PROF_REORTH);
-                tn_reduce(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, h->Hred, 8, 1.0, 0.0);
+                if (h->ev_used + 2 > h->ev_pool.size()) prof_flush(h);
+                ProfPair pp(h, USBS_PROF_REORTH);
+                g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, pp.e0, pp.e1);
             }
+            reorth_finish(s, h->rs, g, cols, 8, h->Hred, 8);
             nn_update(s, n, h->Bm, ldb, cols, h->Hred, 8, 8, h->W, 8, -1.0, 1.0);
             add_small(s, cols, 8, h->Hred, 8, h->Tm + c0, ldb);
             if (j < steps - 1) cholqr2(h, h->W, 8, 8, h->Wt, 8, h->Bm + cols, ldb, h->dead + cols);
@@ -952,7 +969,8 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
         }
         if (y_out) {
             std::vector<double> yv(h->m);
-            HIPCHK(hipMemcpy(yv.data(), h->y, h->m * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpyAsync(yv.data(), h->y, h->m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
             for (int q = 0; q < h->m; ++q) y_out[q] = h->sigma * yv[q];
         }
         if ((U_out || lam_out || res) && h->sketch && h->r > 0) {
@@ -997,7 +1015,8 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
                 for (int j = 0; j < r; ++j) lam_out[j] = h->trace * lam[j];
             if (U_out) {
                 std::vector<double> U((size_t)n * 16);
-                HIPCHK(hipMemcpy(U.data(), h->Zp, (size_t)n * 16 * sizeof(double), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpyAsync(U.data(), h->Zp, (size_t)n * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
                 for (int i = 0; i < n; ++i)
                     for (int j = 0; j < r; ++j) U_out[(size_t)i * r + j] = U[(size_t)i * 16 + j];
             }
@@ -1041,6 +1060,34 @@ int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_tot
 }
 
 const char *usbs_last_error(const usbs_handle *h) { return h ? h->err.c_str() : "NULL handle"; }
+
+int64_t usbs_footprint_bytes(const usbs_problem *p, const usbs_params *prm) {
+    if (!p || !prm || p->n < 1 || p->m < 1 || !p->rowptr || (p->n_triplets > 0 && (!p->a_i || !p->a_j)))
+        return -1;
+    const int64_t n = p->n, m = p->m, nt = p->n_triplets;
+    const int64_t nnzC = p->rowptr[n];
+    if (nnzC < 0) return -1;
+    int64_t offt = 0;
+    for (int64_t t = 0; t < nt; ++t) offt += (p->a_i[t] != p->a_j[t]);
+    const int64_t diagt = nt - offt;
+    const int64_t nnz = nnzC + 2 * offt;   // bound on the off-diagonal pattern
+    const int64_t vsz = prm->precision == USBS_PREC_F64 ? 8 : (prm->precision == USBS_PREC_F32 ? 4 : 2);
+    const int64_t r = p->psi ? std::max(prm->r, 0) : 0;
+    int64_t b = 0;
+    // operator and constraints
+    b += 4 * (n + 1) + 4 * nnz + 8 * nnz + 2 * vsz * nnz + 8 * 2 * n + 4 * (n + 1);
+    b += 12 * diagt + 16 * 2 * offt + 4 * (m + 1) + 16 * nt + 16 * m + 4 * n * r;
+    // iteration state and Lanczos work (see upload)
+    b += 8 * 7 * m;
+    b += 8 * n * 16 * 7;                       // V, Vn, CV, Uritz, Ucpl, Ubuf, Zp
+    b += 8 * n * std::max<int64_t>(r, 1);     // sketch
+    b += 8 * n * kMaxBasis + 8 * n * 8 * 2 + 8 * n * 32;
+    // reduction partials and small matrices
+    const int64_t max_elems = std::max<int64_t>(kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec, kMaxBasis * 16);
+    b += 8 * (int64_t)kRedMaxBlocks * max_elems;
+    b += 8 * (4096 + 6 * 1024 + 8 * kMaxSvec * kMaxSvec) + 4 * 256;
+    return b + b / 20 + (1 << 20);   // allocator rounding
+}
 
 int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace) {
     if (!h || !h->ready) return USBS_E_STATE;
@@ -1167,7 +1214,8 @@ int usbs_op_qp_data(usbs_handle *h, const double *V_dev, int32_t k, const double
         std::vector<double> out(d * d + 2 * d + 2);
         HIPCHK(hipMemcpyAsync(out.data(), h->qp, out.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        HIPCHK(hipMemcpy(h->sc, save.data(), SC_COUNT * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync(h->sc, save.data(), SC_COUNT * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
         if (Q11) std::memcpy(Q11, out.data(), d * d * sizeof(double));
         if (q12) std::memcpy(q12, out.data() + d * d, d * sizeof(double));
         if (q22) *q22 = out[d * d + d];
@@ -1348,7 +1396,8 @@ int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
             HIPCHK(hipStreamSynchronize(s));
             for (int j = 0; j < r; ++j) cbar += K[j * r + j] * uc[j * r + j];
             std::vector<double> Ut(r * r);
-            HIPCHK(hipMemcpy(Ut.data(), h->VtPsi, r * r * sizeof(double), hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpyAsync(Ut.data(), h->VtPsi, r * r * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
             for (int j = 0; j < r; ++j)
                 for (int c = 0; c < r; ++c) Ut[j * r + c] *= K[j * r + j];
             HIPCHK(hipMemcpyAsync(h->Hsk, Ut.data(), r * r * sizeof(double), hipMemcpyHostToDevice, s));

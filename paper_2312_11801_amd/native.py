@@ -28,6 +28,8 @@ EXPORTS = [
     "usbs_default_params", "usbs_create", "usbs_solve", "usbs_warm_start", "usbs_free", "usbs_last_error",
     "usbs_op_apply", "usbs_op_eigs", "usbs_op_lowrank_A", "usbs_op_sketch_update", "usbs_op_qp_data",
     "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling", "usbs_profile",
+    "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
+    "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free",
 ]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
 
@@ -71,6 +73,28 @@ class UsbsResult(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class UsbsServerConfig(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64), ("params", UsbsParams)]
+
+
+class UsbsServedResult(ctypes.Structure):
+    _fields_ = [
+        ("base", UsbsResult), ("grown", UsbsResult),
+        ("status_base", ctypes.c_int32), ("status_grown", ctypes.c_int32), ("has_grown", ctypes.c_int32),
+        ("slot", ctypes.c_int32), ("footprint_bytes", ctypes.c_int64),
+        ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_base_done", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
+
+
+class UsbsServerStats(ctypes.Structure):
+    _fields_ = [
+        ("queued", ctypes.c_int64), ("running", ctypes.c_int64), ("peak_running", ctypes.c_int64),
+        ("completed", ctypes.c_int64), ("budget_bytes", ctypes.c_int64), ("used_bytes", ctypes.c_int64),
+        ("peak_used_bytes", ctypes.c_int64), ("seconds", ctypes.c_double),
+    ]
+
+
 _LIB = None
 
 
@@ -102,6 +126,14 @@ def load_library(path: str | None = None):
         "usbs_step_iterate": (ctypes.c_int, [vp, i32, vp, vp, vp, vp, vp]),
         "usbs_get_scaling": (ctypes.c_int, [vp, vp, vp]),
         "usbs_profile": (ctypes.c_int, [vp, i32, i32, vp, vp]),
+        "usbs_footprint_bytes": (ctypes.c_int64, [ctypes.POINTER(UsbsProblem), ctypes.POINTER(UsbsParams)]),
+        "usbs_server_create": (ctypes.c_int, [ctypes.POINTER(UsbsServerConfig), ctypes.POINTER(vp)]),
+        "usbs_server_submit": (ctypes.c_int, [vp, ctypes.POINTER(UsbsProblem), ctypes.POINTER(UsbsProblem),
+                                              ctypes.POINTER(i64)]),
+        "usbs_server_wait": (ctypes.c_int, [vp, i64, ctypes.POINTER(UsbsServedResult)]),
+        "usbs_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(UsbsServerStats)]),
+        "usbs_server_last_error": (ctypes.c_char_p, [vp]),
+        "usbs_server_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -306,5 +338,67 @@ class Solver:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+def footprint_bytes(prob, params: Params | None = None, psi=None) -> int:
+    """Device bytes usbs_create would allocate at most for this problem."""
+    lib = load_library()
+    arrs = _ProblemArrays(prob, psi)
+    cp = (params or Params()).to_c(None)
+    return int(lib.usbs_footprint_bytes(ctypes.byref(arrs.c), ctypes.byref(cp)))
+
+
+class Server:
+    """Request loop with continuous batching on the current GPU (usbs_server_*).
+
+    submit() queues an instance (and optionally its grown version, warm-started from the
+    first solve's resident state); wait() returns the results and the request's times
+    (seconds since the server started): submit, admit, base solve done, done."""
+
+    def __init__(self, slots: int = 4, params: Params | None = None, hbm_budget_bytes: int = 0):
+        self.lib = load_library()
+        self.params = params or Params()
+        cfg = UsbsServerConfig(slots=slots, hbm_budget_bytes=hbm_budget_bytes, params=self.params.to_c(None))
+        h = ctypes.c_void_p()
+        rc = self.lib.usbs_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if rc != 0:
+            raise UsbsError(rc, "usbs_server_create failed")
+        self.h = h
+
+    def submit(self, prob, psi=None, grown=None, psi_grown=None) -> int:
+        a = _ProblemArrays(prob, psi)
+        g = None if grown is None else _ProblemArrays(grown, psi_grown)
+        rid = ctypes.c_int64()
+        rc = self.lib.usbs_server_submit(self.h, ctypes.byref(a.c), None if g is None else ctypes.byref(g.c),
+                                         ctypes.byref(rid))
+        if rc != 0:
+            raise UsbsError(rc, self.lib.usbs_server_last_error(self.h).decode())
+        return rid.value
+
+    def wait(self, rid: int) -> dict:
+        out = UsbsServedResult()
+        rc = self.lib.usbs_server_wait(self.h, rid, ctypes.byref(out))
+        if rc < 0:
+            raise UsbsError(rc, self.lib.usbs_server_last_error(self.h).decode())
+        d = {k: getattr(out, k) for k, _ in UsbsServedResult._fields_ if k not in ("base", "grown")}
+        d["base"] = out.base.as_dict()
+        d["grown"] = out.grown.as_dict() if out.has_grown else None
+        return d
+
+    def stats(self) -> dict:
+        st = UsbsServerStats()
+        self.lib.usbs_server_get_stats(self.h, ctypes.byref(st))
+        return {k: getattr(st, k) for k, _ in UsbsServerStats._fields_}
+
+    def close(self) -> None:
+        if self.h is not None:
+            self.lib.usbs_server_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

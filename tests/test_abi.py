@@ -32,7 +32,9 @@ def test_struct_layout_matches_header():
     from paper_2312_11801_amd import native
     src = open(os.path.join(ROOT, "include", "usbs.h")).read()
     for cname, py in (("usbs_problem", native.UsbsProblem), ("usbs_params", native.UsbsParams),
-                      ("usbs_result", native.UsbsResult)):
+                      ("usbs_result", native.UsbsResult), ("usbs_server_config", native.UsbsServerConfig),
+                      ("usbs_served_result", native.UsbsServedResult),
+                      ("usbs_server_stats", native.UsbsServerStats)):
         body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (cname, cname), src, re.S).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         names = []
@@ -55,3 +57,16 @@ def test_default_params_call_is_host_only():
     p = UsbsParams()
     assert lib.usbs_default_params(ctypes.byref(p)) == 0
     assert (p.alpha, p.rho, p.beta, p.k_c, p.k_p, p.r) == (2.0, 0.01, 0.25, 10, 1, 10)
+
+
+def test_footprint_is_host_only_and_monotone():
+    """usbs_footprint_bytes (the server's admission estimate) is a host computation that
+    grows with n and covers the n x 80 FP64 Lanczos basis."""
+    from paper_2312_11801_amd.native import LIB_PATH, footprint_bytes, Params
+    import sdp_inputs as si
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("libusbs.so not built")
+    a = footprint_bytes(si.maxcut_er(500, 0.02, seed=0), Params())
+    b = footprint_bytes(si.maxcut_er(2000, 0.005, seed=0), Params())
+    assert 0 < a < b
+    assert b > 2000 * 80 * 8
