@@ -55,12 +55,24 @@ void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int 
 // both events given, they record the first stage's own start and end (timing).
 int reorth_partials(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
                     int ldb, int cb, hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+// (the first stage computes [A B]^T B: A^T B followed by the Gram matrix B^T B; the
+// finisher writes those (ca + cb) x cb values to H)
 void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int cb, double *H, int ldh);
+// one pass of block Gram-Schmidt with Pythagorean inner products from Hg = [Q W]^T W
+// ((cols + 8) x 8): coef ((cols + 8) x 8) = [-H R^{-1}; R^{-1}] with Omega = G - H^T H = R^T R
+// (deflated columns flagged in flags[0..8) if not null, floor 1e-10 * *floor_ref if not
+// null); pass 0 writes T (cols x 8, ldt) = H and saves R; pass 1 adds H * R_saved to T.
+void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave, double *T, int ldt,
+              double *coef, int *flags, const double *floor_ref);
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,
                  const float *B, int ldb, int cb, double *H, int ldh, double alpha);
 // C[i*ldc + c] = beta*C + alpha * sum_a A[i*lda + a] * H[a*ldh + c]   (c < cc <= 16, ca <= 80)
 void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
                int cc, double *C, int ldc, double alpha, double beta);
+// C (n x cc, ldc) = [A A2] H with a second source A2 (n x ca2, ca2 <= 8) whose rows
+// follow A's in H (H is (ca + ca2) x cc); C must not alias A or A2
+void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2, int ca2,
+                const double *H, int ldh, int cc, double *C, int ldc);
 // same with a float32 destination (sketch storage)
 void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
                  int cc, float *C, int ldc, double alpha, double beta);

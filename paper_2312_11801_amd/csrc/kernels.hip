@@ -330,15 +330,17 @@ constexpr int kMaxOut = kMaxBasis * 16;          // 1280 outputs (also >= 32 x 3
 constexpr int kOutPerThread = (kMaxOut + kWG - 1) / kWG;
 
 // TAG only names the instantiation: 1 = the Krylov re-orthogonalisation (its own
-// symbol, so that profilers report those launches separately)
-template <typename TB, int TAG>
+// symbol, so that profilers report those launches separately).  GRAM: the outputs are
+// [A B]^T B ((ca + cb) x cb), i.e. A^T B followed by the Gram matrix B^T B.
+template <typename TB, int TAG, bool GRAM>
 __global__ __launch_bounds__(kWG) void k_tn_reduce(int n, const double *__restrict__ A, int lda, int ca,
                                                    const TB *__restrict__ B, int ldb, int cb,
                                                    double *__restrict__ partials) {
-    __shared__ double sA[kTile][kMaxBasis + 1];
+    __shared__ double sA[kTile][kMaxBasis + kBlk + 1];
     __shared__ double sB[kTile][kMaxCB + 1];
     const int tid = threadIdx.x;
-    const int nout = ca * cb;
+    const int rows_out = GRAM ? ca + cb : ca;
+    const int nout = rows_out * cb;
     double acc[kOutPerThread];
 #pragma unroll
     for (int q = 0; q < kOutPerThread; ++q) acc[q] = 0.0;
@@ -352,7 +354,9 @@ __global__ __launch_bounds__(kWG) void k_tn_reduce(int n, const double *__restri
         for (int e = tid; e < kTile * cb; e += kWG) {
             const int r = e / cb, c = e - r * cb;
             const long i = row0 + r;
-            sB[r][c] = (i < n) ? (double)B[i * ldb + c] : 0.0;
+            const double v = (i < n) ? (double)B[i * ldb + c] : 0.0;
+            sB[r][c] = v;
+            if (GRAM) sA[r][ca + c] = v;
         }
         __syncthreads();
 #pragma unroll
@@ -386,7 +390,7 @@ void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int 
                int ldb, int cb, double *H, int ldh, double alpha, double beta, int post, int *flags,
                const double *floor_ref) {
     const int blocks = tn_blocks(rs, n);
-    hipLaunchKernelGGL((k_tn_reduce<double, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    hipLaunchKernelGGL((k_tn_reduce<double, 0, false>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
     if (post == 0) red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, beta);
     else hipLaunchKernelGGL(k_cholqr_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, ca, H, ldh, flags, floor_ref);
 }
@@ -395,21 +399,93 @@ int reorth_partials(hipStream_t s, const RedScratch &rs, int n, const double *A,
                     int ldb, int cb, hipEvent_t ev_start, hipEvent_t ev_stop) {
     const int blocks = tn_blocks(rs, n);
     if (ev_start && ev_stop)   // events carry this dispatch's own start / end time
-        hipExtLaunchKernelGGL((k_tn_reduce<double, 1>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A,
+        hipExtLaunchKernelGGL((k_tn_reduce<double, 1, true>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A,
                               lda, ca, B, ldb, cb, rs.partials);
     else
-        hipLaunchKernelGGL((k_tn_reduce<double, 1>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
+        hipLaunchKernelGGL((k_tn_reduce<double, 1, true>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
                            rs.partials);
     return blocks;
 }
 void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int cb, double *H, int ldh) {
-    red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, 1.0, 0.0);
+    red_finish(s, rs.partials, blocks, (ca + cb) * cb, H, cb, ldh, 1.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// One pass of block Gram-Schmidt with Pythagorean inner products (one
+// workgroup), from Hg = [Q W]^T W: rows 0..cols-1 hold H = Q^T W, rows
+// cols..cols+7 hold G = W^T W.  With Q^T Q = I,
+//   Omega = G - H^T H = (W - Q H)^T (W - Q H) = R^T R   (Cholesky, deflation)
+//   coef  = [-H R^{-1}; R^{-1}]  so that  [Q W] coef = (W - Q H) R^{-1}.
+// The projections of the block that entered the first pass are H1 + H2 R1
+// (W0 = Q H1 + W1 R1, W1 = Q H2 + W2 R2): pass 0 stores H into T and keeps R;
+// pass 1 adds H R_saved.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_pip_chol(const double *__restrict__ Hg, int cols, int pass,
+                                                  double *__restrict__ Rsave, double *__restrict__ T, int ldt,
+                                                  double *__restrict__ coef, int *flags,
+                                                  const double *__restrict__ floor_ref) {
+    __shared__ double sH[kMaxBasis][kBlk];
+    __shared__ double sOm[kBlk * 17];
+    __shared__ double sRi[kBlk * kBlk];
+    __shared__ double sR[kBlk][kBlk];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < cols * kBlk; e += kWG) sH[e / kBlk][e % kBlk] = Hg[e];
+    if (tid < kBlk * kBlk) {
+        sR[tid / kBlk][tid % kBlk] = (pass == 1) ? Rsave[tid] : 0.0;
+    }
+    __syncthreads();
+    if (tid < kBlk * kBlk) {
+        const int i = tid / kBlk, j = tid % kBlk;
+        double sacc = 0.0;
+        for (int a = 0; a < cols; ++a) sacc += sH[a][i] * sH[a][j];
+        sOm[i * 17 + j] = Hg[(cols + i) * kBlk + j] - sacc;
+    }
+    // projections of the original block into T
+    for (int e = tid; e < cols * kBlk; e += kWG) {
+        const int a = e / kBlk, c = e % kBlk;
+        if (pass == 0) {
+            T[a * ldt + c] = sH[a][c];
+        } else {
+            double v = 0.0;
+            for (int k = 0; k <= c; ++k) v += sH[a][k] * sR[k][c];
+            T[a * ldt + c] += v;
+        }
+    }
+    __syncthreads();
+    double f2 = 0.0;
+    if (floor_ref) {
+        const double rf = 1e-10 * (*floor_ref);
+        f2 = rf * rf;
+    }
+    if (tid < 64) wave_cholqr(kBlk, sOm, 17, sRi, kBlk, flags, f2);
+    __syncthreads();
+    // R = L^T (upper) of this pass, kept for the correction of the next pass
+    if (pass == 0 && tid < kBlk * kBlk) {
+        const int i = tid / kBlk, j = tid % kBlk;
+        Rsave[tid] = (j >= i) ? sOm[j * 17 + i] : 0.0;
+    }
+    for (int e = tid; e < (cols + kBlk) * kBlk; e += kWG) {
+        const int a = e / kBlk, c = e % kBlk;
+        double v;
+        if (a < cols) {
+            v = 0.0;
+            for (int k = 0; k < kBlk; ++k) v -= sH[a][k] * sRi[k * kBlk + c];
+        } else {
+            v = sRi[(a - cols) * kBlk + c];
+        }
+        coef[e] = v;
+    }
+}
+void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave, double *T, int ldt,
+              double *coef, int *flags, const double *floor_ref) {
+    hipLaunchKernelGGL(k_pip_chol, dim3(1), dim3(kWG), 0, s, Hg, cols, pass, Rsave, T, ldt, coef, flags,
+                       floor_ref);
 }
 
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const float *B,
                  int ldb, int cb, double *H, int ldh, double alpha) {
     const int blocks = tn_blocks(rs, n);
-    hipLaunchKernelGGL((k_tn_reduce<float, 0>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    hipLaunchKernelGGL((k_tn_reduce<float, 0, false>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
     red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, 0.0);
 }
 
@@ -417,15 +493,19 @@ void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, in
 // C = beta*C + alpha*A H : rows of A staged through LDS, H (ca x cc) in LDS,
 // L lanes per output row.
 // ---------------------------------------------------------------------------
+// C = beta*C + alpha*[A A2] H with an optional second source A2 (n x ca2, ca2 <= 8):
+// the rows of both are staged side by side in LDS.
 template <typename TC, int L>
 __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restrict__ A, int lda, int ca,
+                                                   const double *__restrict__ A2, int lda2, int ca2,
                                                    const double *__restrict__ H, int ldh, int cc,
                                                    TC *__restrict__ C, int ldc, double alpha, double beta) {
     constexpr int R = kWG / L;  // rows per workgroup
-    __shared__ double sH[kMaxBasis * 16];
-    __shared__ double sA[R][kMaxBasis + 1];
+    __shared__ double sH[(kMaxBasis + kBlk) * 16];
+    __shared__ double sA[R][kMaxBasis + kBlk + 1];
     const int tid = threadIdx.x;
-    for (int e = tid; e < ca * cc; e += kWG) {
+    const int ct = ca + ca2;
+    for (int e = tid; e < ct * cc; e += kWG) {
         const int a = e / cc, c = e - a * cc;
         sH[e] = H[a * ldh + c];
     }
@@ -435,39 +515,49 @@ __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restri
         const long i = row0 + r;
         sA[r][a] = (i < n) ? A[i * lda + a] : 0.0;
     }
+    for (int e = tid; e < R * ca2; e += kWG) {
+        const int r = e / ca2, a = e - r * ca2;
+        const long i = row0 + r;
+        sA[r][ca + a] = (i < n) ? A2[i * lda2 + a] : 0.0;
+    }
     __syncthreads();
     const int r = tid / L, c = tid % L;
     const long i = row0 + r;
     if (i >= n || c >= cc) return;
     double s = 0.0;
-    for (int a = 0; a < ca; ++a) s += sA[r][a] * sH[a * cc + c];
+    for (int a = 0; a < ct; ++a) s += sA[r][a] * sH[a * cc + c];
     double v = alpha * s;
     if (beta != 0.0) v += beta * (double)C[i * ldc + c];
     C[i * ldc + c] = (TC)v;
 }
 
 template <typename TC>
-static void nn_update_t(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
-                        int cc, TC *C, int ldc, double alpha, double beta) {
+static void nn_update_t(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2,
+                        int ca2, const double *H, int ldh, int cc, TC *C, int ldc, double alpha, double beta) {
     if (n <= 0 || cc <= 0) return;
     if (cc <= 4)
-        hipLaunchKernelGGL((k_nn_update<TC, 4>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, A, lda, ca, H, ldh,
-                           cc, C, ldc, alpha, beta);
+        hipLaunchKernelGGL((k_nn_update<TC, 4>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
+                           ca2, H, ldh, cc, C, ldc, alpha, beta);
     else if (cc <= 8)
-        hipLaunchKernelGGL((k_nn_update<TC, 8>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, A, lda, ca, H, ldh,
-                           cc, C, ldc, alpha, beta);
+        hipLaunchKernelGGL((k_nn_update<TC, 8>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
+                           ca2, H, ldh, cc, C, ldc, alpha, beta);
     else
-        hipLaunchKernelGGL((k_nn_update<TC, 16>), dim3(cdiv(n, kWG / 16)), dim3(kWG), 0, s, n, A, lda, ca, H,
-                           ldh, cc, C, ldc, alpha, beta);
+        hipLaunchKernelGGL((k_nn_update<TC, 16>), dim3(cdiv(n, kWG / 16)), dim3(kWG), 0, s, n, A, lda, ca, A2,
+                           lda2, ca2, H, ldh, cc, C, ldc, alpha, beta);
+}
+
+void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2, int ca2,
+                const double *H, int ldh, int cc, double *C, int ldc) {
+    nn_update_t<double>(s, n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, 1.0, 0.0);
 }
 
 void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
                double *C, int ldc, double alpha, double beta) {
-    nn_update_t<double>(s, n, A, lda, ca, H, ldh, cc, C, ldc, alpha, beta);
+    nn_update_t<double>(s, n, A, lda, ca, nullptr, 0, 0, H, ldh, cc, C, ldc, alpha, beta);
 }
 void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
                  float *C, int ldc, double alpha, double beta) {
-    nn_update_t<float>(s, n, A, lda, ca, H, ldh, cc, C, ldc, alpha, beta);
+    nn_update_t<float>(s, n, A, lda, ca, nullptr, 0, 0, H, ldh, cc, C, ldc, alpha, beta);
 }
 
 __global__ void k_copy_cols(int n, const double *__restrict__ A, int lda, int cc, double *__restrict__ C,

@@ -97,6 +97,7 @@ struct usbs_handle {
     double *Bm = nullptr, *W = nullptr, *Wt = nullptr, *W2 = nullptr, *Ubuf = nullptr;
     double *Tm = nullptr, *theta = nullptr, *Ysm = nullptr, *TUU = nullptr, *RtR = nullptr, *Zc = nullptr,
            *Hred = nullptr, *Rinv = nullptr, *res = nullptr, *Hd = nullptr;
+    double *Hg = nullptr, *coef = nullptr, *Rsv = nullptr;   // block Gram-Schmidt (Pythagorean) work
     int *dead = nullptr, *flag = nullptr;
     // QP / model
     double *raw = nullptr, *qp = nullptr, *ipm = nullptr, *VCV = nullptr, *Gy = nullptr, *Kc = nullptr,
@@ -459,6 +460,9 @@ void upload(usbs_handle *h) {
     h->RtR = dalloc<double>(256, o);
     h->Zc = dalloc<double>(128, o);
     h->Hred = dalloc<double>((size_t)ldb * 16, o);
+    h->Hg = dalloc<double>((size_t)(ldb + 8) * 8, o);
+    h->coef = dalloc<double>((size_t)(ldb + 8) * 8, o);
+    h->Rsv = dalloc<double>(64, o);
     h->Rinv = dalloc<double>(256, o);
     h->res = dalloc<double>(16, o);
     h->Hd = dalloc<double>(256, o);
@@ -585,26 +589,26 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
             nn_update(s, n, h->Bm, ldb, 16, h->Hred, 8, 8, h->W, 8, -1.0, 1.0);
         }
         cholqr2(h, h->W, 8, 8, h->Wt, 8, h->Bm + 16, ldb, h->dead + 16);
+        // block steps: W = M q_j, then two passes of block Gram-Schmidt with Pythagorean
+        // inner products against the whole basis (one reduction [Q W]^T W per pass)
         for (int j = 0; j < steps; ++j) {
             const int c0 = 16 + 8 * j, cols = c0 + 8;
+            const bool last = j == steps - 1;
             apply_op(h, h->Bm + c0, ldb, h->W, 8, 8);
-            int g;
-            {
-                if (h->ev_used + 2 > h->ev_pool.size()) prof_flush(h);
-                ProfPair pp(h, USBS_PROF_REORTH);
-                g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, pp.e0, pp.e1);
+            for (int pass = 0; pass < 2; ++pass) {
+                const double *Win = pass == 0 ? h->W : h->Wt;
+                int g;
+                {
+                    if (h->ev_used + 2 > h->ev_pool.size()) prof_flush(h);
+                    ProfPair pp(h, USBS_PROF_REORTH);
+                    g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, Win, 8, 8, pp.e0, pp.e1);
+                }
+                reorth_finish(s, h->rs, g, cols, 8, h->Hg, 8);
+                pip_chol(s, h->Hg, cols, pass, h->Rsv, h->Tm + c0, ldb, h->coef,
+                         (pass == 1 && !last) ? h->dead + cols : nullptr, pass == 0 ? h->sc + SC_SCALE : nullptr);
+                if (pass == 0) nn_update2(s, n, h->Bm, ldb, cols, h->W, 8, 8, h->coef, 8, 8, h->Wt, 8);
+                else if (!last) nn_update2(s, n, h->Bm, ldb, cols, h->Wt, 8, 8, h->coef, 8, 8, h->Bm + cols, ldb);
             }
-            reorth_finish(s, h->rs, g, cols, 8, h->Tm + c0, ldb);
-            nn_update(s, n, h->Bm, ldb, cols, h->Tm + c0, ldb, 8, h->W, 8, -1.0, 1.0);
-            {
-                if (h->ev_used + 2 > h->ev_pool.size()) prof_flush(h);
-                ProfPair pp(h, USBS_PROF_REORTH);
-                g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, pp.e0, pp.e1);
-            }
-            reorth_finish(s, h->rs, g, cols, 8, h->Hred, 8);
-            nn_update(s, n, h->Bm, ldb, cols, h->Hred, 8, 8, h->W, 8, -1.0, 1.0);
-            add_small(s, cols, 8, h->Hred, 8, h->Tm + c0, ldb);
-            if (j < steps - 1) cholqr2(h, h->W, 8, 8, h->Wt, 8, h->Bm + cols, ldb, h->dead + cols);
         }
         {
             ProfScope ps(h, USBS_PROF_RITZ);
