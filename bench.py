@@ -222,8 +222,8 @@ def main() -> int:
     # ---- roofline of the dominant bandwidth kernel (first stage of the re-orthogonalisation
     # reductions, k_tn_reduce<double, 1>) ----
     # algorithmic bytes per launch averaged over the basis widths of a restart cycle
-    # (block j of 8 reduces against 16 + 8 (j + 1) columns, j = 0..7)
-    widths = [16 + 8 * (j + 1) for j in range(8)]
+    # (block j of 8 reduces [Q W] with Q the first 16 + 8 (j + 1) columns, j = 0..s-1)
+    widths = [16 + 8 * (j + 1) for j in range(prm.lanczos_steps)]
     bytes_per_reorth = float(np.mean([reorth_bytes(n, c, 8) for c in widths]))
     avg_reorth_s = (reorth_ms / 1e3) / max(reorth_launches, 1)
     achieved = bytes_per_reorth / avg_reorth_s / 1e9 if reorth_launches else None
@@ -244,7 +244,8 @@ def main() -> int:
         "dtype": "f32 SpMM values / f64 Lanczos, Ritz, QP" if args.precision == "f32" else args.precision,
         "data": "synthetic (seeded random sparse graph standing in for DIMACS10)",
         "config": {"workload": f"maxcut_sparse_pm1 n={n} avg_degree=6 weights=+-1 block=8 r=10",
-                   "rho": args.rho, "k_c": 10, "k_p": 1, "lanczos_steps": 8, "precision": args.precision},
+                   "rho": args.rho, "k_c": 10, "k_p": 1, "lanczos_steps": prm.lanczos_steps,
+                   "lanczos_max_restarts": prm.lanczos_max_restarts, "precision": args.precision},
         "time_to_gap": ttg,
         "roofline": {
             "bound": "hbm", "kernel": "k_tn_reduce<double, 1> (first stage of B^T W in the Krylov re-orthogonalisation)",

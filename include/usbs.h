@@ -91,7 +91,8 @@ typedef struct usbs_params {
     int32_t units;              /* USBS_UNITS_*                            */
     int32_t max_iters;
     double time_limit;          /* seconds, <= 0 for none                  */
-    int32_t lanczos_steps;      /* block steps per restart cycle (b = 8)   */
+    int32_t lanczos_steps;      /* block steps per restart cycle (block 8; default 4, i.e.
+                                   32 new Krylov vectors per cycle)          */
     int32_t lanczos_max_restarts;
     double lanczos_tol;         /* residual / spectral-radius estimate inside the iteration */
     double lanczos_tol_final;   /* same, for f(y0) and the certified f(y_T) at convergence  */

@@ -862,7 +862,7 @@ int usbs_default_params(usbs_params *p) {
     p->units = USBS_UNITS_SCALED;
     p->max_iters = 1000;
     p->time_limit = 0.0;
-    p->lanczos_steps = 8;
+    p->lanczos_steps = 4;   // 32 new Krylov vectors per restart cycle (block 8)
     p->lanczos_max_restarts = 10;
     p->lanczos_tol = 1e-4;
     p->lanczos_tol_final = 1e-9;

@@ -170,7 +170,7 @@ class Params:
     units: str = "scaled"
     max_iters: int = 1000
     time_limit: float = 0.0
-    lanczos_steps: int = 8
+    lanczos_steps: int = 4
     lanczos_max_restarts: int = 10
     lanczos_tol: float = 1e-4
     lanczos_tol_final: float = 1e-9
