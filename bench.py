@@ -154,6 +154,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (counter calibration for HBM traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design "
@@ -166,6 +168,14 @@ def main() -> int:
     from paper_2312_11801_amd import Params, Solver
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        # known traffic: 256 MiB read + 256 MiB written per copy
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "served":
         res = run_served(args)
         print(json.dumps({"metric": "served batch: requests/s and p50/p99 latency (MaxCut SDPs n in [500, 5000], "

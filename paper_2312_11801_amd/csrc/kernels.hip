@@ -628,41 +628,44 @@ __global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__
                                                       double tol_rest, double *__restrict__ res,
                                                       int *__restrict__ flag, double *__restrict__ Z,
                                                       double *__restrict__ scale_est) {
-    // eigenvectors of the 16 x 16 Gram matrix R^T R by cyclic Jacobi on wavefront 0
-    __shared__ double sA[kRitz * kRitz], sV[kRitz * kRitz];
-    __shared__ JacobiWork<64, kRitz> js;
-    __shared__ int rank[kRitz];
+    // Next block: 8 of the 16 residual directions chosen by pivoted Cholesky of the
+    // Gram matrix R^T R (greedy: the residual with the largest component orthogonal to
+    // those already chosen), each scaled by 1 / ||r_p||; the block is orthonormalised
+    // afterwards.  One wavefront, lanes 0..15 own one residual each.
+    __shared__ double sG[kRitz][kRitz + 1];
+    __shared__ double sL[kBlk][kRitz];
+    __shared__ int sel[kBlk];
     const int tid = threadIdx.x;
     if (tid < kRitz) res[tid] = sqrt(fmax(RtR[tid * kRitz + tid], 0.0));
     if (tid >= 64) return;
-    for (int e = tid; e < kRitz * kRitz; e += 64) {
-        const int r = e / kRitz, c = e - r * kRitz;
-        sA[e] = RtR[(r < c ? r : c) * kRitz + (r < c ? c : r)];
-    }
+    for (int e = tid; e < kRitz * kRitz; e += 64) sG[e / kRitz][e % kRitz] = RtR[e];
+    for (int e = tid; e < kRitz * kBlk; e += 64) Z[e] = 0.0;
     wave_sync();
-    jacobi_core<64, kRitz, true>(kRitz, sA, sV, kRitz, &js, tid, 30, 2e-16);
-    if (tid < kRitz) {
-        const double wt = sA[tid * kRitz + tid];
-        int rk = 0;
-        for (int j = 0; j < kRitz; ++j) {
-            const double wj = sA[j * kRitz + j];
-            rk += (wj > wt) || (wj == wt && j < tid);
+    const int i = tid & 15;                    // every row of 16 lanes holds the same data
+    double d = fmax(sG[i][i], 0.0);
+    const double d0 = fmax(row16_max(d), 1e-300);
+    bool taken = false;
+    for (int t = 0; t < kBlk; ++t) {
+        // arg-max of the remaining diagonal (ties: lowest index)
+        const double cand = taken ? -1.0 : d;
+        const double best = row16_max(cand);
+        const double idx = row16_min((cand == best) ? (double)i : 1e9);
+        const int p = (int)idx;
+        if (!(best > 1e-24 * d0)) break;       // the residuals span fewer than t + 1 directions
+        const double piv = sqrt(best);
+        // column t of the pivoted Cholesky factor
+        double l = sG[i][p];
+        for (int u = 0; u < t; ++u) l -= sL[u][i] * sL[u][p];
+        l /= piv;
+        wave_sync();
+        if (tid < kRitz) sL[t][i] = l;
+        if (tid == 0) {
+            sel[t] = p;
+            Z[p * kBlk + t] = 1.0 / sqrt(fmax(sG[p][p], 1e-300));
         }
-        rank[tid] = rk;
-    }
-    wave_sync();
-    // Z[:, rank] = v / sigma for the 8 dominant directions (R Z orthonormal)
-    double top = 0.0;
-    for (int t = 0; t < kRitz; ++t)
-        if (rank[t] == 0) top = sA[t * kRitz + t];
-    const double ref = sqrt(fmax(top, 0.0));
-    for (int e = tid; e < kRitz * kRitz; e += 64) {
-        const int r = e / kRitz, t = e - r * kRitz;
-        const int rk = rank[t];
-        if (rk < kBlk) {
-            const double sg = sqrt(fmax(sA[t * kRitz + t], 0.0));
-            Z[r * kBlk + rk] = (sg > 1e-150 && sg > 1e-14 * ref) ? sV[r * kRitz + t] / sg : 0.0;
-        }
+        wave_sync();
+        d = fmax(d - l * l, 0.0);
+        if (i == p) taken = true;
     }
     if (tid == 0) {
         // tolerances are relative to a Gershgorin bound of the current operator
@@ -670,8 +673,8 @@ __global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__
         if (scale_est) sc = fmax(sc, *scale_est);
         // the top Ritz pair sets f(y): tight tolerance; the others only shape the bundle
         int ok = sqrt(fmax(RtR[0], 0.0)) <= tol * sc;
-        for (int i = 1; i < kc; ++i) {
-            const double r = sqrt(fmax(RtR[i * kRitz + i], 0.0));
+        for (int q = 1; q < kc; ++q) {
+            const double r = sqrt(fmax(RtR[q * kRitz + q], 0.0));
             if (!(r <= tol_rest * sc)) ok = 0;
         }
         *flag = ok;
