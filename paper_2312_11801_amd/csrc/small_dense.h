@@ -388,23 +388,96 @@ __device__ __forceinline__ void wave_congruence(int k, const double *Li, int ldi
 }
 
 // smallest eigenvalue of the symmetric k x k LDS matrix X (destroyed)
+__device__ __forceinline__ double wave_max(double v) {
+    v = row16_max(v);
+    return fmax(fmax(lane_read(v, 0), lane_read(v, 16)), fmax(lane_read(v, 32), lane_read(v, 48)));
+}
+__device__ __forceinline__ double wave_min(double v) {
+    v = row16_min(v);
+    return fmin(fmin(lane_read(v, 0), lane_read(v, 16)), fmin(lane_read(v, 32), lane_read(v, 48)));
+}
+
+// Lower bound (tight to ~1e-13 relative) of the smallest eigenvalue of the symmetric
+// k x k LDS matrix X (k <= 16, full storage, overwritten) on one wavefront: Householder
+// reduction to tridiagonal form (lane r owns row r), then 64-section on Sturm counts.
+// js->red (64 doubles) is the wave's scratch.
 __device__ __forceinline__ double wave_min_eig(int k, double *X, int ldx, JacobiWork<64, 16> *js) {
     const int lane = threadIdx.x & 63;
-    const int Np = k + (k & 1);
-    if (k & 1) {
-        for (int e = lane; e < Np; e += 64) {
-            X[(Np - 1) * ldx + e] = 0.0;
-            X[e * ldx + (Np - 1)] = 0.0;
+    double *vv = js->red, *ww = js->red + 16, *dd = js->red + 32, *ee = js->red + 48;
+    for (int j = 0; j + 2 < k; ++j) {
+        const int m = k - j - 1;
+        const double x = (lane < m) ? X[(j + 1 + lane) * ldx + j] : 0.0;
+        const double nx2 = wave_allsum(x * x);
+        const double xf = X[(j + 1) * ldx + j];
+        const double nx = sqrt(nx2);
+        double alpha = (xf >= 0.0) ? -nx : nx;
+        const double vn2 = nx2 - xf * xf + (xf - alpha) * (xf - alpha);
+        const double b = (nx2 > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+        if (b == 0.0) alpha = xf;
+        const double djj = X[j * ldx + j];
+        wave_sync();
+        if (lane < m) vv[lane] = (lane == 0) ? xf - alpha : x;
+        if (lane == 0) {
+            dd[j] = djj;
+            ee[j] = alpha;
         }
         wave_sync();
-        if (lane == 0) X[(Np - 1) * ldx + (Np - 1)] = 0.0;
-        wave_sync();
+        if (b != 0.0) {
+            double p = 0.0;
+            if (lane < m) {
+                for (int q = 0; q < m; ++q) p += X[(j + 1 + lane) * ldx + j + 1 + q] * vv[q];
+                p *= b;
+            }
+            const double K = 0.5 * b * wave_allsum((lane < m) ? p * vv[lane] : 0.0);
+            if (lane < m) ww[lane] = p - K * vv[lane];
+            wave_sync();
+            if (lane < m) {
+                const double vr = vv[lane], wr = ww[lane];
+                for (int q = 0; q < m; ++q) X[(j + 1 + lane) * ldx + j + 1 + q] -= vr * ww[q] + wr * vv[q];
+            }
+            wave_sync();
+        }
     }
-    jacobi_core<64, 16, false>(Np, X, nullptr, ldx, js, lane, 30, 2e-16);
-    double mn = 1e300;
-    for (int i = 0; i < k; ++i) mn = fmin(mn, X[i * ldx + i]);
+    if (lane == 0) {
+        if (k >= 2) {
+            dd[k - 2] = X[(k - 2) * ldx + (k - 2)];
+            ee[k - 2] = X[(k - 1) * ldx + (k - 2)];
+        }
+        dd[k - 1] = X[(k - 1) * ldx + (k - 1)];
+    }
     wave_sync();
-    return mn;
+    // Gershgorin interval (every lane computes the same values)
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < k ? fabs(ee[i]) : 0.0);
+        lo = fmin(lo, dd[i] - r);
+        hi = fmax(hi, dd[i] + r);
+    }
+    const double tn = fmax(fmax(fabs(lo), fabs(hi)), 1e-300);
+    lo -= 4e-16 * tn;
+    hi += 4e-16 * tn;
+    const double pivmin = fmax(1e-290, 1e-300 * tn * tn);
+    for (int it = 0; it < 12; ++it) {
+        const double x = lo + (hi - lo) * (double)lane * (1.0 / 64.0);
+        int cnt = 0;
+        if (lane > 0) {
+            double q = dd[0] - x;
+            if (fabs(q) < pivmin) q = -pivmin;
+            cnt += (q < 0.0);
+            for (int i = 1; i < k; ++i) {
+                q = dd[i] - x - ee[i - 1] * ee[i - 1] / q;
+                if (fabs(q) < pivmin) q = -pivmin;
+                cnt += (q < 0.0);
+            }
+        }
+        // lambda_min < x  iff  cnt >= 1
+        const double nlo = wave_max((cnt == 0) ? x : -1e308);
+        const double nhi = wave_min((cnt >= 1) ? x : 1e308);
+        lo = nlo;
+        if (nhi < 1e308) hi = nhi;
+        if (hi - lo <= 1e-13 * fmax(fabs(lo), fabs(hi)) + 1e-16 * tn) break;
+    }
+    return lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -431,7 +504,7 @@ struct IpmShared {
     double dS[kMaxK * kMaxK], dT[kMaxK * kMaxK];
     double Y0[16 * 16], X0[16 * 16], Y1[16 * 16], X1[16 * 16];
     double s[kMaxSvec], t[kMaxSvec], F1[kMaxSvec], q12[kMaxSvec], h1[kMaxSvec], svSi[kMaxSvec];
-    double rhs[kMaxD], dt[kMaxSvec];
+    double rhs[kMaxD], dt[kMaxSvec], pv[kMaxD];
     int pi[kMaxSvec], pj[kMaxSvec];
     double red[kWG];
     JacobiWork<64, 16> js0, js1;
@@ -655,25 +728,31 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
         }
         if (tid == 0) sh->okM = 1;
         __syncthreads();
-        // Cholesky of M (lower, right-looking)
-        for (int j = 0; j < D; ++j) {
-            if (tid == 0) {
-                const double piv = sh->M[j * ldm + j];
-                if (!(piv > 0.0)) {
-                    sh->okM = 0;
-                    sh->M[j * ldm + j] = 1.0;
-                } else {
-                    sh->M[j * ldm + j] = sqrt(piv);
+        // Cholesky of M (lower, right-looking), one barrier per column: every thread reads
+        // the pivot itself and updates with the unscaled column (M_il -= M_ij M_lj / piv);
+        // column j - 1, no longer read, is scaled during step j
+        {
+            const int tr = tid >> 4, tc = tid & 15;
+            for (int j = 0; j <= D; ++j) {
+                if (j > 0) {
+                    const int jp = j - 1;
+                    const double sp = sqrt(sh->pv[jp]);
+                    for (int i = jp + 1 + tid; i < D; i += kWG) sh->M[i * ldm + jp] /= sp;
+                    if (tid == 0) sh->M[jp * ldm + jp] = sp;
                 }
-            }
-            __syncthreads();
-            const double ljj = sh->M[j * ldm + j];
-            for (int i = j + 1 + tid; i < D; i += kWG) sh->M[i * ldm + j] /= ljj;
-            __syncthreads();
-            const int m = D - j - 1;
-            for (int e = tid; e < m * m; e += kWG) {
-                const int i = j + 1 + e / m, l = j + 1 + e % m;
-                if (l <= i) sh->M[i * ldm + l] -= sh->M[i * ldm + j] * sh->M[l * ldm + j];
+                if (j == D) break;
+                double piv = sh->M[j * ldm + j];
+                if (!(piv > 0.0)) {
+                    if (tid == 0) sh->okM = 0;
+                    piv = 1.0;
+                }
+                const double ipiv = 1.0 / piv;
+                for (int i = j + 1 + tr; i < D; i += 16) {
+                    const double mij = sh->M[i * ldm + j] * ipiv;
+                    for (int l = j + 1 + tc; l <= i; l += 16) sh->M[i * ldm + l] -= mij * sh->M[l * ldm + j];
+                }
+                if (tid == 0) sh->pv[j] = piv;
+                __syncthreads();
             }
             __syncthreads();
         }
