@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def spmm_bytes(n: int, nnz_off: int, nb: int, val_bytes: int) -> float:
@@ -37,6 +38,29 @@ def reorth_bytes(n: int, cols: int, nb: int) -> float:
     """Algorithmic bytes of one H = B^T W reduction: the basis slice (n x cols FP64) and
     W (n x nb FP64) read once."""
     return n * (cols + nb) * 8
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tn_reduce_reorth_c2_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_11801_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic() -> float | None:
+    """HBM bytes per launch of the roofline kernel from the committed counter summary
+    (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy), or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(TRAFFIC_FILE):
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                kv[key.strip()] = val.strip()
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if kv.get("kernel_source_sha256") != sha:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def run_cpu_baseline(seconds: float = 20.0) -> dict:
@@ -240,6 +264,11 @@ def main() -> int:
     avg_spmm_s = (spmm_ms / 1e3) / max(spmm_launches, 1)
     spmm_gbs = spmm_bytes(n, nnz_off, 8, val_bytes) / avg_spmm_s / 1e9 if spmm_launches else None
 
+    # the Rayleigh-Ritz eigenproblem: Householder tridiagonalisation (4/3 N^3), 16 eigenvectors
+    # by inverse iteration and back-transformation (~ 2 * 16 * 2 N^2)
+    nb = 16 + 8 * prm.lanczos_steps
+    ritz_us = 1e3 * ritz_ms / max(ritz_launches, 1)
+    ritz_flops = 4.0 / 3.0 * nb ** 3 + 64.0 * nb ** 2
     line = {
         "metric": "USBS iterations/sec (MaxCut SDP, n=20000 sparse +-1 graph); time-to-1e-3 rel gap",
         "value": value,
@@ -260,7 +289,7 @@ def main() -> int:
         "roofline": {
             "bound": "hbm", "kernel": "k_tn_reduce<double, 1> (first stage of B^T W in the Krylov re-orthogonalisation)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
             "avg_launch_us": avg_reorth_s * 1e6, "launches": reorth_launches,
             "bytes_per_launch": bytes_per_reorth,
         },
@@ -268,8 +297,10 @@ def main() -> int:
                  "bytes_per_launch": spmm_bytes(n, nnz_off, 8, val_bytes)},
         # the largest single share of kernel time: the one-workgroup Rayleigh-Ritz eigensolver
         # (latency-bound: one CU, a few hundred dependent Householder / bisection steps)
-        "ritz": {"kernel": "k_small_eig (80 x 80 projected eigenproblem)",
-                 "avg_launch_us": 1e3 * ritz_ms / max(ritz_launches, 1), "launches": ritz_launches,
+        "ritz": {"kernel": f"k_small_eig ({nb} x {nb} projected eigenproblem)", "bound": "latency (one workgroup)",
+                 "avg_launch_us": ritz_us, "launches": ritz_launches,
+                 "flops_per_launch": ritz_flops, "achieved_GFLOPs": ritz_flops / max(ritz_us, 1e-9) / 1e3,
+                 "frac_of_fp64_peak": ritz_flops / max(ritz_us, 1e-9) / 1e6 / FP64_PEAK_TFLOPS,
                  "share_of_step_time": (ritz_ms / 1e3) / max(t3 - t2, 1e-12)},
         "final_state": {"f": st["f"], "rel_gap": st["rel_gap"], "rel_infeas": st["rel_infeas"]},
     }
