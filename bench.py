@@ -173,8 +173,9 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solve")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "served"],
-                    help="c2: the single-instance line (default); served: the request loop")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "served"],
+                    help="c2: MaxCut n=20000 (default line); c4: correlation clustering n=10000; "
+                         "c5: MaxCut on a random 4-regular graph, n=1e6, BF16 products; served: the request loop")
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
@@ -210,30 +211,48 @@ def main() -> int:
                                      "slots": args.slots}, **res}))
         return 0
     stream = torch.cuda.current_stream().cuda_stream
-    n = args.n
-    prob = si.maxcut_sparse_pm1(n, 6.0, seed=0)
+    if args.workload == "c2":
+        n = args.n
+        prob = si.maxcut_sparse_pm1(n, 6.0, seed=0)
+        kc, kp = 10, 1
+        workload = f"maxcut_sparse_pm1 n={n} avg_degree=6 weights=+-1 block=8 r=10"
+        metric = f"USBS iterations/sec (MaxCut SDP, n={n} sparse +-1 graph); time-to-1e-3 rel gap"
+    elif args.workload == "c4":
+        n = 10000
+        prob = si.cc_signed(n, avg_degree=10.0, seed=0)
+        kc, kp = 3, 0
+        workload = "cc_signed n=10000 edges=50000 weights=N(0,1) rows: diag=1 and X_ij>=0 per edge (m=60000)"
+        metric = "USBS iterations/sec (correlation-clustering SDP, n=10000); time-to-1e-3 rel gap"
+    else:
+        n = 1_000_000
+        prob = si.maxcut_regular(n, 4, seed=0)
+        kc, kp = 10, 1
+        if args.precision == "f32":
+            args.precision = "bf16"
+        workload = "maxcut_regular n=1000000 degree=4 unit weights, X never formed (n x 10 sketch)"
+        metric = "USBS iterations/sec (MaxCut SDP, n=1e6 random 4-regular graph)"
     psi = si.test_matrix(n, 10, seed=0)
     val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[args.precision]
     nnz_off = prob.nnz - n
-    prm = Params(precision=args.precision, rho=args.rho, max_iters=100000)
+    prm = Params(precision=args.precision, rho=args.rho, max_iters=100000, k_c=kc, k_p=kp)
 
     # ---- throughput: K timed iterations of Alg. 1 ----
     s = Solver(prob, prm, psi=psi, stream=stream)
-    s.step_iterate(args.warmup, 11)
+    s.step_iterate(args.warmup, kc + kp)
     s.profile("reorth", reset=True)       # time the roofline kernel live (HIP events)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    st = s.step_iterate(args.steps, 11)
+    st = s.step_iterate(args.steps, kc + kp)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     reorth_ms, reorth_launches = s.profile("spmm", reset=True)
     # two more short stretches for secondary figures: the SpMM and the Ritz eigenproblem
     extra = max(2, args.steps // 4)
-    s.step_iterate(extra, 11)
+    s.step_iterate(extra, kc + kp)
     spmm_ms, spmm_launches = s.profile("ritz", reset=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    s.step_iterate(extra, 11)
+    s.step_iterate(extra, kc + kp)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     ritz_ms, ritz_launches = s.profile(None, reset=True)
@@ -245,8 +264,8 @@ def main() -> int:
     # ---- time to the paper's 1e-3 criterion from a cold start ----
     ttg = None
     if not args.no_ttg:
-        s2 = Solver(prob, Params(precision=args.precision, rho=args.rho, max_iters=3000, time_limit=120.0),
-                    psi=psi, stream=stream)
+        s2 = Solver(prob, Params(precision=args.precision, rho=args.rho, max_iters=3000, time_limit=120.0,
+                                 k_c=kc, k_p=kp), psi=psi, stream=stream)
         out = s2.solve(want_y=False)
         s2.free()
         ttg = {"seconds": out["seconds"], "iters": out["iters"], "converged": out["converged"],
@@ -270,7 +289,7 @@ def main() -> int:
     ritz_us = 1e3 * ritz_ms / max(ritz_launches, 1)
     ritz_flops = 4.0 / 3.0 * nb ** 3 + 64.0 * nb ** 2
     line = {
-        "metric": "USBS iterations/sec (MaxCut SDP, n=20000 sparse +-1 graph); time-to-1e-3 rel gap",
+        "metric": metric,
         "value": value,
         "unit": "iterations/s",
         "n_gpus": 1,
@@ -282,14 +301,15 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32 SpMM values / f64 Lanczos, Ritz, QP" if args.precision == "f32" else args.precision,
         "data": "synthetic (seeded random sparse graph standing in for DIMACS10)",
-        "config": {"workload": f"maxcut_sparse_pm1 n={n} avg_degree=6 weights=+-1 block=8 r=10",
-                   "rho": args.rho, "k_c": 10, "k_p": 1, "lanczos_steps": prm.lanczos_steps,
+        "config": {"workload": workload,
+                   "rho": args.rho, "k_c": kc, "k_p": kp, "lanczos_steps": prm.lanczos_steps,
                    "lanczos_max_restarts": prm.lanczos_max_restarts, "precision": args.precision},
         "time_to_gap": ttg,
         "roofline": {
             "bound": "hbm", "kernel": "k_tn_reduce<double, 1> (first stage of B^T W in the Krylov re-orthogonalisation)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": measured_traffic(),
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": measured_traffic() if (args.workload == "c2" and n == 20000 and args.precision == "f32") else None,
             "avg_launch_us": avg_reorth_s * 1e6, "launches": reorth_launches,
             "bytes_per_launch": bytes_per_reorth,
         },
@@ -304,7 +324,7 @@ def main() -> int:
                  "share_of_step_time": (ritz_ms / 1e3) / max(t3 - t2, 1e-12)},
         "final_state": {"f": st["f"], "rel_gap": st["rel_gap"], "rel_infeas": st["rel_infeas"]},
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "c2":
         line["cpu_baseline"] = run_cpu_baseline(args.cpu_seconds)
     print(json.dumps(line))
     return 0

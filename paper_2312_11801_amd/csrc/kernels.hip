@@ -395,15 +395,93 @@ void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int 
     else hipLaunchKernelGGL(k_cholqr_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, ca, H, ldh, flags, floor_ref);
 }
 
+// ---------------------------------------------------------------------------
+// [A B]^T B for an 8-column B (the Krylov re-orthogonalisation) on the FP64 matrix
+// cores: V_MFMA_F64_16X16X4F64 accumulates X (16 x 4) Y (4 x 16) with X[m][k] in lane
+// m + 16 k, Y[k][j] in lane j + 16 k, and D[m][j] in lane j + 16 (m % 4), element m / 4.
+// A wavefront takes 4 rows at a time: X = 16 columns of A of those rows (one double
+// per lane, 128 contiguous bytes per row), Y = the 8 columns of B (lanes j >= 8 hold 0),
+// so every element of A is loaded once and no lane replicates another's data.  The
+// Gram block B^T B uses Y as X.  UNR row groups are in flight per wavefront; the four
+// wavefronts of a workgroup are summed in LDS in a fixed order into one partial per
+// workgroup (layout as k_tn_reduce: (ca + 8) x 8).
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kMfmaMaxCh = kMaxBasis / 16;   // 16-column chunks of A (ca <= 80)
+template <int TAG, int UNR>
+__global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
+                                                 const double *__restrict__ B, int ldb,
+                                                 double *__restrict__ partials) {
+    __shared__ double sred[3][kMfmaMaxCh + 1][4][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kk = lane >> 4;
+    const int nch = (ca + 15) >> 4;
+    v4d acc[kMfmaMaxCh + 1];
+#pragma unroll
+    for (int q = 0; q <= kMfmaMaxCh; ++q) acc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+    const long ngroups = ((long)n + 3) >> 2;
+    const long gstride = (long)gridDim.x * 4;
+    for (long g0 = (long)blockIdx.x * 4 + wave; g0 < ngroups; g0 += UNR * gstride) {
+        double yv[UNR], xv[UNR][kMfmaMaxCh];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const long row = 4 * (g0 + u * gstride) + kk;
+            const bool ok = (g0 + u * gstride < ngroups) && row < n;
+            yv[u] = (ok && m < kBlk) ? B[row * ldb + m] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kMfmaMaxCh; ++q) {
+                const int col = 16 * q + m;
+                xv[u][q] = (ok && q < nch && col < ca) ? A[row * lda + col] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+            for (int q = 0; q < kMfmaMaxCh; ++q)
+                if (q < nch) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][q], yv[u], acc[q], 0, 0, 0);
+            acc[kMfmaMaxCh] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[u], yv[u], acc[kMfmaMaxCh], 0, 0, 0);
+        }
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int q = 0; q <= kMfmaMaxCh; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sred[wave - 1][q][v][lane] = acc[q][v];
+    __syncthreads();
+    if (wave == 0) {
+        const int rows_out = ca + kBlk;
+        const int j = lane & 15;
+        double *dst = partials + (size_t)blockIdx.x * rows_out * kBlk;
+#pragma unroll
+        for (int q = 0; q <= kMfmaMaxCh; ++q) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double t = ((acc[q][v] + sred[0][q][v][lane]) + sred[1][q][v][lane]) + sred[2][q][v][lane];
+                const int mm = (lane >> 4) + 4 * v;   // row of D held in this element
+                const int a = (q < kMfmaMaxCh) ? 16 * q + mm : ca + mm;
+                const bool valid = (q < kMfmaMaxCh) ? (q < nch && a < ca) : (mm < kBlk);
+                if (valid && j < kBlk) dst[a * kBlk + j] = t;
+            }
+        }
+    }
+}
+
+static int direct_blocks(const RedScratch &rs, int n) {
+    int blocks = cdiv(n, 64);   // at least 16 rows per wavefront
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks < 1) blocks = 1;
+    return blocks;
+}
+
 int reorth_partials(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
                     int ldb, int cb, hipEvent_t ev_start, hipEvent_t ev_stop) {
-    const int blocks = tn_blocks(rs, n);
+    (void)cb;   // always 8 (one Lanczos block)
+    const int blocks = direct_blocks(rs, n);
     if (ev_start && ev_stop)   // events carry this dispatch's own start / end time
-        hipExtLaunchKernelGGL((k_tn_reduce<double, 1, true>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A,
-                              lda, ca, B, ldb, cb, rs.partials);
+        hipExtLaunchKernelGGL((k_tn_mfma<1, 4>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A, lda, ca,
+                              B, ldb, rs.partials);
     else
-        hipLaunchKernelGGL((k_tn_reduce<double, 1, true>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
-                           rs.partials);
+        hipLaunchKernelGGL((k_tn_mfma<1, 4>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, rs.partials);
     return blocks;
 }
 void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int cb, double *H, int ldh) {
