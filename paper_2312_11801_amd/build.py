@@ -38,7 +38,7 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     while procs:
         _wait(procs.pop(0))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-Wl,--no-undefined", "-o", tmp, *objs]
     out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if out.returncode != 0:
         raise RuntimeError("link failed:\n" + out.stdout)

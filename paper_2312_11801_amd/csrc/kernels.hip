@@ -36,6 +36,7 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
+typedef double v4d __attribute__((ext_vector_type(4)));   // one lane's MFMA FP64 accumulator
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
@@ -386,15 +387,6 @@ static int tn_blocks(const RedScratch &rs, int n) {
     return blocks;
 }
 
-void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
-               int ldb, int cb, double *H, int ldh, double alpha, double beta, int post, int *flags,
-               const double *floor_ref) {
-    const int blocks = tn_blocks(rs, n);
-    hipLaunchKernelGGL((k_tn_reduce<double, 0, false>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
-    if (post == 0) red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, beta);
-    else hipLaunchKernelGGL(k_cholqr_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, ca, H, ldh, flags, floor_ref);
-}
-
 // ---------------------------------------------------------------------------
 // [A B]^T B for an 8-column B (the Krylov re-orthogonalisation) on the FP64 matrix
 // cores: V_MFMA_F64_16X16X4F64 accumulates X (16 x 4) Y (4 x 16) with X[m][k] in lane
@@ -406,11 +398,10 @@ void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int 
 // wavefronts of a workgroup are summed in LDS in a fixed order into one partial per
 // workgroup (layout as k_tn_reduce: (ca + 8) x 8).
 // ---------------------------------------------------------------------------
-typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int kMfmaMaxCh = kMaxBasis / 16;   // 16-column chunks of A (ca <= 80)
-template <int TAG, int UNR>
+template <int TAG, int UNR, bool GRAM>
 __global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
-                                                 const double *__restrict__ B, int ldb,
+                                                 const double *__restrict__ B, int ldb, int cb,
                                                  double *__restrict__ partials) {
     __shared__ double sred[3][kMfmaMaxCh + 1][4][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -427,7 +418,7 @@ __global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict
         for (int u = 0; u < UNR; ++u) {
             const long row = 4 * (g0 + u * gstride) + kk;
             const bool ok = (g0 + u * gstride < ngroups) && row < n;
-            yv[u] = (ok && m < kBlk) ? B[row * ldb + m] : 0.0;
+            yv[u] = (ok && m < cb) ? B[row * ldb + m] : 0.0;
 #pragma unroll
             for (int q = 0; q < kMfmaMaxCh; ++q) {
                 const int col = 16 * q + m;
@@ -439,7 +430,7 @@ __global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict
 #pragma unroll
             for (int q = 0; q < kMfmaMaxCh; ++q)
                 if (q < nch) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][q], yv[u], acc[q], 0, 0, 0);
-            acc[kMfmaMaxCh] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[u], yv[u], acc[kMfmaMaxCh], 0, 0, 0);
+            if (GRAM) acc[kMfmaMaxCh] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[u], yv[u], acc[kMfmaMaxCh], 0, 0, 0);
         }
     }
     if (wave > 0)
@@ -449,9 +440,9 @@ __global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict
             for (int v = 0; v < 4; ++v) sred[wave - 1][q][v][lane] = acc[q][v];
     __syncthreads();
     if (wave == 0) {
-        const int rows_out = ca + kBlk;
+        const int rows_out = GRAM ? ca + cb : ca;
         const int j = lane & 15;
-        double *dst = partials + (size_t)blockIdx.x * rows_out * kBlk;
+        double *dst = partials + (size_t)blockIdx.x * rows_out * cb;
 #pragma unroll
         for (int q = 0; q <= kMfmaMaxCh; ++q) {
 #pragma unroll
@@ -459,14 +450,14 @@ __global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict
                 const double t = ((acc[q][v] + sred[0][q][v][lane]) + sred[1][q][v][lane]) + sred[2][q][v][lane];
                 const int mm = (lane >> 4) + 4 * v;   // row of D held in this element
                 const int a = (q < kMfmaMaxCh) ? 16 * q + mm : ca + mm;
-                const bool valid = (q < kMfmaMaxCh) ? (q < nch && a < ca) : (mm < kBlk);
-                if (valid && j < kBlk) dst[a * kBlk + j] = t;
+                const bool valid = (q < kMfmaMaxCh) ? (q < nch && a < ca) : (GRAM && mm < cb);
+                if (valid && j < cb) dst[a * cb + j] = t;
             }
         }
     }
 }
 
-static int direct_blocks(const RedScratch &rs, int n) {
+static int mfma_blocks(const RedScratch &rs, int n) {
     int blocks = cdiv(n, 64);   // at least 16 rows per wavefront
     if (blocks > rs.max_blocks) blocks = rs.max_blocks;
     if (blocks < 1) blocks = 1;
@@ -476,14 +467,32 @@ static int direct_blocks(const RedScratch &rs, int n) {
 int reorth_partials(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
                     int ldb, int cb, hipEvent_t ev_start, hipEvent_t ev_stop) {
     (void)cb;   // always 8 (one Lanczos block)
-    const int blocks = direct_blocks(rs, n);
+    const int blocks = mfma_blocks(rs, n);
     if (ev_start && ev_stop)   // events carry this dispatch's own start / end time
-        hipExtLaunchKernelGGL((k_tn_mfma<1, 4>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A, lda, ca,
-                              B, ldb, rs.partials);
+        hipExtLaunchKernelGGL((k_tn_mfma<1, 4, true>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A, lda,
+                              ca, B, ldb, kBlk, rs.partials);
     else
-        hipLaunchKernelGGL((k_tn_mfma<1, 4>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, rs.partials);
+        hipLaunchKernelGGL((k_tn_mfma<1, 4, true>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, kBlk,
+                           rs.partials);
     return blocks;
 }
+void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
+               int ldb, int cb, double *H, int ldh, double alpha, double beta, int post, int *flags,
+               const double *floor_ref) {
+    int blocks;
+    if (cb <= 16 && ca <= kMaxBasis) {
+        blocks = mfma_blocks(rs, n);
+        hipLaunchKernelGGL((k_tn_mfma<0, 4, false>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
+                           rs.partials);
+    } else {
+        blocks = tn_blocks(rs, n);
+        hipLaunchKernelGGL((k_tn_reduce<double, 0, false>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
+                           rs.partials);
+    }
+    if (post == 0) red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, beta);
+    else hipLaunchKernelGGL(k_cholqr_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, ca, H, ldh, flags, floor_ref);
+}
+
 void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int cb, double *H, int ldh) {
     red_finish(s, rs.partials, blocks, (ca + cb) * cb, H, cb, ldh, 1.0, 0.0);
 }
@@ -609,10 +618,79 @@ __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restri
     C[i * ldc + c] = (TC)v;
 }
 
+// ---------------------------------------------------------------------------
+// C = beta*C + alpha*[A A2] H on the FP64 matrix cores for wide n: a wavefront takes 16
+// rows at a time and runs V_MFMA_F64_16X16X4F64 over the (ca + ca2) columns four at a
+// time: X[m][k] = [A A2][row0 + m][4 q + k] (one double per lane), Y[k][j] = H[4 q + k][j]
+// (held in registers for the whole launch), D[m][j] = output row row0 + m, column j.
+// Each element of A is loaded once per launch.
+// ---------------------------------------------------------------------------
+constexpr int kNnMaxQ = (kMaxBasis + kBlk) / 4;   // 22 four-column steps
+__global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict__ A, int lda, int ca,
+                                                 const double *__restrict__ A2, int lda2, int ca2,
+                                                 const double *__restrict__ H, int ldh, int cc,
+                                                 double *__restrict__ C, int ldc, double alpha, double beta) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kk = lane >> 4, j = lane & 15;
+    const int ct = ca + ca2;
+    const int nq = (ct + 3) >> 2;
+    double yv[kNnMaxQ];
+#pragma unroll
+    for (int q = 0; q < kNnMaxQ; ++q) {
+        const int a = 4 * q + kk;
+        yv[q] = (q < nq && a < ct && j < cc) ? H[a * ldh + j] : 0.0;
+    }
+    const long ngroups = ((long)n + 15) >> 4;
+    const long gstride = (long)gridDim.x * 4;
+    for (long g = (long)blockIdx.x * 4 + wave; g < ngroups; g += gstride) {
+        const long row = 16 * g + m;
+        const bool rok = row < n;
+        double xv[kNnMaxQ];
+#pragma unroll
+        for (int q = 0; q < kNnMaxQ; ++q) {
+            const int a = 4 * q + kk;
+            double x = 0.0;
+            if (q < nq && rok) {
+                if (a < ca) x = A[row * lda + a];
+                else if (a < ct) x = A2[row * lda2 + (a - ca)];
+            }
+            xv[q] = x;
+        }
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < kNnMaxQ; ++q)
+            if (q < nq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[q], yv[q], acc, 0, 0, 0);
+        if (j < cc) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const long r = 16 * g + (lane >> 4) + 4 * v;
+                if (r < n) {
+                    double o = alpha * acc[v];
+                    if (beta != 0.0) o += beta * C[r * ldc + j];
+                    C[r * ldc + j] = o;
+                }
+            }
+        }
+    }
+}
+
+static bool use_nn_mfma(int n, int cc) { return n > 0 && cc <= 16; }
+static int nn_mfma_blocks(int n) {
+    int b = cdiv(((long)n + 15) / 16, 4);   // one row group per wavefront, up to 2 per wavefront
+    return b < 1 ? 1 : (b > 8192 ? 8192 : b);
+}
+
 template <typename TC>
 static void nn_update_t(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2,
                         int ca2, const double *H, int ldh, int cc, TC *C, int ldc, double alpha, double beta) {
     if (n <= 0 || cc <= 0) return;
+    if constexpr (sizeof(TC) == 8) {
+        if (use_nn_mfma(n, cc)) {
+            hipLaunchKernelGGL(k_nn_mfma, dim3(nn_mfma_blocks(n)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2, ca2, H,
+                               ldh, cc, (double *)C, ldc, alpha, beta);
+            return;
+        }
+    }
     if (cc <= 4)
         hipLaunchKernelGGL((k_nn_update<TC, 4>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
                            ca2, H, ldh, cc, C, ldc, alpha, beta);
