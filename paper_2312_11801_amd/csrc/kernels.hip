@@ -619,17 +619,20 @@ __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restri
 }
 
 // ---------------------------------------------------------------------------
-// C = beta*C + alpha*[A A2] H on the FP64 matrix cores for wide n: a wavefront takes 16
-// rows at a time and runs V_MFMA_F64_16X16X4F64 over the (ca + ca2) columns four at a
-// time: X[m][k] = [A A2][row0 + m][4 q + k] (one double per lane), Y[k][j] = H[4 q + k][j]
-// (held in registers for the whole launch), D[m][j] = output row row0 + m, column j.
-// Each element of A is loaded once per launch.
+// C = beta*C + alpha*[A A2] H on the FP64 matrix cores: a wavefront takes 16 rows at a
+// time, loads them with row-contiguous loads into its own LDS tile, then runs
+// V_MFMA_F64_16X16X4F64 over the (ca + ca2) columns four at a time:
+// X[m][k] = tile[m][4 q + k], Y[k][j] = H[4 q + k][j] (held in registers for the whole
+// launch), D[m][j] = output row row0 + m, column j.  Each element of A is read from
+// memory once per launch.
 // ---------------------------------------------------------------------------
 constexpr int kNnMaxQ = (kMaxBasis + kBlk) / 4;   // 22 four-column steps
+constexpr int kNnLd = kMaxBasis + kBlk + 1;
 __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                                  const double *__restrict__ A2, int lda2, int ca2,
                                                  const double *__restrict__ H, int ldh, int cc,
                                                  double *__restrict__ C, int ldc, double alpha, double beta) {
+    __shared__ double tile[4][16][kNnLd];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, kk = lane >> 4, j = lane & 15;
     const int ct = ca + ca2;
@@ -640,32 +643,53 @@ __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict
         const int a = 4 * q + kk;
         yv[q] = (q < nq && a < ct && j < cc) ? H[a * ldh + j] : 0.0;
     }
+    double(*T)[kNnLd] = tile[wave];
     const long ngroups = ((long)n + 15) >> 4;
     const long gstride = (long)gridDim.x * 4;
     for (long g = (long)blockIdx.x * 4 + wave; g < ngroups; g += gstride) {
-        const long row = 16 * g + m;
-        const bool rok = row < n;
-        double xv[kNnMaxQ];
+        const long row0 = 16 * g;
+        // rows of A: lanes over columns (two passes when ca > 64); A2 (<= 8 columns): 8 rows
+        // of 8 lanes per load
+        double v[16];
 #pragma unroll
-        for (int q = 0; q < kNnMaxQ; ++q) {
-            const int a = 4 * q + kk;
-            double x = 0.0;
-            if (q < nq && rok) {
-                if (a < ca) x = A[row * lda + a];
-                else if (a < ct) x = A2[row * lda2 + (a - ca)];
-            }
-            xv[q] = x;
+        for (int r = 0; r < 16; ++r) v[r] = (lane < ca && row0 + r < n) ? A[(row0 + r) * lda + lane] : 0.0;
+        double w2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = 8 * h + (lane >> 3), c = lane & 7;
+            w2[h] = (c < ca2 && row0 + r < n) ? A2[(row0 + r) * lda2 + c] : 0.0;
         }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (lane < ca) T[r][lane] = v[r];
+        if (ca > 64) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = (64 + lane < ca && row0 + r < n) ? A[(row0 + r) * lda + 64 + lane] : 0.0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (64 + lane < ca) T[r][64 + lane] = v[r];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = 8 * h + (lane >> 3), c = lane & 7;
+            if (c < ca2) T[r][ca + c] = w2[h];
+        }
+        wave_sync();
         v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < kNnMaxQ; ++q)
-            if (q < nq) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[q], yv[q], acc, 0, 0, 0);
+            if (q < nq) {
+                const int a = 4 * q + kk;
+                const double x = (a < ct) ? T[m][a] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, yv[q], acc, 0, 0, 0);
+            }
+        wave_sync();   // the tile is reloaded for the next row group
         if (j < cc) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const long r = 16 * g + (lane >> 4) + 4 * v;
+            for (int vv = 0; vv < 4; ++vv) {
+                const long r = row0 + (lane >> 4) + 4 * vv;
                 if (r < n) {
-                    double o = alpha * acc[v];
+                    double o = alpha * acc[vv];
                     if (beta != 0.0) o += beta * C[r * ldc + j];
                     C[r * ldc + j] = o;
                 }
@@ -676,8 +700,8 @@ __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict
 
 static bool use_nn_mfma(int n, int cc) { return n > 0 && cc <= 16; }
 static int nn_mfma_blocks(int n) {
-    int b = cdiv(((long)n + 15) / 16, 4);   // one row group per wavefront, up to 2 per wavefront
-    return b < 1 ? 1 : (b > 8192 ? 8192 : b);
+    int b = cdiv(((long)n + 15) / 16, 4);   // one row group per wavefront up to 4096 workgroups
+    return b < 1 ? 1 : (b > 4096 ? 4096 : b);
 }
 
 template <typename TC>
