@@ -207,6 +207,16 @@ int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *z
 #define USBS_PROF_COUNT 4
 int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_total, int64_t *launches);
 
+/* Rounding of a MaxCut relaxation (App. E.1): the r cuts x_c = sign(U[:, c]) (ties to
+ * +1) given by the columns of the Nystrom factor of the current sketch are evaluated as
+ * x_c^T C x_c in FP64 (original units; for C = L/4 this is the cut weight) and the largest
+ * is returned: x_out[n] (host, +1/-1, may be NULL), *cut_out, *column_out (the column of U,
+ * first of equal values) and cuts_out[r] (every column's value); each output may be NULL.
+ * Needs a sketch (r > 0); the handle state is unchanged.  Defined for any problem, it is a
+ * cut only for the MaxCut form. */
+int usbs_round_maxcut(usbs_handle *h, int8_t *x_out, double *cut_out, int32_t *column_out,
+                      double *cuts_out);
+
 /* Scaling factors of the handle's problem: sigma = ||C||_F, trace. */
 int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace);
 

@@ -64,6 +64,8 @@ void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int 
 // null); pass 0 writes T (cols x 8, ldt) = H and saves R; pass 1 adds H * R_saved to T.
 void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave, double *T, int ldt,
               double *coef, int *flags, const double *floor_ref);
+// out[o] = sum over g < G of part[g * nout + o] (fixed order), o < nout
+void sum_partials(hipStream_t s, const double *part, int G, int nout, double *out);
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,
                  const float *B, int ldb, int cb, double *H, int ldh, double alpha);
 // C[i*ldc + c] = beta*C + alpha * sum_a A[i*lda + a] * H[a*ldh + c]   (c < cc <= 16, ca <= 80)

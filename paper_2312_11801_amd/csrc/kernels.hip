@@ -493,6 +493,10 @@ void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int 
     else hipLaunchKernelGGL(k_cholqr_finish, dim3(1), dim3(kWG), 0, s, rs.partials, blocks, ca, H, ldh, flags, floor_ref);
 }
 
+void sum_partials(hipStream_t s, const double *part, int G, int nout, double *out) {
+    red_finish(s, part, G, nout, out, nout, nout, 1.0, 0.0);
+}
+
 void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int cb, double *H, int ldh) {
     red_finish(s, rs.partials, blocks, (ca + cb) * cb, H, cb, ldh, 1.0, 0.0);
 }

@@ -63,6 +63,10 @@ void add_small(hipStream_t s, int rows, int cols, const double *H, int ldh, doub
 void set_int(hipStream_t s, int *p, int count, int v);
 void nystrom_core(hipStream_t s, int n, int r, const double *Gm, double *H, double *lam, int *status);
 void interleave(hipStream_t s, int n, int r, const double *P, const float *Psi, double *out);
+// MaxCut rounding (App. E.1): S (n x 16) = sign of the first r columns of U (ties +1);
+// out[c] = S[:, c]^T C_s S[:, c] in FP64 (off-diagonal CSR values val, diagonal diag)
+int quad_forms(hipStream_t s, const RedScratch &rs, int n, int r, const int *rowptr, const int *col,
+               const double *val, const double *diag, const double *U, int ldu, double *S, double *out);
 void psi_to_double(hipStream_t s, long count, const float *a, double *b);
 
 }  // namespace usbs

@@ -403,3 +403,52 @@ void psi_to_double(hipStream_t s, long count, const float *a, double *b) {
 }
 
 }  // namespace usbs
+
+namespace usbs {
+// ---------------------------------------------------------------------------
+// MaxCut rounding (App. E.1): x_c = sign(U[:, c]) (ties to +1) for the r columns of the
+// Nystrom factor, and the quadratic forms x_c^T C_s x_c = sum_i c_ii + sum_{e in row i}
+// c_e x_ic x_{col(e)c} in FP64 from the FP64 copy of the off-diagonal values.  16 lanes
+// per row (lane = column); one partial sum per workgroup and column.
+// ---------------------------------------------------------------------------
+__global__ void k_sign_cols(int n, int r, const double *__restrict__ U, int ldu, double *__restrict__ S) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < (long)n * 16) {
+        const long i = e >> 4;
+        const int c = (int)(e & 15);
+        S[e] = (c < r) ? ((U[i * ldu + c] >= 0.0) ? 1.0 : -1.0) : 0.0;
+    }
+}
+__global__ __launch_bounds__(kWG) void k_quad_partials(int n, int r, const int *__restrict__ rowptr,
+                                                       const int *__restrict__ col, const double *__restrict__ val,
+                                                       const double *__restrict__ diag, const double *__restrict__ S,
+                                                       double *__restrict__ part) {
+    __shared__ double red[kWG];
+    const int c = threadIdx.x & 15;
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * (kWG / 16) + (threadIdx.x >> 4); i < n; i += (long)gridDim.x * (kWG / 16)) {
+        const double xi = S[i * 16 + c];
+        double s = 0.0;
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s += val[e] * S[(long)col[e] * 16 + c];
+        acc += diag[i] * xi * xi + xi * s;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        double t = 0.0;
+        for (int g = 0; g < kWG / 16; ++g) t += red[g * 16 + threadIdx.x];
+        if (threadIdx.x < r) part[(size_t)blockIdx.x * r + threadIdx.x] = t;
+    }
+}
+int quad_forms(hipStream_t s, const RedScratch &rs, int n, int r, const int *rowptr, const int *col,
+               const double *val, const double *diag, const double *U, int ldu, double *S, double *out) {
+    if (n <= 0 || r <= 0) return 0;
+    hipLaunchKernelGGL(k_sign_cols, dim3(cdiv_((long)n * 16, kWG)), dim3(kWG), 0, s, n, r, U, ldu, S);
+    int blocks = cdiv_(n, kWG / 16 * 4);
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_quad_partials, dim3(blocks), dim3(kWG), 0, s, n, r, rowptr, col, val, diag, S, rs.partials);
+    sum_partials(s, rs.partials, blocks, r, out);
+    return blocks;
+}
+}  // namespace usbs

@@ -1293,6 +1293,47 @@ int usbs_op_nystrom(usbs_handle *h, const double *P_dev, double *U_dev, double *
     }
 }
 
+int usbs_round_maxcut(usbs_handle *h, int8_t *x_out, double *cut_out, int32_t *column_out, double *cuts_out) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!h->sketch || h->r < 1) {
+        set_err(h, "usbs_round_maxcut: needs the Nystrom sketch (r > 0 and a test matrix)");
+        return USBS_E_INVALID;
+    }
+    try {
+        hipStream_t s = h->stream;
+        const int n = h->n, r = h->r;
+        // U of the Nystrom reconstruction of the current sketch (App. C.1)
+        interleave(s, n, r, h->P, h->psi, h->W2);
+        tn_reduce(s, h->rs, n, h->W2, 2 * r, 2 * r, h->W2, 2 * r, 2 * r, h->small, 2 * r, 1.0, 0.0);
+        nystrom_core(s, n, r, h->small, h->small + 1024, h->small + 2048, h->flag);
+        nn_update(s, n, h->W2, 2 * r, 2 * r, h->small + 1024, r, r, h->Zp, 16, 1.0, 0.0);
+        // x_c^T C x_c for the r sign vectors, FP64 (the base values, not the compute copy)
+        quad_forms(s, h->rs, n, r, h->rowptr, h->col, h->cbase, h->cdiag, h->Zp, 16, h->Ubuf, h->small + 3072);
+        std::vector<double> q(r);
+        int bad = 0;
+        HIPCHK(hipMemcpyAsync(q.data(), h->small + 3072, r * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (bad) throw DevError(USBS_E_NUMERIC, "Nystrom core matrix not positive definite");
+        int best = 0;
+        for (int c = 1; c < r; ++c)
+            if (q[c] > q[best]) best = c;   // first of equal values
+        if (cut_out) *cut_out = h->sigma * q[best];
+        if (column_out) *column_out = best;
+        if (cuts_out)
+            for (int c = 0; c < r; ++c) cuts_out[c] = h->sigma * q[c];
+        if (x_out) {
+            std::vector<double> S((size_t)n * 16);
+            HIPCHK(hipMemcpyAsync(S.data(), h->Ubuf, (size_t)n * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int i = 0; i < n; ++i) x_out[i] = S[(size_t)i * 16 + best] > 0.0 ? 1 : -1;
+        }
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
 int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *zbar, double *Pbar, double *scal) {
     if (!h || !h->ready) return USBS_E_STATE;
     if (t < 0) return USBS_E_INVALID;

@@ -29,7 +29,7 @@ EXPORTS = [
     "usbs_op_apply", "usbs_op_eigs", "usbs_op_lowrank_A", "usbs_op_sketch_update", "usbs_op_qp_data",
     "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling", "usbs_profile",
     "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
-    "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free",
+    "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free", "usbs_round_maxcut",
 ]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
 
@@ -134,6 +134,7 @@ def load_library(path: str | None = None):
         "usbs_server_get_stats": (ctypes.c_int, [vp, ctypes.POINTER(UsbsServerStats)]),
         "usbs_server_last_error": (ctypes.c_char_p, [vp]),
         "usbs_server_free": (None, [vp]),
+        "usbs_round_maxcut": (ctypes.c_int, [vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -256,6 +257,15 @@ class Solver:
         arrs = _ProblemArrays(grown, psi)
         self._check(self.lib.usbs_warm_start(self.h, ctypes.byref(arrs.c)))
         self.n, self.m = grown.n, grown.m
+
+    def round_maxcut(self) -> dict:
+        """Best of the r cuts sign(U[:, c]) of the current sketch (App. E.1)."""
+        x = np.zeros(self.n, dtype=np.int8)
+        cut = ctypes.c_double()
+        colm = ctypes.c_int32()
+        cuts = np.zeros(max(self.r, 1))
+        self._check(self.lib.usbs_round_maxcut(self.h, _ptr(x), ctypes.byref(cut), ctypes.byref(colm), _ptr(cuts)))
+        return {"cut": cut.value, "x": x, "column": colm.value, "cuts": cuts[:self.r]}
 
     def scaling(self) -> tuple[float, float]:
         s, t = ctypes.c_double(), ctypes.c_double()

@@ -268,3 +268,30 @@ def test_warm_start_grown_maxcut(cuda):
     p_ref = orc.to_original(sc, ref.primal_obj)
     assert abs(warm["primal_obj_scaled"] - ref.primal_obj) / (1 + abs(ref.primal_obj)) <= 1e-3
     assert abs(warm["primal_obj"] - p_ref) / abs(p_ref) <= 5e-3
+
+
+@pytest.mark.parametrize("kind", ["er", "planted"])
+def test_round_maxcut(cuda, kind):
+    """Rounding (App. E.1): the best of the r cuts sign(U[:, c]) equals the oracle's rounding
+    of the same Nystrom factor; the returned x achieves the reported weight; no cut exceeds
+    the certified dual bound, and on the planted graph none exceeds p* = #positive edges."""
+    from paper_2312_11801_amd import Params, Solver
+    if kind == "er":
+        prob = si.maxcut_er(301, 0.05, seed=11)
+    else:
+        prob = si.maxcut_planted_pm1(400, 6.0, seed=2)
+    psi = si.test_matrix(prob.n, 10, seed=3)
+    s = Solver(prob, Params(rho=0.1, max_iters=300), psi=psi)
+    out = s.solve()
+    rd = s.round_maxcut()
+    s.free()
+    i, j, w = prob.meta["edges_i"], prob.meta["edges_j"], prob.meta["weights"]
+    best, _ = orc.maxcut_round(out["U"], i, j, w)
+    x = rd["x"].astype(np.int64)
+    assert set(np.unique(x)) <= {-1, 1}
+    assert abs(orc.cut_value(i, j, w, x > 0) - rd["cut"]) <= 1e-9 * (1 + abs(rd["cut"]))
+    assert abs(best - rd["cut"]) <= 1e-9 * (1 + abs(best))
+    assert np.all(rd["cuts"] <= rd["cut"] + 1e-9 * (1 + abs(rd["cut"])))
+    assert rd["cut"] <= out["dual_bound"] * (1 + 1e-9)
+    if kind == "planted":
+        assert rd["cut"] <= prob.meta["p_star"] + 1e-9
