@@ -58,8 +58,8 @@ typedef struct usbs_handle usbs_handle;
  *   C: symmetric, CSR with both triangles and the diagonal (rowptr[n+1],
  *      col[nnz], val[nnz]); columns within a row in any order.
  *   A: triplets (a_row[t], a_i[t], a_j[t], a_v[t]) with a_i <= a_j, meaning
- *      <A_k, X> = sum over the triplets of row k of v * X_ij.  Each off-diagonal
- *      pair (i,j) may appear in at most one triplet.
+ *      <A_k, X> = sum over the triplets of row k of v * X_ij.  A pair (i,j) may
+ *      appear in several rows (and several times in one row: the values add).
  *   b[m], is_ineq[m] (1 = row belongs to I, i.e. <A_k, X> <= b_k).
  *   trace: tr(X*) (or the value the constraints fix, e.g. n for MaxCut),
  *      used by the scaling of App. E.

@@ -32,8 +32,9 @@ void spmm(hipStream_t s, int prec, int n, const int *rowptr, const int *col, con
 // d[i] = cdiag[i] - sum over the diagonal triplets of vertex i of v * y[k]
 void diag_shift(hipStream_t s, int n, const int *dptr, const int *dk, const double *dv,
                 const double *cdiag, const double *y, double *d);
-// val[slot[t]] = (cbase[slot[t]] - hv[t] * y[k[t]]) / scale  (constrained off-diagonal slots)
-void offdiag_refresh(hipStream_t s, int prec, int nt, const int *slot, const int *k,
+// val[slot[u]] = (cbase[slot[u]] - sum_{t in [ptr[u], ptr[u+1])} hv[t] * y[k[t]]) / scale for the
+// ns constrained off-diagonal slots (a slot may belong to several constraint rows)
+void offdiag_refresh(hipStream_t s, int prec, int ns, const int *slot, const int *ptr, const int *k,
                      const double *hv, const double *cbase, const double *y, double inv_scale,
                      void *val);
 // Gershgorin bound max_i (|d_i| + scale sum_e |val_e|) of the shifted operator into *out

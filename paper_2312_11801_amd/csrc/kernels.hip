@@ -273,29 +273,32 @@ void diag_shift(hipStream_t s, int n, const int *dptr, const int *dk, const doub
 }
 
 template <typename VT>
-__global__ void k_offdiag_refresh(int nt, const int *__restrict__ slot, const int *__restrict__ kk,
-                                  const double *__restrict__ hv, const double *__restrict__ cbase,
-                                  const double *__restrict__ y, double inv_scale, VT *__restrict__ val) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
-    const int sl = slot[t];
-    const double v = (cbase[sl] - hv[t] * y[kk[t]]) * inv_scale;
+__global__ void k_offdiag_refresh(int ns, const int *__restrict__ slot, const int *__restrict__ ptr,
+                                  const int *__restrict__ kk, const double *__restrict__ hv,
+                                  const double *__restrict__ cbase, const double *__restrict__ y, double inv_scale,
+                                  VT *__restrict__ val) {
+    const int u = blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= ns) return;
+    const int sl = slot[u];
+    double v = cbase[sl];
+    for (int t = ptr[u]; t < ptr[u + 1]; ++t) v -= hv[t] * y[kk[t]];
+    v *= inv_scale;
     if constexpr (sizeof(VT) == 2) val[sl] = f32_to_bf16((float)v);
     else val[sl] = (VT)v;
 }
 
-void offdiag_refresh(hipStream_t s, int prec, int nt, const int *slot, const int *k, const double *hv,
-                     const double *cbase, const double *y, double inv_scale, void *val) {
-    if (nt <= 0) return;
-    dim3 g(cdiv(nt, kWG));
+void offdiag_refresh(hipStream_t s, int prec, int ns, const int *slot, const int *ptr, const int *k,
+                     const double *hv, const double *cbase, const double *y, double inv_scale, void *val) {
+    if (ns <= 0) return;
+    dim3 g(cdiv(ns, kWG));
     if (prec == 0)
-        hipLaunchKernelGGL(k_offdiag_refresh<double>, g, dim3(kWG), 0, s, nt, slot, k, hv, cbase, y,
+        hipLaunchKernelGGL(k_offdiag_refresh<double>, g, dim3(kWG), 0, s, ns, slot, ptr, k, hv, cbase, y,
                            inv_scale, (double *)val);
     else if (prec == 1)
-        hipLaunchKernelGGL(k_offdiag_refresh<float>, g, dim3(kWG), 0, s, nt, slot, k, hv, cbase, y,
+        hipLaunchKernelGGL(k_offdiag_refresh<float>, g, dim3(kWG), 0, s, ns, slot, ptr, k, hv, cbase, y,
                            inv_scale, (float *)val);
     else
-        hipLaunchKernelGGL(k_offdiag_refresh<uint16_t>, g, dim3(kWG), 0, s, nt, slot, k, hv, cbase, y,
+        hipLaunchKernelGGL(k_offdiag_refresh<uint16_t>, g, dim3(kWG), 0, s, ns, slot, ptr, k, hv, cbase, y,
                            inv_scale, (uint16_t *)val);
 }
 

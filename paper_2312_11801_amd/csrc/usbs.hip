@@ -35,11 +35,14 @@ struct DevError : std::runtime_error {
                            std::string(#x) + ": " + hipGetErrorString(e_));                            \
     } while (0)
 
+// Device memory is stream-ordered (hipMallocAsync / hipFreeAsync on the handle's stream):
+// creating or releasing one handle never waits for work that other handles run on
+// other streams (a plain hipFree synchronises the whole device).
 template <typename T>
-T *dalloc(size_t count, std::vector<void *> &owned) {
+T *dalloc(size_t count, std::vector<void *> &owned, hipStream_t s) {
     void *p = nullptr;
     if (count == 0) count = 1;
-    HIPCHK(hipMalloc(&p, count * sizeof(T)));
+    HIPCHK(hipMallocAsync(&p, count * sizeof(T), s));
     owned.push_back(p);
     return (T *)p;
 }
@@ -78,7 +81,7 @@ struct usbs_handle {
     int *dptr = nullptr, *dk = nullptr;
     double *dv = nullptr;
     int n_offt = 0;
-    int *off_slot = nullptr, *off_k = nullptr;
+    int *off_slot = nullptr, *off_ptr = nullptr, *off_k = nullptr;
     double *off_hv = nullptr;
     int *kptr = nullptr, *ti = nullptr, *tj = nullptr;
     double *tv = nullptr, *b = nullptr, *ineq = nullptr;
@@ -244,9 +247,8 @@ HostProblem copy_problem(const usbs_problem *p, int r) {
 }
 
 void free_problem(usbs_handle *h) {
-    if (h->stream) (void)hipStreamSynchronize(h->stream);
-    else (void)hipDeviceSynchronize();
-    for (void *p : h->owned) (void)hipFree(p);
+    for (void *p : h->owned) (void)hipFreeAsync(p, h->stream);
+    (void)hipStreamSynchronize(h->stream);
     h->owned.clear();
 }
 
@@ -320,25 +322,31 @@ void upload(usbs_handle *h) {
         auto it = std::lower_bound(colv.begin() + rp[i], colv.begin() + rp[i + 1], j);
         return (int)(it - colv.begin());
     };
-    std::vector<int> osl, ok;
+    // constrained off-diagonal slots: both CSR slots of every off-diagonal triplet, grouped
+    // by slot (a pair may appear in several rows), so that each slot's value
+    // c_ij - sum_k (v_k / 2) y_k is formed by one thread in a fixed order
+    std::vector<int> osl, ok, optr;
     std::vector<double> ohv;
     {
-        std::vector<int64_t> seen;
-        for (auto &ot : offt) seen.push_back((int64_t)ot.i * n + ot.j);
-        std::sort(seen.begin(), seen.end());
-        for (size_t q = 1; q < seen.size(); ++q)
-            if (seen[q] == seen[q - 1])
-                throw DevError(USBS_E_INVALID, "an off-diagonal pair appears in more than one constraint triplet");
+        struct SlotEntry { int slot, k; double hv; };
+        std::vector<SlotEntry> ent;
+        ent.reserve(2 * offt.size());
+        for (auto &ot : offt) {
+            ent.push_back({slot_of(ot.i, ot.j), ot.k, ot.hv});
+            ent.push_back({slot_of(ot.j, ot.i), ot.k, ot.hv});
+        }
+        std::stable_sort(ent.begin(), ent.end(), [](const SlotEntry &a, const SlotEntry &b) { return a.slot < b.slot; });
+        for (size_t t = 0; t < ent.size(); ++t) {
+            if (t == 0 || ent[t].slot != ent[t - 1].slot) {
+                osl.push_back(ent[t].slot);
+                optr.push_back((int)t);
+            }
+            ok.push_back(ent[t].k);
+            ohv.push_back(ent[t].hv);
+        }
+        optr.push_back((int)ent.size());
     }
-    for (auto &ot : offt) {
-        osl.push_back(slot_of(ot.i, ot.j));
-        ok.push_back(ot.k);
-        ohv.push_back(ot.hv);
-        osl.push_back(slot_of(ot.j, ot.i));
-        ok.push_back(ot.k);
-        ohv.push_back(ot.hv);
-    }
-    h->n_offt = (int)osl.size();
+    h->n_offt = (int)osl.size();   // constrained slots
     h->has_offc = h->n_offt > 0;
     std::vector<int> dp(n + 1, 0), dkv;
     std::vector<double> dvv;
@@ -370,26 +378,27 @@ void upload(usbs_handle *h) {
     h->val_scale = (h->prec == USBS_PREC_BF16 && mx > 0.0) ? mx : 1.0;
 
     hipStream_t s = h->stream;
-    h->rowptr = dalloc<int>(n + 1, o);
-    h->col = dalloc<int>(nnz, o);
-    h->cbase = dalloc<double>(nnz, o);
+    h->rowptr = dalloc<int>(n + 1, o, h->stream);
+    h->col = dalloc<int>(nnz, o, h->stream);
+    h->cbase = dalloc<double>(nnz, o, h->stream);
     const size_t vsz = h->prec == 0 ? 8 : (h->prec == 1 ? 4 : 2);
-    h->val_cur = dalloc<char>(std::max(nnz, 1) * vsz, o);
-    h->val_c = h->has_offc ? (void *)dalloc<char>(std::max(nnz, 1) * vsz, o) : h->val_cur;
-    h->cdiag = dalloc<double>(n, o);
-    h->dshift = dalloc<double>(n, o);
-    h->dptr = dalloc<int>(n + 1, o);
-    h->dk = dalloc<int>(dkv.size(), o);
-    h->dv = dalloc<double>(dvv.size(), o);
-    h->off_slot = dalloc<int>(osl.size(), o);
-    h->off_k = dalloc<int>(ok.size(), o);
-    h->off_hv = dalloc<double>(ohv.size(), o);
-    h->kptr = dalloc<int>(m + 1, o);
-    h->ti = dalloc<int>(tiv.size(), o);
-    h->tj = dalloc<int>(tjv.size(), o);
-    h->tv = dalloc<double>(tvv.size(), o);
-    h->b = dalloc<double>(m, o);
-    h->ineq = dalloc<double>(m, o);
+    h->val_cur = dalloc<char>(std::max(nnz, 1) * vsz, o, h->stream);
+    h->val_c = h->has_offc ? (void *)dalloc<char>(std::max(nnz, 1) * vsz, o, h->stream) : h->val_cur;
+    h->cdiag = dalloc<double>(n, o, h->stream);
+    h->dshift = dalloc<double>(n, o, h->stream);
+    h->dptr = dalloc<int>(n + 1, o, h->stream);
+    h->dk = dalloc<int>(dkv.size(), o, h->stream);
+    h->dv = dalloc<double>(dvv.size(), o, h->stream);
+    h->off_slot = dalloc<int>(osl.size(), o, h->stream);
+    h->off_ptr = dalloc<int>(optr.size(), o, h->stream);
+    h->off_k = dalloc<int>(ok.size(), o, h->stream);
+    h->off_hv = dalloc<double>(ohv.size(), o, h->stream);
+    h->kptr = dalloc<int>(m + 1, o, h->stream);
+    h->ti = dalloc<int>(tiv.size(), o, h->stream);
+    h->tj = dalloc<int>(tjv.size(), o, h->stream);
+    h->tv = dalloc<double>(tvv.size(), o, h->stream);
+    h->b = dalloc<double>(m, o, h->stream);
+    h->ineq = dalloc<double>(m, o, h->stream);
     HIPCHK(hipMemcpyAsync(h->rowptr, rp.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->col, colv.data(), nnz * sizeof(int), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->cbase, cb.data(), nnz * sizeof(double), hipMemcpyHostToDevice, s));
@@ -401,6 +410,7 @@ void upload(usbs_handle *h) {
     }
     if (!osl.empty()) {
         HIPCHK(hipMemcpyAsync(h->off_slot, osl.data(), osl.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(h->off_ptr, optr.data(), optr.size() * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(h->off_k, ok.data(), ok.size() * sizeof(int), hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(h->off_hv, ohv.data(), ohv.size() * sizeof(double), hipMemcpyHostToDevice, s));
     }
@@ -417,7 +427,7 @@ void upload(usbs_handle *h) {
     HIPCHK(hipMemcpyAsync(h->ineq, inq.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
     h->sketch = !hp.psi.empty();
     if (h->sketch) {
-        h->psi = dalloc<float>((size_t)n * h->r, o);
+        h->psi = dalloc<float>((size_t)n * h->r, o, h->stream);
         HIPCHK(hipMemcpyAsync(h->psi, hp.psi.data(), (size_t)n * h->r * sizeof(float), hipMemcpyHostToDevice, s));
     }
     convert_values(s, h->prec, nnz, h->cbase, 1.0 / h->val_scale, h->val_cur);
@@ -425,68 +435,68 @@ void upload(usbs_handle *h) {
 
     // state and work arrays
     const int ldb = h->ldb;
-    h->y = dalloc<double>(m, o);
-    h->yc = dalloc<double>(m, o);
-    h->nu = dalloc<double>(m, o);
-    h->dnu = dalloc<double>(m, o);
-    h->zbar = dalloc<double>(m, o);
-    h->AX = dalloc<double>(m, o);
-    h->evec = dalloc<double>(m, o);
-    h->V = dalloc<double>((size_t)n * 16, o);
-    h->Vn = dalloc<double>((size_t)n * 16, o);
-    h->CV = dalloc<double>((size_t)n * 16, o);
-    h->Uritz = dalloc<double>((size_t)n * 16, o);
-    h->plan = dalloc<int>(16, o);
+    h->y = dalloc<double>(m, o, h->stream);
+    h->yc = dalloc<double>(m, o, h->stream);
+    h->nu = dalloc<double>(m, o, h->stream);
+    h->dnu = dalloc<double>(m, o, h->stream);
+    h->zbar = dalloc<double>(m, o, h->stream);
+    h->AX = dalloc<double>(m, o, h->stream);
+    h->evec = dalloc<double>(m, o, h->stream);
+    h->V = dalloc<double>((size_t)n * 16, o, h->stream);
+    h->Vn = dalloc<double>((size_t)n * 16, o, h->stream);
+    h->CV = dalloc<double>((size_t)n * 16, o, h->stream);
+    h->Uritz = dalloc<double>((size_t)n * 16, o, h->stream);
+    h->plan = dalloc<int>(16, o, h->stream);
     if (h->n_iso > 0) {
-        h->iso_idx = dalloc<int>(h->n_iso, o);
+        h->iso_idx = dalloc<int>(h->n_iso, o, h->stream);
         HIPCHK(hipMemcpyAsync(h->iso_idx, iso.data(), h->n_iso * sizeof(int), hipMemcpyHostToDevice, s));
-        h->Ucpl = dalloc<double>((size_t)n * 16, o);
+        h->Ucpl = dalloc<double>((size_t)n * 16, o, h->stream);
         HIPCHK(hipMemsetAsync(h->Ucpl, 0, (size_t)n * 16 * sizeof(double), s));
     } else {
         h->iso_idx = nullptr;
         h->Ucpl = h->Uritz;
     }
-    h->P = dalloc<double>((size_t)n * std::max(h->r, 1), o);
-    h->Bm = dalloc<double>((size_t)n * ldb, o);
-    h->W = dalloc<double>((size_t)n * 8, o);
-    h->Wt = dalloc<double>((size_t)n * 8, o);
-    h->W2 = dalloc<double>((size_t)n * 32, o);
-    h->Ubuf = dalloc<double>((size_t)n * 16, o);
-    h->Zp = dalloc<double>((size_t)n * 16, o);
-    h->Tm = dalloc<double>((size_t)ldb * ldb, o);
-    h->theta = dalloc<double>(ldb, o);
-    h->Ysm = dalloc<double>((size_t)ldb * 16, o);
-    h->TUU = dalloc<double>(256, o);
-    h->RtR = dalloc<double>(256, o);
-    h->Zc = dalloc<double>(128, o);
-    h->Hred = dalloc<double>((size_t)ldb * 16, o);
-    h->Hg = dalloc<double>((size_t)(ldb + 8) * 8, o);
-    h->coef = dalloc<double>((size_t)(ldb + 8) * 8, o);
-    h->Rsv = dalloc<double>(64, o);
-    h->Rinv = dalloc<double>(256, o);
-    h->res = dalloc<double>(16, o);
-    h->Hd = dalloc<double>(256, o);
-    h->dead = dalloc<int>(ldb, o);
-    h->flag = dalloc<int>(16, o);
-    h->zdead = dalloc<int>(16, o);
+    h->P = dalloc<double>((size_t)n * std::max(h->r, 1), o, h->stream);
+    h->Bm = dalloc<double>((size_t)n * ldb, o, h->stream);
+    h->W = dalloc<double>((size_t)n * 8, o, h->stream);
+    h->Wt = dalloc<double>((size_t)n * 8, o, h->stream);
+    h->W2 = dalloc<double>((size_t)n * 32, o, h->stream);
+    h->Ubuf = dalloc<double>((size_t)n * 16, o, h->stream);
+    h->Zp = dalloc<double>((size_t)n * 16, o, h->stream);
+    h->Tm = dalloc<double>((size_t)ldb * ldb, o, h->stream);
+    h->theta = dalloc<double>(ldb, o, h->stream);
+    h->Ysm = dalloc<double>((size_t)ldb * 16, o, h->stream);
+    h->TUU = dalloc<double>(256, o, h->stream);
+    h->RtR = dalloc<double>(256, o, h->stream);
+    h->Zc = dalloc<double>(128, o, h->stream);
+    h->Hred = dalloc<double>((size_t)ldb * 16, o, h->stream);
+    h->Hg = dalloc<double>((size_t)(ldb + 8) * 8, o, h->stream);
+    h->coef = dalloc<double>((size_t)(ldb + 8) * 8, o, h->stream);
+    h->Rsv = dalloc<double>(64, o, h->stream);
+    h->Rinv = dalloc<double>(256, o, h->stream);
+    h->res = dalloc<double>(16, o, h->stream);
+    h->Hd = dalloc<double>(256, o, h->stream);
+    h->dead = dalloc<int>(ldb, o, h->stream);
+    h->flag = dalloc<int>(16, o, h->stream);
+    h->zdead = dalloc<int>(16, o, h->stream);
     const int d = kMaxSvec;
-    h->raw = dalloc<double>(d * d + 4 * d, o);
-    h->qp = dalloc<double>(d * d + 2 * d + 2, o);
-    h->ipm = dalloc<double>(2 * kMaxK * kMaxK + 8, o);
-    h->VCV = dalloc<double>(256, o);
-    h->Gy = dalloc<double>(d * d + 4 * d, o);
-    h->Kc = dalloc<double>(256, o);
-    h->Qp = dalloc<double>(256, o);
-    h->Hsk = dalloc<double>(16 * 32, o);
-    h->VtPsi = dalloc<double>(16 * 32, o);
-    h->hz = dalloc<double>(256, o);
-    h->Rz = dalloc<double>(256, o);
-    h->sc = dalloc<double>(SC_COUNT, o);
-    h->small = dalloc<double>(4096, o);
+    h->raw = dalloc<double>(d * d + 4 * d, o, h->stream);
+    h->qp = dalloc<double>(d * d + 2 * d + 2, o, h->stream);
+    h->ipm = dalloc<double>(2 * kMaxK * kMaxK + 8, o, h->stream);
+    h->VCV = dalloc<double>(256, o, h->stream);
+    h->Gy = dalloc<double>(d * d + 4 * d, o, h->stream);
+    h->Kc = dalloc<double>(256, o, h->stream);
+    h->Qp = dalloc<double>(256, o, h->stream);
+    h->Hsk = dalloc<double>(16 * 32, o, h->stream);
+    h->VtPsi = dalloc<double>(16 * 32, o, h->stream);
+    h->hz = dalloc<double>(256, o, h->stream);
+    h->Rz = dalloc<double>(256, o, h->stream);
+    h->sc = dalloc<double>(SC_COUNT, o, h->stream);
+    h->small = dalloc<double>(4096, o, h->stream);
     h->rs.max_blocks = kRedMaxBlocks;
     h->rs.max_elems = kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec;
     if (h->rs.max_elems < kMaxBasis * 16) h->rs.max_elems = kMaxBasis * 16;
-    h->rs.partials = dalloc<double>((size_t)h->rs.max_blocks * h->rs.max_elems, o);
+    h->rs.partials = dalloc<double>((size_t)h->rs.max_blocks * h->rs.max_elems, o, h->stream);
     HIPCHK(hipMemsetAsync(h->V, 0, (size_t)n * 16 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(h->Vn, 0, (size_t)n * 16 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(h->CV, 0, (size_t)n * 16 * sizeof(double), s));
@@ -501,7 +511,7 @@ void upload(usbs_handle *h) {
 void shift_operator(usbs_handle *h, const double *y) {
     diag_shift(h->stream, h->n, h->dptr, h->dk, h->dv, h->cdiag, y, h->dshift);
     if (h->has_offc)
-        offdiag_refresh(h->stream, h->prec, h->n_offt, h->off_slot, h->off_k, h->off_hv, h->cbase, y,
+        offdiag_refresh(h->stream, h->prec, h->n_offt, h->off_slot, h->off_ptr, h->off_k, h->off_hv, h->cbase, y,
                         1.0 / h->val_scale, h->val_cur);
     // scale of the Lanczos tolerances and of the Cholesky-QR deflation floor
     op_bound(h->stream, h->rs, h->prec, h->n, h->rowptr, h->val_cur, h->val_scale, h->dshift, h->sc + SC_SCALE);

@@ -332,3 +332,36 @@ def served_batch(count: int = 256, n_lo: int = 500, n_hi: int = 5000, avg_degree
         grown = maxcut_problem(n2, i2, j2, np.ones(i2.size), name=f"req{r}_n{n2}")
         reqs.append({"id": r, "arrival": float(t[r]), "problem": base, "grown": grown})
     return reqs
+
+
+def general_overlap(n: int = 120, avg_degree: float = 6.0, n_rows: int = 40, terms: int = 3,
+                    pool: int = 30, seed: int = 0) -> SDPProblem:
+    """A general sparse constraint operator: C = W (signed graph, N(0,1) weights), rows
+    X_vv = 1 for every v, then n_rows inequality rows  -sum_{(i,j) in S_k} X_ij <= 0.2  whose
+    off-diagonal pairs S_k (terms each) are drawn from a small pool, so that the same pair
+    appears in several rows (the form of the existence-constraint rows of Sec. 5.3)."""
+    rng = np.random.default_rng([seed, 7])
+    m_e = int(round(n * avg_degree / 2))
+    i, j = random_edges(n, m_e, rng)
+    w = rng.standard_normal(m_e)
+    rowptr, col, val = sym_csr(n, i, j, w, None)
+    pi, pj = random_edges(n, pool, rng)
+    a_row = list(range(n))
+    a_i = list(range(n))
+    a_j = list(range(n))
+    a_v = [1.0] * n
+    for k in range(n_rows):
+        pick = rng.choice(pool, size=terms, replace=False)
+        for p in pick:
+            a_row.append(n + k)
+            a_i.append(int(pi[p]))
+            a_j.append(int(pj[p]))
+            a_v.append(-1.0)
+    b = np.concatenate([np.ones(n), np.full(n_rows, 0.2)])
+    ineq = np.concatenate([np.zeros(n, dtype=np.uint8), np.ones(n_rows, dtype=np.uint8)])
+    return SDPProblem(
+        n=n, rowptr=rowptr, col=col, val=val,
+        a_row=np.asarray(a_row, dtype=np.int32), a_i=np.asarray(a_i, dtype=np.int32),
+        a_j=np.asarray(a_j, dtype=np.int32), a_v=np.asarray(a_v, dtype=np.float64),
+        b=b, is_ineq=ineq, trace=float(n), name=f"general_overlap_n{n}_s{seed}",
+        meta={"edges_i": i, "edges_j": j, "weights": w})

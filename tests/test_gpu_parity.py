@@ -295,3 +295,39 @@ def test_round_maxcut(cuda, kind):
     assert rd["cut"] <= out["dual_bound"] * (1 + 1e-9)
     if kind == "planted":
         assert rd["cut"] <= prob.meta["p_star"] + 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_overlapping_rows_operator_and_solve(cuda, prec, tol):
+    """Constraint rows that share off-diagonal pairs (up to eight rows per pair): the refreshed
+    operator C_s - A^* y, A on low-rank factors, and a full solve against the oracle's solve."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob = si.general_overlap(120, seed=4)
+    rng = np.random.default_rng(9)
+    y = rng.standard_normal(prob.m) * 0.01
+    sc = orc.scale_problem(prob)
+    M = sc.C - orc.A_adjoint(prob, y)
+    s = Solver(prob, Params(precision=prec, k_c=3, k_p=0))
+    X = rng.standard_normal((prob.n, 8))
+    Y = torch.zeros((prob.n, 8), dtype=torch.float64, device="cuda")
+    s.op_apply(_dev(y, torch), _dev(X, torch), Y)
+    torch.cuda.synchronize()
+    ref = M @ X
+    assert np.abs(Y.cpu().numpy() - ref).max() / np.abs(ref).max() <= tol
+    W = rng.standard_normal((prob.n, 3))
+    lam = rng.random(3)
+    out = torch.zeros(prob.m, dtype=torch.float64, device="cuda")
+    s.op_lowrank_A(_dev(W, torch), lam, out)
+    refA = orc.A_lowrank(prob, W, lam)
+    assert np.abs(out.cpu().numpy() - refA).max() <= 1e-12 * (1 + np.abs(refA).max())
+    s.free()
+    if prec == "f64":
+        prm = Params(precision="f64", k_c=3, k_p=0, rho=0.1, max_iters=800)
+        s = Solver(prob, prm)
+        res = s.solve()
+        s.free()
+        assert res["converged"], res
+        ref = orc.usbs_solve(prob, orc.Params(rho=0.1, k_c=3, k_p=0, max_iters=800), keep_history=False)
+        assert ref.converged
+        assert abs(res["primal_obj_scaled"] - ref.primal_obj) / (1 + abs(ref.primal_obj)) <= 2e-3

@@ -201,15 +201,23 @@ def test_nystrom_error_bound_fact_c1():
 # ---------------------------------------------------------------------------
 # operators and scaling
 # ---------------------------------------------------------------------------
-def test_adjoint_identity_and_lowrank():
-    prob = si.cc_signed(30, avg_degree=4, seed=1)
+@pytest.mark.parametrize("kind", ["cc", "overlap"])
+def test_adjoint_identity_and_lowrank(kind):
+    """<A X, y> = <X, A^* y>, and A on low-rank factors equals A on the formed matrix; the
+    overlap case has off-diagonal pairs shared by up to eight rows."""
+    prob = si.cc_signed(30, avg_degree=4, seed=1) if kind == "cc" else si.general_overlap(60, seed=2)
     rng = np.random.default_rng(5)
     F = rng.standard_normal((prob.n, 3))
     lam = rng.random(3)
     X = (F * lam) @ F.T
     y = rng.standard_normal(prob.m)
-    assert abs(orc.A_apply(prob, X) @ y - np.sum(X * orc.A_adjoint(prob, y))) < 1e-10
-    assert np.abs(orc.A_lowrank(prob, F, lam) - orc.A_apply(prob, X)).max() < 1e-12
+    assert abs(orc.A_apply(prob, X) @ y - np.sum(X * orc.A_adjoint(prob, y))) < 1e-10 * (1 + abs(orc.A_apply(prob, X) @ y))
+    assert np.abs(orc.A_lowrank(prob, F, lam) - orc.A_apply(prob, X)).max() < 1e-12 * (1 + np.abs(X).max())
+    # a row's value is the sum of its triplets written out entry by entry
+    k = prob.n + 3 if kind == "overlap" else prob.n
+    sel = prob.a_row == k
+    direct = sum(v * X[i, j] for i, j, v in zip(prob.a_i[sel], prob.a_j[sel], prob.a_v[sel]))
+    assert abs(orc.A_apply(prob, X)[k] - direct) < 1e-12 * (1 + abs(direct))
 
 
 def test_scaling_units():
