@@ -106,7 +106,7 @@ def run_served(args) -> dict:
     Three passes over the same requests: all submitted at once (capacity, requests/s),
     then Poisson arrivals at 0.5x and 0.8x of that capacity (latency = arrival -> result,
     p50/p99).  Beside them, the plain form: one slot, FP64 products, requests one after
-    the other.  Both forms stop at the paper's 1e-3 criterion."""
+    the other.  Both forms stop at the paper's 1e-3 criterion or the same iteration cap."""
     import time as _t
     import sdp_inputs as si
     from paper_2312_11801_amd import Params, Server
@@ -116,7 +116,7 @@ def run_served(args) -> dict:
         q["psi_g"] = si.test_matrix(q["grown"].n, 10, seed=q["id"])
 
     def serve(slots, prec, gaps):
-        prm = Params(precision=prec, max_iters=2000, time_limit=0.0)
+        prm = Params(precision=prec, max_iters=args.served_max_iters, time_limit=0.0)
         sv = Server(slots=slots, params=prm)
         t0 = _t.perf_counter()
         rids, arrive = [], []
@@ -179,6 +179,8 @@ def main() -> int:
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--served-max-iters", type=int, default=500,
+                    help="iteration cap of every served solve (both forms)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration for HBM traffic)")
     args = ap.parse_args()

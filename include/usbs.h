@@ -100,6 +100,13 @@ typedef struct usbs_params {
     uint64_t seed;              /* start block of the cold Lanczos solve   */
     void *stream;               /* hipStream_t, NULL = default stream       */
     int32_t verbose;
+    int32_t autotune;           /* launch-shape tuning at usbs_create, cached per
+                                   (device, n bucket, nonzeros per row, precision):
+                                   0 = built-in shapes; 1 (default) = shapes that
+                                   leave every result bitwise unchanged (SpMM columns
+                                   per lane, grid of the MFMA updates); 2 = also the
+                                   partition of the matrix-core reductions (faster,
+                                   but rounding then depends on the choice)          */
 } usbs_params;
 
 typedef struct usbs_result {
@@ -216,6 +223,11 @@ int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_tot
  * cut only for the MaxCut form. */
 int usbs_round_maxcut(usbs_handle *h, int8_t *x_out, double *cut_out, int32_t *column_out,
                       double *cuts_out);
+
+/* Launch shapes chosen for this handle: out[5] = {SpMM variant for 8 columns, for 16
+ * columns (0/1/2 = 1/2/4 columns per lane), grid cap of the MFMA update, workgroup cap
+ * and rows in flight of the matrix-core reductions}; 0 = built-in default. */
+int usbs_get_tuning(const usbs_handle *h, int32_t *out);
 
 /* Scaling factors of the handle's problem: sigma = ||C||_F, trace. */
 int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace);

@@ -25,6 +25,17 @@ struct RedScratch {
     int max_elems;      // doubles per partial
 };
 
+// Launch-shape choices made by the autotuner (usbs.hip).  spmm8 / spmm16: 0 = one column
+// per lane, 1 = two, 2 = four (bitwise identical results); nn_cap: grid cap of the MFMA
+// update (identical results); red_cap / red_unr: workgroups and rows in flight of the
+// matrix-core reductions (these change the partition of the sum, hence rounding).
+// 0 everywhere means the built-in defaults.
+struct Tuning {
+    int spmm8 = 0, spmm16 = 0, nn_cap = 0, red_cap = 0, red_unr = 0;
+};
+// the tuning used by the launchers called from this host thread (nullptr: defaults)
+void set_tuning(const Tuning *t);
+
 // ---- sparse operator --------------------------------------------------
 // Y[i, c] = diag[i] * X[i, c] + scale * sum_e val[e] * X[col[e], c],  c < nb
 void spmm(hipStream_t s, int prec, int n, const int *rowptr, const int *col, const void *val,

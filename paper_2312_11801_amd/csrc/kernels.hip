@@ -177,10 +177,90 @@ __global__ __launch_bounds__(kWG) void k_spmm(int n, const int *__restrict__ row
     }
 }
 
+// Variant with P consecutive columns per lane (one P-wide load per gathered row
+// segment), L lanes per row.  Every (row, column) output accumulates the same products
+// in the same order as k_spmm (even and odd nonzeros in two partial sums), so the
+// variants give bitwise identical results and the choice is a pure launch-shape tuning.
+template <typename VT, typename ACC, int L, int P>
+__global__ __launch_bounds__(kWG) void k_spmm_p(int n, const int *__restrict__ rowptr,
+                                                const int *__restrict__ col,
+                                                const VT *__restrict__ val, ACC scale,
+                                                const double *__restrict__ diag,
+                                                const double *__restrict__ X, int ldx,
+                                                double *__restrict__ Y, int ldy, int nb) {
+    const int i = blockIdx.x * (kWG / L) + threadIdx.x / L;
+    const int c0 = (threadIdx.x % L) * P;
+    if (i >= n) return;
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    const int cc = (c0 + P <= nb) ? c0 : 0;   // lanes past nb read column block 0 and store nothing
+    ACC acc0[P], acc1[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc0[p] = acc1[p] = 0;
+    int e = e0;
+    for (; e + 1 < e1; e += 2) {
+        const int j0 = col[e], j1 = col[e + 1];
+        ACC v0, v1;
+        if constexpr (sizeof(VT) == 2) {
+            v0 = (ACC)bf16_to_f32(val[e]);
+            v1 = (ACC)bf16_to_f32(val[e + 1]);
+        } else {
+            v0 = (ACC)val[e];
+            v1 = (ACC)val[e + 1];
+        }
+        const double *x0 = X + (size_t)j0 * ldx + cc;
+        const double *x1 = X + (size_t)j1 * ldx + cc;
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            acc0[p] += v0 * (ACC)x0[p];
+            acc1[p] += v1 * (ACC)x1[p];
+        }
+    }
+    if (e < e1) {
+        const int j0 = col[e];
+        ACC v0;
+        if constexpr (sizeof(VT) == 2) v0 = (ACC)bf16_to_f32(val[e]);
+        else v0 = (ACC)val[e];
+        const double *x0 = X + (size_t)j0 * ldx + cc;
+#pragma unroll
+        for (int p = 0; p < P; ++p) acc0[p] += v0 * (ACC)x0[p];
+    }
+    if (c0 + P <= nb) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            const double xi = X[(size_t)i * ldx + c0 + p];
+            Y[(size_t)i * ldy + c0 + p] = diag[i] * xi + (double)(scale * (acc0[p] + acc1[p]));
+        }
+    }
+}
+
+// launch-shape choices of the tuned kernels (per handle; see usbs.hip for the tuner)
+static thread_local const Tuning *g_tune = nullptr;
+void set_tuning(const Tuning *t) { g_tune = t; }
+
 template <typename VT, typename ACC>
 static void spmm_t(hipStream_t s, int n, const int *rowptr, const int *col, const VT *val, ACC scale,
                    const double *diag, const double *X, int ldx, double *Y, int ldy, int nb) {
     if (n <= 0) return;
+    // P columns per lane needs nb to be a multiple of P (every column owned by one lane)
+    const int var = g_tune ? (nb <= 8 ? g_tune->spmm8 : g_tune->spmm16) : 0;
+    if (var == 1 && nb % 2 == 0) {
+        if (nb <= 8)
+            hipLaunchKernelGGL((k_spmm_p<VT, ACC, 4, 2>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, rowptr, col,
+                               val, scale, diag, X, ldx, Y, ldy, nb);
+        else
+            hipLaunchKernelGGL((k_spmm_p<VT, ACC, 8, 2>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, rowptr, col,
+                               val, scale, diag, X, ldx, Y, ldy, nb);
+        return;
+    }
+    if (var == 2 && nb % 4 == 0) {
+        if (nb <= 8)
+            hipLaunchKernelGGL((k_spmm_p<VT, ACC, 2, 4>), dim3(cdiv(n, kWG / 2)), dim3(kWG), 0, s, n, rowptr, col,
+                               val, scale, diag, X, ldx, Y, ldy, nb);
+        else
+            hipLaunchKernelGGL((k_spmm_p<VT, ACC, 4, 4>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, rowptr, col,
+                               val, scale, diag, X, ldx, Y, ldy, nb);
+        return;
+    }
     if (nb <= 8) {
         hipLaunchKernelGGL((k_spmm<VT, ACC, 8>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, rowptr, col,
                            val, scale, diag, X, ldx, Y, ldy, nb);
@@ -462,6 +542,7 @@ __global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict
 
 static int mfma_blocks(const RedScratch &rs, int n) {
     int blocks = cdiv(n, 64);   // at least 16 rows per wavefront
+    if (g_tune && g_tune->red_cap > 0 && blocks > g_tune->red_cap) blocks = g_tune->red_cap;
     if (blocks > rs.max_blocks) blocks = rs.max_blocks;
     if (blocks < 1) blocks = 1;
     return blocks;
@@ -471,12 +552,21 @@ int reorth_partials(hipStream_t s, const RedScratch &rs, int n, const double *A,
                     int ldb, int cb, hipEvent_t ev_start, hipEvent_t ev_stop) {
     (void)cb;   // always 8 (one Lanczos block)
     const int blocks = mfma_blocks(rs, n);
-    if (ev_start && ev_stop)   // events carry this dispatch's own start / end time
-        hipExtLaunchKernelGGL((k_tn_mfma<1, 4, true>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A, lda,
-                              ca, B, ldb, kBlk, rs.partials);
-    else
+    const bool u2 = g_tune && g_tune->red_unr == 2;
+    if (ev_start && ev_stop) {   // events carry this dispatch's own start / end time
+        if (u2)
+            hipExtLaunchKernelGGL((k_tn_mfma<1, 2, true>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A,
+                                  lda, ca, B, ldb, kBlk, rs.partials);
+        else
+            hipExtLaunchKernelGGL((k_tn_mfma<1, 4, true>), dim3(blocks), dim3(kWG), 0, s, ev_start, ev_stop, 0, n, A,
+                                  lda, ca, B, ldb, kBlk, rs.partials);
+    } else if (u2) {
+        hipLaunchKernelGGL((k_tn_mfma<1, 2, true>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, kBlk,
+                           rs.partials);
+    } else {
         hipLaunchKernelGGL((k_tn_mfma<1, 4, true>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, kBlk,
                            rs.partials);
+    }
     return blocks;
 }
 void tn_reduce(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *B,
@@ -707,8 +797,11 @@ __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict
 
 static bool use_nn_mfma(int n, int cc) { return n > 0 && cc <= 16; }
 static int nn_mfma_blocks(int n) {
-    int b = cdiv(((long)n + 15) / 16, 4);   // one row group per wavefront up to 4096 workgroups
-    return b < 1 ? 1 : (b > 4096 ? 4096 : b);
+    // one row group per wavefront up to the tuned cap (4096 workgroups by default); the
+    // grid size does not change any output value
+    const int cap = (g_tune && g_tune->nn_cap > 0) ? g_tune->nn_cap : 4096;
+    int b = cdiv(((long)n + 15) / 16, 4);
+    return b < 1 ? 1 : (b > cap ? cap : b);
 }
 
 template <typename TC>

@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <stdexcept>
 #include <string>
 #include <utility>
@@ -108,6 +110,8 @@ struct usbs_handle {
            *hz = nullptr, *Rz = nullptr;
     int *zdead = nullptr;
     RedScratch rs{};
+
+    Tuning tune;   // launch shapes (autotuner)
 
     int64_t matvecs = 0;
     int iters = 0;
@@ -825,7 +829,126 @@ void check_params(const usbs_params *p) {
     if (p->precision < 0 || p->precision > 2) throw DevError(USBS_E_INVALID, "unknown precision");
     if (p->units != USBS_UNITS_SCALED && p->units != USBS_UNITS_ORIGINAL)
         throw DevError(USBS_E_INVALID, "unknown units");
+    if (p->autotune < 0 || p->autotune > 2) throw DevError(USBS_E_INVALID, "autotune must be 0, 1 or 2");
 }
+
+// ---------------------------------------------------------------------------
+// autotuner: times the candidate launch shapes of the tuned kernels on the handle's own
+// buffers and shapes (hipEvents on its stream, best of three after a warm-up launch)
+// and keeps the fastest; results are cached per (device, log2 n, log2 nonzeros per row,
+// precision, mode) for the life of the process
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int dev, nb, zb, prec, mode;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(dev, nb, zb, prec, mode) < std::tie(o.dev, o.nb, o.zb, o.prec, o.mode);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuning> g_tune_cache;
+
+template <typename F>
+float time_launch(hipStream_t s, F &&launch) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    launch();
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+        HIPCHK(hipEventRecord(e0, s));
+        launch();
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+void autotune(usbs_handle *h) {
+    h->tune = Tuning{};
+    const int mode = h->prm.autotune;
+    if (mode == 0) return;
+    const int n = h->n;
+    auto lg = [](double v) { int b = 0; while (v >= 2.0) { v *= 0.5; ++b; } return b; };
+    const TuneKey key{h->dev, lg(n), lg(1.0 + (double)h->nnz / std::max(n, 1)), h->prec, mode};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            h->tune = it->second;
+            return;
+        }
+    }
+    hipStream_t s = h->stream;
+    const int ldb = h->ldb, cols = ldb - 8;
+    Tuning t;
+    set_tuning(&t);
+    // SpMM with 8 and 16 columns: 1, 2 or 4 columns per lane
+    for (int nb : {8, 16}) {
+        float best = 1e30f;
+        int arg = 0;
+        for (int var = 0; var < 3; ++var) {
+            (nb == 8 ? t.spmm8 : t.spmm16) = var;
+            const float ms = time_launch(s, [&] {
+                spmm(s, h->prec, n, h->rowptr, h->col, h->val_cur, h->val_scale, h->dshift, h->Bm, ldb,
+                     nb == 8 ? h->W : h->Ubuf, nb == 8 ? 8 : 16, nb);
+            });
+            if (ms < best) {
+                best = ms;
+                arg = var;
+            }
+        }
+        (nb == 8 ? t.spmm8 : t.spmm16) = arg;
+    }
+    // grid cap of the MFMA update ([Q W] coef as in a Lanczos block step)
+    {
+        float best = 1e30f;
+        int arg = 4096;
+        for (int cap : {1024, 2048, 4096, 8192}) {
+            t.nn_cap = cap;
+            const float ms = time_launch(s, [&] {
+                nn_update2(s, n, h->Bm, ldb, cols, h->W, 8, 8, h->coef, 8, 8, h->Wt, 8);
+            });
+            if (ms < best) {
+                best = ms;
+                arg = cap;
+            }
+        }
+        t.nn_cap = arg;
+    }
+    // partition of the matrix-core reductions (changes rounding: only on request)
+    if (mode == 2) {
+        float best = 1e30f;
+        int bc = 512, bu = 4;
+        for (int cap : {128, 256, 512})
+            for (int unr : {2, 4}) {
+                t.red_cap = cap;
+                t.red_unr = unr;
+                const float ms = time_launch(s, [&] { reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8); });
+                if (ms < best) {
+                    best = ms;
+                    bc = cap;
+                    bu = unr;
+                }
+            }
+        t.red_cap = bc;
+        t.red_unr = bu;
+    }
+    set_tuning(nullptr);
+    h->tune = t;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = t;
+}
+
+// the handle's launch shapes for every kernel launched from this thread during a call
+struct TuneScope {
+    explicit TuneScope(const usbs_handle *h) { set_tuning(h ? &h->tune : nullptr); }
+    ~TuneScope() { set_tuning(nullptr); }
+};
 
 void configure(usbs_handle *h, const usbs_params *p) {
     h->prm = *p;
@@ -880,6 +1003,7 @@ int usbs_default_params(usbs_params *p) {
     p->seed = 0;
     p->stream = nullptr;
     p->verbose = 0;
+    p->autotune = 1;
     return USBS_OK;
 }
 
@@ -895,6 +1019,8 @@ int usbs_create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **
         if (h->hp.psi.empty()) h->r = 0;
         set_geometry(h, h->hp.n);
         upload(h);
+        autotune(h);
+        TuneScope tsc(h);
         cold_start(h);
         h->ready = true;
     } catch (const DevError &e) {
@@ -914,6 +1040,7 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
         return USBS_E_STATE;
     }
     try {
+        TuneScope tsc(h);
         const auto t0 = std::chrono::steady_clock::now();
         const usbs_params &p = h->prm;
         std::vector<double> sc(SC_COUNT);
@@ -1103,6 +1230,16 @@ int64_t usbs_footprint_bytes(const usbs_problem *p, const usbs_params *prm) {
     return b + b / 20 + (1 << 20);   // allocator rounding
 }
 
+int usbs_get_tuning(const usbs_handle *h, int32_t *out) {
+    if (!h || !out) return USBS_E_INVALID;
+    out[0] = h->tune.spmm8;
+    out[1] = h->tune.spmm16;
+    out[2] = h->tune.nn_cap;
+    out[3] = h->tune.red_cap;
+    out[4] = h->tune.red_unr;
+    return USBS_OK;
+}
+
 int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace) {
     if (!h || !h->ready) return USBS_E_STATE;
     if (sigma) *sigma = h->sigma;
@@ -1118,6 +1255,7 @@ int usbs_op_apply(usbs_handle *h, const double *y_dev, const double *X_dev, int3
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         shift_operator(h, y_dev);
         apply_op(h, X_dev, ldx, Y_dev, ldy, nb);
         HIPCHK(hipStreamSynchronize(h->stream));
@@ -1135,6 +1273,7 @@ int usbs_op_eigs(usbs_handle *h, const double *y_dev, int32_t k, const double *s
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         hipStream_t s = h->stream;
         shift_operator(h, y_dev);
         if (start_dev) copy_cols(s, h->n, start_dev, 16, 16, h->Ubuf, 16);
@@ -1159,6 +1298,7 @@ int usbs_op_lowrank_A(usbs_handle *h, const double *W_dev, int32_t q, const doub
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         std::vector<double> K(q * q, 0.0);
         for (int j = 0; j < q; ++j) K[j * q + j] = lam[j];
         HIPCHK(hipMemcpyAsync(h->Kc, K.data(), q * q * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -1182,6 +1322,7 @@ int usbs_op_sketch_update(usbs_handle *h, double g, const double *W_dev, int32_t
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         hipStream_t s = h->stream;
         const int r = h->r;
         tn_reduce_f(s, h->rs, h->n, W_dev, q, q, h->psi, r, r, h->VtPsi, r, 1.0);
@@ -1208,6 +1349,7 @@ int usbs_op_qp_data(usbs_handle *h, const double *V_dev, int32_t k, const double
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         hipStream_t s = h->stream;
         const int n = h->n, m = h->m, d = k * (k + 1) / 2;
         copy_cols(s, n, V_dev, k, k, h->Zp, 16);
@@ -1249,6 +1391,7 @@ int usbs_op_ipm(usbs_handle *h, int32_t k, const double *Q11, const double *q12,
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         hipStream_t s = h->stream;
         const int d = k * (k + 1) / 2;
         std::vector<double> qpv(d * d + 2 * d + 2);
@@ -1283,6 +1426,7 @@ int usbs_op_nystrom(usbs_handle *h, const double *P_dev, double *U_dev, double *
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         hipStream_t s = h->stream;
         const int n = h->n, r = h->r;
         interleave(s, n, r, P_dev, h->psi, h->W2);
@@ -1310,6 +1454,7 @@ int usbs_round_maxcut(usbs_handle *h, int8_t *x_out, double *cut_out, int32_t *c
         return USBS_E_INVALID;
     }
     try {
+        TuneScope tsc(h);
         hipStream_t s = h->stream;
         const int n = h->n, r = h->r;
         // U of the Nystrom reconstruction of the current sketch (App. C.1)
@@ -1348,6 +1493,7 @@ int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *z
     if (!h || !h->ready) return USBS_E_STATE;
     if (t < 0) return USBS_E_INVALID;
     try {
+        TuneScope tsc(h);
         for (int q = 0; q < t; ++q) iterate(h);
         hipStream_t s = h->stream;
         std::vector<double> sc(SC_COUNT);
@@ -1380,6 +1526,7 @@ int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
         return USBS_E_STATE;
     }
     try {
+        TuneScope tsc(h);
         hipStream_t s = h->stream;
         const int n0 = h->n, m0 = h->m, r = h->r, k = h->k;
         HostProblem hp = copy_problem(grown, r);
@@ -1411,6 +1558,8 @@ int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
         h->hp = std::move(hp);
         set_geometry(h, h->hp.n);
         upload(h);
+        autotune(h);
+        set_tuning(&h->tune);
         const int n = h->n, m = h->m;
         init_scalars(h);
         // y: pad with zeros; y_s = y / ||C||_F rescales by sigma_old / sigma_new

@@ -30,6 +30,7 @@ EXPORTS = [
     "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling", "usbs_profile",
     "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
     "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free", "usbs_round_maxcut",
+    "usbs_get_tuning",
 ]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
 
@@ -52,7 +53,7 @@ class UsbsParams(ctypes.Structure):
         ("lanczos_max_restarts", ctypes.c_int32), ("lanczos_tol", ctypes.c_double),
         ("lanczos_tol_final", ctypes.c_double),
         ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
-        ("verbose", ctypes.c_int32),
+        ("verbose", ctypes.c_int32), ("autotune", ctypes.c_int32),
     ]
 
 
@@ -135,6 +136,7 @@ def load_library(path: str | None = None):
         "usbs_server_last_error": (ctypes.c_char_p, [vp]),
         "usbs_server_free": (None, [vp]),
         "usbs_round_maxcut": (ctypes.c_int, [vp, vp, vp, vp, vp]),
+        "usbs_get_tuning": (ctypes.c_int, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -178,12 +180,14 @@ class Params:
     precision: str = "f64"
     seed: int = 0
     verbose: int = 0
+    autotune: int = 1
 
     def to_c(self, stream: int | None) -> UsbsParams:
         p = UsbsParams()
         load_library().usbs_default_params(ctypes.byref(p))
         for f in ("alpha", "rho", "beta", "k_c", "k_p", "r", "eps_gap", "eps_infeas", "max_iters", "time_limit",
-                  "lanczos_steps", "lanczos_max_restarts", "lanczos_tol", "lanczos_tol_final", "seed", "verbose"):
+                  "lanczos_steps", "lanczos_max_restarts", "lanczos_tol", "lanczos_tol_final", "seed", "verbose",
+                  "autotune"):
             setattr(p, f, getattr(self, f))
         p.units = UNITS[self.units]
         p.precision = PREC[self.precision]
@@ -266,6 +270,11 @@ class Solver:
         cuts = np.zeros(max(self.r, 1))
         self._check(self.lib.usbs_round_maxcut(self.h, _ptr(x), ctypes.byref(cut), ctypes.byref(colm), _ptr(cuts)))
         return {"cut": cut.value, "x": x, "column": colm.value, "cuts": cuts[:self.r]}
+
+    def tuning(self) -> dict:
+        t = np.zeros(5, dtype=np.int32)
+        self._check(self.lib.usbs_get_tuning(self.h, _ptr(t)))
+        return dict(zip(("spmm8", "spmm16", "nn_cap", "red_cap", "red_unr"), t.tolist()))
 
     def scaling(self) -> tuple[float, float]:
         s, t = ctypes.c_double(), ctypes.c_double()

@@ -331,3 +331,27 @@ def test_overlapping_rows_operator_and_solve(cuda, prec, tol):
         ref = orc.usbs_solve(prob, orc.Params(rho=0.1, k_c=3, k_p=0, max_iters=800), keep_history=False)
         assert ref.converged
         assert abs(res["primal_obj_scaled"] - ref.primal_obj) / (1 + abs(ref.primal_obj)) <= 2e-3
+
+
+def test_autotune_invariant_shapes(cuda):
+    """Mode 1 of the launch-shape tuner only picks shapes that leave results bitwise
+    unchanged: twenty iterations at n = 20,000 give identical states with tuning off and
+    on; the chosen shapes are among the candidates."""
+    from paper_2312_11801_amd import Params, Solver
+    prob = si.maxcut_sparse_pm1(20000, 6.0, seed=0)
+    psi = si.test_matrix(prob.n, 10, seed=0)
+    outs = []
+    for mode in (0, 1):
+        s = Solver(prob, Params(precision="f32", autotune=mode), psi=psi)
+        st = s.step_iterate(20, 11)
+        tune = s.tuning()
+        s.free()
+        outs.append((st, tune))
+    (a, t0), (b, t1) = outs
+    print("tuning", t1)
+    assert t0 == {"spmm8": 0, "spmm16": 0, "nn_cap": 0, "red_cap": 0, "red_unr": 0}
+    assert t1["spmm8"] in (0, 1, 2) and t1["spmm16"] in (0, 1, 2) and t1["nn_cap"] in (1024, 2048, 4096, 8192)
+    assert t1["red_cap"] == 0 and t1["red_unr"] == 0
+    for key in ("f", "rel_gap", "rel_infeas", "lambda1", "descents"):
+        assert a[key] == b[key], key
+    assert np.array_equal(a["y"], b["y"]) and np.array_equal(a["V"], b["V"])
