@@ -166,7 +166,7 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
                 cand_hi = row16_min(cand_hi);
                 if (cand_lo > -1e308) lo = cand_lo;
                 if (cand_hi < 1e308) hi = cand_hi;
-                if (hi - lo <= 2.2e-16 * fmax(fabs(lo), fabs(hi)) + 1e-3 * 2.2e-16 * tn) break;
+                if (hi - lo <= 1e-15 * tn) break;   // absolute accuracy eps * ||T||, as a stable solver
             }
             if (l == 0) ws->lam[g] = 0.5 * (lo + hi);
         }
@@ -188,7 +188,10 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
                 st = st * 1664525u + 1013904223u;
                 x[i] = ((double)(st >> 8) * (1.0 / 16777216.0)) - 0.5;
             }
-            for (int rep = 0; rep < 2; ++rep) {
+            // one solve: with lambda accurate to ~1e-15 ||T|| the target component grows by
+            // ~gap / 1e-15 against the others (vectors of a cluster span its invariant
+            // subspace and are orthonormalised below)
+            for (int rep = 0; rep < 1; ++rep) {
                 // eliminate T - lambda I with partial pivoting; rows of U in U0/U1/U2.
                 // Branch-free (the four lanes of a wave follow different vectors) with the
                 // next row's entries loaded one step ahead.
