@@ -40,7 +40,7 @@ def reorth_bytes(n: int, cols: int, nb: int) -> float:
     return n * (cols + nb) * 8
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tn_reduce_reorth_c2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tn_mfma_reorth_c2_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2312_11801_amd", "csrc", "kernels.hip")
 
 
@@ -275,7 +275,7 @@ def main() -> int:
                "dual_bound": out["dual_bound"], "lanczos_matvecs": out["lanczos_matvecs"]}
 
     # ---- roofline of the dominant bandwidth kernel (first stage of the re-orthogonalisation
-    # reductions, k_tn_reduce<double, 1>) ----
+    # reductions, k_tn_mfma<1, UNR, true>) ----
     # algorithmic bytes per launch averaged over the basis widths of a restart cycle
     # (block j of 8 reduces [Q W] with Q the first 16 + 8 (j + 1) columns, j = 0..s-1)
     widths = [16 + 8 * (j + 1) for j in range(prm.lanczos_steps)]
@@ -308,7 +308,7 @@ def main() -> int:
                    "lanczos_max_restarts": prm.lanczos_max_restarts, "precision": args.precision},
         "time_to_gap": ttg,
         "roofline": {
-            "bound": "hbm", "kernel": "k_tn_reduce<double, 1> (first stage of B^T W in the Krylov re-orthogonalisation)",
+            "bound": "hbm", "kernel": "k_tn_mfma<1, UNR, true> (first stage of [Q W]^T W in the Krylov re-orthogonalisation, FP64 MFMA)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": measured_traffic() if (args.workload == "c2" and n == 20000 and args.precision == "f32") else None,

@@ -208,7 +208,7 @@ int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *z
  * the category being timed (optionally resetting them), then times 'category' from now
  * on (-1 = none).  Used by the benchmark for the roofline of the dominant kernel. */
 #define USBS_PROF_SPMM 0   /* (C - A^* y) X block products                    */
-#define USBS_PROF_REORTH 1 /* first stage of the B^T W reductions of the Krylov block re-orthogonalisation (kernel k_tn_reduce<double, 1>; the finisher is not included) */
+#define USBS_PROF_REORTH 1 /* first stage of the B^T W reductions of the Krylov block re-orthogonalisation (kernel k_tn_mfma<1, UNR, true>; the finisher is not included) */
 #define USBS_PROF_RITZ 2   /* projected (Rayleigh-Ritz) eigenproblem          */
 #define USBS_PROF_IPM 3    /* master-QP interior point solve                  */
 #define USBS_PROF_COUNT 4
