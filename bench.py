@@ -103,10 +103,13 @@ def percentile(xs, q):
 def run_served(args) -> dict:
     """Served batch: MaxCut SDPs of uneven n (500..5000, G(n, 8/(n-1)), unit weights), each
     followed by its grown version (+1% vertices) warm-started from the resident state.
-    Three passes over the same requests: all submitted at once (capacity, requests/s),
-    then Poisson arrivals at 0.5x and 0.8x of that capacity (latency = arrival -> result,
-    p50/p99).  Beside them, the plain form: one slot, FP64 products, requests one after
-    the other.  Both forms stop at the paper's 1e-3 criterion or the same iteration cap."""
+    Passes over the same requests: all submitted at once (capacity, requests/s), then
+    Poisson arrivals at fractions of that capacity (latency = arrival -> result, p50/p99).
+    The served form is the packed server (every admitted instance one workgroup of the
+    packed launches, FP32 products) or the streams server (one worker thread and stream per
+    slot).  Beside it, the plain form: one slot, FP64 products, requests one after the other,
+    on the first --plain-requests requests.  Every form stops at the paper's 1e-3 criterion
+    or the same iteration cap."""
     import time as _t
     import sdp_inputs as si
     from paper_2312_11801_amd import Params, Server
@@ -115,22 +118,22 @@ def run_served(args) -> dict:
         q["psi"] = si.test_matrix(q["problem"].n, 10, seed=q["id"])
         q["psi_g"] = si.test_matrix(q["grown"].n, 10, seed=q["id"])
 
-    def serve(slots, prec, gaps):
+    def serve(mode, slots, prec, gaps, count):
         prm = Params(precision=prec, max_iters=args.served_max_iters, time_limit=0.0)
-        sv = Server(slots=slots, params=prm)
+        sv = Server(slots=slots, params=prm, mode=mode, iters_per_launch=args.iters_per_launch)
         t0 = _t.perf_counter()
-        rids, arrive = [], []
-        for q, g in zip(reqs, gaps):
+        rids = []
+        for q, g in zip(reqs[:count], gaps):
             wait = t0 + g - _t.perf_counter()
             if wait > 0:
                 _t.sleep(wait)
-            arrive.append(_t.perf_counter() - t0)
             rids.append(sv.submit(q["problem"], q["psi"], q["grown"], q["psi_g"]))
         outs = []
         for i, r in enumerate(rids):
             outs.append(sv.wait(r))
-            print(f"[served] slots={slots} {prec}: request {i + 1}/{len(rids)} done at "
-                  f"{_t.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+            if (i + 1) % max(1, len(rids) // 8) == 0 or i + 1 == len(rids):
+                print(f"[served] {mode} slots={slots} {prec}: request {i + 1}/{len(rids)} done at "
+                      f"{_t.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
         t1 = _t.perf_counter()
         st = sv.stats()
         sv.close()
@@ -139,26 +142,29 @@ def run_served(args) -> dict:
         gap = max(max(o["base"]["rel_gap"], o["grown"]["rel_gap"]) for o in outs)
         inf = max(max(o["base"]["rel_infeas"], o["grown"]["rel_infeas"]) for o in outs)
         warm_speedup = [o["base"]["iters"] / max(o["grown"]["iters"], 1) for o in outs]
-        return {"slots": slots, "precision": prec, "seconds": t1 - t0, "requests_per_s": len(outs) / (t1 - t0),
+        iters = sum(o["base"]["iters"] + o["grown"]["iters"] for o in outs)
+        return {"mode": mode, "slots": slots, "precision": prec, "requests": len(outs), "seconds": t1 - t0,
+                "requests_per_s": len(outs) / (t1 - t0), "usbs_iterations_per_s": iters / (t1 - t0),
                 "p50_latency_s": percentile(lat, 50), "p99_latency_s": percentile(lat, 99),
                 "converged": ok, "max_rel_gap": gap, "max_rel_infeas": inf,
                 "median_iters_cold_over_warm": percentile(warm_speedup, 50), "peak_running": st["peak_running"],
                 "peak_hbm_bytes": st["peak_used_bytes"]}
 
     import numpy as np
-    zero = [0.0] * len(reqs)
-    cap = serve(args.slots, args.precision, zero)
+    slots = args.slots if args.slots > 0 else (256 if args.serve_mode == "packed" else 4)
+    nreq = len(reqs)
+    cap = serve(args.serve_mode, slots, args.precision, [0.0] * nreq, nreq)
     rng = np.random.default_rng(7)
     out = {"capacity": cap, "loads": []}
-    for load in (0.5, 0.8):
+    for load in [float(x) for x in args.loads.split(",") if x.strip()]:
         rate = load * cap["requests_per_s"]
-        gaps = np.concatenate([[0.0], np.cumsum(rng.exponential(1.0 / rate, size=len(reqs) - 1))])
-        r = serve(args.slots, args.precision, list(gaps))
+        gaps = np.concatenate([[0.0], np.cumsum(rng.exponential(1.0 / rate, size=nreq - 1))])
+        r = serve(args.serve_mode, slots, args.precision, list(gaps), nreq)
         r["offered_load"] = load
         out["loads"].append(r)
-    if not args.no_plain:
-        out["plain_fp64_one_slot"] = serve(1, "f64", zero)
-        out["speedup_vs_plain"] = out["plain_fp64_one_slot"]["seconds"] / cap["seconds"]
+    if args.plain_requests > 0:
+        out["plain_fp64_one_slot"] = serve("streams", 1, "f64", [0.0] * nreq, min(args.plain_requests, nreq))
+        out["throughput_vs_plain"] = cap["requests_per_s"] / out["plain_fp64_one_slot"]["requests_per_s"]
     return out
 
 
@@ -176,9 +182,13 @@ def main() -> int:
     ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "served"],
                     help="c2: MaxCut n=20000 (default line); c4: correlation clustering n=10000; "
                          "c5: MaxCut on a random 4-regular graph, n=1e6, BF16 products; served: the request loop")
-    ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--slots", type=int, default=4)
-    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--slots", type=int, default=0, help="served: instances at once (0: 256 packed, 4 streams)")
+    ap.add_argument("--serve-mode", default="packed", choices=["packed", "streams"])
+    ap.add_argument("--iters-per-launch", type=int, default=8)
+    ap.add_argument("--loads", default="0.5,0.8", help="served: offered loads (fractions of capacity)")
+    ap.add_argument("--plain-requests", type=int, default=16,
+                    help="served: requests of the plain FP64 one-slot form (0: skip)")
     ap.add_argument("--served-max-iters", type=int, default=500,
                     help="iteration cap of every served solve (both forms)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -210,7 +220,8 @@ def main() -> int:
                           "value": res["capacity"]["requests_per_s"], "n_gpus": 1, "requests": args.requests,
                           "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
                           "config": {"workload": "served_batch n=U[500,5000] ER deg 8 unit weights +1% growth",
-                                     "slots": args.slots}, **res}))
+                                     "mode": res["capacity"]["mode"], "slots": res["capacity"]["slots"],
+                                     "iters_per_launch": args.iters_per_launch}, **res}))
         return 0
     stream = torch.cuda.current_stream().cuda_stream
     if args.workload == "c2":

@@ -150,6 +150,28 @@ int usbs_warm_start(usbs_handle *h, const usbs_problem *grown);
 void usbs_free(usbs_handle *h); /* NULL-safe */
 const char *usbs_last_error(const usbs_handle *h);
 
+/* Packed solve of several instances in persistent launches (Sec. 3-4, Alg. 1, on
+ * one workgroup per instance).  Each launch of the packed kernel runs, for every
+ * listed handle that has not finished, up to iters_per_launch iterations of Alg. 1
+ * with the same steps as usbs_solve: operator shift, block Lanczos with restarts,
+ * master QP (App. B.2), model and sketch update (Sec. 3.1, Sec. 4), the stopping
+ * test of Sec. 5 and the certifying eigen-solve; every decision (restart test,
+ * alternating maximisation, stall recovery, stopping test) is taken on the device.
+ * Launches repeat until every instance has converged or hit max_iters; time_limit
+ * is checked between launches.  One workgroup of 256 threads per instance, so up to
+ * one instance per compute unit runs at once; instances with small n gain the most.
+ *   hs[count]: distinct ready handles of the current device (n >= 48 each).  Each
+ *      handle's own stream is synchronised first; the launches run on 'stream'
+ *      (hipStream_t, NULL = default stream).
+ *   res[count] (may be NULL), status[count] (may be NULL): per-instance results and
+ *      statuses as usbs_solve reports them (y, U and lam are read afterwards with
+ *      usbs_solve-free calls such as usbs_step_iterate(h, 0, ...)).
+ * Returns USBS_OK when all converged, USBS_NOT_CONVERGED if any stopped at a limit,
+ * else the first negative status.  Results do not depend on which other handles
+ * share the launch (each workgroup reads only its own instance). */
+int usbs_solve_packed(usbs_handle *const *hs, int32_t count, int32_t iters_per_launch, void *stream,
+                      usbs_result *res, int32_t *status);
+
 /* ---------------------------------------------------------------------
  * Step-level entry points: each runs one row of the hot path on device
  * arrays, for parity testing and for callers that drive the iteration.
@@ -242,22 +264,35 @@ int64_t usbs_footprint_bytes(const usbs_problem *prob, const usbs_params *prm);
  *
  * A request is one SDP instance, optionally with a grown version of it (more
  * vertices / rows appended, as in the incremental setting of Sec. 5.1) that is
- * warm-started (usbs_warm_start) from the first solve's resident state.  The
- * server owns `slots` worker threads, each with its own non-blocking HIP stream
- * of default priority.  A free slot admits the first queued request (arrival
- * order) whose usbs_footprint_bytes fits in the remaining HBM budget, so work
- * of several instances overlaps on the device and new arrivals join as slots
- * and memory free up.  Results do not depend on the mix: each request's
+ * warm-started (usbs_warm_start) from the first solve's resident state.  A free
+ * slot admits the first queued request (arrival order) whose
+ * usbs_footprint_bytes fits in the remaining HBM budget, so new arrivals join as
+ * slots and memory free up.  In USBS_SERVE_STREAMS mode the server owns `slots`
+ * worker threads, each with its own non-blocking HIP stream of default priority,
+ * and the work of several instances overlaps on the device.  In USBS_SERVE_PACKED
+ * mode one scheduler thread runs every admitted instance as a workgroup of the
+ * packed launches (see usbs_solve_packed): between two launches it retires
+ * finished solves, prepares warm restarts of grown instances (whose f(y0) is then
+ * evaluated inside the next launch) and admits queued requests, whose cold start
+ * also runs inside the launch.  Results do not depend on the mix: each request's
  * computation reads only its own data and every kernel is deterministic.
  * Times are seconds since usbs_server_create.
  * ------------------------------------------------------------------------ */
 typedef struct usbs_server usbs_server;
 
+#define USBS_SERVE_STREAMS 0 /* one worker thread and stream per slot, usbs_solve per request */
+#define USBS_SERVE_PACKED 1  /* one scheduler thread; every admitted instance is a workgroup of
+                                the packed launches (usbs_solve_packed); arrivals join and
+                                finished requests leave between launches                     */
+
 typedef struct usbs_server_config {
-    int32_t slots;            /* instances on the device at once, 1..64                */
+    int32_t slots;            /* instances on the device at once: 1..64 (streams), 1..1024
+                                 (packed)                                              */
     int64_t hbm_budget_bytes; /* admission limit on summed footprints; <= 0: 90% of the
                                  free device memory at creation                      */
     usbs_params params;       /* parameters of every solve (the stream field is ignored) */
+    int32_t mode;             /* USBS_SERVE_STREAMS or USBS_SERVE_PACKED              */
+    int32_t iters_per_launch; /* packed mode: iterations per launch (<= 0: 8)         */
 } usbs_server_config;
 
 typedef struct usbs_served_result {

@@ -6,7 +6,8 @@ also in HIP kernels, behind the C ABI of include/usbs.h.
 
 Importing the package loads nothing; `native.load_library()` loads libusbs.so.
 """
-from .native import (Params, Solver, Server, UsbsError, footprint_bytes, load_library, EXPORTS,  # noqa: F401
-                     LIB_PATH)
+from .native import (Params, Solver, Server, UsbsError, footprint_bytes, load_library, solve_packed,  # noqa: F401
+                     EXPORTS, LIB_PATH)
 
-__all__ = ["Params", "Solver", "Server", "UsbsError", "footprint_bytes", "load_library", "EXPORTS", "LIB_PATH"]
+__all__ = ["Params", "Solver", "Server", "UsbsError", "footprint_bytes", "load_library", "solve_packed", "EXPORTS",
+           "LIB_PATH"]

@@ -9,6 +9,7 @@
 #include "kernels.h"
 #include "small_dense.h"
 #include "syev.h"
+#include "wg_steps.h"
 
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
@@ -19,24 +20,6 @@ namespace usbs {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
-    return __uint_as_float(((uint32_t)h) << 16);
-}
-__host__ __device__ inline uint16_t f32_to_bf16(float f) {
-    // round to nearest even
-    uint32_t u;
-#if defined(__HIP_DEVICE_COMPILE__)
-    u = __float_as_uint(f);
-#else
-    memcpy(&u, &f, 4);
-#endif
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
-    uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7fffu + lsb;
-    return (uint16_t)(u >> 16);
-}
-
-typedef double v4d __attribute__((ext_vector_type(4)));   // one lane's MFMA FP64 accumulator
 static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
@@ -144,37 +127,9 @@ __global__ __launch_bounds__(kWG) void k_spmm(int n, const int *__restrict__ row
     const int i = blockIdx.x * (kWG / L) + threadIdx.x / L;
     const int c = threadIdx.x % L;
     if (i >= n) return;
-    const int e0 = rowptr[i], e1 = rowptr[i + 1];
     const bool act = c < nb;
-    const int cc = act ? c : 0;
-    ACC acc0 = 0, acc1 = 0;
-    int e = e0;
-    for (; e + 1 < e1; e += 2) {
-        const int j0 = col[e], j1 = col[e + 1];
-        ACC v0, v1;
-        if constexpr (sizeof(VT) == 2) {
-            v0 = (ACC)bf16_to_f32(val[e]);
-            v1 = (ACC)bf16_to_f32(val[e + 1]);
-        } else {
-            v0 = (ACC)val[e];
-            v1 = (ACC)val[e + 1];
-        }
-        const ACC x0 = (ACC)X[(size_t)j0 * ldx + cc];
-        const ACC x1 = (ACC)X[(size_t)j1 * ldx + cc];
-        acc0 += v0 * x0;
-        acc1 += v1 * x1;
-    }
-    if (e < e1) {
-        const int j0 = col[e];
-        ACC v0;
-        if constexpr (sizeof(VT) == 2) v0 = (ACC)bf16_to_f32(val[e]);
-        else v0 = (ACC)val[e];
-        acc0 += v0 * (ACC)X[(size_t)j0 * ldx + cc];
-    }
-    if (act) {
-        const double xi = X[(size_t)i * ldx + c];
-        Y[(size_t)i * ldy + c] = diag[i] * xi + (double)(scale * (acc0 + acc1));
-    }
+    const double v = spmm_row<VT, ACC>(i, act ? c : 0, rowptr, col, val, scale, diag, X, ldx);
+    if (act) Y[(size_t)i * ldy + c] = v;
 }
 
 // Variant with P consecutive columns per lane (one P-wide load per gathered row
@@ -481,63 +436,14 @@ static int tn_blocks(const RedScratch &rs, int n) {
 // wavefronts of a workgroup are summed in LDS in a fixed order into one partial per
 // workgroup (layout as k_tn_reduce: (ca + 8) x 8).
 // ---------------------------------------------------------------------------
-constexpr int kMfmaMaxCh = kMaxBasis / 16;   // 16-column chunks of A (ca <= 80)
 template <int TAG, int UNR, bool GRAM>
 __global__ __launch_bounds__(kWG) void k_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                                  const double *__restrict__ B, int ldb, int cb,
                                                  double *__restrict__ partials) {
-    __shared__ double sred[3][kMfmaMaxCh + 1][4][64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m = lane & 15, kk = lane >> 4;
-    const int nch = (ca + 15) >> 4;
-    v4d acc[kMfmaMaxCh + 1];
-#pragma unroll
-    for (int q = 0; q <= kMfmaMaxCh; ++q) acc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
-    const long ngroups = ((long)n + 3) >> 2;
-    const long gstride = (long)gridDim.x * 4;
-    for (long g0 = (long)blockIdx.x * 4 + wave; g0 < ngroups; g0 += UNR * gstride) {
-        double yv[UNR], xv[UNR][kMfmaMaxCh];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const long row = 4 * (g0 + u * gstride) + kk;
-            const bool ok = (g0 + u * gstride < ngroups) && row < n;
-            yv[u] = (ok && m < cb) ? B[row * ldb + m] : 0.0;
-#pragma unroll
-            for (int q = 0; q < kMfmaMaxCh; ++q) {
-                const int col = 16 * q + m;
-                xv[u][q] = (ok && q < nch && col < ca) ? A[row * lda + col] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-#pragma unroll
-            for (int q = 0; q < kMfmaMaxCh; ++q)
-                if (q < nch) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][q], yv[u], acc[q], 0, 0, 0);
-            if (GRAM) acc[kMfmaMaxCh] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[u], yv[u], acc[kMfmaMaxCh], 0, 0, 0);
-        }
-    }
-    if (wave > 0)
-#pragma unroll
-        for (int q = 0; q <= kMfmaMaxCh; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) sred[wave - 1][q][v][lane] = acc[q][v];
-    __syncthreads();
-    if (wave == 0) {
-        const int rows_out = GRAM ? ca + cb : ca;
-        const int j = lane & 15;
-        double *dst = partials + (size_t)blockIdx.x * rows_out * cb;
-#pragma unroll
-        for (int q = 0; q <= kMfmaMaxCh; ++q) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const double t = ((acc[q][v] + sred[0][q][v][lane]) + sred[1][q][v][lane]) + sred[2][q][v][lane];
-                const int mm = (lane >> 4) + 4 * v;   // row of D held in this element
-                const int a = (q < kMfmaMaxCh) ? 16 * q + mm : ca + mm;
-                const bool valid = (q < kMfmaMaxCh) ? (q < nch && a < ca) : (GRAM && mm < cb);
-                if (valid && j < cb) dst[a * cb + j] = t;
-            }
-        }
-    }
+    __shared__ TnWork w;
+    const int rows_out = GRAM ? ca + cb : ca;
+    wg_tn_mfma<double, UNR, GRAM>(n, A, lda, ca, B, ldb, cb, blockIdx.x, gridDim.x,
+                                  partials + (size_t)blockIdx.x * rows_out * cb, cb, 1.0, 0.0, &w);
 }
 
 static int mfma_blocks(const RedScratch &rs, int n) {
@@ -608,57 +514,8 @@ __global__ __launch_bounds__(kWG) void k_pip_chol(const double *__restrict__ Hg,
                                                   double *__restrict__ Rsave, double *__restrict__ T, int ldt,
                                                   double *__restrict__ coef, int *flags,
                                                   const double *__restrict__ floor_ref) {
-    __shared__ double sH[kMaxBasis][kBlk];
-    __shared__ double sOm[kBlk * 17];
-    __shared__ double sRi[kBlk * kBlk];
-    __shared__ double sR[kBlk][kBlk];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < cols * kBlk; e += kWG) sH[e / kBlk][e % kBlk] = Hg[e];
-    if (tid < kBlk * kBlk) {
-        sR[tid / kBlk][tid % kBlk] = (pass == 1) ? Rsave[tid] : 0.0;
-    }
-    __syncthreads();
-    if (tid < kBlk * kBlk) {
-        const int i = tid / kBlk, j = tid % kBlk;
-        double sacc = 0.0;
-        for (int a = 0; a < cols; ++a) sacc += sH[a][i] * sH[a][j];
-        sOm[i * 17 + j] = Hg[(cols + i) * kBlk + j] - sacc;
-    }
-    // projections of the original block into T
-    for (int e = tid; e < cols * kBlk; e += kWG) {
-        const int a = e / kBlk, c = e % kBlk;
-        if (pass == 0) {
-            T[a * ldt + c] = sH[a][c];
-        } else {
-            double v = 0.0;
-            for (int k = 0; k <= c; ++k) v += sH[a][k] * sR[k][c];
-            T[a * ldt + c] += v;
-        }
-    }
-    __syncthreads();
-    double f2 = 0.0;
-    if (floor_ref) {
-        const double rf = 1e-10 * (*floor_ref);
-        f2 = rf * rf;
-    }
-    if (tid < 64) wave_cholqr(kBlk, sOm, 17, sRi, kBlk, flags, f2);
-    __syncthreads();
-    // R = L^T (upper) of this pass, kept for the correction of the next pass
-    if (pass == 0 && tid < kBlk * kBlk) {
-        const int i = tid / kBlk, j = tid % kBlk;
-        Rsave[tid] = (j >= i) ? sOm[j * 17 + i] : 0.0;
-    }
-    for (int e = tid; e < (cols + kBlk) * kBlk; e += kWG) {
-        const int a = e / kBlk, c = e % kBlk;
-        double v;
-        if (a < cols) {
-            v = 0.0;
-            for (int k = 0; k < kBlk; ++k) v -= sH[a][k] * sRi[k * kBlk + c];
-        } else {
-            v = sRi[(a - cols) * kBlk + c];
-        }
-        coef[e] = v;
-    }
+    __shared__ PipWork w;
+    wg_pip_chol(Hg, cols, pass, Rsave, T, ldt, coef, flags, floor_ref, &w);
 }
 void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave, double *T, int ldt,
               double *coef, int *flags, const double *floor_ref) {
@@ -723,76 +580,12 @@ __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restri
 // launch), D[m][j] = output row row0 + m, column j.  Each element of A is read from
 // memory once per launch.
 // ---------------------------------------------------------------------------
-constexpr int kNnMaxQ = (kMaxBasis + kBlk) / 4;   // 22 four-column steps
-constexpr int kNnLd = kMaxBasis + kBlk + 1;
 __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                                  const double *__restrict__ A2, int lda2, int ca2,
                                                  const double *__restrict__ H, int ldh, int cc,
                                                  double *__restrict__ C, int ldc, double alpha, double beta) {
-    __shared__ double tile[4][16][kNnLd];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int m = lane & 15, kk = lane >> 4, j = lane & 15;
-    const int ct = ca + ca2;
-    const int nq = (ct + 3) >> 2;
-    double yv[kNnMaxQ];
-#pragma unroll
-    for (int q = 0; q < kNnMaxQ; ++q) {
-        const int a = 4 * q + kk;
-        yv[q] = (q < nq && a < ct && j < cc) ? H[a * ldh + j] : 0.0;
-    }
-    double(*T)[kNnLd] = tile[wave];
-    const long ngroups = ((long)n + 15) >> 4;
-    const long gstride = (long)gridDim.x * 4;
-    for (long g = (long)blockIdx.x * 4 + wave; g < ngroups; g += gstride) {
-        const long row0 = 16 * g;
-        // rows of A: lanes over columns (two passes when ca > 64); A2 (<= 8 columns): 8 rows
-        // of 8 lanes per load
-        double v[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = (lane < ca && row0 + r < n) ? A[(row0 + r) * lda + lane] : 0.0;
-        double w2[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = 8 * h + (lane >> 3), c = lane & 7;
-            w2[h] = (c < ca2 && row0 + r < n) ? A2[(row0 + r) * lda2 + c] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            if (lane < ca) T[r][lane] = v[r];
-        if (ca > 64) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = (64 + lane < ca && row0 + r < n) ? A[(row0 + r) * lda + 64 + lane] : 0.0;
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (64 + lane < ca) T[r][64 + lane] = v[r];
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = 8 * h + (lane >> 3), c = lane & 7;
-            if (c < ca2) T[r][ca + c] = w2[h];
-        }
-        wave_sync();
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int q = 0; q < kNnMaxQ; ++q)
-            if (q < nq) {
-                const int a = 4 * q + kk;
-                const double x = (a < ct) ? T[m][a] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, yv[q], acc, 0, 0, 0);
-            }
-        wave_sync();   // the tile is reloaded for the next row group
-        if (j < cc) {
-#pragma unroll
-            for (int vv = 0; vv < 4; ++vv) {
-                const long r = row0 + (lane >> 4) + 4 * vv;
-                if (r < n) {
-                    double o = alpha * acc[vv];
-                    if (beta != 0.0) o += beta * C[r * ldc + j];
-                    C[r * ldc + j] = o;
-                }
-            }
-        }
-    }
+    __shared__ NnWork w;
+    wg_nn_mfma(n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, blockIdx.x, gridDim.x, &w);
 }
 
 static bool use_nn_mfma(int n, int cc) { return n > 0 && cc <= 16; }
@@ -862,20 +655,12 @@ void fill(hipStream_t s, size_t count, double v, double *p) {
     hipLaunchKernelGGL(k_fill, dim3(cdiv((long)count, kWG)), dim3(kWG), 0, s, count, v, p);
 }
 
-__device__ __forceinline__ uint64_t mix64(uint64_t x) {
-    // splitmix64 finaliser
-    x += 0x9E3779B97F4A7C15ull;
-    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
-    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
-    return x ^ (x >> 31);
-}
 __global__ void k_random_block(int n, int cc, uint64_t seed, double *C, int ldc) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)n * cc) return;
     const long i = e / cc;
     const int c = (int)(e - i * cc);
-    const uint64_t h = mix64(seed * 0x100000001B3ull + (uint64_t)e);
-    C[i * ldc + c] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    C[i * ldc + c] = hash_uniform(seed, (uint64_t)e);
 }
 void random_block(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ldc) {
     if (n <= 0 || cc <= 0) return;
@@ -907,58 +692,9 @@ __global__ __launch_bounds__(kWG) void k_restart_prep(const double *__restrict__
                                                       const double *__restrict__ theta, int kc, double tol,
                                                       double tol_rest, double *__restrict__ res,
                                                       int *__restrict__ flag, double *__restrict__ Z,
-                                                      double *__restrict__ scale_est) {
-    // Next block: 8 of the 16 residual directions chosen by pivoted Cholesky of the
-    // Gram matrix R^T R (greedy: the residual with the largest component orthogonal to
-    // those already chosen), each scaled by 1 / ||r_p||; the block is orthonormalised
-    // afterwards.  One wavefront, lanes 0..15 own one residual each.
-    __shared__ double sG[kRitz][kRitz + 1];
-    __shared__ double sL[kBlk][kRitz];
-    __shared__ int sel[kBlk];
-    const int tid = threadIdx.x;
-    if (tid < kRitz) res[tid] = sqrt(fmax(RtR[tid * kRitz + tid], 0.0));
-    if (tid >= 64) return;
-    for (int e = tid; e < kRitz * kRitz; e += 64) sG[e / kRitz][e % kRitz] = RtR[e];
-    for (int e = tid; e < kRitz * kBlk; e += 64) Z[e] = 0.0;
-    wave_sync();
-    const int i = tid & 15;                    // every row of 16 lanes holds the same data
-    double d = fmax(sG[i][i], 0.0);
-    const double d0 = fmax(row16_max(d), 1e-300);
-    bool taken = false;
-    for (int t = 0; t < kBlk; ++t) {
-        // arg-max of the remaining diagonal (ties: lowest index)
-        const double cand = taken ? -1.0 : d;
-        const double best = row16_max(cand);
-        const double idx = row16_min((cand == best) ? (double)i : 1e9);
-        const int p = (int)idx;
-        if (!(best > 1e-24 * d0)) break;       // the residuals span fewer than t + 1 directions
-        const double piv = sqrt(best);
-        // column t of the pivoted Cholesky factor
-        double l = sG[i][p];
-        for (int u = 0; u < t; ++u) l -= sL[u][i] * sL[u][p];
-        l /= piv;
-        wave_sync();
-        if (tid < kRitz) sL[t][i] = l;
-        if (tid == 0) {
-            sel[t] = p;
-            Z[p * kBlk + t] = 1.0 / sqrt(fmax(sG[p][p], 1e-300));
-        }
-        wave_sync();
-        d = fmax(d - l * l, 0.0);
-        if (i == p) taken = true;
-    }
-    if (tid == 0) {
-        // tolerances are relative to a Gershgorin bound of the current operator
-        double sc = fmax(fabs(theta[0]), fabs(theta[kRitz - 1]));
-        if (scale_est) sc = fmax(sc, *scale_est);
-        // the top Ritz pair sets f(y): tight tolerance; the others only shape the bundle
-        int ok = sqrt(fmax(RtR[0], 0.0)) <= tol * sc;
-        for (int q = 1; q < kc; ++q) {
-            const double r = sqrt(fmax(RtR[q * kRitz + q], 0.0));
-            if (!(r <= tol_rest * sc)) ok = 0;
-        }
-        *flag = ok;
-    }
+                                                      const double *__restrict__ scale_est) {
+    __shared__ RestartWork w;
+    wg_restart_prep(RtR, theta, kc, tol, tol_rest, res, flag, Z, scale_est, &w);
 }
 
 void lanczos_restart_prep(hipStream_t s, const double *RtR, const double *theta, int kc, double tol,
@@ -1001,94 +737,17 @@ void neg_diag(hipStream_t s, const double *theta, int N, double *H) {
 // ---------------------------------------------------------------------------
 // constraint-side kernels of the bundle (App. B.2 and App. C)
 // ---------------------------------------------------------------------------
-// g_k = svec(V^T A_k V) for one constraint row k into g[0..d)
-__device__ __forceinline__ void svec_constraint(int k, const int *__restrict__ kptr, const int *__restrict__ ti,
-                                                const int *__restrict__ tj, const double *__restrict__ tv,
-                                                const double *__restrict__ V, int ldv, int kd, double *g) {
-    // g may live in LDS
-    const double r2 = 1.4142135623730951;
-    int d = kd * (kd + 1) / 2;
-    for (int p = 0; p < d; ++p) g[p] = 0.0;
-    for (int t = kptr[k]; t < kptr[k + 1]; ++t) {
-        const double *vi = V + (size_t)ti[t] * ldv;
-        const double *vj = V + (size_t)tj[t] * ldv;
-        const double v = tv[t];
-        int p = 0;
-        for (int b = 0; b < kd; ++b) {
-            const double vib = vi[b], vjb = vj[b];
-            for (int a = b; a < kd; ++a) {
-                if (a == b) g[p] += v * vi[a] * vjb;
-                else g[p] += v * r2 * 0.5 * (vi[a] * vjb + vib * vj[a]);
-                ++p;
-            }
-        }
-    }
-}
-
-// Q11 raw sum and G^T w_j.  Constraints are processed in batches of 64 staged
-// in LDS; each thread owns a fixed set of (P,Q) entries of the upper triangle.
-constexpr int kQB = 64;
+// Q11 raw sum and G^T w_j: one partial per workgroup (wg_qp_gram)
 __global__ __launch_bounds__(kWG) void k_qp_gram(int m, const int *__restrict__ kptr, const int *__restrict__ ti,
                                                  const int *__restrict__ tj, const double *__restrict__ tv,
                                                  const double *__restrict__ V, int ldv, int kd, int do_q11,
                                                  const double *w0, const double *w1, const double *w2,
                                                  const double *w3, int nw, double *partials) {
-    __shared__ double sg[kQB][kMaxSvec + 1];
-    __shared__ double sw[4][kQB];
-    const int tid = threadIdx.x;
+    __shared__ QpGramWork w;
     const int d = kd * (kd + 1) / 2;
-    const int nupper = do_q11 ? d * (d + 1) / 2 : 0;
-    const int nout = nupper + nw * d;
-    constexpr int kPer = (kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec + kWG - 1) / kWG;
-    double acc[kPer];
-    int pP[kPer], pQ[kPer];
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        acc[q] = 0.0;
-        const int o = tid + q * kWG;
-        pP[q] = -1;
-        pQ[q] = -1;
-        if (o < nupper) {
-            // o -> (P, Q) with P <= Q in row-major upper-triangle order
-            int P = 0, rem = o;
-            while (rem >= d - P) { rem -= d - P; ++P; }
-            pP[q] = P;
-            pQ[q] = P + rem;
-        } else if (o < nout) {
-            const int j = (o - nupper) / d;
-            pP[q] = -(j + 2);               // weight vector j
-            pQ[q] = (o - nupper) - j * d;   // svec entry
-        }
-    }
-    const double *ws[4] = {w0, w1, w2, w3};
-    for (long k0 = (long)blockIdx.x * kQB; k0 < m; k0 += (long)gridDim.x * kQB) {
-        if (tid < kQB) {
-            const long k = k0 + tid;
-            if (k < m) svec_constraint((int)k, kptr, ti, tj, tv, V, ldv, kd, &sg[tid][0]);
-            else for (int p = 0; p < d; ++p) sg[tid][p] = 0.0;
-            for (int j = 0; j < nw; ++j) sw[j][tid] = (k < m) ? ws[j][k] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int P = pP[q], Q = pQ[q];
-            if (Q < 0) continue;
-            double s = 0.0;
-            if (P >= 0) {
-                for (int r = 0; r < kQB; ++r) s += sg[r][P] * sg[r][Q];
-            } else {
-                const int j = -P - 2;
-                for (int r = 0; r < kQB; ++r) s += sw[j][r] * sg[r][Q];
-            }
-            acc[q] += s;
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int o = tid + q * kWG;
-        if (o < nout) partials[(size_t)blockIdx.x * nout + o] = acc[q];
-    }
+    const int nout = (do_q11 ? d * (d + 1) / 2 : 0) + nw * d;
+    wg_qp_gram(m, kptr, ti, tj, tv, V, ldv, kd, do_q11, w0, w1, w2, w3, nw, blockIdx.x, gridDim.x,
+               partials + (size_t)blockIdx.x * nout, &w);
 }
 
 void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const int *ti, const int *tj,
@@ -1121,23 +780,7 @@ __global__ __launch_bounds__(kWG) void k_lowrank_A(int m, const int *__restrict_
     __syncthreads();
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
-    double acc = 0.0;
-    for (int t = kptr[k]; t < kptr[k + 1]; ++t) {
-        const double *vi = V + (size_t)ti[t] * ldv;
-        const double *vj = V + (size_t)tj[t] * ldv;
-        double xj[16];
-#pragma unroll
-        for (int b = 0; b < 16; ++b) xj[b] = (b < kd) ? vj[b] : 0.0;
-        double q = 0.0;
-#pragma unroll 1
-        for (int a = 0; a < kd; ++a) {
-            double s = 0.0;
-#pragma unroll
-            for (int b = 0; b < 16; ++b) s += sK[a * 16 + b] * xj[b];
-            q += vi[a] * s;
-        }
-        acc += tv[t] * q;
-    }
+    const double acc = lowrank_row(k, kptr, ti, tj, tv, V, ldv, kd, sK);
     double v = alpha * acc;
     if (zb) v += (gamma_dev ? *gamma_dev : gamma_host) * zb[k];
     if (beta != 0.0) v += beta * z[k];
@@ -1227,78 +870,14 @@ void mask_rows(hipStream_t s, int count, const int *idx, double *X, int ldx, int
                        ldx, nc);
 }
 
-// one workgroup: the 16 largest d_i over the decoupled rows (ties by row index) by
-// repeated arg-max, then a merge with the 16 descending coupled Ritz values.
+// one workgroup: the 16 largest d_i over the decoupled rows, merged with the coupled
+// Ritz values (wg_iso_merge)
 __global__ __launch_bounds__(kWG) void k_iso_merge(int count, const int *__restrict__ idx,
                                                    const double *__restrict__ d, int have_coupled,
                                                    double *__restrict__ theta, double *__restrict__ res,
                                                    int *__restrict__ plan) {
-    __shared__ double bv[kWG];
-    __shared__ int bq[kWG];
-    __shared__ double iv[kRitz];
-    __shared__ int ii[kRitz];
-    const int tid = threadIdx.x;
-    const int want = count < kRitz ? count : kRitz;
-    for (int t = 0; t < want; ++t) {
-        double best = -INFINITY;
-        int bestq = -1;
-        for (int q = tid; q < count; q += kWG) {
-            bool taken = false;
-            for (int u = 0; u < t; ++u) taken |= (ii[u] == q);
-            const double v = d[idx[q]];
-            if (!taken && (bestq < 0 || v > best)) {
-                best = v;
-                bestq = q;
-            }
-        }
-        bv[tid] = best;
-        bq[tid] = bestq;
-        __syncthreads();
-        for (int o = kWG / 2; o > 0; o >>= 1) {
-            if (tid < o) {
-                const double v2 = bv[tid + o];
-                const int q2 = bq[tid + o];
-                if (q2 >= 0 && (bq[tid] < 0 || v2 > bv[tid] || (v2 == bv[tid] && q2 < bq[tid]))) {
-                    bv[tid] = v2;
-                    bq[tid] = q2;
-                }
-            }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            iv[t] = bv[0];
-            ii[t] = bq[0];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double th[kRitz], rr[kRitz];
-        int pl[kRitz];
-        int a = 0, b = 0;
-        const int nc = have_coupled ? kRitz : 0;
-        for (int q = 0; q < kRitz; ++q) {
-            const bool take_c = a < nc && (b >= want || theta[a] >= iv[b]);
-            if (take_c) {
-                th[q] = theta[a];
-                rr[q] = res[a];
-                pl[q] = a++;
-            } else if (b < want) {
-                th[q] = iv[b];
-                rr[q] = 0.0;
-                pl[q] = -(idx[ii[b]] + 1);
-                ++b;
-            } else {   // fewer than 16 eigenpairs in total: pad with empty columns
-                th[q] = -1e300;
-                rr[q] = 0.0;
-                pl[q] = kRitz;
-            }
-        }
-        for (int q = 0; q < kRitz; ++q) {
-            theta[q] = th[q];
-            res[q] = rr[q];
-            plan[q] = pl[q];
-        }
-    }
+    __shared__ IsoWork w;
+    wg_iso_merge(count, idx, d, have_coupled, theta, res, plan, &w);
 }
 void iso_merge(hipStream_t s, int count, const int *idx, const double *d, int have_coupled, double *theta,
                double *res, int *plan) {

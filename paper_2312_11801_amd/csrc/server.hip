@@ -10,6 +10,11 @@
 // zbar) and the sketch resident in its handle between the base solve and the
 // warm restart.  Each request's computation depends only on its own data and the
 // kernels are deterministic, so a result does not depend on what else runs.
+//
+// Packed mode replaces the slot threads by one scheduler thread: every admitted
+// instance is one workgroup of the packed launches (one launch advances all of them
+// by a few iterations of Alg. 1); between launches the scheduler retires finished
+// solves, prepares the warm restarts of grown instances and admits queued requests.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,6 +30,7 @@
 #include <vector>
 
 #include "../../include/usbs.h"
+#include "packed_host.h"
 
 namespace {
 
@@ -176,6 +182,142 @@ void worker(usbs_server *sv, int slot) {
     if (stream) (void)hipStreamDestroy(stream);
 }
 
+
+// ---------------------------------------------------------------------------
+// packed mode: one scheduler thread, one workgroup per admitted instance
+// ---------------------------------------------------------------------------
+struct Active {
+    Request *rq = nullptr;
+    usbs_handle *h = nullptr;
+    usbs::PackState st{};
+    bool grown = false;     // solving the grown instance (after the warm restart)
+    double t_phase = 0.0;   // start of the current solve (time limit)
+};
+
+void finish_request(usbs_server *sv, Active &a) {
+    if (a.h && (a.rq->status_base < 0 || a.rq->status_grown < 0)) a.rq->err = usbs_last_error(a.h);
+    usbs_free(a.h);
+    a.h = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        a.rq->t_done = sv->now();
+        a.rq->done = true;
+        sv->used -= a.rq->footprint;
+        sv->running--;
+        sv->completed++;
+    }
+    sv->cv_done.notify_all();
+}
+
+void packer(usbs_server *sv) {
+    (void)hipSetDevice(sv->dev);
+    // default priority on purpose: every stream of the library runs at the same priority
+    hipStream_t launch_stream = nullptr, side_stream = nullptr;
+    if (hipStreamCreateWithFlags(&launch_stream, hipStreamNonBlocking) != hipSuccess) launch_stream = nullptr;
+    if (hipStreamCreateWithFlags(&side_stream, hipStreamNonBlocking) != hipSuccess) side_stream = nullptr;
+    const int iters = sv->cfg.iters_per_launch > 0 ? sv->cfg.iters_per_launch : 8;
+    {
+        usbs_pack::Runner R(launch_stream);
+        std::vector<Active> act;
+        for (;;) {
+            // admission: first fit in arrival order while a slot is free
+            std::vector<Request *> admit;
+            {
+                std::unique_lock<std::mutex> lk(sv->mu);
+                if (act.empty())
+                    sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
+                if (act.empty() && sv->stop && sv->queue.empty()) break;
+                for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)(act.size() + admit.size()) < sv->cfg.slots;) {
+                    if (sv->used + (*it)->footprint <= sv->budget) {
+                        Request *rq = *it;
+                        it = sv->queue.erase(it);
+                        sv->used += rq->footprint;
+                        sv->peak_used = std::max(sv->peak_used, sv->used);
+                        sv->running++;
+                        sv->peak_running = std::max(sv->peak_running, sv->running);
+                        rq->t_admit = sv->now();
+                        admit.push_back(rq);
+                    } else {
+                        ++it;
+                    }
+                }
+            }
+            for (Request *rq : admit) {
+                usbs_params prm = sv->cfg.params;
+                prm.stream = side_stream;
+                prm.autotune = 0;   // the packed kernel has one launch shape
+                Active a;
+                a.rq = rq;
+                a.t_phase = sv->now();
+                usbs_problem pb = rq->base.view();
+                const int st = usbs_pack::create(&pb, &prm, &a.h, false);
+                rq->slot = (int)act.size();
+                if (st != USBS_OK) {
+                    rq->status_base = st;
+                    rq->t_base_done = sv->now();
+                    finish_request(sv, a);
+                    continue;
+                }
+                a.st = usbs_pack::begin(a.h, usbs::PACK_INIT_COLD);
+                act.push_back(a);
+            }
+            if (act.empty()) continue;
+            // one packed launch over every active instance
+            std::vector<usbs_handle *> hs(act.size());
+            std::vector<usbs::PackState> sts(act.size());
+            const double now0 = sv->now();
+            for (size_t q = 0; q < act.size(); ++q) {
+                hs[q] = act[q].h;
+                sts[q] = act[q].st;
+                const double lim = sv->cfg.params.time_limit;
+                if (lim > 0.0 && now0 - act[q].t_phase > lim) sts[q].stop = 1;
+            }
+            std::string err;
+            const int rc = usbs_pack::launch(R, hs.data(), sts.data(), (int)act.size(), iters, &err);
+            for (size_t q = 0; q < act.size(); ++q) {
+                act[q].st = sts[q];
+                if (rc < 0) act[q].st.done = usbs::PACK_FAILED;
+            }
+            if (rc < 0) {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->err = err;
+            }
+            // retire finished solves; warm restarts of grown instances stay in the table
+            std::vector<Active> keep;
+            for (Active &a : act) {
+                if (a.st.done == usbs::PACK_RUNNING) {
+                    keep.push_back(a);
+                    continue;
+                }
+                const double secs = sv->now() - a.t_phase;
+                Request *rq = a.rq;
+                if (!a.grown) {
+                    rq->status_base = rc < 0 ? rc : usbs_pack::finish(a.h, a.st, &rq->res_base, secs);
+                    rq->t_base_done = sv->now();
+                    if (rq->status_base >= 0 && rq->has_grown) {
+                        usbs_problem pg = rq->grown.view();
+                        const int st2 = usbs_pack::warm_prepare(a.h, &pg, false);
+                        if (st2 == USBS_OK) {
+                            a.grown = true;
+                            a.t_phase = sv->now();
+                            a.st = usbs_pack::begin(a.h, usbs::PACK_INIT_WARM);
+                            keep.push_back(a);
+                            continue;
+                        }
+                        rq->status_grown = st2;
+                    }
+                } else {
+                    rq->status_grown = rc < 0 ? rc : usbs_pack::finish(a.h, a.st, &rq->res_grown, secs);
+                }
+                finish_request(sv, a);
+            }
+            act.swap(keep);
+            sv->cv_work.notify_all();
+        }
+    }
+    if (side_stream) (void)hipStreamDestroy(side_stream);
+    if (launch_stream) (void)hipStreamDestroy(launch_stream);
+}
 }  // namespace
 
 extern "C" {
@@ -183,7 +325,8 @@ extern "C" {
 int usbs_server_create(const usbs_server_config *cfg, usbs_server **out) {
     if (!out || !cfg) return USBS_E_INVALID;
     *out = nullptr;
-    if (cfg->slots < 1 || cfg->slots > 64) return USBS_E_INVALID;
+    if (cfg->mode != USBS_SERVE_STREAMS && cfg->mode != USBS_SERVE_PACKED) return USBS_E_INVALID;
+    if (cfg->slots < 1 || cfg->slots > (cfg->mode == USBS_SERVE_PACKED ? 1024 : 64)) return USBS_E_INVALID;
     auto *sv = new usbs_server();
     sv->cfg = *cfg;
     sv->t0 = std::chrono::steady_clock::now();
@@ -200,7 +343,9 @@ int usbs_server_create(const usbs_server_config *cfg, usbs_server **out) {
         }
         sv->budget = (int64_t)(0.9 * (double)fr);
     }
-    for (int q = 0; q < cfg->slots; ++q) sv->workers.emplace_back(worker, sv, q);
+    if (cfg->mode == USBS_SERVE_PACKED) sv->workers.emplace_back(packer, sv);
+    else
+        for (int q = 0; q < cfg->slots; ++q) sv->workers.emplace_back(worker, sv, q);
     *out = sv;
     return USBS_OK;
 }

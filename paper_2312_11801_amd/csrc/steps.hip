@@ -6,6 +6,7 @@
 #include "steps.h"
 #include "small_dense.h"
 #include "syev.h"
+#include "wg_steps.h"
 
 namespace usbs {
 
@@ -17,30 +18,7 @@ static inline int cdiv_(long a, long b) { return (int)((a + b - 1) / b); }
 // ---------------------------------------------------------------------------
 __global__ void k_qp_finalize(int k, const double *__restrict__ raw, const double *__restrict__ VCV,
                               const double *__restrict__ sc, int has_nu, double *__restrict__ qp) {
-    const int d = k * (k + 1) / 2, nup = d * (d + 1) / 2;
-    const double alpha = sc[SC_ALPHA], rho = sc[SC_RHO], tau = sc[SC_TAU];
-    const double a2r = alpha * alpha / rho;
-    const double *Gz = raw + nup, *Gy = Gz + d, *Gb = Gy + d, *Gn = Gb + d;
-    for (int e = threadIdx.x; e < d * d; e += blockDim.x) {
-        const int P = e / d, Q = e - P * d;
-        const int lo = P < Q ? P : Q, hi = P < Q ? Q : P;
-        qp[e] = a2r * raw[lo * d - lo * (lo - 1) / 2 + (hi - lo)];
-    }
-    for (int p = threadIdx.x; p < d; p += blockDim.x) {
-        // p -> (i, j), i >= j, column-wise lower triangle
-        int j = 0, rem = p;
-        while (rem >= k - j) { rem -= k - j; ++j; }
-        const int i = j + rem;
-        const double sv = (i == j ? 1.0 : 1.4142135623730951) * VCV[i * k + j];
-        const double gw = Gb[p] - (has_nu ? Gn[p] : 0.0);
-        qp[d * d + p] = (tau > 0.0) ? a2r / tau * Gz[p] : 0.0;               // q12
-        qp[d * d + d + 1 + p] = alpha * (Gy[p] - gw / rho - sv);             // h1
-    }
-    if (threadIdx.x == 0) {
-        const double zz = sc[SC_ZZ], yz = sc[SC_YZBAR], bz = sc[SC_BZ], nz = has_nu ? sc[SC_NUZ] : 0.0;
-        qp[d * d + d] = (tau > 0.0) ? a2r * zz / (tau * tau) : 0.0;                          // q22
-        qp[d * d + 2 * d + 1] = (tau > 0.0) ? alpha / tau * (yz - (bz - nz) / rho - sc[SC_CBAR]) : 0.0; // h2
-    }
+    wg_qp_finalize(k, raw, VCV, sc, has_nu, qp);
 }
 
 void qp_finalize(hipStream_t s, int k, const double *raw, const double *VCV, const double *sc, int has_nu,
@@ -50,17 +28,7 @@ void qp_finalize(hipStream_t s, int k, const double *raw, const double *VCV, con
 
 // g = alpha eta / tau, <C, X_{t+1}> = g cbar + alpha <V^T C V, S>
 __global__ void k_post_ipm(int k, const double *__restrict__ st, const double *__restrict__ VCV, double *sc) {
-    if (threadIdx.x != 0) return;
-    const double alpha = sc[SC_ALPHA], tau = sc[SC_TAU];
-    const double eta = st[2 * k * k];
-    const double g = (tau > 0.0) ? alpha * eta / tau : 0.0;
-    double vs = 0.0;
-    for (int e = 0; e < k * k; ++e) vs += VCV[e] * st[e];
-    sc[SC_ETA] = eta;
-    sc[SC_G] = g;
-    sc[SC_CX] = g * sc[SC_CBAR] + alpha * vs;
-    sc[SC_IPMIT] += st[2 * k * k + 3];
-    if (st[2 * k * k + 4] != 0.0) sc[SC_IPMSTATUS] = st[2 * k * k + 4];
+    if (threadIdx.x == 0) post_ipm_scalar(k, st, VCV, sc);
 }
 void post_ipm(hipStream_t s, int k, const double *st, const double *VCV, double *sc) {
     hipLaunchKernelGGL(k_post_ipm, dim3(1), dim3(64), 0, s, k, st, VCV, sc);
@@ -71,10 +39,7 @@ __global__ void k_nu_update(int m, const double *__restrict__ b, const double *_
                             const double *__restrict__ y, const double *__restrict__ ineq, double rho,
                             double *__restrict__ nu, double *__restrict__ dnu) {
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    const double v = (ineq[k] != 0.0) ? fmax(b[k] - AX[k] - rho * y[k], 0.0) : 0.0;
-    dnu[k] = v - nu[k];
-    nu[k] = v;
+    if (k < m) nu_update_elem(k, b, AX, y, ineq, rho, nu, dnu);
 }
 void nu_update(hipStream_t s, int m, const double *b, const double *AX, const double *y, const double *ineq,
                double rho, double *nu, double *dnu) {
@@ -87,16 +52,7 @@ __global__ void k_candidate(int m, const double *__restrict__ b, const double *_
                             const double *__restrict__ y, const double *__restrict__ ineq, double rho,
                             double *__restrict__ yc, double *__restrict__ e) {
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= m) return;
-    const double r = b[k] - AX[k];
-    double v = y[k] - r / rho;
-    if (ineq[k] != 0.0) {
-        v = fmax(v, 0.0);
-        e[k] = fmax(-r, 0.0);
-    } else {
-        e[k] = -r;
-    }
-    yc[k] = v;
+    if (k < m) candidate_elem(k, b, AX, y, ineq, rho, yc, e);
 }
 void candidate(hipStream_t s, int m, const double *b, const double *AX, const double *y, const double *ineq,
                double rho, double *yc, double *e) {
@@ -107,61 +63,16 @@ void candidate(hipStream_t s, int m, const double *b, const double *AX, const do
 // lambda_max(V^T (C - A^* y~) V) with V^T A^* y~ V = smat(G^T y~)
 __global__ __launch_bounds__(kWG) void k_fhat_prep(int k, const double *__restrict__ VCV,
                                                    const double *__restrict__ Gy, double *sc) {
-    __shared__ SyevWork ws;
-    __shared__ double Mv[kMaxK * kMaxK];
-    __shared__ double w[kMaxK + 1];
-    const double r2 = 1.4142135623730951;
-    for (int e = threadIdx.x; e < k * k; e += kWG) {
-        const int i = e / k, j = e - i * k;
-        const int lo = i > j ? j : i, hi = i > j ? i : j;
-        const int p = lo * k - lo * (lo - 1) / 2 + (hi - lo);
-        Mv[e] = VCV[e] - ((i == j) ? Gy[p] : Gy[p] / r2);
-    }
-    __syncthreads();
-    wg_syev_load(k, Mv, k, nullptr, &ws);
-    wg_syev_top(k, 1, 0, &ws, w, nullptr, 0);
-    if (threadIdx.x == 0) sc[SC_LAMV] = w[0];
+    __shared__ FhatWork w;
+    wg_fhat_prep(k, VCV, Gy, sc, &w);
 }
 void fhat_prep(hipStream_t s, int k, const double *VCV, const double *Gy, double *sc) {
     hipLaunchKernelGGL(k_fhat_prep, dim3(1), dim3(kWG), 0, s, k, VCV, Gy, sc);
 }
 
-// relative errors of eq. relative_error_tol (suboptimality through the upper bound of eq.
-// objective_subopt_upper_bound) in the units selected by SC_UNITS
-__device__ void set_metrics(double *sc, double fn) {
-    const double cx = sc[SC_CX];
-    const double dist = sqrt(fmax(sc[SC_DIST2], 0.0));
-    if (sc[SC_UNITS] != 0.0) {
-        const double s = sc[SC_SIGMA] * sc[SC_TRACE];
-        const double fo = s * fn, co = s * cx;
-        sc[SC_GAP] = fabs(fo - co) / (1.0 + fabs(co));
-        sc[SC_INF] = sc[SC_TRACE] * dist / (1.0 + sc[SC_TRACE] * sc[SC_BNORM]);
-    } else {
-        sc[SC_GAP] = fabs(fn - cx) / (1.0 + fabs(cx));
-        sc[SC_INF] = dist / (1.0 + sc[SC_BNORM]);
-    }
-}
-
 // descent test (Alg. 1), f, f^ and the relative errors
 __global__ void k_decide(const double *__restrict__ theta, double *sc) {
-    if (threadIdx.x != 0) return;
-    const double alpha = sc[SC_ALPHA], beta = sc[SC_BETA], tau = sc[SC_TAU];
-    const double by = sc[SC_BY];
-    const double lam1 = theta[0];
-    const double fc = alpha * fmax(lam1, 0.0) + by;
-    double best = fmax(0.0, sc[SC_LAMV]);
-    if (tau > 0.0) best = fmax(best, (sc[SC_CBAR] - sc[SC_YZ]) / tau);
-    const double fhat = alpha * best + by;
-    const double f = sc[SC_F];
-    const int desc = (beta * (f - fhat) <= f - fc) ? 1 : 0;
-    const double fn = desc ? fc : f;
-    sc[SC_FCAND] = fc;
-    sc[SC_FHAT] = fhat;
-    sc[SC_THETA1] = lam1;
-    sc[SC_DESC] = desc;
-    sc[SC_NDESC] += desc;
-    sc[SC_F] = fn;
-    set_metrics(sc, fn);
+    if (threadIdx.x == 0) decide_scalar(theta, sc);
 }
 void decide(hipStream_t s, const double *theta, double *sc) {
     hipLaunchKernelGGL(k_decide, dim3(1), dim3(64), 0, s, theta, sc);
@@ -171,12 +82,7 @@ void decide(hipStream_t s, const double *theta, double *sc) {
 // A Ritz value never exceeds lambda_max, so both the stored f and the new one are lower
 // bounds of f(y_t) when y_t is unchanged: keep_max then keeps the larger.
 __global__ void k_refresh_f(const double *__restrict__ theta, double *sc, int keep_max) {
-    if (threadIdx.x != 0) return;
-    double fn = sc[SC_ALPHA] * fmax(theta[0], 0.0) + sc[SC_BYT];
-    if (keep_max) fn = fmax(fn, sc[SC_F]);
-    sc[SC_F] = fn;
-    sc[SC_THETA1] = theta[0];
-    set_metrics(sc, fn);
+    if (threadIdx.x == 0) refresh_f_scalar(theta, sc, keep_max);
 }
 void recompute_f(hipStream_t s, const double *theta, const double *y, const double *b, int m, const RedScratch &rs,
                  double *sc, int keep_max) {
@@ -205,44 +111,8 @@ __global__ __launch_bounds__(kWG) void k_model_update(int k, int kp, int r, cons
                                                       const double *__restrict__ VtPsi, double *sc,
                                                       double *__restrict__ Kc, double *__restrict__ Qp,
                                                       double *__restrict__ Hsk) {
-    __shared__ SyevWork ws;
-    __shared__ double aS[kMaxK * kMaxK];
-    __shared__ double lam[kMaxK + 1];
-    __shared__ double Q[kMaxK * kMaxK];
-    __shared__ double sK[kMaxK * kMaxK];
-    const double alpha = sc[SC_ALPHA];
-    for (int e = threadIdx.x; e < k * k; e += kWG) aS[e] = alpha * st[e];
-    __syncthreads();
-    wg_syev_load(k, aS, k, nullptr, &ws);
-    wg_syev_top(k, k, k, &ws, lam, Q, k);
-    __syncthreads();
-    for (int e = threadIdx.x; e < k * k; e += kWG) {
-        const int i = e / k, j = e - i * k;
-        double v = 0.0;
-        for (int c = kp; c < k; ++c) v += Q[i * k + c] * lam[c] * Q[j * k + c];
-        sK[e] = v;
-        Kc[e] = v;
-    }
-    for (int e = threadIdx.x; e < k * kp; e += kWG) {
-        const int i = e / kp, c = e - i * kp;
-        Qp[e] = Q[i * k + c];
-    }
-    __syncthreads();
-    if (Hsk)
-        for (int e = threadIdx.x; e < k * r; e += kWG) {
-            const int i = e / r, c = e - i * r;
-            double v = 0.0;
-            for (int a = 0; a < k; ++a) v += sK[i * k + a] * VtPsi[a * r + c];
-            Hsk[e] = v;
-        }
-    if (threadIdx.x == 0) {
-        const double g = sc[SC_G];
-        double trc = 0.0, kv = 0.0;
-        for (int c = kp; c < k; ++c) trc += lam[c];
-        for (int e = 0; e < k * k; ++e) kv += sK[e] * VCV[e];
-        sc[SC_TAU] = g * sc[SC_TAU] + trc;
-        sc[SC_CBAR] = g * sc[SC_CBAR] + kv;
-    }
+    __shared__ ModelWork w;
+    wg_model_update(k, kp, r, st, VCV, VtPsi, sc, Kc, Qp, Hsk, &w);
 }
 void model_update(hipStream_t s, int k, int kp, int r, const double *st, const double *VCV, const double *VtPsi,
                   double *sc, double *Kc, double *Qp, double *Hsk) {

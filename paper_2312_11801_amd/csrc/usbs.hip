@@ -4,6 +4,8 @@
 #include "../../include/usbs.h"
 #include "kernels.h"
 #include "steps.h"
+#include "packed.h"
+#include "packed_host.h"
 
 #include <hip/hip_runtime.h>
 
@@ -976,6 +978,99 @@ int fail(usbs_handle *h, const DevError &e) {
 
 }  // namespace
 
+namespace {
+// Results of a finished solve (usbs_result, y in original units, Nystrom factors of the
+// sketch and their certificate terms) from the device state of the handle.
+void fill_result(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, double *lam_out, int status, int it,
+                 double secs) {
+    const usbs_params &p = h->prm;
+    std::vector<double> sc(SC_COUNT);
+    HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    if (res) {
+        std::memset(res, 0, sizeof(*res));
+        const double s = h->sigma * h->trace;
+        res->primal_obj_scaled = sc[SC_CX];
+        res->f_scaled = sc[SC_F];
+        res->primal_obj = s * sc[SC_CX];
+        res->dual_bound = s * sc[SC_F];
+        res->rel_gap = sc[SC_GAP];
+        res->rel_infeas = sc[SC_INF];
+        {
+            const double s2 = h->sigma * h->trace, dist = std::sqrt(std::max(sc[SC_DIST2], 0.0));
+            res->rel_gap_scaled = std::fabs(sc[SC_F] - sc[SC_CX]) / (1.0 + std::fabs(sc[SC_CX]));
+            res->rel_infeas_scaled = dist / (1.0 + h->bnorm);
+            res->rel_gap_original = std::fabs(s2 * sc[SC_F] - s2 * sc[SC_CX]) / (1.0 + std::fabs(s2 * sc[SC_CX]));
+            res->rel_infeas_original = h->trace * dist / (1.0 + h->trace * h->bnorm);
+        }
+        res->lanczos_unconverged = h->lz_unconverged;
+        res->stall_recoveries = h->recoveries;
+        res->lambda_max = sc[SC_THETA1];
+        res->seconds = secs;
+        res->lanczos_matvecs = h->matvecs;
+        res->iters = it;
+        res->descents = (int)sc[SC_NDESC];
+        res->ipm_iters = (int)sc[SC_IPMIT];
+        res->status = status;
+    }
+    if (y_out) {
+        std::vector<double> yv(h->m);
+        HIPCHK(hipMemcpyAsync(yv.data(), h->y, h->m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int q = 0; q < h->m; ++q) y_out[q] = h->sigma * yv[q];
+    }
+    if ((U_out || lam_out || res) && h->sketch && h->r > 0) {
+        // Nystrom reconstruction of Xbar (App. C.1) and its certificate terms
+        const int n = h->n, r = h->r;
+        hipStream_t s = h->stream;
+        interleave(s, n, r, h->P, h->psi, h->W2);
+        tn_reduce(s, h->rs, n, h->W2, 2 * r, 2 * r, h->W2, 2 * r, 2 * r, h->small, 2 * r, 1.0, 0.0);
+        nystrom_core(s, n, r, h->small, h->small + 1024, h->small + 2048, h->flag);
+        nn_update(s, n, h->W2, 2 * r, 2 * r, h->small + 1024, r, r, h->Zp, 16, 1.0, 0.0);
+        std::vector<double> lam(r);
+        HIPCHK(hipMemcpyAsync(lam.data(), h->small + 2048, r * sizeof(double), hipMemcpyDeviceToHost, s));
+        // <C_s, Xhat> = sum_j lam_j u_j^T C_s u_j ; A(Xhat)
+        apply_C(h, h->Zp, 16, h->CV, 16, r);
+        tn_reduce(s, h->rs, n, h->Zp, 16, r, h->CV, 16, r, h->TUU, r, 1.0, 0.0);
+        std::vector<double> uc(r * r);
+        HIPCHK(hipMemcpyAsync(uc.data(), h->TUU, r * r * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double cx = 0.0;
+        for (int j = 0; j < r; ++j) cx += lam[j] * uc[j * r + j];
+        std::vector<double> K(r * r, 0.0);
+        for (int j = 0; j < r; ++j) K[j * r + j] = lam[j];
+        HIPCHK(hipMemcpyAsync(h->Kc, K.data(), r * r * sizeof(double), hipMemcpyHostToDevice, s));
+        lowrank_A(s, h->m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, r, h->Kc, 1.0, nullptr, nullptr, 0.0, h->AX,
+                  0.0);
+        std::vector<double> ax(h->m), bs(h->m);
+        HIPCHK(hipMemcpyAsync(ax.data(), h->AX, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(bs.data(), h->b, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double d2 = 0.0;
+        for (int q = 0; q < h->m; ++q) {
+            const double e = h->hp.ineq[q] ? std::max(ax[q] - bs[q], 0.0) : ax[q] - bs[q];
+            d2 += e * e;
+        }
+        if (res) {
+            res->sketch_primal_obj = h->sigma * h->trace * cx;
+            res->sketch_rel_infeas = (p.units == USBS_UNITS_ORIGINAL)
+                                         ? h->trace * std::sqrt(d2) / (1.0 + h->trace * h->bnorm)
+                                         : std::sqrt(d2) / (1.0 + h->bnorm);
+        }
+        if (lam_out)
+            for (int j = 0; j < r; ++j) lam_out[j] = h->trace * lam[j];
+        if (U_out) {
+            std::vector<double> U((size_t)n * 16);
+            HIPCHK(hipMemcpyAsync(U.data(), h->Zp, (size_t)n * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < r; ++j) U_out[(size_t)i * r + j] = U[(size_t)i * 16 + j];
+        }
+    }
+}
+
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -1008,6 +1103,15 @@ int usbs_default_params(usbs_params *p) {
 }
 
 int usbs_create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **out) {
+    return usbs_pack::create(prob, prm, out, true);
+}
+
+}  // extern "C"
+
+namespace usbs_pack {
+// usbs_create; with cold = false the cold start is left to the packed kernel
+// (PACK_INIT_COLD): the scalars are initialised and the work arrays cleared here
+int create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **out, bool cold) {
     if (!out) return USBS_E_INVALID;
     *out = nullptr;
     usbs_handle *h = new usbs_handle();
@@ -1019,9 +1123,14 @@ int usbs_create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **
         if (h->hp.psi.empty()) h->r = 0;
         set_geometry(h, h->hp.n);
         upload(h);
-        autotune(h);
-        TuneScope tsc(h);
-        cold_start(h);
+        if (cold) {
+            autotune(h);
+            TuneScope tsc(h);
+            cold_start(h);
+        } else {
+            init_scalars(h);
+            HIPCHK(hipStreamSynchronize(h->stream));
+        }
         h->ready = true;
     } catch (const DevError &e) {
         *out = h;   // the handle carries the message; caller frees it
@@ -1033,6 +1142,9 @@ int usbs_create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **
     *out = h;
     return USBS_OK;
 }
+}  // namespace usbs_pack
+
+extern "C" {
 
 int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, double *lam_out) {
     if (!h || !h->ready) {
@@ -1082,86 +1194,7 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
             HIPCHK(hipStreamSynchronize(h->stream));
         }
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        if (res) {
-            std::memset(res, 0, sizeof(*res));
-            const double s = h->sigma * h->trace;
-            res->primal_obj_scaled = sc[SC_CX];
-            res->f_scaled = sc[SC_F];
-            res->primal_obj = s * sc[SC_CX];
-            res->dual_bound = s * sc[SC_F];
-            res->rel_gap = sc[SC_GAP];
-            res->rel_infeas = sc[SC_INF];
-            {
-                const double s2 = h->sigma * h->trace, dist = std::sqrt(std::max(sc[SC_DIST2], 0.0));
-                res->rel_gap_scaled = std::fabs(sc[SC_F] - sc[SC_CX]) / (1.0 + std::fabs(sc[SC_CX]));
-                res->rel_infeas_scaled = dist / (1.0 + h->bnorm);
-                res->rel_gap_original = std::fabs(s2 * sc[SC_F] - s2 * sc[SC_CX]) / (1.0 + std::fabs(s2 * sc[SC_CX]));
-                res->rel_infeas_original = h->trace * dist / (1.0 + h->trace * h->bnorm);
-            }
-            res->lanczos_unconverged = h->lz_unconverged;
-            res->stall_recoveries = h->recoveries;
-            res->lambda_max = sc[SC_THETA1];
-            res->seconds = secs;
-            res->lanczos_matvecs = h->matvecs;
-            res->iters = it;
-            res->descents = (int)sc[SC_NDESC];
-            res->ipm_iters = (int)sc[SC_IPMIT];
-            res->status = status;
-        }
-        if (y_out) {
-            std::vector<double> yv(h->m);
-            HIPCHK(hipMemcpyAsync(yv.data(), h->y, h->m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(hipStreamSynchronize(h->stream));
-            for (int q = 0; q < h->m; ++q) y_out[q] = h->sigma * yv[q];
-        }
-        if ((U_out || lam_out || res) && h->sketch && h->r > 0) {
-            // Nystrom reconstruction of Xbar (App. C.1) and its certificate terms
-            const int n = h->n, r = h->r;
-            hipStream_t s = h->stream;
-            interleave(s, n, r, h->P, h->psi, h->W2);
-            tn_reduce(s, h->rs, n, h->W2, 2 * r, 2 * r, h->W2, 2 * r, 2 * r, h->small, 2 * r, 1.0, 0.0);
-            nystrom_core(s, n, r, h->small, h->small + 1024, h->small + 2048, h->flag);
-            nn_update(s, n, h->W2, 2 * r, 2 * r, h->small + 1024, r, r, h->Zp, 16, 1.0, 0.0);
-            std::vector<double> lam(r);
-            HIPCHK(hipMemcpyAsync(lam.data(), h->small + 2048, r * sizeof(double), hipMemcpyDeviceToHost, s));
-            // <C_s, Xhat> = sum_j lam_j u_j^T C_s u_j ; A(Xhat)
-            apply_C(h, h->Zp, 16, h->CV, 16, r);
-            tn_reduce(s, h->rs, n, h->Zp, 16, r, h->CV, 16, r, h->TUU, r, 1.0, 0.0);
-            std::vector<double> uc(r * r);
-            HIPCHK(hipMemcpyAsync(uc.data(), h->TUU, r * r * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            double cx = 0.0;
-            for (int j = 0; j < r; ++j) cx += lam[j] * uc[j * r + j];
-            std::vector<double> K(r * r, 0.0);
-            for (int j = 0; j < r; ++j) K[j * r + j] = lam[j];
-            HIPCHK(hipMemcpyAsync(h->Kc, K.data(), r * r * sizeof(double), hipMemcpyHostToDevice, s));
-            lowrank_A(s, h->m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, r, h->Kc, 1.0, nullptr, nullptr, 0.0, h->AX,
-                      0.0);
-            std::vector<double> ax(h->m), bs(h->m);
-            HIPCHK(hipMemcpyAsync(ax.data(), h->AX, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipMemcpyAsync(bs.data(), h->b, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            double d2 = 0.0;
-            for (int q = 0; q < h->m; ++q) {
-                const double e = h->hp.ineq[q] ? std::max(ax[q] - bs[q], 0.0) : ax[q] - bs[q];
-                d2 += e * e;
-            }
-            if (res) {
-                res->sketch_primal_obj = h->sigma * h->trace * cx;
-                res->sketch_rel_infeas = (p.units == USBS_UNITS_ORIGINAL)
-                                             ? h->trace * std::sqrt(d2) / (1.0 + h->trace * h->bnorm)
-                                             : std::sqrt(d2) / (1.0 + h->bnorm);
-            }
-            if (lam_out)
-                for (int j = 0; j < r; ++j) lam_out[j] = h->trace * lam[j];
-            if (U_out) {
-                std::vector<double> U((size_t)n * 16);
-                HIPCHK(hipMemcpyAsync(U.data(), h->Zp, (size_t)n * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                for (int i = 0; i < n; ++i)
-                    for (int j = 0; j < r; ++j) U_out[(size_t)i * r + j] = U[(size_t)i * 16 + j];
-            }
-        }
+        fill_result(h, res, y_out, U_out, lam_out, status, it, secs);
         return status;
     } catch (const DevError &e) {
         return fail(h, e);
@@ -1520,7 +1553,14 @@ int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *z
     }
 }
 
-int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
+int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) { return usbs_pack::warm_prepare(h, grown, true); }
+
+}  // extern "C"
+
+namespace usbs_pack {
+// usbs_warm_start; with eval_f = false the closing eigen-solve for f(y0) is left to the
+// packed kernel (PACK_INIT_WARM)
+int warm_prepare(usbs_handle *h, const usbs_problem *grown, bool eval_f) {
     if (!h || !h->ready) {
         set_err(h, "usbs_warm_start: handle not ready");
         return USBS_E_STATE;
@@ -1611,17 +1651,278 @@ int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) {
         }
         const double tc[2] = {tau, cbar};
         HIPCHK(hipMemcpyAsync(h->sc + SC_TAU, tc, 2 * sizeof(double), hipMemcpyHostToDevice, s));
-        // f(y0) with a tight tolerance
-        shift_operator(h, h->y);
-        lanczos(h, h->Uritz, k, h->prm.lanczos_tol_final, std::sqrt(h->prm.lanczos_tol_final),
-                std::max(h->prm.lanczos_max_restarts, 30), false);
-        recompute_f(s, h->theta, h->y, h->b, m, h->rs, h->sc, 0);
+        if (eval_f) {
+            // f(y0) with a tight tolerance
+            shift_operator(h, h->y);
+            lanczos(h, h->Uritz, k, h->prm.lanczos_tol_final, std::sqrt(h->prm.lanczos_tol_final),
+                    std::max(h->prm.lanczos_max_restarts, 30), false);
+            recompute_f(s, h->theta, h->y, h->b, m, h->rs, h->sc, 0);
+        }
         HIPCHK(hipStreamSynchronize(s));
         h->ready = true;
         return USBS_OK;
     } catch (const DevError &e) {
         return fail(h, e);
     }
+}
+
+}  // namespace usbs_pack
+
+// ===========================================================================
+// packed solver: host side
+// ===========================================================================
+namespace {
+
+void fill_desc(const usbs_handle *h, PackDesc &d) {
+    std::memset(&d, 0, sizeof(d));
+    const usbs_params &p = h->prm;
+    d.n = h->n;
+    d.m = h->m;
+    d.k = h->k;
+    d.kc = h->kc;
+    d.kp = h->kp;
+    d.r = h->r;
+    d.steps = h->steps;
+    d.ldb = h->ldb;
+    d.prec = h->prec;
+    d.n_iso = h->n_iso;
+    d.n_offt = h->has_offc ? h->n_offt : 0;
+    d.has_ineq = h->has_ineq ? 1 : 0;
+    d.sketch = h->sketch ? 1 : 0;
+    d.max_restarts = p.lanczos_max_restarts;
+    d.max_iters = p.max_iters;
+    d.val_scale = h->val_scale;
+    d.tol = p.lanczos_tol;
+    d.tol_final = p.lanczos_tol_final;
+    d.alpha = p.alpha;
+    d.rho = p.rho;
+    d.eps_gap = p.eps_gap;
+    d.eps_inf = p.eps_infeas;
+    d.seed = p.seed;
+    d.rowptr = h->rowptr;
+    d.col = h->col;
+    d.val_cur = h->val_cur;
+    d.val_c = h->val_c;
+    d.cbase = h->cbase;
+    d.cdiag = h->cdiag;
+    d.dshift = h->dshift;
+    d.dptr = h->dptr;
+    d.dk = h->dk;
+    d.dv = h->dv;
+    d.off_slot = h->off_slot;
+    d.off_ptr = h->off_ptr;
+    d.off_k = h->off_k;
+    d.off_hv = h->off_hv;
+    d.kptr = h->kptr;
+    d.ti = h->ti;
+    d.tj = h->tj;
+    d.tv = h->tv;
+    d.b = h->b;
+    d.ineq = h->ineq;
+    d.psi = h->psi;
+    d.y = h->y;
+    d.yc = h->yc;
+    d.nu = h->nu;
+    d.dnu = h->dnu;
+    d.zbar = h->zbar;
+    d.AX = h->AX;
+    d.evec = h->evec;
+    d.V = h->V;
+    d.Vn = h->Vn;
+    d.CV = h->CV;
+    d.Uritz = h->Uritz;
+    d.P = h->P;
+    d.Ucpl = h->Ucpl;
+    d.iso_idx = h->iso_idx;
+    d.plan = h->plan;
+    d.Bm = h->Bm;
+    d.W = h->W;
+    d.Wt = h->Wt;
+    d.W2 = h->W2;
+    d.Ubuf = h->Ubuf;
+    d.Zp = h->Zp;
+    d.Tm = h->Tm;
+    d.theta = h->theta;
+    d.Ysm = h->Ysm;
+    d.TUU = h->TUU;
+    d.RtR = h->RtR;
+    d.Zc = h->Zc;
+    d.Hred = h->Hred;
+    d.Hg = h->Hg;
+    d.coef = h->coef;
+    d.Rsv = h->Rsv;
+    d.Rinv = h->Rinv;
+    d.res = h->res;
+    d.Hd = h->Hd;
+    d.dead = h->dead;
+    d.flag = h->flag;
+    d.zdead = h->zdead;
+    d.raw = h->raw;
+    d.qp = h->qp;
+    d.ipm = h->ipm;
+    d.VCV = h->VCV;
+    d.Gy = h->Gy;
+    d.Kc = h->Kc;
+    d.Qp = h->Qp;
+    d.Hsk = h->Hsk;
+    d.VtPsi = h->VtPsi;
+    d.hz = h->hz;
+    d.sc = h->sc;
+}
+
+}  // namespace
+
+namespace usbs_pack {
+
+Runner::~Runner() {
+    if (desc_dev) (void)hipFreeAsync(desc_dev, stream);
+    if (state_dev) (void)hipFreeAsync(state_dev, stream);
+    (void)hipStreamSynchronize(stream);
+    if (desc_host) (void)hipHostFree(desc_host);
+    if (state_host) (void)hipHostFree(state_host);
+}
+
+PackState begin(const usbs_handle *h, int init) {
+    PackState s;
+    std::memset(&s, 0, sizeof(s));
+    s.iters = h->iters;
+    s.null_run = h->null_run;
+    s.lz_unconverged = h->lz_unconverged;
+    s.recoveries = h->recoveries;
+    s.matvecs = h->matvecs;
+    s.init = init;
+    s.done = PACK_RUNNING;
+    return s;
+}
+
+int launch(Runner &R, usbs_handle *const *hs, PackState *st, int count, int iters, std::string *err) {
+    try {
+        std::vector<int> act;
+        for (int q = 0; q < count; ++q)
+            if (st[q].done == PACK_RUNNING) act.push_back(q);
+        const int na = (int)act.size();
+        if (na == 0) return USBS_OK;
+        if (na > R.cap) {
+            if (R.desc_dev) HIPCHK(hipFreeAsync(R.desc_dev, R.stream));
+            if (R.state_dev) HIPCHK(hipFreeAsync(R.state_dev, R.stream));
+            HIPCHK(hipStreamSynchronize(R.stream));
+            if (R.desc_host) HIPCHK(hipHostFree(R.desc_host));
+            if (R.state_host) HIPCHK(hipHostFree(R.state_host));
+            R.desc_dev = nullptr;
+            R.state_dev = nullptr;
+            R.desc_host = nullptr;
+            R.state_host = nullptr;
+            R.cap = 0;
+            const int cap = std::max(na, 64);
+            HIPCHK(hipMallocAsync((void **)&R.desc_dev, cap * sizeof(PackDesc), R.stream));
+            HIPCHK(hipMallocAsync((void **)&R.state_dev, cap * sizeof(PackState), R.stream));
+            HIPCHK(hipHostMalloc((void **)&R.desc_host, cap * sizeof(PackDesc), hipHostMallocDefault));
+            HIPCHK(hipHostMalloc((void **)&R.state_host, cap * sizeof(PackState), hipHostMallocDefault));
+            R.cap = cap;
+        }
+        for (int a = 0; a < na; ++a) {
+            const int q = act[a];
+            usbs_handle *h = hs[q];
+            if (!h || !h->ready) throw DevError(USBS_E_STATE, "packed launch: handle not ready");
+            if (h->n < 2 * (16 + 8)) throw DevError(USBS_E_INVALID, "packed launch: n < 48");
+            fill_desc(h, R.desc_host[a]);
+            R.state_host[a] = st[q];
+        }
+        HIPCHK(hipMemcpyAsync(R.desc_dev, R.desc_host, na * sizeof(PackDesc), hipMemcpyHostToDevice, R.stream));
+        HIPCHK(hipMemcpyAsync(R.state_dev, R.state_host, na * sizeof(PackState), hipMemcpyHostToDevice, R.stream));
+        packed_launch(R.stream, R.desc_dev, R.state_dev, na, iters);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(R.state_host, R.state_dev, na * sizeof(PackState), hipMemcpyDeviceToHost, R.stream));
+        HIPCHK(hipStreamSynchronize(R.stream));
+        for (int a = 0; a < na; ++a) {
+            const int q = act[a];
+            usbs_handle *h = hs[q];
+            st[q] = R.state_host[a];
+            if (st[q].swapped) std::swap(h->V, h->Vn);
+            st[q].swapped = 0;
+            h->iters = st[q].iters;
+            h->null_run = st[q].null_run;
+            h->lz_unconverged = st[q].lz_unconverged;
+            h->recoveries = st[q].recoveries;
+            h->matvecs = st[q].matvecs;
+        }
+        return USBS_OK;
+    } catch (const DevError &e) {
+        if (err) *err = e.what();
+        return e.code;
+    }
+}
+
+int finish(usbs_handle *h, const PackState &st, usbs_result *res, double secs) {
+    try {
+        if (st.done == PACK_FAILED) throw DevError(USBS_E_NUMERIC, "non-finite iterate or failed interior point solve");
+        const int status = st.done == PACK_CONVERGED ? USBS_OK : USBS_NOT_CONVERGED;
+        fill_result(h, res, nullptr, nullptr, nullptr, status, st.solve_iters, secs);
+        return status;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+}  // namespace usbs_pack
+
+extern "C" {
+
+int usbs_solve_packed(usbs_handle *const *hs, int32_t count, int32_t iters_per_launch, void *stream,
+                      usbs_result *res, int32_t *status) {
+    if (!hs || count < 1 || iters_per_launch < 1) return USBS_E_INVALID;
+    int dev = -1;
+    for (int q = 0; q < count; ++q) {
+        if (!hs[q] || !hs[q]->ready) return USBS_E_STATE;
+        if (dev < 0) dev = hs[q]->dev;
+        if (hs[q]->dev != dev) {
+            set_err(hs[q], "usbs_solve_packed: handles of different devices");
+            return USBS_E_INVALID;
+        }
+        for (int p = 0; p < q; ++p)
+            if (hs[p] == hs[q]) {
+                set_err(hs[q], "usbs_solve_packed: a handle is listed twice");
+                return USBS_E_INVALID;
+            }
+    }
+    try {
+        for (int q = 0; q < count; ++q) HIPCHK(hipStreamSynchronize(hs[q]->stream));
+    } catch (const DevError &e) {
+        return fail(hs[0], e);
+    }
+    usbs_pack::Runner R((hipStream_t)stream);
+    std::vector<PackState> st(count);
+    std::vector<double> secs(count, 0.0);
+    for (int q = 0; q < count; ++q) st[q] = usbs_pack::begin(hs[q], PACK_INIT_NONE);
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = USBS_OK;
+    for (;;) {
+        bool any = false;
+        for (int q = 0; q < count; ++q) any |= st[q].done == PACK_RUNNING;
+        if (!any) break;
+        std::string err;
+        rc = usbs_pack::launch(R, hs, st.data(), count, iters_per_launch, &err);
+        if (rc < 0) {
+            for (int q = 0; q < count; ++q) set_err(hs[q], err);
+            return rc;
+        }
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int q = 0; q < count; ++q) {
+            if (st[q].done != PACK_RUNNING) {
+                if (secs[q] == 0.0) secs[q] = el;
+            } else if (hs[q]->prm.time_limit > 0.0 && el > hs[q]->prm.time_limit) {
+                st[q].stop = 1;   // the next launch certifies f at the centre and stops
+            }
+        }
+    }
+    int worst = USBS_OK;
+    for (int q = 0; q < count; ++q) {
+        const int s = usbs_pack::finish(hs[q], st[q], res ? res + q : nullptr, secs[q]);
+        if (status) status[q] = s;
+        if (s < 0 && worst >= 0) worst = s;
+        else if (s == USBS_NOT_CONVERGED && worst == USBS_OK) worst = s;
+    }
+    return worst;
 }
 
 }  // extern "C"

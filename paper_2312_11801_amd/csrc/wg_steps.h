@@ -1,0 +1,769 @@
+// Device-side bodies of the hot-path steps, shared by the per-instance kernels
+// (kernels.hip, steps.hip: one launch per step, possibly many workgroups) and
+// the packed solver (packed.hip: one workgroup runs every step of one
+// instance).  A body that reduces over rows takes its workgroup's share of the
+// rows as (blk, nblk): the per-instance kernels pass (blockIdx.x, gridDim.x)
+// and write a partial result per workgroup; the packed solver passes (0, 1) and
+// writes the final value.  Bodies that need LDS take it as a pointer to a
+// workspace struct, so the packed kernel can overlay the workspaces of steps
+// that never run at the same time.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "kernels.h"
+#include "small_dense.h"
+#include "steps.h"
+#include "syev.h"
+
+namespace usbs {
+
+typedef double v4d __attribute__((ext_vector_type(4)));   // one lane's MFMA FP64 accumulator
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float(((uint32_t)h) << 16);
+}
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    // round to nearest even
+    uint32_t u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    u = __float_as_uint(f);
+#else
+    memcpy(&u, &f, 4);
+#endif
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);   // inf / nan
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+// splitmix64 finaliser; the start blocks of the eigen-solver are uniform in [-1, 1]
+// from the hash of (seed, element index)
+__device__ __forceinline__ uint64_t mix64(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+__device__ __forceinline__ double hash_uniform(uint64_t seed, uint64_t e) {
+    const uint64_t h = mix64(seed * 0x100000001B3ull + e);
+    return (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// ---------------------------------------------------------------------------
+// one output row of the shifted operator: sum over the row's off-diagonal
+// nonzeros in two partial sums (even / odd position), then the diagonal term
+//   Y[i, c] = diag[i] X[i, c] + scale * sum_e val[e] X[col[e], c]
+// ---------------------------------------------------------------------------
+template <typename VT, typename ACC>
+__device__ __forceinline__ ACC spmm_value(const VT *__restrict__ val, int e) {
+    if constexpr (sizeof(VT) == 2) return (ACC)bf16_to_f32(val[e]);
+    else return (ACC)val[e];
+}
+template <typename VT, typename ACC>
+__device__ __forceinline__ double spmm_row(int i, int cc, const int *__restrict__ rowptr, const int *__restrict__ col,
+                                           const VT *__restrict__ val, ACC scale, const double *__restrict__ diag,
+                                           const double *__restrict__ X, int ldx) {
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    ACC acc0 = 0, acc1 = 0;
+    int e = e0;
+    for (; e + 1 < e1; e += 2) {
+        const int j0 = col[e], j1 = col[e + 1];
+        const ACC v0 = spmm_value<VT, ACC>(val, e), v1 = spmm_value<VT, ACC>(val, e + 1);
+        const ACC x0 = (ACC)X[(size_t)j0 * ldx + cc];
+        const ACC x1 = (ACC)X[(size_t)j1 * ldx + cc];
+        acc0 += v0 * x0;
+        acc1 += v1 * x1;
+    }
+    if (e < e1) acc0 += spmm_value<VT, ACC>(val, e) * (ACC)X[(size_t)col[e] * ldx + cc];
+    return diag[i] * X[(size_t)i * ldx + cc] + (double)(scale * (acc0 + acc1));
+}
+
+// ---------------------------------------------------------------------------
+// H = A^T B (and with GRAM also B^T B below it) for cb <= 16 on the FP64 matrix
+// cores: V_MFMA_F64_16X16X4F64 accumulates X (16 x 4) Y (4 x 16) with X[m][k] in
+// lane m + 16 k, Y[k][j] in lane j + 16 k, and D[m][j] in lane j + 16 (m % 4),
+// element m / 4.  A wavefront takes 4 rows at a time: X = 16 columns of A of those
+// rows (one double per lane, 128 contiguous bytes per row), Y = the columns of B
+// (lanes j >= cb hold 0), so every element of A is loaded once.  The Gram block
+// B^T B uses Y as X.  UNR row groups are in flight per wavefront; the four
+// wavefronts are summed in LDS in a fixed order and wavefront 0 writes
+//   dst[a * ldd + j] = alpha * sum (+ beta * dst),  a < ca (+ cb with GRAM), j < cb.
+// Row groups of this workgroup: g = 4 blk + wave + u * 4 nblk.
+// ---------------------------------------------------------------------------
+constexpr int kMfmaMaxCh = kMaxBasis / 16;   // 16-column chunks of A (ca <= 80)
+struct TnWork {
+    double sred[3][kMfmaMaxCh + 1][4][64];
+};
+template <typename TB, int UNR, bool GRAM>
+__device__ __forceinline__ void wg_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
+                                           const TB *__restrict__ B, int ldb, int cb, int blk, int nblk,
+                                           double *dst, int ldd, double alpha, double beta, TnWork *w) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kk = lane >> 4;
+    const int nch = (ca + 15) >> 4;
+    v4d acc[kMfmaMaxCh + 1];
+#pragma unroll
+    for (int q = 0; q <= kMfmaMaxCh; ++q) acc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+    const long ngroups = ((long)n + 3) >> 2;
+    const long gstride = (long)nblk * 4;
+    for (long g0 = (long)blk * 4 + wave; g0 < ngroups; g0 += UNR * gstride) {
+        double yv[UNR], xv[UNR][kMfmaMaxCh];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const long row = 4 * (g0 + u * gstride) + kk;
+            const bool ok = (g0 + u * gstride < ngroups) && row < n;
+            yv[u] = (ok && m < cb) ? (double)B[row * ldb + m] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kMfmaMaxCh; ++q) {
+                const int c = 16 * q + m;
+                xv[u][q] = (ok && q < nch && c < ca) ? A[row * lda + c] : 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+#pragma unroll
+            for (int q = 0; q < kMfmaMaxCh; ++q)
+                if (q < nch) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[u][q], yv[u], acc[q], 0, 0, 0);
+            if (GRAM) acc[kMfmaMaxCh] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[u], yv[u], acc[kMfmaMaxCh], 0, 0, 0);
+        }
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int q = 0; q <= kMfmaMaxCh; ++q)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) w->sred[wave - 1][q][v][lane] = acc[q][v];
+    __syncthreads();
+    if (wave == 0) {
+        const int j = lane & 15;
+#pragma unroll
+        for (int q = 0; q <= kMfmaMaxCh; ++q) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double t =
+                    ((acc[q][v] + w->sred[0][q][v][lane]) + w->sred[1][q][v][lane]) + w->sred[2][q][v][lane];
+                const int mm = (lane >> 4) + 4 * v;   // row of D held in this element
+                const int a = (q < kMfmaMaxCh) ? 16 * q + mm : ca + mm;
+                const bool valid = (q < kMfmaMaxCh) ? (q < nch && a < ca) : (GRAM && mm < cb);
+                if (valid && j < cb) {
+                    double *p = dst + (size_t)a * ldd + j;
+                    *p = (beta != 0.0) ? alpha * t + beta * (*p) : alpha * t;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// C = beta*C + alpha*[A A2] H on the FP64 matrix cores: a wavefront takes 16 rows at a
+// time, loads them with row-contiguous loads into its own LDS tile, then runs
+// V_MFMA_F64_16X16X4F64 over the (ca + ca2) columns four at a time:
+// X[m][k] = tile[m][4 q + k], Y[k][j] = H[4 q + k][j] (held in registers), D[m][j] =
+// output row row0 + m, column j.  Each element of A is read once.  C must not alias
+// A or A2.  Row groups of this workgroup: g = 4 blk + wave + t * 4 nblk.
+// ---------------------------------------------------------------------------
+constexpr int kNnMaxQ = (kMaxBasis + kBlk) / 4;   // 22 four-column steps
+constexpr int kNnLd = kMaxBasis + kBlk + 1;
+struct NnWork {
+    double tile[4][16][kNnLd];
+};
+__device__ __forceinline__ void wg_nn_mfma(int n, const double *__restrict__ A, int lda, int ca,
+                                           const double *__restrict__ A2, int lda2, int ca2,
+                                           const double *__restrict__ H, int ldh, int cc, double *__restrict__ C,
+                                           int ldc, double alpha, double beta, int blk, int nblk, NnWork *w) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kk = lane >> 4, j = lane & 15;
+    const int ct = ca + ca2;
+    const int nq = (ct + 3) >> 2;
+    double yv[kNnMaxQ];
+#pragma unroll
+    for (int q = 0; q < kNnMaxQ; ++q) {
+        const int a = 4 * q + kk;
+        yv[q] = (q < nq && a < ct && j < cc) ? H[a * ldh + j] : 0.0;
+    }
+    double(*T)[kNnLd] = w->tile[wave];
+    const long ngroups = ((long)n + 15) >> 4;
+    const long gstride = (long)nblk * 4;
+    for (long g = (long)blk * 4 + wave; g < ngroups; g += gstride) {
+        const long row0 = 16 * g;
+        // rows of A: lanes over columns (two passes when ca > 64); A2 (<= 8 columns): 8 rows
+        // of 8 lanes per load
+        double v[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r] = (lane < ca && row0 + r < n) ? A[(row0 + r) * lda + lane] : 0.0;
+        double w2[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = 8 * h + (lane >> 3), c = lane & 7;
+            w2[h] = (c < ca2 && row0 + r < n) ? A2[(row0 + r) * lda2 + c] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            if (lane < ca) T[r][lane] = v[r];
+        if (ca > 64) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                v[r] = (64 + lane < ca && row0 + r < n) ? A[(row0 + r) * lda + 64 + lane] : 0.0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (64 + lane < ca) T[r][64 + lane] = v[r];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = 8 * h + (lane >> 3), c = lane & 7;
+            if (c < ca2) T[r][ca + c] = w2[h];
+        }
+        wave_sync();
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < kNnMaxQ; ++q)
+            if (q < nq) {
+                const int a = 4 * q + kk;
+                const double x = (a < ct) ? T[m][a] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, yv[q], acc, 0, 0, 0);
+            }
+        wave_sync();   // the tile is reloaded for the next row group
+        if (j < cc) {
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                const long r = row0 + (lane >> 4) + 4 * vv;
+                if (r < n) {
+                    double o = alpha * acc[vv];
+                    if (beta != 0.0) o += beta * C[r * ldc + j];
+                    C[r * ldc + j] = o;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// constraint-side bodies (App. B.2 and App. C)
+// ---------------------------------------------------------------------------
+// g_k = svec(V^T A_k V) for one constraint row k into g[0..d) (g may live in LDS)
+__device__ __forceinline__ void svec_constraint(int k, const int *__restrict__ kptr, const int *__restrict__ ti,
+                                                const int *__restrict__ tj, const double *__restrict__ tv,
+                                                const double *__restrict__ V, int ldv, int kd, double *g) {
+    const double r2 = 1.4142135623730951;
+    int d = kd * (kd + 1) / 2;
+    for (int p = 0; p < d; ++p) g[p] = 0.0;
+    for (int t = kptr[k]; t < kptr[k + 1]; ++t) {
+        const double *vi = V + (size_t)ti[t] * ldv;
+        const double *vj = V + (size_t)tj[t] * ldv;
+        const double v = tv[t];
+        int p = 0;
+        for (int b = 0; b < kd; ++b) {
+            const double vib = vi[b], vjb = vj[b];
+            for (int a = b; a < kd; ++a) {
+                if (a == b) g[p] += v * vi[a] * vjb;
+                else g[p] += v * r2 * 0.5 * (vi[a] * vjb + vib * vj[a]);
+                ++p;
+            }
+        }
+    }
+}
+
+// Q11 raw sum and G^T w_j over the constraint rows of this workgroup.  Rows are
+// processed in batches of 64 staged in LDS; each thread owns a fixed set of (P,Q)
+// entries of the upper triangle.  out layout (d = kd(kd+1)/2): if do_q11, the upper
+// triangle of sum_k g_k g_k^T row by row; then G^T w_j, j < nw.
+constexpr int kQB = 64;
+struct QpGramWork {
+    double sg[kQB][kMaxSvec + 1];
+    double sw[4][kQB];
+};
+__device__ __forceinline__ void wg_qp_gram(int m, const int *__restrict__ kptr, const int *__restrict__ ti,
+                                           const int *__restrict__ tj, const double *__restrict__ tv,
+                                           const double *__restrict__ V, int ldv, int kd, int do_q11,
+                                           const double *w0, const double *w1, const double *w2, const double *w3,
+                                           int nw, int blk, int nblk, double *out, QpGramWork *w) {
+    const int tid = threadIdx.x;
+    const int d = kd * (kd + 1) / 2;
+    const int nupper = do_q11 ? d * (d + 1) / 2 : 0;
+    const int nout = nupper + nw * d;
+    constexpr int kPer = (kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec + kWG - 1) / kWG;
+    double acc[kPer];
+    int pP[kPer], pQ[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        acc[q] = 0.0;
+        const int o = tid + q * kWG;
+        pP[q] = -1;
+        pQ[q] = -1;
+        if (o < nupper) {
+            // o -> (P, Q) with P <= Q in row-major upper-triangle order
+            int P = 0, rem = o;
+            while (rem >= d - P) {
+                rem -= d - P;
+                ++P;
+            }
+            pP[q] = P;
+            pQ[q] = P + rem;
+        } else if (o < nout) {
+            const int j = (o - nupper) / d;
+            pP[q] = -(j + 2);               // weight vector j
+            pQ[q] = (o - nupper) - j * d;   // svec entry
+        }
+    }
+    const double *ws[4] = {w0, w1, w2, w3};
+    for (long k0 = (long)blk * kQB; k0 < m; k0 += (long)nblk * kQB) {
+        if (tid < kQB) {
+            const long k = k0 + tid;
+            if (k < m) svec_constraint((int)k, kptr, ti, tj, tv, V, ldv, kd, &w->sg[tid][0]);
+            else
+                for (int p = 0; p < d; ++p) w->sg[tid][p] = 0.0;
+            for (int j = 0; j < nw; ++j) w->sw[j][tid] = (k < m) ? ws[j][k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int P = pP[q], Q = pQ[q];
+            if (Q < 0) continue;
+            double s = 0.0;
+            if (P >= 0) {
+                for (int r = 0; r < kQB; ++r) s += w->sg[r][P] * w->sg[r][Q];
+            } else {
+                const int j = -P - 2;
+                for (int r = 0; r < kQB; ++r) s += w->sw[j][r] * w->sg[r][Q];
+            }
+            acc[q] += s;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int o = tid + q * kWG;
+        if (o < nout) out[o] = acc[q];
+    }
+}
+
+// (A(V K V^T))_k for one constraint row: sum_t v_t V_i^T K V_j, K (16 x 16 padded) in LDS
+__device__ __forceinline__ double lowrank_row(long k, const int *__restrict__ kptr, const int *__restrict__ ti,
+                                              const int *__restrict__ tj, const double *__restrict__ tv,
+                                              const double *__restrict__ V, int ldv, int kd, const double *sK) {
+    double acc = 0.0;
+    for (int t = kptr[k]; t < kptr[k + 1]; ++t) {
+        const double *vi = V + (size_t)ti[t] * ldv;
+        const double *vj = V + (size_t)tj[t] * ldv;
+        double xj[16];
+#pragma unroll
+        for (int b = 0; b < 16; ++b) xj[b] = (b < kd) ? vj[b] : 0.0;
+        double q = 0.0;
+#pragma unroll 1
+        for (int a = 0; a < kd; ++a) {
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b < 16; ++b) s += sK[a * 16 + b] * xj[b];
+            q += vi[a] * s;
+        }
+        acc += tv[t] * q;
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// One pass of block Gram-Schmidt with Pythagorean inner products (one
+// workgroup), from Hg = [Q W]^T W: rows 0..cols-1 hold H = Q^T W, rows
+// cols..cols+7 hold G = W^T W.  With Q^T Q = I,
+//   Omega = G - H^T H = (W - Q H)^T (W - Q H) = R^T R   (Cholesky, deflation)
+//   coef  = [-H R^{-1}; R^{-1}]  so that  [Q W] coef = (W - Q H) R^{-1}.
+// The projections of the block that entered the first pass are H1 + H2 R1
+// (W0 = Q H1 + W1 R1, W1 = Q H2 + W2 R2): pass 0 stores H into T and keeps R;
+// pass 1 adds H R_saved.
+// ---------------------------------------------------------------------------
+struct PipWork {
+    double sH[kMaxBasis][kBlk];
+    double sOm[kBlk * 17];
+    double sRi[kBlk * kBlk];
+    double sR[kBlk][kBlk];
+};
+__device__ __forceinline__ void wg_pip_chol(const double *__restrict__ Hg, int cols, int pass,
+                                            double *__restrict__ Rsave, double *__restrict__ T, int ldt,
+                                            double *__restrict__ coef, int *flags,
+                                            const double *__restrict__ floor_ref, PipWork *w) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < cols * kBlk; e += kWG) w->sH[e / kBlk][e % kBlk] = Hg[e];
+    if (tid < kBlk * kBlk) w->sR[tid / kBlk][tid % kBlk] = (pass == 1) ? Rsave[tid] : 0.0;
+    __syncthreads();
+    if (tid < kBlk * kBlk) {
+        const int i = tid / kBlk, j = tid % kBlk;
+        double sacc = 0.0;
+        for (int a = 0; a < cols; ++a) sacc += w->sH[a][i] * w->sH[a][j];
+        w->sOm[i * 17 + j] = Hg[(cols + i) * kBlk + j] - sacc;
+    }
+    // projections of the original block into T
+    for (int e = tid; e < cols * kBlk; e += kWG) {
+        const int a = e / kBlk, c = e % kBlk;
+        if (pass == 0) {
+            T[a * ldt + c] = w->sH[a][c];
+        } else {
+            double v = 0.0;
+            for (int k = 0; k <= c; ++k) v += w->sH[a][k] * w->sR[k][c];
+            T[a * ldt + c] += v;
+        }
+    }
+    __syncthreads();
+    double f2 = 0.0;
+    if (floor_ref) {
+        const double rf = 1e-10 * (*floor_ref);
+        f2 = rf * rf;
+    }
+    if (tid < 64) wave_cholqr(kBlk, w->sOm, 17, w->sRi, kBlk, flags, f2);
+    __syncthreads();
+    // R = L^T (upper) of this pass, kept for the correction of the next pass
+    if (pass == 0 && tid < kBlk * kBlk) {
+        const int i = tid / kBlk, j = tid % kBlk;
+        Rsave[tid] = (j >= i) ? w->sOm[j * 17 + i] : 0.0;
+    }
+    for (int e = tid; e < (cols + kBlk) * kBlk; e += kWG) {
+        const int a = e / kBlk, c = e % kBlk;
+        double v;
+        if (a < cols) {
+            v = 0.0;
+            for (int k = 0; k < kBlk; ++k) v -= w->sH[a][k] * w->sRi[k * kBlk + c];
+        } else {
+            v = w->sRi[(a - cols) * kBlk + c];
+        }
+        coef[e] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos restart: residual norms, convergence test and the compression of the
+// 16 Ritz residuals to the 8 dominant directions (next block): 8 of the 16
+// residual directions chosen by pivoted Cholesky of the Gram matrix R^T R (greedy:
+// the residual with the largest component orthogonal to those already chosen), each
+// scaled by 1 / ||r_p||; the block is orthonormalised afterwards.  Wavefront 0 does
+// the work, lanes 0..15 own one residual each.
+// convergence: residual of Ritz pair 0 <= tol * scale and of pairs 1..kc-1 <= tol_rest * scale
+// ---------------------------------------------------------------------------
+struct RestartWork {
+    double sG[kRitz][kRitz + 1];
+    double sL[kBlk][kRitz];
+    int sel[kBlk];
+};
+__device__ __forceinline__ void wg_restart_prep(const double *__restrict__ RtR, const double *__restrict__ theta,
+                                                int kc, double tol, double tol_rest, double *__restrict__ res,
+                                                int *__restrict__ flag, double *__restrict__ Z,
+                                                const double *__restrict__ scale_est, RestartWork *w) {
+    const int tid = threadIdx.x;
+    if (tid < kRitz) res[tid] = sqrt(fmax(RtR[tid * kRitz + tid], 0.0));
+    if (tid < 64) {
+        for (int e = tid; e < kRitz * kRitz; e += 64) w->sG[e / kRitz][e % kRitz] = RtR[e];
+        for (int e = tid; e < kRitz * kBlk; e += 64) Z[e] = 0.0;
+        wave_sync();
+        const int i = tid & 15;   // every row of 16 lanes holds the same data
+        double d = fmax(w->sG[i][i], 0.0);
+        const double d0 = fmax(row16_max(d), 1e-300);
+        bool taken = false;
+        for (int t = 0; t < kBlk; ++t) {
+            // arg-max of the remaining diagonal (ties: lowest index)
+            const double cand = taken ? -1.0 : d;
+            const double best = row16_max(cand);
+            const double idx = row16_min((cand == best) ? (double)i : 1e9);
+            const int p = (int)idx;
+            if (!(best > 1e-24 * d0)) break;   // the residuals span fewer than t + 1 directions
+            const double piv = sqrt(best);
+            // column t of the pivoted Cholesky factor
+            double l = w->sG[i][p];
+            for (int u = 0; u < t; ++u) l -= w->sL[u][i] * w->sL[u][p];
+            l /= piv;
+            wave_sync();
+            if (tid < kRitz) w->sL[t][i] = l;
+            if (tid == 0) {
+                w->sel[t] = p;
+                Z[p * kBlk + t] = 1.0 / sqrt(fmax(w->sG[p][p], 1e-300));
+            }
+            wave_sync();
+            d = fmax(d - l * l, 0.0);
+            if (i == p) taken = true;
+        }
+        if (tid == 0) {
+            // tolerances are relative to a Gershgorin bound of the current operator
+            double sc = fmax(fabs(theta[0]), fabs(theta[kRitz - 1]));
+            if (scale_est) sc = fmax(sc, *scale_est);
+            // the top Ritz pair sets f(y): tight tolerance; the others only shape the bundle
+            int ok = sqrt(fmax(RtR[0], 0.0)) <= tol * sc;
+            for (int q = 1; q < kc; ++q) {
+                const double r = sqrt(fmax(RtR[q * kRitz + q], 0.0));
+                if (!(r <= tol_rest * sc)) ok = 0;
+            }
+            *flag = ok;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// decoupled rows (no off-diagonal entry in C - A^*(y) for any y): the 16 largest d
+// over those rows (ties by row index) by repeated arg-max, then a merge with the 16
+// descending coupled Ritz values; plan[q] = coupled column, -(row + 1) or 16 (empty).
+// ---------------------------------------------------------------------------
+struct IsoWork {
+    double bv[kWG];
+    int bq[kWG];
+    double iv[kRitz];
+    int ii[kRitz];
+};
+__device__ __forceinline__ void wg_iso_merge(int count, const int *__restrict__ idx, const double *__restrict__ d,
+                                             int have_coupled, double *__restrict__ theta, double *__restrict__ res,
+                                             int *__restrict__ plan, IsoWork *w) {
+    const int tid = threadIdx.x;
+    const int want = count < kRitz ? count : kRitz;
+    for (int t = 0; t < want; ++t) {
+        double best = -INFINITY;
+        int bestq = -1;
+        for (int q = tid; q < count; q += kWG) {
+            bool taken = false;
+            for (int u = 0; u < t; ++u) taken |= (w->ii[u] == q);
+            const double v = d[idx[q]];
+            if (!taken && (bestq < 0 || v > best)) {
+                best = v;
+                bestq = q;
+            }
+        }
+        w->bv[tid] = best;
+        w->bq[tid] = bestq;
+        __syncthreads();
+        for (int o = kWG / 2; o > 0; o >>= 1) {
+            if (tid < o) {
+                const double v2 = w->bv[tid + o];
+                const int q2 = w->bq[tid + o];
+                if (q2 >= 0 && (w->bq[tid] < 0 || v2 > w->bv[tid] || (v2 == w->bv[tid] && q2 < w->bq[tid]))) {
+                    w->bv[tid] = v2;
+                    w->bq[tid] = q2;
+                }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+            w->iv[t] = w->bv[0];
+            w->ii[t] = w->bq[0];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        double th[kRitz], rr[kRitz];
+        int pl[kRitz];
+        int a = 0, b = 0;
+        const int nc = have_coupled ? kRitz : 0;
+        for (int q = 0; q < kRitz; ++q) {
+            const bool take_c = a < nc && (b >= want || theta[a] >= w->iv[b]);
+            if (take_c) {
+                th[q] = theta[a];
+                rr[q] = res[a];
+                pl[q] = a++;
+            } else if (b < want) {
+                th[q] = w->iv[b];
+                rr[q] = 0.0;
+                pl[q] = -(idx[w->ii[b]] + 1);
+                ++b;
+            } else {   // fewer than 16 eigenpairs in total: pad with empty columns
+                th[q] = -1e300;
+                rr[q] = 0.0;
+                pl[q] = kRitz;
+            }
+        }
+        for (int q = 0; q < kRitz; ++q) {
+            theta[q] = th[q];
+            res[q] = rr[q];
+            plan[q] = pl[q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small steps of the iteration on the device scalar array sc
+// ---------------------------------------------------------------------------
+// relative errors of eq. relative_error_tol (suboptimality through the upper bound of eq.
+// objective_subopt_upper_bound) in the units selected by SC_UNITS
+__device__ __forceinline__ void set_metrics(double *sc, double fn) {
+    const double cx = sc[SC_CX];
+    const double dist = sqrt(fmax(sc[SC_DIST2], 0.0));
+    if (sc[SC_UNITS] != 0.0) {
+        const double s = sc[SC_SIGMA] * sc[SC_TRACE];
+        const double fo = s * fn, co = s * cx;
+        sc[SC_GAP] = fabs(fo - co) / (1.0 + fabs(co));
+        sc[SC_INF] = sc[SC_TRACE] * dist / (1.0 + sc[SC_TRACE] * sc[SC_BNORM]);
+    } else {
+        sc[SC_GAP] = fabs(fn - cx) / (1.0 + fabs(cx));
+        sc[SC_INF] = dist / (1.0 + sc[SC_BNORM]);
+    }
+}
+
+// master QP coefficients (App. B.2, eq. compressed_subprob_2, normalised form)
+//   raw = [upper triangle of sum g g^T | G^T zbar | G^T y | G^T b | G^T nu]
+__device__ __forceinline__ void wg_qp_finalize(int k, const double *__restrict__ raw, const double *__restrict__ VCV,
+                                               const double *__restrict__ sc, int has_nu, double *__restrict__ qp) {
+    const int d = k * (k + 1) / 2, nup = d * (d + 1) / 2;
+    const double alpha = sc[SC_ALPHA], rho = sc[SC_RHO], tau = sc[SC_TAU];
+    const double a2r = alpha * alpha / rho;
+    const double *Gz = raw + nup, *Gy = Gz + d, *Gb = Gy + d, *Gn = Gb + d;
+    for (int e = threadIdx.x; e < d * d; e += kWG) {
+        const int P = e / d, Q = e - P * d;
+        const int lo = P < Q ? P : Q, hi = P < Q ? Q : P;
+        qp[e] = a2r * raw[lo * d - lo * (lo - 1) / 2 + (hi - lo)];
+    }
+    for (int p = threadIdx.x; p < d; p += kWG) {
+        // p -> (i, j), i >= j, column-wise lower triangle
+        int j = 0, rem = p;
+        while (rem >= k - j) {
+            rem -= k - j;
+            ++j;
+        }
+        const int i = j + rem;
+        const double sv = (i == j ? 1.0 : 1.4142135623730951) * VCV[i * k + j];
+        const double gw = Gb[p] - (has_nu ? Gn[p] : 0.0);
+        qp[d * d + p] = (tau > 0.0) ? a2r / tau * Gz[p] : 0.0;               // q12
+        qp[d * d + d + 1 + p] = alpha * (Gy[p] - gw / rho - sv);             // h1
+    }
+    if (threadIdx.x == 0) {
+        const double zz = sc[SC_ZZ], yz = sc[SC_YZBAR], bz = sc[SC_BZ], nz = has_nu ? sc[SC_NUZ] : 0.0;
+        qp[d * d + d] = (tau > 0.0) ? a2r * zz / (tau * tau) : 0.0;                                        // q22
+        qp[d * d + 2 * d + 1] = (tau > 0.0) ? alpha / tau * (yz - (bz - nz) / rho - sc[SC_CBAR]) : 0.0;   // h2
+    }
+}
+
+// g = alpha eta / tau, <C, X_{t+1}> = g cbar + alpha <V^T C V, S>  (thread 0)
+__device__ __forceinline__ void post_ipm_scalar(int k, const double *__restrict__ st, const double *__restrict__ VCV,
+                                                double *sc) {
+    const double alpha = sc[SC_ALPHA], tau = sc[SC_TAU];
+    const double eta = st[2 * k * k];
+    const double g = (tau > 0.0) ? alpha * eta / tau : 0.0;
+    double vs = 0.0;
+    for (int e = 0; e < k * k; ++e) vs += VCV[e] * st[e];
+    sc[SC_ETA] = eta;
+    sc[SC_G] = g;
+    sc[SC_CX] = g * sc[SC_CBAR] + alpha * vs;
+    sc[SC_IPMIT] += st[2 * k * k + 3];
+    if (st[2 * k * k + 4] != 0.0) sc[SC_IPMSTATUS] = st[2 * k * k + 4];
+}
+
+// descent test (Alg. 1), f, f^ and the relative errors  (thread 0)
+__device__ __forceinline__ void decide_scalar(const double *__restrict__ theta, double *sc) {
+    const double alpha = sc[SC_ALPHA], beta = sc[SC_BETA], tau = sc[SC_TAU];
+    const double by = sc[SC_BY];
+    const double lam1 = theta[0];
+    const double fc = alpha * fmax(lam1, 0.0) + by;
+    double best = fmax(0.0, sc[SC_LAMV]);
+    if (tau > 0.0) best = fmax(best, (sc[SC_CBAR] - sc[SC_YZ]) / tau);
+    const double fhat = alpha * best + by;
+    const double f = sc[SC_F];
+    const int desc = (beta * (f - fhat) <= f - fc) ? 1 : 0;
+    const double fn = desc ? fc : f;
+    sc[SC_FCAND] = fc;
+    sc[SC_FHAT] = fhat;
+    sc[SC_THETA1] = lam1;
+    sc[SC_DESC] = desc;
+    sc[SC_NDESC] += desc;
+    sc[SC_F] = fn;
+    set_metrics(sc, fn);
+}
+
+// f(y_t) = alpha [theta_1]_+ + <b, y_t> from an accurate Ritz value (SC_BYT holds <b, y_t>).
+// A Ritz value never exceeds lambda_max, so both the stored f and the new one are lower
+// bounds of f(y_t) when y_t is unchanged: keep_max then keeps the larger.  (thread 0)
+__device__ __forceinline__ void refresh_f_scalar(const double *__restrict__ theta, double *sc, int keep_max) {
+    double fn = sc[SC_ALPHA] * fmax(theta[0], 0.0) + sc[SC_BYT];
+    if (keep_max) fn = fmax(fn, sc[SC_F]);
+    sc[SC_F] = fn;
+    sc[SC_THETA1] = theta[0];
+    set_metrics(sc, fn);
+}
+
+// alternating maximisation (eq. dual_slack_update): nu = proj_N(b - AX - rho y), one row
+__device__ __forceinline__ void nu_update_elem(long k, const double *__restrict__ b, const double *__restrict__ AX,
+                                              const double *__restrict__ y, const double *__restrict__ ineq,
+                                              double rho, double *__restrict__ nu, double *__restrict__ dnu) {
+    const double v = (ineq[k] != 0.0) ? fmax(b[k] - AX[k] - rho * y[k], 0.0) : 0.0;
+    dnu[k] = v - nu[k];
+    nu[k] = v;
+}
+
+// candidate (eq. dual_update, feasible form of Sec. 3.2) and the infeasibility vector, one row
+__device__ __forceinline__ void candidate_elem(long k, const double *__restrict__ b, const double *__restrict__ AX,
+                                              const double *__restrict__ y, const double *__restrict__ ineq,
+                                              double rho, double *__restrict__ yc, double *__restrict__ e) {
+    const double r = b[k] - AX[k];
+    double v = y[k] - r / rho;
+    if (ineq[k] != 0.0) {
+        v = fmax(v, 0.0);
+        e[k] = fmax(-r, 0.0);
+    } else {
+        e[k] = -r;
+    }
+    yc[k] = v;
+}
+
+// lambda_max(V^T (C - A^* y~) V) with V^T A^* y~ V = smat(G^T y~)
+struct FhatWork {
+    SyevWork ws;
+    double Mv[kMaxK * kMaxK];
+    double w[kMaxK + 1];
+};
+__device__ __forceinline__ void wg_fhat_prep(int k, const double *__restrict__ VCV, const double *__restrict__ Gy,
+                                             double *sc, FhatWork *f) {
+    const double r2 = 1.4142135623730951;
+    for (int e = threadIdx.x; e < k * k; e += kWG) {
+        const int i = e / k, j = e - i * k;
+        const int lo = i > j ? j : i, hi = i > j ? i : j;
+        const int p = lo * k - lo * (lo - 1) / 2 + (hi - lo);
+        f->Mv[e] = VCV[e] - ((i == j) ? Gy[p] : Gy[p] / r2);
+    }
+    __syncthreads();
+    wg_syev_load(k, f->Mv, k, nullptr, &f->ws);
+    wg_syev_top(k, 1, 0, &f->ws, f->w, nullptr, 0);
+    if (threadIdx.x == 0) sc[SC_LAMV] = f->w[0];
+}
+
+// model update (eqs. model_update_eigendecomposition, x_bar_def; App. C tracking):
+// alpha S = Q diag(lam) Q^T (descending), Q_p = first k_p columns, Q_c = rest,
+// Kc = Q_c Lam_c Q_c^T, tau <- g tau + tr Lam_c, cbar <- g cbar + <Kc, V^T C V>,
+// Hsk = Kc (V^T Psi) (k x r) for the sketch.
+struct ModelWork {
+    SyevWork ws;
+    double aS[kMaxK * kMaxK];
+    double lam[kMaxK + 1];
+    double Q[kMaxK * kMaxK];
+    double sK[kMaxK * kMaxK];
+};
+__device__ __forceinline__ void wg_model_update(int k, int kp, int r, const double *__restrict__ st,
+                                                const double *__restrict__ VCV, const double *__restrict__ VtPsi,
+                                                double *sc, double *__restrict__ Kc, double *__restrict__ Qp,
+                                                double *__restrict__ Hsk, ModelWork *w) {
+    const double alpha = sc[SC_ALPHA];
+    for (int e = threadIdx.x; e < k * k; e += kWG) w->aS[e] = alpha * st[e];
+    __syncthreads();
+    wg_syev_load(k, w->aS, k, nullptr, &w->ws);
+    wg_syev_top(k, k, k, &w->ws, w->lam, w->Q, k);
+    __syncthreads();
+    for (int e = threadIdx.x; e < k * k; e += kWG) {
+        const int i = e / k, j = e - i * k;
+        double v = 0.0;
+        for (int c = kp; c < k; ++c) v += w->Q[i * k + c] * w->lam[c] * w->Q[j * k + c];
+        w->sK[e] = v;
+        Kc[e] = v;
+    }
+    for (int e = threadIdx.x; e < k * kp; e += kWG) {
+        const int i = e / kp, c = e - i * kp;
+        Qp[e] = w->Q[i * k + c];
+    }
+    __syncthreads();
+    if (Hsk)
+        for (int e = threadIdx.x; e < k * r; e += kWG) {
+            const int i = e / r, c = e - i * r;
+            double v = 0.0;
+            for (int a = 0; a < k; ++a) v += w->sK[i * k + a] * VtPsi[a * r + c];
+            Hsk[e] = v;
+        }
+    if (threadIdx.x == 0) {
+        const double g = sc[SC_G];
+        double trc = 0.0, kv = 0.0;
+        for (int c = kp; c < k; ++c) trc += w->lam[c];
+        for (int e = 0; e < k * k; ++e) kv += w->sK[e] * VCV[e];
+        sc[SC_TAU] = g * sc[SC_TAU] + trc;
+        sc[SC_CBAR] = g * sc[SC_CBAR] + kv;
+    }
+}
+
+}  // namespace usbs

@@ -30,7 +30,7 @@ EXPORTS = [
     "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling", "usbs_profile",
     "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
     "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free", "usbs_round_maxcut",
-    "usbs_get_tuning",
+    "usbs_get_tuning", "usbs_solve_packed",
 ]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
 
@@ -75,7 +75,11 @@ class UsbsResult(ctypes.Structure):
 
 
 class UsbsServerConfig(ctypes.Structure):
-    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64), ("params", UsbsParams)]
+    _fields_ = [("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64), ("params", UsbsParams),
+                ("mode", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32)]
+
+
+SERVE = {"streams": 0, "packed": 1}
 
 
 class UsbsServedResult(ctypes.Structure):
@@ -137,6 +141,7 @@ def load_library(path: str | None = None):
         "usbs_server_free": (None, [vp]),
         "usbs_round_maxcut": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "usbs_get_tuning": (ctypes.c_int, [vp, vp]),
+        "usbs_solve_packed": (ctypes.c_int, [vp, i32, i32, vp, ctypes.POINTER(UsbsResult), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -361,6 +366,29 @@ class Solver:
             pass
 
 
+def solve_packed(solvers: list, iters_per_launch: int = 8, stream: int | None = None) -> list:
+    """Solve several instances together in packed launches (usbs_solve_packed): one
+    workgroup per instance, up to iters_per_launch iterations per launch.  Returns one
+    result dict per solver (as Solver.solve, with y in original units)."""
+    lib = load_library()
+    cnt = len(solvers)
+    hs = (ctypes.c_void_p * cnt)(*[s.h.value for s in solvers])
+    res = (UsbsResult * cnt)()
+    st = np.zeros(cnt, dtype=np.int32)
+    rc = lib.usbs_solve_packed(hs, cnt, int(iters_per_launch), stream, res, _ptr(st))
+    if rc < 0:
+        raise UsbsError(rc, lib.usbs_last_error(solvers[0].h).decode())
+    outs = []
+    for q, s in enumerate(solvers):
+        d = res[q].as_dict()
+        y = np.zeros(s.m)
+        s._check(lib.usbs_step_iterate(s.h, 0, _ptr(y), None, None, None, None))
+        sigma, _ = s.scaling()
+        d.update({"y": y * sigma, "converged": int(st[q]) == USBS_OK, "status_code": int(st[q])})
+        outs.append(d)
+    return outs
+
+
 def footprint_bytes(prob, params: Params | None = None, psi=None) -> int:
     """Device bytes usbs_create would allocate at most for this problem."""
     lib = load_library()
@@ -376,10 +404,12 @@ class Server:
     first solve's resident state); wait() returns the results and the request's times
     (seconds since the server started): submit, admit, base solve done, done."""
 
-    def __init__(self, slots: int = 4, params: Params | None = None, hbm_budget_bytes: int = 0):
+    def __init__(self, slots: int = 4, params: Params | None = None, hbm_budget_bytes: int = 0,
+                 mode: str = "streams", iters_per_launch: int = 8):
         self.lib = load_library()
         self.params = params or Params()
-        cfg = UsbsServerConfig(slots=slots, hbm_budget_bytes=hbm_budget_bytes, params=self.params.to_c(None))
+        cfg = UsbsServerConfig(slots=slots, hbm_budget_bytes=hbm_budget_bytes, params=self.params.to_c(None),
+                               mode=SERVE[mode], iters_per_launch=iters_per_launch)
         h = ctypes.c_void_p()
         rc = self.lib.usbs_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != 0:

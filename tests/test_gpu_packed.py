@@ -1,0 +1,223 @@
+"""GPU: packed solves (usbs_solve_packed), one workgroup per instance in one launch.
+
+The packed kernel runs the same steps as usbs_solve with every reduction done by one
+workgroup, so its trajectory differs from the per-instance path only by rounding.  Each
+packed result is certified by the FP64 oracle (f(y) from a Jacobi eigen-decomposition,
+relative gap and infeasibility re-evaluated), its objective is compared with the
+oracle's own solve and with the per-instance GPU solve, and an instance gives bitwise
+the same result alone and packed with others.
+"""
+import numpy as np
+import pytest
+
+import sdp_inputs as si
+from oracle import usbs_oracle as orc
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("primal_obj", "dual_bound", "rel_gap", "rel_infeas", "iters", "descents", "status",
+          "lanczos_matvecs", "ipm_iters")
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _certify(prob, out, tol=1e-3):
+    """FP64 re-evaluation of the packed result's certificate (scaled units)."""
+    sc = orc.scale_problem(prob)
+    y_s = out["y"] / sc.sigma
+    lam1 = orc.jacobi_eigh(sc.C - orc.A_adjoint(prob, orc.proj_Y(prob, y_s)))[0][0]
+    f_ref = 2.0 * max(lam1, 0.0) + float(sc.b @ orc.proj_Y(prob, y_s))
+    assert abs(f_ref - out["f_scaled"]) <= 1e-7 * (1 + abs(f_ref)), (f_ref, out["f_scaled"])
+    gap = abs(f_ref - out["primal_obj_scaled"]) / (1 + abs(out["primal_obj_scaled"]))
+    assert gap <= tol + 1e-9, gap
+    assert out["rel_infeas"] <= tol
+    return f_ref
+
+
+def _instances():
+    """(name, problem, params kwargs, psi): MaxCut with sketch and k_p = 1 (the paper's
+    MaxCut setting at rho = 0.1), a planted +-1 graph in FP32 and a graph with isolated
+    vertices."""
+    out = []
+    p = si.maxcut_er(120, 0.08, seed=7)
+    out.append(("er120", p, dict(rho=0.1, max_iters=600), si.test_matrix(p.n, 10, seed=7)))
+    p = si.maxcut_planted_pm1(203, 6.0, seed=2)
+    out.append(("planted203", p, dict(rho=0.1, max_iters=600, precision="f32"), si.test_matrix(p.n, 10, seed=2)))
+    p = si.maxcut_er(180, 0.025, seed=4)   # two isolated vertices
+    out.append(("iso180", p, dict(rho=0.1, max_iters=600), si.test_matrix(p.n, 10, seed=4)))
+    return out
+
+
+def _cc_planted():
+    """Correlation clustering with two planted clusters (positive weights inside, negative
+    across): X = blockdiag(J, J) is optimal, p* = 2 x the within-cluster weight."""
+    rng = np.random.default_rng(3)
+    n = 64
+    i, j = si.random_edges(n, 200, rng)
+    w = 0.5 + rng.random(i.size)
+    side = np.arange(n) < n // 2
+    w = np.where(side[i] == side[j], w, -w)
+    return si.cc_problem(n, i, j, w), 2 * w[side[i] == side[j]].sum()
+
+
+def _solvers(items):
+    from paper_2312_11801_amd import Params, Solver
+    return [Solver(p, Params(**kw), psi=psi) for _, p, kw, psi in items]
+
+
+def test_packed_certified_by_oracle(cuda):
+    from paper_2312_11801_amd import solve_packed
+    items = _instances()
+    assert orc.decoupled_rows(items[2][1]).any()
+    _say("packed solve of " + ", ".join(f"{nm} (n={p.n}, m={p.m})" for nm, p, _, _ in items))
+    ss = _solvers(items)
+    outs = solve_packed(ss, iters_per_launch=8)
+    for s in ss:
+        s.free()
+    for (nm, prob, kw, psi), out in zip(items, outs):
+        _say(f"{nm}: iters {out['iters']} primal {out['primal_obj']:.6f} dual {out['dual_bound']:.6f} "
+             f"gap {out['rel_gap']:.2e} inf {out['rel_infeas']:.2e}")
+        assert out["converged"], (nm, out)
+        _certify(prob, out)
+    # objective against the oracle's own solve of the first instance
+    nm, prob, kw, psi = items[0]
+    ref = orc.usbs_solve(prob, orc.Params(rho=0.1, max_iters=600), Psi=psi, keep_history=False)
+    assert ref.converged
+    assert abs(outs[0]["primal_obj_scaled"] - ref.primal_obj) / (1 + abs(ref.primal_obj)) <= 1e-3
+
+
+def test_packed_cc_planted_closed_form(cuda):
+    """Correlation clustering (inequality rows on off-diagonal pairs, refreshed operator
+    values, alternating maximisation) packed with a MaxCut instance: f(y) is certified by
+    the oracle's Jacobi eigenvalues, weak duality f(y) >= p* holds against the closed form,
+    the primal objective is within 1e-2 of p* after 600 iterations (the oracle reaches the
+    same distance on this instance) and y_I >= 0."""
+    from paper_2312_11801_amd import Params, Solver, solve_packed
+    prob, pstar = _cc_planted()
+    mc = _instances()[0]
+    _say(f"packed cc (n={prob.n}, m={prob.m}) with {mc[0]}")
+    ss = [Solver(prob, Params(rho=0.1, k_c=3, k_p=0, max_iters=600)), Solver(mc[1], Params(**mc[2]), psi=mc[3])]
+    outs = solve_packed(ss, iters_per_launch=10)
+    for x in ss:
+        x.free()
+    out = outs[0]
+    _say(f"cc: iters {out['iters']} primal {out['primal_obj']:.6f} dual {out['dual_bound']:.6f} p* {pstar:.6f} "
+         f"gap {out['rel_gap']:.2e} inf {out['rel_infeas']:.2e}")
+    assert out["status_code"] >= 0
+    sc = orc.scale_problem(prob)
+    y_s = out["y"] / sc.sigma
+    assert np.all(y_s[prob.is_ineq.astype(bool)] >= 0)
+    lam1 = orc.jacobi_eigh(sc.C - orc.A_adjoint(prob, y_s))[0][0]
+    f_ref = 2.0 * max(lam1, 0.0) + float(sc.b @ y_s)
+    assert abs(f_ref - out["f_scaled"]) <= 1e-7 * (1 + abs(f_ref))
+    assert orc.to_original(sc, f_ref) >= pstar - 1e-9 * pstar
+    assert abs(out["primal_obj"] - pstar) / pstar <= 1e-2
+    assert outs[1]["converged"]
+
+
+def test_packed_matches_per_instance_solve(cuda):
+    """Same instances through usbs_solve (many kernels per step) and usbs_solve_packed: both
+    converge, and the certified objectives agree to the 1e-3 relative criterion."""
+    from paper_2312_11801_amd import solve_packed
+    items = _instances()[:3]
+    _say("per-instance solves")
+    per = []
+    for s in _solvers(items):
+        per.append(s.solve(want_y=True, want_factors=False))
+        s.free()
+    _say("packed solve")
+    ss = _solvers(items)
+    outs = solve_packed(ss, iters_per_launch=16)
+    for s in ss:
+        s.free()
+    for (nm, prob, kw, psi), a, b in zip(items, per, outs):
+        assert a["converged"] and b["converged"], nm
+        ref = max(abs(a["primal_obj_scaled"]), abs(b["primal_obj_scaled"]))
+        assert abs(a["primal_obj_scaled"] - b["primal_obj_scaled"]) / (1 + ref) <= 1e-3, nm
+
+
+def test_packed_alone_equals_mix(cuda):
+    """An instance's packed result is bitwise the same alone and packed with others, and
+    does not depend on the number of iterations per launch."""
+    from paper_2312_11801_amd import solve_packed
+    items = _instances()
+    _say("alone")
+    s = _solvers(items[:1])
+    alone = solve_packed(s, iters_per_launch=8)[0]
+    s[0].free()
+    _say("mix")
+    from paper_2312_11801_amd import Params, Solver
+    cc, _ = _cc_planted()
+    ss = _solvers([items[1], items[0], items[2]]) + [Solver(cc, Params(rho=0.1, k_c=3, k_p=0, max_iters=200))]
+    mixed = solve_packed(ss, iters_per_launch=5)
+    for x in ss:
+        x.free()
+    assert tuple(alone[f] for f in FIELDS) == tuple(mixed[1][f] for f in FIELDS)
+    assert np.array_equal(alone["y"], mixed[1]["y"])
+
+
+def test_packed_rejects_bad_lists(cuda):
+    from paper_2312_11801_amd import UsbsError, solve_packed
+    items = _instances()[:1]
+    ss = _solvers(items)
+    with pytest.raises(UsbsError):
+        solve_packed([ss[0], ss[0]])
+    ss[0].free()
+
+
+def _served_requests(count, seed):
+    reqs = si.served_batch(count=count, n_lo=300, n_hi=700, avg_degree=8.0, seed=seed)
+    for q in reqs:
+        q["psi"] = si.test_matrix(q["problem"].n, 10, seed=q["id"])
+        q["psi_grown"] = si.test_matrix(q["grown"].n, 10, seed=q["id"])
+    return reqs
+
+
+def _rkey(res):
+    return tuple(res[f] for f in FIELDS)
+
+
+def test_packed_server_alone_equals_mix(cuda):
+    """Packed serving (cold start and warm restart inside the launches): every request's
+    results are bitwise the same served alone and in a mix with other requests and another
+    number of iterations per launch; the certified objectives agree with the streams server
+    (one usbs_solve per request) to the 1e-3 criterion where both converged."""
+    from paper_2312_11801_amd import Params, Server
+    reqs = _served_requests(3, seed=3)
+    fillers = _served_requests(3, seed=4)
+    prm = Params(precision="f32", max_iters=150, time_limit=0.0)
+    _say("packed server, alone")
+    alone = {}
+    sv = Server(slots=1, params=prm, mode="packed", iters_per_launch=8)
+    for q in reqs:
+        out = sv.wait(sv.submit(q["problem"], q["psi"], q["grown"], q["psi_grown"]))
+        alone[q["id"]] = out
+    sv.close()
+    _say("packed server, mix")
+    sv = Server(slots=8, params=prm, mode="packed", iters_per_launch=5)
+    ids = {}
+    for a, b in zip(reqs, fillers):
+        ids[a["id"]] = sv.submit(a["problem"], a["psi"], a["grown"], a["psi_grown"])
+        sv.submit(b["problem"], b["psi"], b["grown"], b["psi_grown"])
+    mixed = {k: sv.wait(v) for k, v in ids.items()}
+    st = sv.stats()
+    sv.close()
+    assert st["peak_running"] >= 2, st
+    for q in reqs:
+        a, m = alone[q["id"]], mixed[q["id"]]
+        assert a["status_base"] >= 0 and a["status_grown"] >= 0, a
+        assert _rkey(a["base"]) == _rkey(m["base"]) and _rkey(a["grown"]) == _rkey(m["grown"]), q["id"]
+        assert m["t_submit"] <= m["t_admit"] <= m["t_base_done"] <= m["t_done"]
+    _say("streams server")
+    sv = Server(slots=3, params=prm, mode="streams")
+    ref = {q["id"]: sv.wait(sv.submit(q["problem"], q["psi"], q["grown"], q["psi_grown"])) for q in reqs}
+    sv.close()
+    for q in reqs:
+        for part in ("base", "grown"):
+            a, b = alone[q["id"]][part], ref[q["id"]][part]
+            _say(f"{q['id']} {part}: packed {a['primal_obj']:.6f} ({a['iters']} it, status {a['status']}), "
+                 f"streams {b['primal_obj']:.6f} ({b['iters']} it, status {b['status']})")
+            if a["status"] == 0 and b["status"] == 0:
+                assert abs(a["primal_obj"] - b["primal_obj"]) / (1 + abs(b["primal_obj"])) <= 2e-3
