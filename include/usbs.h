@@ -172,6 +172,18 @@ const char *usbs_last_error(const usbs_handle *h);
 int usbs_solve_packed(usbs_handle *const *hs, int32_t count, int32_t iters_per_launch, void *stream,
                       usbs_result *res, int32_t *status);
 
+/* Device time of the handle's packed launches per phase, from the GPU's wall clock
+ * (milliseconds, accumulated since the handle was created or last reset; every
+ * instance of a launch counts its own time).  ms_out[USBS_PACK_PHASES] in this order:
+ * operator products; matrix-core reductions A^T B; matrix-core updates [A A2] H;
+ * Rayleigh-Ritz eigenproblems; master-QP interior point method; constraint side (QP
+ * Gram sums, A on low-rank factors, dot products); small dense steps (Gram-Schmidt
+ * Cholesky, restart block, model update, f^); operator shift and bound; the whole
+ * launch (the rest is copies, fills and scalar steps).  reset != 0 clears the counters
+ * after reading. */
+#define USBS_PACK_PHASES 9
+int usbs_packed_profile(usbs_handle *h, int32_t reset, double *ms_out);
+
 /* ---------------------------------------------------------------------
  * Step-level entry points: each runs one row of the hot path on device
  * arrays, for parity testing and for callers that drive the iteration.

@@ -58,6 +58,20 @@ enum PackDone {
     PACK_FAILED = -1,     // non-finite iterate or failed interior point solve
 };
 
+// phases of the packed kernel timed with the device wall clock (usbs_packed_profile)
+enum PackPhase {
+    PH_SPMM = 0,     // products with the shifted operator / with C
+    PH_TN,           // tall-skinny reductions A^T B on the matrix cores
+    PH_NN,           // tall-skinny updates C = [A A2] H on the matrix cores
+    PH_RITZ,         // projected (Rayleigh-Ritz) eigenproblems
+    PH_IPM,          // master-QP interior point method
+    PH_CONSTR,       // constraint side: QP Gram sums, A on low-rank factors, dot products, candidate
+    PH_SMALL,        // small dense steps: Gram-Schmidt Cholesky, restart block, model update, f^
+    PH_OTHER,        // operator shift and Gershgorin bound
+    PH_ALL,          // the whole launch (the rest: copies, fills, random directions, scalars)
+    kPackPhases
+};
+
 // counters carried across launches (host <-> device), one per instance
 struct PackState {
     int iters;            // iterations of Alg. 1 over the handle's life (seeds random directions)
@@ -71,6 +85,7 @@ struct PackState {
     int stop;             // host request: certify f at the centre and stop
     int pad;
     long long matvecs;    // columns multiplied by the shifted operator
+    unsigned long long ticks[kPackPhases];   // device wall-clock ticks spent per PackPhase
 };
 
 // Largest LDS footprint of the packed kernel (bytes), for the launch check.

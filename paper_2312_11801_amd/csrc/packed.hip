@@ -42,16 +42,30 @@ struct PackShared {
     double sK[16 * 16];    // K of the low-rank constraint map
 };
 
-// instance context: descriptor and counters in registers / LDS-free scalars
+// The workgroup's LDS workspace.  Named directly by every helper (never passed as a
+// pointer across a call), so that the compiler sees its address space and emits LDS
+// instructions for it even in functions it does not inline.
+__shared__ PackShared g_sh;
+
+// instance context: descriptor and counters
 struct Ctx {
     const PackDesc *D;
     PackState st;
-    PackShared *sh;
     double *V, *Vn;        // current bundle and its successor (exchanged every iteration)
     bool last_conv;
 };
 
 constexpr int kPackUnr = 8;   // row groups in flight per wavefront in the reductions
+
+// adds the device wall-clock time of its scope to one phase (every thread keeps the same
+// counters; thread 0 writes them back)
+struct Tick {
+    unsigned long long *acc;
+    unsigned long long t0;
+    __device__ Tick(unsigned long long *a) : acc(a), t0(wall_clock64()) {}
+    __device__ ~Tick() { *acc += wall_clock64() - t0; }
+};
+#define PK_TICK(c, ph) Tick tick_##ph(&(c).st.ticks[ph])
 
 __device__ __forceinline__ void sync() { __syncthreads(); }
 
@@ -112,7 +126,8 @@ __device__ double pk_row_abs(const PackDesc &D, const VT *val, int i) {
 // d = diag(C_s) - diag(A^* y), refreshed constrained off-diagonal values, and the
 // Gershgorin bound of C_s - A^* y into sc[SC_SCALE]
 __device__ void pk_shift_operator(Ctx &c, const double *y) {
-    const PackDesc &D = *c.D;
+    PK_TICK(c, PH_OTHER);
+    const PackDesc &D = *uni(c.D);
     for (int i = threadIdx.x; i < D.n; i += kWG) {
         double v = D.cdiag[i];
         for (int e = D.dptr[i]; e < D.dptr[i + 1]; ++e) v -= D.dv[e] * y[D.dk[e]];
@@ -132,7 +147,7 @@ __device__ void pk_shift_operator(Ctx &c, const double *y) {
         else s = pk_row_abs<uint16_t>(D, (const uint16_t *)D.val_cur, i);
         mx = fmax(mx, fabs(D.dshift[i]) + fabs(D.val_scale) * s);
     }
-    double *red = c.sh->u.red[0];
+    double *red = g_sh.u.red[0];
     red[threadIdx.x] = mx;
     sync();
     for (int st = kWG / 2; st > 0; st >>= 1) {
@@ -148,6 +163,8 @@ __device__ void pk_shift_operator(Ctx &c, const double *y) {
 template <typename VT, typename ACC>
 __device__ void pk_spmm_t(int n, const int *rowptr, const int *col, const VT *val, ACC scale, const double *diag,
                           const double *X, int ldx, double *Y, int ldy, int nb) {
+    n = uni(n), ldx = uni(ldx), ldy = uni(ldy), nb = uni(nb);
+    rowptr = uni(rowptr), col = uni(col), val = uni(val), diag = uni(diag), X = uni(X), Y = uni(Y);
     const int L = nb <= 8 ? 8 : 16;
     const int R = kWG / L;
     const int c = threadIdx.x % L, r0 = threadIdx.x / L;
@@ -176,12 +193,14 @@ __device__ void pk_spmm(const PackDesc &D, const void *val, const double *diag, 
 }
 // (C_s - A^* y) X with the current shift
 __device__ void pk_apply_op(Ctx &c, const double *X, int ldx, double *Y, int ldy, int nb) {
-    pk_spmm(*c.D, c.D->val_cur, c.D->dshift, X, ldx, Y, ldy, nb);
+    PK_TICK(c, PH_SPMM);
+    pk_spmm(*c.D, uni(c.D)->val_cur, uni(c.D)->dshift, X, ldx, Y, ldy, nb);
     c.st.matvecs += nb;
 }
 // C_s X
 __device__ void pk_apply_C(Ctx &c, const double *X, int ldx, double *Y, int ldy, int nb) {
-    pk_spmm(*c.D, c.D->val_c, c.D->cdiag, X, ldx, Y, ldy, nb);
+    PK_TICK(c, PH_SPMM);
+    pk_spmm(*c.D, uni(c.D)->val_c, uni(c.D)->cdiag, X, ldx, Y, ldy, nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,18 +210,21 @@ __device__ void pk_apply_C(Ctx &c, const double *X, int ldx, double *Y, int ldy,
 template <typename TB>
 __device__ void pk_tn(Ctx &c, const double *A, int lda, int ca, const TB *B, int ldb, int cb, double *H, int ldh,
                       double alpha, double beta) {
-    wg_tn_mfma<TB, kPackUnr, false>(c.D->n, A, lda, ca, B, ldb, cb, 0, 1, H, ldh, alpha, beta, &c.sh->u.tn);
+    PK_TICK(c, PH_TN);
+    wg_tn_mfma<TB, kPackUnr, false>(uni(c.D)->n, A, lda, ca, B, ldb, cb, 0, 1, H, ldh, alpha, beta, &g_sh.u.tn);
     sync();
 }
 // Hg ((ca + 8) x 8) = [A B]^T B for an 8-column B
 __device__ void pk_tn_gram(Ctx &c, const double *A, int lda, int ca, const double *B, int ldb, double *Hg) {
-    wg_tn_mfma<double, kPackUnr, true>(c.D->n, A, lda, ca, B, ldb, kBlk, 0, 1, Hg, kBlk, 1.0, 0.0, &c.sh->u.tn);
+    PK_TICK(c, PH_TN);
+    wg_tn_mfma<double, kPackUnr, true>(uni(c.D)->n, A, lda, ca, B, ldb, kBlk, 0, 1, Hg, kBlk, 1.0, 0.0, &g_sh.u.tn);
     sync();
 }
 // C = beta C + alpha [A A2] H
 __device__ void pk_nn2(Ctx &c, const double *A, int lda, int ca, const double *A2, int lda2, int ca2, const double *H,
                        int ldh, int cc, double *C, int ldc, double alpha, double beta) {
-    wg_nn_mfma(c.D->n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, 0, 1, &c.sh->u.nn);
+    PK_TICK(c, PH_NN);
+    wg_nn_mfma(uni(c.D)->n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, 0, 1, &g_sh.u.nn);
     sync();
 }
 __device__ void pk_nn(Ctx &c, const double *A, int lda, int ca, const double *H, int ldh, int cc, double *C, int ldc,
@@ -213,30 +235,34 @@ __device__ void pk_nn(Ctx &c, const double *A, int lda, int ca, const double *H,
 // Cholesky-QR factor of the n x nc block src: Rinv = R^{-1} of src^T src = R^T R with
 // deflation flags (floor 1e-10 * *floor_ref when given)
 __device__ void pk_cholqr_factor(Ctx &c, const double *src, int lds, int nc, int *flags, const double *floor_ref) {
-    pk_tn<double>(c, src, lds, nc, src, lds, nc, c.sh->G16, 17, 1.0, 0.0);
+    pk_tn<double>(c, src, lds, nc, src, lds, nc, g_sh.G16, 17, 1.0, 0.0);
+    PK_TICK(c, PH_SMALL);
     double f2 = 0.0;
     if (floor_ref) {
         const double rf = 1e-10 * (*floor_ref);
         f2 = rf * rf;
     }
-    if (threadIdx.x < 64) wave_cholqr(nc, c.sh->G16, 17, c.D->Rinv, nc, flags, f2);
+    if (threadIdx.x < 64) wave_cholqr(nc, g_sh.G16, 17, uni(c.D)->Rinv, nc, flags, f2);
     sync();
 }
 // Cholesky-QR twice of src (n x nc) into dst; deflated columns are zero and flagged
 __device__ void pk_cholqr2(Ctx &c, const double *src, int lds, int nc, double *tmp, int ldt, double *dst, int ldd,
                            int *flags) {
-    pk_cholqr_factor(c, src, lds, nc, flags, c.D->sc + SC_SCALE);
-    pk_nn(c, src, lds, nc, c.D->Rinv, nc, nc, tmp, ldt, 1.0, 0.0);
+    pk_cholqr_factor(c, src, lds, nc, flags, uni(c.D)->sc + SC_SCALE);
+    pk_nn(c, src, lds, nc, uni(c.D)->Rinv, nc, nc, tmp, ldt, 1.0, 0.0);
     pk_cholqr_factor(c, tmp, ldt, nc, flags, nullptr);
-    pk_nn(c, tmp, ldt, nc, c.D->Rinv, nc, nc, dst, ldd, 1.0, 0.0);
+    pk_nn(c, tmp, ldt, nc, uni(c.D)->Rinv, nc, nc, dst, ldd, 1.0, 0.0);
 }
 
 // top eigenpairs of the symmetric N x N matrix A (upper triangle read)
 __device__ void pk_small_eig(Ctx &c, int N, const double *A, int lda, double *w, double *Y, int ldy, int ny,
                              const int *dead) {
-    wg_syev_load(N, A, lda, dead, &c.sh->u.syev);
+    PK_TICK(c, PH_RITZ);
+    N = uni(N), lda = uni(lda), ldy = uni(ldy), ny = uni(ny);
+    A = uni(A), w = uni(w), Y = uni(Y), dead = uni(dead);
+    wg_syev_load(N, A, lda, dead, &g_sh.u.syev);
     const int nv = N < kSyevMaxV ? N : kSyevMaxV;
-    wg_syev_top(N, nv, ny < nv ? ny : nv, &c.sh->u.syev, w, Y, ldy);
+    wg_syev_top(N, nv, ny < nv ? ny : nv, &g_sh.u.syev, w, Y, ldy);
     sync();
 }
 
@@ -248,7 +274,7 @@ __device__ void pk_small_eig(Ctx &c, int N, const double *A, int lda, double *w,
 // Returns the number of restart cycles; c.last_conv tells whether the test passed.
 // ---------------------------------------------------------------------------
 __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start) {
-    const PackDesc &D = *c.D;
+    const PackDesc &D = *uni(c.D);
     const int n = D.n, ldb = D.ldb, steps = D.steps;
     if (start != D.Ubuf) pk_copy_cols(n, start, 16, 16, D.Ubuf, 16);
     if (D.n_iso > 0) {
@@ -257,7 +283,7 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
         sync();
         orth_start = true;
         if (D.n_iso == n) {   // a diagonal operator: every eigenpair is exact
-            wg_iso_merge(D.n_iso, D.iso_idx, D.dshift, 0, D.theta, D.res, D.plan, &c.sh->u.iso);
+            wg_iso_merge(D.n_iso, D.iso_idx, D.dshift, 0, D.theta, D.res, D.plan, &g_sh.u.iso);
             sync();
             for (long e = threadIdx.x; e < (long)n * kRitz; e += kWG) {
                 const int i = (int)(e / kRitz), q = (int)(e - (long)i * kRitz);
@@ -294,8 +320,11 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
         sync();
         pk_nn(c, D.Bm, ldb, 16, D.Hd, 16, 16, D.Ubuf, 16, 1.0, 1.0);
         pk_tn<double>(c, D.Ubuf, 16, 16, D.Ubuf, 16, 16, D.RtR, 16, 1.0, 0.0);
-        wg_restart_prep(D.RtR, D.theta, kc, tol, tol_rest, D.res, D.flag, D.Zc, D.sc + SC_SCALE, &c.sh->u.rp);
-        sync();
+        {
+            PK_TICK(c, PH_SMALL);
+            wg_restart_prep(D.RtR, D.theta, kc, tol, tol_rest, D.res, D.flag, D.Zc, D.sc + SC_SCALE, &g_sh.u.rp);
+            sync();
+        }
         const int conv = D.flag[0];
         sync();   // every thread has read the flag before it is reused
         c.last_conv = conv != 0;
@@ -320,9 +349,13 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
             for (int pass = 0; pass < 2; ++pass) {
                 const double *Win = pass == 0 ? D.W : D.Wt;
                 pk_tn_gram(c, D.Bm, ldb, cols, Win, 8, D.Hg);
-                wg_pip_chol(D.Hg, cols, pass, D.Rsv, D.Tm + c0, ldb, D.coef, (pass == 1 && !last) ? D.dead + cols : nullptr,
-                            pass == 0 ? D.sc + SC_SCALE : nullptr, &c.sh->u.pip);
-                sync();
+                {
+                    PK_TICK(c, PH_SMALL);
+                    wg_pip_chol(D.Hg, cols, pass, D.Rsv, D.Tm + c0, ldb, D.coef,
+                                (pass == 1 && !last) ? D.dead + cols : nullptr, pass == 0 ? D.sc + SC_SCALE : nullptr,
+                                &g_sh.u.pip);
+                    sync();
+                }
                 if (pass == 0) pk_nn2(c, D.Bm, ldb, cols, D.W, 8, 8, D.coef, 8, 8, D.Wt, 8, 1.0, 0.0);
                 else if (!last) pk_nn2(c, D.Bm, ldb, cols, D.Wt, 8, 8, D.coef, 8, 8, D.Bm + cols, ldb, 1.0, 0.0);
             }
@@ -332,7 +365,7 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
     }
     pk_copy_cols(n, D.Bm, ldb, 16, D.Ucpl, 16);
     if (D.n_iso > 0) {
-        wg_iso_merge(D.n_iso, D.iso_idx, D.dshift, 1, D.theta, D.res, D.plan, &c.sh->u.iso);
+        wg_iso_merge(D.n_iso, D.iso_idx, D.dshift, 1, D.theta, D.res, D.plan, &g_sh.u.iso);
         sync();
         for (long e = threadIdx.x; e < (long)n * kRitz; e += kWG) {
             const int i = (int)(e / kRitz), q = (int)(e - (long)i * kRitz);
@@ -353,11 +386,14 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
 // out[j] = sum_i a_j[i] b_j[i] (np <= 3), fixed-order workgroup reduction
 __device__ void pk_dots(Ctx &c, int m, const double *a0, const double *b0, const double *a1, const double *b1,
                         const double *a2, const double *b2, int np, double *out) {
+    PK_TICK(c, PH_CONSTR);
+    m = uni(m), np = uni(np);
+    a0 = uni(a0), b0 = uni(b0), a1 = uni(a1), b1 = uni(b1), a2 = uni(a2), b2 = uni(b2), out = uni(out);
     double acc[3] = {0.0, 0.0, 0.0};
     const double *as[3] = {a0, a1, a2}, *bs[3] = {b0, b1, b2};
     for (int i = threadIdx.x; i < m; i += kWG)
         for (int j = 0; j < np; ++j) acc[j] += as[j][i] * bs[j][i];
-    double(*red)[kWG] = c.sh->u.red;
+    double(*red)[kWG] = g_sh.u.red;
     for (int j = 0; j < np; ++j) red[j][threadIdx.x] = acc[j];
     sync();
     for (int st = kWG / 2; st > 0; st >>= 1) {
@@ -370,15 +406,17 @@ __device__ void pk_dots(Ctx &c, int m, const double *a0, const double *b0, const
 }
 __device__ void pk_qp_gram(Ctx &c, const double *V, const double *w0, const double *w1, const double *w2, int nw,
                            double *out, int do_q11) {
-    const PackDesc &D = *c.D;
-    wg_qp_gram(D.m, D.kptr, D.ti, D.tj, D.tv, V, 16, D.k, do_q11, w0, w1, w2, nullptr, nw, 0, 1, out, &c.sh->u.qg);
+    PK_TICK(c, PH_CONSTR);
+    const PackDesc &D = *uni(c.D);
+    wg_qp_gram(D.m, D.kptr, D.ti, D.tj, D.tv, V, 16, D.k, do_q11, w0, w1, w2, nullptr, nw, 0, 1, out, &g_sh.u.qg);
     sync();
 }
 // z = beta z + gamma zb + alpha A(V K V^T) (K k x k, gamma from the device scalar when given)
 __device__ void pk_lowrank_A(Ctx &c, const double *V, int kd, const double *K, double alpha, const double *zb,
                              const double *gamma_dev, double *z) {
-    const PackDesc &D = *c.D;
-    double *sK = c.sh->sK;
+    PK_TICK(c, PH_CONSTR);
+    const PackDesc &D = *uni(c.D);
+    double *sK = g_sh.sK;
     for (int e = threadIdx.x; e < 256; e += kWG) {
         const int a = e >> 4, b = e & 15;
         sK[e] = (a < kd && b < kd) ? K[a * kd + b] : 0.0;
@@ -398,7 +436,7 @@ __device__ void pk_lowrank_A(Ctx &c, const double *V, int kd, const double *K, d
 // f and the relative errors are recomputed from it (keep_max: the larger of the two
 // lower bounds of the same f(y_t))
 __device__ void pk_polish(Ctx &c, int keep_max) {
-    const PackDesc &D = *c.D;
+    const PackDesc &D = *uni(c.D);
     pk_shift_operator(c, D.y);
     pk_copy_cols(D.n, D.Ucpl, 16, 12, D.Ubuf, 16);
     pk_random_block(D.n, 4, D.seed + 1000003ull * (uint64_t)(c.st.iters + 1), D.W, 8);
@@ -411,7 +449,7 @@ __device__ void pk_polish(Ctx &c, int keep_max) {
 
 // cold start: y0 = 0, V0 = top-k eigenvectors of C_s (tight tolerance), f(y0)
 __device__ void pk_cold_start(Ctx &c) {
-    const PackDesc &D = *c.D;
+    const PackDesc &D = *uni(c.D);
     pk_fill(D.y, D.m, 0.0);
     pk_fill(D.zbar, D.m, 0.0);
     if (D.sketch) pk_fill(D.P, (long)D.n * D.r, 0.0);
@@ -426,7 +464,7 @@ __device__ void pk_cold_start(Ctx &c) {
 
 // f(y0) of a warm-started instance (its padded state is in place)
 __device__ void pk_warm_f(Ctx &c) {
-    const PackDesc &D = *c.D;
+    const PackDesc &D = *uni(c.D);
     pk_shift_operator(c, D.y);
     pk_lanczos(c, D.Uritz, D.k, D.tol_final, sqrt(D.tol_final), D.max_restarts > 30 ? D.max_restarts : 30, false);
     pk_dots(c, D.m, D.b, D.y, nullptr, nullptr, nullptr, nullptr, 1, D.sc + SC_BYT);
@@ -438,7 +476,7 @@ constexpr int kStallWindow = 25;   // consecutive null steps before f at the cen
 
 // one iteration of Alg. 1 (same steps as the per-instance driver)
 __device__ void pk_iterate(Ctx &c) {
-    const PackDesc &D = *c.D;
+    const PackDesc &D = *uni(c.D);
     const int n = D.n, m = D.m, k = D.k, kc = D.kc, kp = D.kp, r = D.r;
     const int d = k * (k + 1) / 2;
     double *sc = D.sc;
@@ -461,8 +499,11 @@ __device__ void pk_iterate(Ctx &c) {
         wg_qp_finalize(k, D.raw, D.VCV, sc, pass > 0, D.qp);
         sync();
         ia.warm = pass > 0;
-        wg_ipm(ia, D.qp, D.ipm, &c.sh->u.ipm);
-        sync();
+        {
+            PK_TICK(c, PH_IPM);
+            wg_ipm(ia, D.qp, D.ipm, &g_sh.u.ipm);
+            sync();
+        }
         if (threadIdx.x == 0) post_ipm_scalar(k, D.ipm, D.VCV, sc);
         sync();
         // A X_{t+1} = g zbar + alpha A(V S V^T)
@@ -480,8 +521,11 @@ __device__ void pk_iterate(Ctx &c) {
     sync();
     pk_dots(c, m, D.b, D.yc, D.yc, D.zbar, D.evec, D.evec, 3, sc + SC_BY);   // SC_BY, SC_YZ, SC_DIST2
     pk_qp_gram(c, c.V, D.yc, nullptr, nullptr, 1, D.Gy, 0);
-    wg_fhat_prep(k, D.VCV, D.Gy, sc, &c.sh->u.fh);
-    sync();
+    {
+        PK_TICK(c, PH_SMALL);
+        wg_fhat_prep(k, D.VCV, D.Gy, sc, &g_sh.u.fh);
+        sync();
+    }
     // eigen step at the candidate: the previous Ritz block with its last two columns
     // replaced by fresh random directions
     pk_shift_operator(c, D.yc);
@@ -497,8 +541,11 @@ __device__ void pk_iterate(Ctx &c) {
     sync();
     // model update
     if (D.sketch) pk_tn<float>(c, c.V, 16, k, D.psi, r, r, D.VtPsi, r, 1.0, 0.0);
-    wg_model_update(k, kp, r, D.ipm, D.VCV, D.VtPsi, sc, D.Kc, D.Qp, D.sketch ? D.Hsk : nullptr, &c.sh->u.mu);
-    sync();
+    {
+        PK_TICK(c, PH_SMALL);
+        wg_model_update(k, kp, r, D.ipm, D.VCV, D.VtPsi, sc, D.Kc, D.Qp, D.sketch ? D.Hsk : nullptr, &g_sh.u.mu);
+        sync();
+    }
     pk_lowrank_A(c, c.V, k, D.Kc, 1.0, D.zbar, sc + SC_G, D.zbar);
     if (D.sketch) {   // P <- g P + V (Kc V^T Psi)
         const double g = sc[SC_G];
@@ -540,16 +587,15 @@ __device__ void pk_iterate(Ctx &c) {
 }
 
 __global__ __launch_bounds__(kWG) void k_packed(const PackDesc *__restrict__ descs, PackState *states, int iters) {
-    __shared__ PackShared sh;
     const PackDesc *D = descs + blockIdx.x;
     Ctx c;
     c.D = D;
     c.st = states[blockIdx.x];
-    c.sh = &sh;
     c.V = D->V;
     c.Vn = D->Vn;
     c.last_conv = false;
     c.st.swapped = 0;
+    const unsigned long long t_start = wall_clock64();
     if (c.st.init == PACK_INIT_COLD) pk_cold_start(c);
     else if (c.st.init == PACK_INIT_WARM) pk_warm_f(c);
     c.st.init = PACK_INIT_NONE;
@@ -577,6 +623,7 @@ __global__ __launch_bounds__(kWG) void k_packed(const PackDesc *__restrict__ des
             if (gap2 <= D->eps_gap && inf2 <= D->eps_inf) c.st.done = PACK_CONVERGED;
         }
     }
+    c.st.ticks[PH_ALL] += wall_clock64() - t_start;
     if (threadIdx.x == 0) states[blockIdx.x] = c.st;
 }
 

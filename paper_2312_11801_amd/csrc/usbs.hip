@@ -116,6 +116,7 @@ struct usbs_handle {
     Tuning tune;   // launch shapes (autotuner)
 
     int64_t matvecs = 0;
+    uint64_t pack_ticks[kPackPhases] = {};   // device wall-clock ticks per phase of packed launches
     int iters = 0;
     int lz_unconverged = 0;   // in-iteration eigen-solves that hit the restart limit
     int null_run = 0;         // consecutive null steps
@@ -1845,6 +1846,8 @@ int launch(Runner &R, usbs_handle *const *hs, PackState *st, int count, int iter
             h->lz_unconverged = st[q].lz_unconverged;
             h->recoveries = st[q].recoveries;
             h->matvecs = st[q].matvecs;
+            for (int ph = 0; ph < kPackPhases; ++ph) h->pack_ticks[ph] += st[q].ticks[ph];
+            std::memset(st[q].ticks, 0, sizeof(st[q].ticks));
         }
         return USBS_OK;
     } catch (const DevError &e) {
@@ -1923,6 +1926,21 @@ int usbs_solve_packed(usbs_handle *const *hs, int32_t count, int32_t iters_per_l
         else if (s == USBS_NOT_CONVERGED && worst == USBS_OK) worst = s;
     }
     return worst;
+}
+
+int usbs_packed_profile(usbs_handle *h, int32_t reset, double *ms_out) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    try {
+        int khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->dev));
+        if (khz <= 0) throw DevError(USBS_E_DEVICE, "no device wall-clock rate");
+        if (ms_out)
+            for (int ph = 0; ph < kPackPhases; ++ph) ms_out[ph] = (double)h->pack_ticks[ph] / (double)khz;
+        if (reset) std::memset(h->pack_ticks, 0, sizeof(h->pack_ticks));
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
 }
 
 }  // extern "C"

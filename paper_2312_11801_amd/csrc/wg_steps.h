@@ -38,6 +38,22 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
     return (uint16_t)(u >> 16);
 }
 
+// Values that are the same on every lane, re-read from the first lane: inside a function
+// the compiler does not inline, its arguments arrive in vector registers; this moves
+// sizes and pointers back to scalar registers (uniform loop control, scalar address
+// arithmetic).  A no-op where the compiler already knows the value is uniform.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ long uni(long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (long)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double v) { return __longlong_as_double(uni((long)__double_as_longlong(v))); }
+template <typename T>
+__device__ __forceinline__ T *uni(T *p) {
+    return (T *)uni((long)(uintptr_t)p);
+}
+
 // splitmix64 finaliser; the start blocks of the eigen-solver are uniform in [-1, 1]
 // from the hash of (seed, element index)
 __device__ __forceinline__ uint64_t mix64(uint64_t x) {
@@ -100,6 +116,8 @@ template <typename TB, int UNR, bool GRAM>
 __device__ __forceinline__ void wg_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                            const TB *__restrict__ B, int ldb, int cb, int blk, int nblk,
                                            double *dst, int ldd, double alpha, double beta, TnWork *w) {
+    n = uni(n), lda = uni(lda), ca = uni(ca), ldb = uni(ldb), cb = uni(cb), blk = uni(blk), nblk = uni(nblk);
+    A = uni(A), B = uni(B), dst = uni(dst), ldd = uni(ldd), alpha = uni(alpha), beta = uni(beta);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int m = lane & 15, kk = lane >> 4;
     const int nch = (ca + 15) >> 4;
@@ -172,6 +190,9 @@ __device__ __forceinline__ void wg_nn_mfma(int n, const double *__restrict__ A, 
                                            const double *__restrict__ A2, int lda2, int ca2,
                                            const double *__restrict__ H, int ldh, int cc, double *__restrict__ C,
                                            int ldc, double alpha, double beta, int blk, int nblk, NnWork *w) {
+    n = uni(n), lda = uni(lda), ca = uni(ca), lda2 = uni(lda2), ca2 = uni(ca2), ldh = uni(ldh), cc = uni(cc);
+    ldc = uni(ldc), blk = uni(blk), nblk = uni(nblk), alpha = uni(alpha), beta = uni(beta);
+    A = uni(A), A2 = uni(A2), H = uni(H), C = uni(C);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int m = lane & 15, kk = lane >> 4, j = lane & 15;
     const int ct = ca + ca2;
@@ -278,6 +299,9 @@ __device__ __forceinline__ void wg_qp_gram(int m, const int *__restrict__ kptr, 
                                            const double *__restrict__ V, int ldv, int kd, int do_q11,
                                            const double *w0, const double *w1, const double *w2, const double *w3,
                                            int nw, int blk, int nblk, double *out, QpGramWork *w) {
+    m = uni(m), kd = uni(kd), do_q11 = uni(do_q11), nw = uni(nw), blk = uni(blk), nblk = uni(nblk), ldv = uni(ldv);
+    kptr = uni(kptr), ti = uni(ti), tj = uni(tj), tv = uni(tv), V = uni(V), out = uni(out);
+    w0 = uni(w0), w1 = uni(w1), w2 = uni(w2), w3 = uni(w3);
     const int tid = threadIdx.x;
     const int d = kd * (kd + 1) / 2;
     const int nupper = do_q11 ? d * (d + 1) / 2 : 0;

@@ -30,8 +30,9 @@ EXPORTS = [
     "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling", "usbs_profile",
     "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
     "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free", "usbs_round_maxcut",
-    "usbs_get_tuning", "usbs_solve_packed",
+    "usbs_get_tuning", "usbs_solve_packed", "usbs_packed_profile",
 ]
+PACK_PHASES = ["spmm", "tn", "nn", "ritz", "ipm", "constraints", "small", "shift", "all"]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
 
 
@@ -142,6 +143,7 @@ def load_library(path: str | None = None):
         "usbs_round_maxcut": (ctypes.c_int, [vp, vp, vp, vp, vp]),
         "usbs_get_tuning": (ctypes.c_int, [vp, vp]),
         "usbs_solve_packed": (ctypes.c_int, [vp, i32, i32, vp, ctypes.POINTER(UsbsResult), vp]),
+        "usbs_packed_profile": (ctypes.c_int, [vp, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -353,6 +355,12 @@ class Solver:
         cat = -1 if category is None else PROF[category]
         self._check(self.lib.usbs_profile(self.h, cat, int(reset), ctypes.byref(ms), ctypes.byref(cnt)))
         return ms.value, cnt.value
+
+    def packed_profile(self, reset: bool = False) -> dict:
+        """Device milliseconds of this handle's packed launches per phase."""
+        ms = np.zeros(len(PACK_PHASES))
+        self._check(self.lib.usbs_packed_profile(self.h, int(reset), _ptr(ms)))
+        return dict(zip(PACK_PHASES, ms.tolist()))
 
     def free(self) -> None:
         if self.h is not None:
