@@ -19,12 +19,20 @@ int create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **out, 
 int warm_prepare(usbs_handle *h, const usbs_problem *grown, bool eval_f);
 
 // descriptor and state tables of the launches on one stream (pinned host copies and
-// device copies, grown on demand and released by the destructor)
+// device copies, grown on demand and released by the destructor).  On a non-null stream a
+// launch is the replay of a captured graph (table uploads, packed kernel, state download),
+// captured again when the number of instances, the iterations per launch or the tables
+// change; on the null stream the steps are issued directly.
 struct Runner {
     hipStream_t stream = nullptr;
     usbs::PackDesc *desc_dev = nullptr, *desc_host = nullptr;
     usbs::PackState *state_dev = nullptr, *state_host = nullptr;
     int cap = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_count = 0, graph_iters = 0;
+    bool graph_failed = false;   // capture not available: issue the steps directly
+    int graph_replays = 0;
     explicit Runner(hipStream_t s) : stream(s) {}
     ~Runner();
     Runner(const Runner &) = delete;

@@ -1775,7 +1775,54 @@ void fill_desc(const usbs_handle *h, PackDesc &d) {
 
 namespace usbs_pack {
 
+namespace {
+void drop_graph(Runner &R) {
+    if (R.graph_exec) (void)hipGraphExecDestroy(R.graph_exec);
+    if (R.graph) (void)hipGraphDestroy(R.graph);
+    R.graph_exec = nullptr;
+    R.graph = nullptr;
+    R.graph_count = R.graph_iters = 0;
+}
+// the steps of one launch over the first na table entries
+void issue_launch(Runner &R, int na, int iters) {
+    HIPCHK(hipMemcpyAsync(R.desc_dev, R.desc_host, na * sizeof(PackDesc), hipMemcpyHostToDevice, R.stream));
+    HIPCHK(hipMemcpyAsync(R.state_dev, R.state_host, na * sizeof(PackState), hipMemcpyHostToDevice, R.stream));
+    packed_launch(R.stream, R.desc_dev, R.state_dev, na, iters);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(R.state_host, R.state_dev, na * sizeof(PackState), hipMemcpyDeviceToHost, R.stream));
+}
+// capture the launch steps as a graph (the host tables are read when the graph runs)
+bool capture_launch(Runner &R, int na, int iters) {
+    drop_graph(R);
+    if (hipStreamBeginCapture(R.stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    bool ok = true;
+    try {
+        issue_launch(R, na, iters);
+    } catch (const DevError &) {
+        ok = false;
+    }
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(R.stream, &g) != hipSuccess || !ok || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return false;
+    }
+    hipGraphExec_t ge = nullptr;
+    if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return false;
+    }
+    R.graph = g;
+    R.graph_exec = ge;
+    R.graph_count = na;
+    R.graph_iters = iters;
+    return true;
+}
+}  // namespace
+
 Runner::~Runner() {
+    drop_graph(*this);
     if (desc_dev) (void)hipFreeAsync(desc_dev, stream);
     if (state_dev) (void)hipFreeAsync(state_dev, stream);
     (void)hipStreamSynchronize(stream);
@@ -1804,6 +1851,7 @@ int launch(Runner &R, usbs_handle *const *hs, PackState *st, int count, int iter
         const int na = (int)act.size();
         if (na == 0) return USBS_OK;
         if (na > R.cap) {
+            drop_graph(R);   // the graph holds the old table addresses
             if (R.desc_dev) HIPCHK(hipFreeAsync(R.desc_dev, R.stream));
             if (R.state_dev) HIPCHK(hipFreeAsync(R.state_dev, R.stream));
             HIPCHK(hipStreamSynchronize(R.stream));
@@ -1829,11 +1877,17 @@ int launch(Runner &R, usbs_handle *const *hs, PackState *st, int count, int iter
             fill_desc(h, R.desc_host[a]);
             R.state_host[a] = st[q];
         }
-        HIPCHK(hipMemcpyAsync(R.desc_dev, R.desc_host, na * sizeof(PackDesc), hipMemcpyHostToDevice, R.stream));
-        HIPCHK(hipMemcpyAsync(R.state_dev, R.state_host, na * sizeof(PackState), hipMemcpyHostToDevice, R.stream));
-        packed_launch(R.stream, R.desc_dev, R.state_dev, na, iters);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(R.state_host, R.state_dev, na * sizeof(PackState), hipMemcpyDeviceToHost, R.stream));
+        bool replayed = false;
+        if (R.stream && !R.graph_failed) {
+            if (!(R.graph_exec && R.graph_count == na && R.graph_iters == iters) && !capture_launch(R, na, iters))
+                R.graph_failed = true;
+            if (R.graph_exec && R.graph_count == na && R.graph_iters == iters) {
+                HIPCHK(hipGraphLaunch(R.graph_exec, R.stream));
+                R.graph_replays++;
+                replayed = true;
+            }
+        }
+        if (!replayed) issue_launch(R, na, iters);
         HIPCHK(hipStreamSynchronize(R.stream));
         for (int a = 0; a < na; ++a) {
             const int q = act[a];

@@ -221,3 +221,66 @@ def test_packed_server_alone_equals_mix(cuda):
                  f"streams {b['primal_obj']:.6f} ({b['iters']} it, status {b['status']})")
             if a["status"] == 0 and b["status"] == 0:
                 assert abs(a["primal_obj"] - b["primal_obj"]) / (1 + abs(b["primal_obj"])) <= 2e-3
+
+
+def test_packed_graph_replay_equals_eager(cuda):
+    """On a non-null stream each packed launch is the replay of a captured graph (table
+    uploads, kernel, state download); the null stream issues the same steps directly.
+    Three instances, three iterations per launch: the graph is replayed many times and
+    re-captured whenever an instance finishes; every result equals the eager one bit for bit."""
+    import torch
+    from paper_2312_11801_amd import solve_packed
+    items = _instances()
+    _say("eager (null stream)")
+    ss = _solvers(items)
+    eager = solve_packed(ss, iters_per_launch=3)
+    for x in ss:
+        x.free()
+    _say("graph replays (torch stream)")
+    st = torch.cuda.Stream()
+    ss = _solvers(items)
+    graph = solve_packed(ss, iters_per_launch=3, stream=st.cuda_stream)
+    for x in ss:
+        x.free()
+    for a, b in zip(eager, graph):
+        assert _rkey(a) == _rkey(b)
+        assert np.array_equal(a["y"], b["y"])
+
+
+def test_packed_bf16_planted_closed_form(cuda):
+    """BF16 products (exact for +-1 weights with the common scale factor) in the packed
+    kernel: the planted +-1 graph reaches the criterion, f(y) is certified by the oracle and
+    weak duality holds against p* = #positive edges."""
+    from paper_2312_11801_amd import Params, Solver, solve_packed
+    prob = si.maxcut_planted_pm1(240, 6.0, seed=5)
+    psi = si.test_matrix(prob.n, 10, seed=5)
+    s = Solver(prob, Params(rho=0.1, max_iters=600, precision="bf16"), psi=psi)
+    out = solve_packed([s], iters_per_launch=8)[0]
+    s.free()
+    _say(f"bf16 planted: iters {out['iters']} primal {out['primal_obj']:.6f} dual {out['dual_bound']:.6f} "
+         f"p* {prob.meta['p_star']}")
+    assert out["converged"], out
+    _certify(prob, out)
+    assert out["dual_bound"] >= prob.meta["p_star"] * (1 - 1e-9)
+    assert abs(out["primal_obj"] - prob.meta["p_star"]) / prob.meta["p_star"] <= 2e-3
+
+
+def test_packed_server_admission_by_footprint(cuda):
+    """Packed serving with a budget that fits one request at a time: all complete, never
+    two at once; a request larger than the whole budget is refused."""
+    from paper_2312_11801_amd import Params, Server, UsbsError, footprint_bytes
+    reqs = _served_requests(3, seed=5)
+    prm = Params(precision="f32", max_iters=60, time_limit=0.0)
+    fps = [max(footprint_bytes(q["problem"], prm, q["psi"]), footprint_bytes(q["grown"], prm, q["psi_grown"]))
+           for q in reqs]
+    budget = int(max(fps) * 1.5)
+    sv = Server(slots=8, params=prm, hbm_budget_bytes=budget, mode="packed")
+    rids = [sv.submit(q["problem"], q["psi"], q["grown"], q["psi_grown"]) for q in reqs]
+    outs = [sv.wait(r) for r in rids]
+    st = sv.stats()
+    assert st["peak_used_bytes"] <= budget and st["peak_running"] == 1, st
+    big = si.maxcut_sparse_pm1(200000, 6.0, seed=1)
+    with pytest.raises(UsbsError):
+        sv.submit(big, si.test_matrix(big.n, 10, seed=0))
+    sv.close()
+    assert all(o["status_base"] >= 0 and o["status_grown"] >= 0 for o in outs)
