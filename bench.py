@@ -118,8 +118,10 @@ def run_served(args) -> dict:
         q["psi"] = si.test_matrix(q["problem"].n, 10, seed=q["id"])
         q["psi_g"] = si.test_matrix(q["grown"].n, 10, seed=q["id"])
 
+    maxr = args.lanczos_max_restarts if args.lanczos_max_restarts is not None else 3
+
     def serve(mode, slots, prec, gaps, count):
-        prm = Params(precision=prec, max_iters=args.served_max_iters, time_limit=0.0)
+        prm = Params(precision=prec, max_iters=args.served_max_iters, time_limit=0.0, lanczos_max_restarts=maxr)
         sv = Server(slots=slots, params=prm, mode=mode, iters_per_launch=args.iters_per_launch)
         t0 = _t.perf_counter()
         rids = []
@@ -191,6 +193,9 @@ def main() -> int:
                     help="served: requests of the plain FP64 one-slot form (0: skip)")
     ap.add_argument("--served-max-iters", type=int, default=500,
                     help="iteration cap of every served solve (both forms)")
+    ap.add_argument("--lanczos-max-restarts", type=int, default=None,
+                    help="restart cap of the in-iteration eigen-solve (default: 3 for the MaxCut workloads, "
+                         "10 = the paper's for c4)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration for HBM traffic)")
     args = ap.parse_args()
@@ -221,7 +226,9 @@ def main() -> int:
                           "higher_is_better": True, "dtype": args.precision, "data": "synthetic",
                           "config": {"workload": "served_batch n=U[500,5000] ER deg 8 unit weights +1% growth",
                                      "mode": res["capacity"]["mode"], "slots": res["capacity"]["slots"],
-                                     "iters_per_launch": args.iters_per_launch}, **res}))
+                                     "iters_per_launch": args.iters_per_launch,
+                                     "lanczos_max_restarts": args.lanczos_max_restarts
+                                     if args.lanczos_max_restarts is not None else 3}, **res}))
         return 0
     stream = torch.cuda.current_stream().cuda_stream
     if args.workload == "c2":
@@ -247,7 +254,8 @@ def main() -> int:
     psi = si.test_matrix(n, 10, seed=0)
     val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[args.precision]
     nnz_off = prob.nnz - n
-    prm = Params(precision=args.precision, rho=args.rho, max_iters=100000, k_c=kc, k_p=kp)
+    maxr = args.lanczos_max_restarts if args.lanczos_max_restarts is not None else (10 if args.workload == "c4" else 3)
+    prm = Params(precision=args.precision, rho=args.rho, max_iters=100000, k_c=kc, k_p=kp, lanczos_max_restarts=maxr)
 
     # ---- throughput: K timed iterations of Alg. 1 ----
     s = Solver(prob, prm, psi=psi, stream=stream)
@@ -278,7 +286,7 @@ def main() -> int:
     ttg = None
     if not args.no_ttg:
         s2 = Solver(prob, Params(precision=args.precision, rho=args.rho, max_iters=3000, time_limit=120.0,
-                                 k_c=kc, k_p=kp), psi=psi, stream=stream)
+                                 k_c=kc, k_p=kp, lanczos_max_restarts=maxr), psi=psi, stream=stream)
         out = s2.solve(want_y=False)
         s2.free()
         ttg = {"seconds": out["seconds"], "iters": out["iters"], "converged": out["converged"],

@@ -93,7 +93,8 @@ typedef struct usbs_params {
     double time_limit;          /* seconds, <= 0 for none                  */
     int32_t lanczos_steps;      /* block steps per restart cycle (block 8; default 4, i.e.
                                    32 new Krylov vectors per cycle)          */
-    int32_t lanczos_max_restarts;
+    int32_t lanczos_max_restarts; /* restart cycles of the in-iteration eigen-solve (default 10,
+                                     the paper's; the certifying solves use at least 30)     */
     double lanczos_tol;         /* residual / spectral-radius estimate inside the iteration */
     double lanczos_tol_final;   /* same, for f(y0) and the certified f(y_T) at convergence  */
     int32_t precision;          /* USBS_PREC_*                             */
@@ -107,6 +108,8 @@ typedef struct usbs_params {
                                    per lane, grid of the MFMA updates); 2 = also the
                                    partition of the matrix-core reductions (faster,
                                    but rounding then depends on the choice)          */
+    double lanczos_tol_rest;    /* residual tolerance of Ritz pairs 2..k_c inside the iteration
+                                   (pair 1 uses lanczos_tol); <= 0: sqrt(lanczos_tol)          */
 } usbs_params;
 
 typedef struct usbs_result {

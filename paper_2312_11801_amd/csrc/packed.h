@@ -17,7 +17,7 @@ struct PackDesc {
     int n, m, k, kc, kp, r, steps, ldb, prec;
     int n_iso, n_offt, has_ineq, sketch;
     int max_restarts, max_iters;
-    double val_scale, tol, tol_final, alpha, rho, eps_gap, eps_inf;
+    double val_scale, tol, tol_rest, tol_final, alpha, rho, eps_gap, eps_inf;
     uint64_t seed;
     // operator: off-diagonal CSR (values in the compute precision), diagonal apart
     const int *rowptr, *col;

@@ -532,7 +532,7 @@ __device__ void pk_iterate(Ctx &c) {
     pk_copy_cols(n, D.Ucpl, 16, 14, D.Ubuf, 16);
     pk_random_block(n, 2, D.seed + 7919ull * (uint64_t)(c.st.iters + 1), D.W, 8);
     pk_copy_cols(n, D.W, 8, 2, D.Ubuf + 14, 16);
-    const int cyc = pk_lanczos(c, D.Ubuf, kc, D.tol, sqrt(D.tol), D.max_restarts, true);
+    const int cyc = pk_lanczos(c, D.Ubuf, kc, D.tol, D.tol_rest, D.max_restarts, true);
     if (cyc >= D.max_restarts && !c.last_conv) c.st.lz_unconverged++;
     if (threadIdx.x == 0) decide_scalar(D.theta, sc);
     sync();

@@ -714,7 +714,8 @@ void iterate(usbs_handle *h) {
     copy_cols(s, n, h->Ucpl, 16, 14, h->Ubuf, 16);
     random_block(s, n, 2, prm.seed + 7919ull * (uint64_t)(h->iters + 1), h->W, 8);
     copy_cols(s, n, h->W, 8, 2, h->Ubuf + 14, 16);
-    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, std::sqrt(prm.lanczos_tol), prm.lanczos_max_restarts, true);
+    const double tol_rest = prm.lanczos_tol_rest > 0.0 ? prm.lanczos_tol_rest : std::sqrt(prm.lanczos_tol);
+    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, tol_rest, prm.lanczos_max_restarts, true);
     if (cyc >= prm.lanczos_max_restarts && !h->last_conv) h->lz_unconverged++;
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
@@ -1092,7 +1093,7 @@ int usbs_default_params(usbs_params *p) {
     p->max_iters = 1000;
     p->time_limit = 0.0;
     p->lanczos_steps = 4;   // 32 new Krylov vectors per restart cycle (block 8)
-    p->lanczos_max_restarts = 10;
+    p->lanczos_max_restarts = 10;   // the paper's restart limit
     p->lanczos_tol = 1e-4;
     p->lanczos_tol_final = 1e-9;
     p->precision = USBS_PREC_F64;
@@ -1100,6 +1101,7 @@ int usbs_default_params(usbs_params *p) {
     p->stream = nullptr;
     p->verbose = 0;
     p->autotune = 1;
+    p->lanczos_tol_rest = 0.0;
     return USBS_OK;
 }
 
@@ -1694,6 +1696,7 @@ void fill_desc(const usbs_handle *h, PackDesc &d) {
     d.max_iters = p.max_iters;
     d.val_scale = h->val_scale;
     d.tol = p.lanczos_tol;
+    d.tol_rest = p.lanczos_tol_rest > 0.0 ? p.lanczos_tol_rest : std::sqrt(p.lanczos_tol);
     d.tol_final = p.lanczos_tol_final;
     d.alpha = p.alpha;
     d.rho = p.rho;

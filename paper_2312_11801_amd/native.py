@@ -54,7 +54,7 @@ class UsbsParams(ctypes.Structure):
         ("lanczos_max_restarts", ctypes.c_int32), ("lanczos_tol", ctypes.c_double),
         ("lanczos_tol_final", ctypes.c_double),
         ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
-        ("verbose", ctypes.c_int32), ("autotune", ctypes.c_int32),
+        ("verbose", ctypes.c_int32), ("autotune", ctypes.c_int32), ("lanczos_tol_rest", ctypes.c_double),
     ]
 
 
@@ -188,13 +188,14 @@ class Params:
     seed: int = 0
     verbose: int = 0
     autotune: int = 1
+    lanczos_tol_rest: float = 0.0
 
     def to_c(self, stream: int | None) -> UsbsParams:
         p = UsbsParams()
         load_library().usbs_default_params(ctypes.byref(p))
         for f in ("alpha", "rho", "beta", "k_c", "k_p", "r", "eps_gap", "eps_infeas", "max_iters", "time_limit",
                   "lanczos_steps", "lanczos_max_restarts", "lanczos_tol", "lanczos_tol_final", "seed", "verbose",
-                  "autotune"):
+                  "autotune", "lanczos_tol_rest"):
             setattr(p, f, getattr(self, f))
         p.units = UNITS[self.units]
         p.precision = PREC[self.precision]
