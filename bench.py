@@ -41,22 +41,29 @@ def reorth_bytes(n: int, cols: int, nb: int) -> float:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tn_mfma_reorth_c2_traffic.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2312_11801_amd", "csrc", "kernels.hip")
+# the roofline kernel: its launcher (kernels.hip) and its body (wg_steps.h)
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2312_11801_amd", "csrc", f) for f in ("kernels.hip", "wg_steps.h")]
+
+
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic() -> float | None:
     """HBM bytes per launch of the roofline kernel from the committed counter summary
     (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy), or None when the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+    kernel source (launcher and body) has changed since the counters were taken."""
     try:
         kv = {}
         for line in open(TRAFFIC_FILE):
             if ":" in line and not line.startswith("#"):
                 key, val = line.split(":", 1)
                 kv[key.strip()] = val.strip()
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if kv.get("kernel_source_sha256") != sha:
+        if kv.get("kernel_source_sha256") != kernel_source_sha256():
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
