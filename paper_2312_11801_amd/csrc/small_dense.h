@@ -760,37 +760,65 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
             status = 2;
             break;
         }
-        // solves on wavefront 0
+        // solves L L^T x = rhs on wavefront 0: lane l keeps rows l and l + 64 of the right-hand
+        // side in registers; each solved component is broadcast from its lane (no LDS round
+        // trip or divide on the dependent chain: the pivots' reciprocals are formed first)
         if (wave == 0) {
-            for (int j = 0; j < D; ++j) {
-                if (lane == 0) sh->rhs[j] /= sh->M[j * ldm + j];
-                wave_sync();
-                const double xj = sh->rhs[j];
-                for (int i = j + 1 + lane; i < D; i += 64) sh->rhs[i] -= sh->M[i * ldm + j] * xj;
-                wave_sync();
+            const int i0 = lane, i1 = lane + 64;
+            double r0 = (i0 < D) ? sh->rhs[i0] : 0.0, r1 = (i1 < D) ? sh->rhs[i1] : 0.0;
+            const double v0 = (i0 < D) ? 1.0 / sh->M[i0 * ldm + i0] : 0.0;
+            const double v1 = (i1 < D) ? 1.0 / sh->M[i1 * ldm + i1] : 0.0;
+            for (int j = 0; j < D; ++j) {   // forward: L y = rhs
+                const double xj = (j < 64) ? lane_read(r0, j) * lane_read(v0, j) : lane_read(r1, j - 64) * lane_read(v1, j - 64);
+                const double m0 = (i0 > j && i0 < D) ? sh->M[i0 * ldm + j] : 0.0;
+                const double m1 = (i1 > j && i1 < D) ? sh->M[i1 * ldm + j] : 0.0;
+                if (i0 == j) r0 = xj;
+                if (i1 == j) r1 = xj;
+                r0 -= m0 * xj;
+                r1 -= m1 * xj;
             }
-            for (int j = D - 1; j >= 0; --j) {
-                if (lane == 0) sh->rhs[j] /= sh->M[j * ldm + j];
-                wave_sync();
-                const double xj = sh->rhs[j];
-                for (int i = lane; i < j; i += 64) sh->rhs[i] -= sh->M[j * ldm + i] * xj;
-                wave_sync();
+            for (int j = D - 1; j >= 0; --j) {   // backward: L^T x = y
+                const double xj = (j < 64) ? lane_read(r0, j) * lane_read(v0, j) : lane_read(r1, j - 64) * lane_read(v1, j - 64);
+                const double m0 = (i0 < j) ? sh->M[j * ldm + i0] : 0.0;
+                const double m1 = (i1 < j) ? sh->M[j * ldm + i1] : 0.0;
+                if (i0 == j) r0 = xj;
+                if (i1 == j) r1 = xj;
+                r0 -= m0 * xj;
+                r1 -= m1 * xj;
             }
+            if (i0 < D) sh->rhs[i0] = r0;
+            if (i1 < D) sh->rhs[i1] = r1;
         }
         __syncthreads();
-        // back substitution of the eliminated unknowns
-        for (int p = tid; p < d; p += kWG) {
-            const int i = sh->pi[p], j = sh->pj[p];
-            double v = 0.0;
-            for (int q = 0; q < d; ++q) v += skron_entry(i, j, sh->pi[q], sh->pj[q], sh->T, sh->Si, kMaxK) * sh->rhs[q];
-            sh->dt[p] = sh->mu * sh->svSi[p] - sh->t[p] - v;
-        }
+        // back substitution of the eliminated unknowns: dt = mu svec(S^{-1}) - t - (T (x)_s S^{-1}) ds,
+        // where (G (x)_s H) svec(X) = svec((H X G^T + G X H^T) / 2) for the symmetric Kronecker
+        // product: with W = S^{-1} dS T the product is svec((W + W^T) / 2), two k x k products
         for (int e = tid; e < k * k; e += kWG) {
             const int i = e / k, j = e - i * k;
             const int lo = i > j ? j : i, hi = i > j ? i : j;
             const int p = lo * k - lo * (lo - 1) / 2 + (hi - lo);
             const double f = (i == j) ? 1.0 : (1.0 / r2);
             sh->dS[i * kMaxK + j] = f * sh->rhs[p];
+        }
+        __syncthreads();
+        for (int e = tid; e < k * k; e += kWG) {   // Y0 = S^{-1} dS
+            const int i = e / k, j = e - i * k;
+            double v = 0.0;
+            for (int l = 0; l < k; ++l) v += sh->Si[i * kMaxK + l] * sh->dS[l * kMaxK + j];
+            sh->Y0[i * 16 + j] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < k * k; e += kWG) {   // X0 = S^{-1} dS T
+            const int i = e / k, j = e - i * k;
+            double v = 0.0;
+            for (int l = 0; l < k; ++l) v += sh->Y0[i * 16 + l] * sh->T[l * kMaxK + j];
+            sh->X0[i * 16 + j] = v;
+        }
+        __syncthreads();
+        for (int p = tid; p < d; p += kWG) {
+            const int i = sh->pi[p], j = sh->pj[p];
+            const double v = ((i == j) ? 1.0 : r2) * 0.5 * (sh->X0[i * 16 + j] + sh->X0[j * 16 + i]);
+            sh->dt[p] = sh->mu * sh->svSi[p] - sh->t[p] - v;
         }
         __syncthreads();
         for (int e = tid; e < k * k; e += kWG) {
