@@ -177,6 +177,30 @@ def run_served(args) -> dict:
     return out
 
 
+def run_sweep(args) -> dict:
+    """k_c / k_p sweep (the paper's experiment on the bundle size, on the c2 graph): for each
+    (k_c, k_p), a cold solve to the 1e-3 criterion; time, iterations, objective, dual bound and
+    both relative errors, so that objective and infeasibility can be read against time."""
+    import sdp_inputs as si
+    from paper_2312_11801_amd import Params, Solver
+    prob = si.maxcut_sparse_pm1(args.n, 6.0, seed=0)
+    psi = si.test_matrix(args.n, 10, seed=0)
+    rows = []
+    for kc, kp in [(2, 0), (5, 0), (10, 0), (2, 1), (5, 1), (10, 1), (5, 2), (8, 2)]:
+        prm = Params(precision=args.precision, rho=args.rho, max_iters=3000, time_limit=60.0, k_c=kc, k_p=kp,
+                     lanczos_max_restarts=args.lanczos_max_restarts if args.lanczos_max_restarts is not None else 3)
+        s = Solver(prob, prm, psi=psi)
+        out = s.solve(want_y=False, want_factors=False)
+        s.free()
+        rows.append({"k_c": kc, "k_p": kp, "seconds": out["seconds"], "iters": out["iters"],
+                     "converged": out["converged"], "primal_obj": out["primal_obj"], "dual_bound": out["dual_bound"],
+                     "rel_gap": out["rel_gap"], "rel_infeas": out["rel_infeas"],
+                     "iters_per_s": out["iters"] / max(out["seconds"], 1e-9)})
+        print(f"[sweep] k_c={kc} k_p={kp}: {out['seconds']:.2f} s, {out['iters']} iterations, "
+              f"converged={out['converged']}", file=sys.stderr, flush=True)
+    return {"rows": rows}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,7 +212,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solve")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "served"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "served", "sweep"],
                     help="c2: MaxCut n=20000 (default line); c4: correlation clustering n=10000; "
                          "c5: MaxCut on a random 4-regular graph, n=1e6, BF16 products; served: the request loop")
     ap.add_argument("--requests", type=int, default=256)
@@ -225,6 +249,13 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "sweep":
+        res = run_sweep(args)
+        print(json.dumps({"metric": "k_c / k_p sweep: time to the 1e-3 criterion (MaxCut SDP, c2 graph)",
+                          "unit": "s", "n_gpus": 1, "dtype": args.precision, "data": "synthetic",
+                          "config": {"workload": f"maxcut_sparse_pm1 n={args.n} avg_degree=6 weights=+-1",
+                                     "rho": args.rho}, **res}))
+        return 0
     if args.workload == "served":
         res = run_served(args)
         print(json.dumps({"metric": "served batch: requests/s and p50/p99 latency (MaxCut SDPs n in [500, 5000], "
