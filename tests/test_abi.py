@@ -70,3 +70,39 @@ def test_footprint_is_host_only_and_monotone():
     b = footprint_bytes(si.maxcut_er(2000, 0.005, seed=0), Params())
     assert 0 < a < b
     assert b > 2000 * 80 * 8
+
+
+def test_missing_library_raises(tmp_path):
+    """No CPU fallback: loading from a path without the built library raises."""
+    from paper_2312_11801_amd import native
+    saved = native._LIB
+    native._LIB = None
+    try:
+        with pytest.raises(FileNotFoundError):
+            native.load_library(str(tmp_path / "libusbs.so"))
+    finally:
+        native._LIB = saved
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and a message, touching no GPU."""
+    import json
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_packed_structs_fit_the_launch_tables():
+    """The packed kernel's per-instance state mirrors the header's phase count (usbs_packed_profile)."""
+    src = open(os.path.join(ROOT, "include", "usbs.h")).read()
+    ph = int(re.search(r"#define USBS_PACK_PHASES (\d+)", src).group(1))
+    hdr = open(os.path.join(ROOT, "paper_2312_11801_amd", "csrc", "packed.h")).read()
+    body = re.search(r"enum PackPhase \{(.*?)\};", hdr, re.S).group(1)
+    names = [x.split("=")[0].split("//")[0].strip() for x in body.split("\n")]
+    names = [x.rstrip(",") for x in names if x and not x.startswith("//")]
+    assert names[-1] == "kPackPhases" and len(names) - 1 == ph
+    from paper_2312_11801_amd.native import PACK_PHASES
+    assert len(PACK_PHASES) == ph

@@ -284,3 +284,19 @@ def test_packed_server_admission_by_footprint(cuda):
         sv.submit(big, si.test_matrix(big.n, 10, seed=0))
     sv.close()
     assert all(o["status_base"] >= 0 and o["status_grown"] >= 0 for o in outs)
+
+
+def test_packed_profile_phases(cuda):
+    """usbs_packed_profile: every phase's device time is non-negative, the whole launch
+    covers the sum of the timed phases, and reset clears the counters."""
+    from paper_2312_11801_amd import solve_packed
+    items = _instances()[:1]
+    ss = _solvers(items)
+    solve_packed(ss, iters_per_launch=8)
+    prof = ss[0].packed_profile(reset=True)
+    parts = sum(v for k, v in prof.items() if k != "all")
+    _say("phases (ms): " + " ".join(f"{k}={v:.2f}" for k, v in prof.items()))
+    assert all(v >= 0.0 for v in prof.values())
+    assert prof["all"] > 0.0 and parts <= prof["all"] * (1 + 1e-9)
+    assert all(v == 0.0 for v in ss[0].packed_profile().values())
+    ss[0].free()
