@@ -308,12 +308,19 @@ typedef struct usbs_server_config {
     usbs_params params;       /* parameters of every solve (the stream field is ignored) */
     int32_t mode;             /* USBS_SERVE_STREAMS or USBS_SERVE_PACKED              */
     int32_t iters_per_launch; /* packed mode: iterations per launch (<= 0: 8)         */
+    int64_t packed_max_n;     /* packed mode: requests whose larger instance has more
+                                 vertices go to per-instance workers (usbs_solve on
+                                 their own streams, the whole chip per launch) that run
+                                 beside the packed launches; <= 0: 20000            */
+    int32_t large_slots;      /* packed mode: number of those workers, 0..16 (< 0: 2) */
 } usbs_server_config;
 
 typedef struct usbs_served_result {
     usbs_result base;         /* the solve of the submitted instance                 */
     usbs_result grown;        /* the warm-started solve of the grown instance         */
-    int32_t status_base, status_grown, has_grown, slot;
+    int32_t status_base, status_grown, has_grown;
+    int32_t slot;             /* streams mode: the worker; packed mode: -1 inside the packed
+                                 launches, else the per-instance worker (>= 0)          */
     int64_t footprint_bytes;
     double t_submit, t_admit, t_base_done, t_done;
 } usbs_served_result;

@@ -86,6 +86,7 @@ struct Request {
     OwnedProblem base, grown;
     bool has_grown = false;
     int64_t footprint = 0;
+    int64_t nmax = 0;   // vertices of the larger of the two instances (packed-mode routing)
     double t_submit = 0.0, t_admit = 0.0, t_base_done = 0.0, t_done = 0.0;
     usbs_result res_base{}, res_grown{};
     int status_base = 0, status_grown = 0;
@@ -109,6 +110,8 @@ struct usbs_server {
     int running = 0, peak_running = 0;
     int64_t completed = 0;
     bool stop = false;
+    bool packed = false;      // packed mode: small requests go to the packed launches
+    int64_t packed_max_n = 0; // larger requests go to the per-instance workers
     std::vector<std::thread> workers;
     std::string err;
 
@@ -119,6 +122,18 @@ struct usbs_server {
 
 namespace {
 
+// which requests a consumer takes: the per-instance workers take all of them in streams mode
+// and the large ones in packed mode; the packed scheduler takes the rest
+bool eligible(const usbs_server *sv, const Request *rq, bool packed_consumer) {
+    if (!sv->packed) return !packed_consumer;
+    return packed_consumer == (rq->nmax <= sv->packed_max_n);
+}
+bool any_eligible(const usbs_server *sv, bool packed_consumer, bool must_fit) {
+    for (const Request *q : sv->queue)
+        if (eligible(sv, q, packed_consumer) && (!must_fit || sv->used + q->footprint <= sv->budget)) return true;
+    return false;
+}
+
 void worker(usbs_server *sv, int slot) {
     (void)hipSetDevice(sv->dev);
     hipStream_t stream = nullptr;
@@ -128,17 +143,16 @@ void worker(usbs_server *sv, int slot) {
         Request *rq = nullptr;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            // wake when a queued request fits, or to exit once stopping with nothing queued
+            // wake when a queued request of this worker fits, or to exit once stopping with
+            // none of its requests queued
             sv->cv_work.wait(lk, [&] {
-                if (sv->stop && sv->queue.empty()) return true;
-                for (Request *q : sv->queue)
-                    if (sv->used + q->footprint <= sv->budget) return true;
-                return false;
+                if (sv->stop && !any_eligible(sv, false, false)) return true;
+                return any_eligible(sv, false, true);
             });
-            if (sv->stop && sv->queue.empty()) break;
+            if (sv->stop && !any_eligible(sv, false, false)) break;
             // first fit in arrival order
             for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
-                if (sv->used + (*it)->footprint <= sv->budget) {
+                if (eligible(sv, *it, false) && sv->used + (*it)->footprint <= sv->budget) {
                     rq = *it;
                     sv->queue.erase(it);
                     break;
@@ -225,10 +239,10 @@ void packer(usbs_server *sv) {
             {
                 std::unique_lock<std::mutex> lk(sv->mu);
                 if (act.empty())
-                    sv->cv_work.wait(lk, [&] { return sv->stop || !sv->queue.empty(); });
-                if (act.empty() && sv->stop && sv->queue.empty()) break;
+                    sv->cv_work.wait(lk, [&] { return sv->stop || any_eligible(sv, true, true); });
+                if (act.empty() && sv->stop && !any_eligible(sv, true, false)) break;
                 for (auto it = sv->queue.begin(); it != sv->queue.end() && (int)(act.size() + admit.size()) < sv->cfg.slots;) {
-                    if (sv->used + (*it)->footprint <= sv->budget) {
+                    if (eligible(sv, *it, true) && sv->used + (*it)->footprint <= sv->budget) {
                         Request *rq = *it;
                         it = sv->queue.erase(it);
                         sv->used += rq->footprint;
@@ -251,7 +265,7 @@ void packer(usbs_server *sv) {
                 a.t_phase = sv->now();
                 usbs_problem pb = rq->base.view();
                 const int st = usbs_pack::create(&pb, &prm, &a.h, false);
-                rq->slot = (int)act.size();
+                rq->slot = -1;
                 if (st != USBS_OK) {
                     rq->status_base = st;
                     rq->t_base_done = sv->now();
@@ -326,6 +340,7 @@ int usbs_server_create(const usbs_server_config *cfg, usbs_server **out) {
     if (!out || !cfg) return USBS_E_INVALID;
     *out = nullptr;
     if (cfg->mode != USBS_SERVE_STREAMS && cfg->mode != USBS_SERVE_PACKED) return USBS_E_INVALID;
+    if (cfg->large_slots > 16) return USBS_E_INVALID;
     if (cfg->slots < 1 || cfg->slots > (cfg->mode == USBS_SERVE_PACKED ? 1024 : 64)) return USBS_E_INVALID;
     auto *sv = new usbs_server();
     sv->cfg = *cfg;
@@ -343,9 +358,15 @@ int usbs_server_create(const usbs_server_config *cfg, usbs_server **out) {
         }
         sv->budget = (int64_t)(0.9 * (double)fr);
     }
-    if (cfg->mode == USBS_SERVE_PACKED) sv->workers.emplace_back(packer, sv);
-    else
+    sv->packed = cfg->mode == USBS_SERVE_PACKED;
+    sv->packed_max_n = cfg->packed_max_n > 0 ? cfg->packed_max_n : 20000;
+    if (sv->packed) {
+        sv->workers.emplace_back(packer, sv);
+        const int large = cfg->large_slots < 0 ? 2 : cfg->large_slots;
+        for (int q = 0; q < large; ++q) sv->workers.emplace_back(worker, sv, q);
+    } else {
         for (int q = 0; q < cfg->slots; ++q) sv->workers.emplace_back(worker, sv, q);
+    }
     *out = sv;
     return USBS_OK;
 }
@@ -369,6 +390,11 @@ int usbs_server_submit(usbs_server *sv, const usbs_problem *prob, const usbs_pro
         return USBS_E_NOMEM;
     }
     rq->footprint = fp;
+    rq->nmax = grown ? std::max(prob->n, grown->n) : prob->n;
+    if (sv->packed && rq->nmax > sv->packed_max_n && sv->cfg.large_slots == 0) {
+        sv->err = "request above packed_max_n and no per-instance worker (large_slots = 0)";
+        return USBS_E_INVALID;
+    }
     rq->id = sv->next_id++;
     rq->t_submit = sv->now();
     *request_id = rq->id;

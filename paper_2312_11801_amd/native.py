@@ -77,7 +77,8 @@ class UsbsResult(ctypes.Structure):
 
 class UsbsServerConfig(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_int64), ("params", UsbsParams),
-                ("mode", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("iters_per_launch", ctypes.c_int32), ("packed_max_n", ctypes.c_int64),
+                ("large_slots", ctypes.c_int32)]
 
 
 SERVE = {"streams": 0, "packed": 1}
@@ -414,11 +415,12 @@ class Server:
     (seconds since the server started): submit, admit, base solve done, done."""
 
     def __init__(self, slots: int = 4, params: Params | None = None, hbm_budget_bytes: int = 0,
-                 mode: str = "streams", iters_per_launch: int = 8):
+                 mode: str = "streams", iters_per_launch: int = 8, packed_max_n: int = 0, large_slots: int = -1):
         self.lib = load_library()
         self.params = params or Params()
         cfg = UsbsServerConfig(slots=slots, hbm_budget_bytes=hbm_budget_bytes, params=self.params.to_c(None),
-                               mode=SERVE[mode], iters_per_launch=iters_per_launch)
+                               mode=SERVE[mode], iters_per_launch=iters_per_launch, packed_max_n=packed_max_n,
+                               large_slots=large_slots)
         h = ctypes.c_void_p()
         rc = self.lib.usbs_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc != 0:

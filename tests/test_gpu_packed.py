@@ -300,3 +300,29 @@ def test_packed_profile_phases(cuda):
     assert prof["all"] > 0.0 and parts <= prof["all"] * (1 + 1e-9)
     assert all(v == 0.0 for v in ss[0].packed_profile().values())
     ss[0].free()
+
+
+def test_packed_server_routes_large_requests(cuda):
+    """Packed serving with packed_max_n = 450 and one per-instance worker: requests whose larger
+    instance has more vertices run through usbs_solve on the worker (slot 0) beside the packed
+    launches (slot -1); each routed result equals the streams server's bit for bit."""
+    from paper_2312_11801_amd import Params, Server
+    reqs = _served_requests(4, seed=8)
+    prm = Params(precision="f32", max_iters=60, time_limit=0.0)
+    big = [q for q in reqs if max(q["problem"].n, q["grown"].n) > 450]
+    small = [q for q in reqs if max(q["problem"].n, q["grown"].n) <= 450]
+    _say(f"routing: {len(small)} packed, {len(big)} per-instance")
+    assert big and small
+    sv = Server(slots=8, params=prm, mode="packed", packed_max_n=450, large_slots=1)
+    ids = {q["id"]: sv.submit(q["problem"], q["psi"], q["grown"], q["psi_grown"]) for q in reqs}
+    outs = {k: sv.wait(v) for k, v in ids.items()}
+    sv.close()
+    for q in small:
+        assert outs[q["id"]]["slot"] == -1 and outs[q["id"]]["status_base"] >= 0
+    sv = Server(slots=1, params=prm, mode="streams")
+    for q in big:
+        o = outs[q["id"]]
+        assert o["slot"] == 0 and o["status_base"] >= 0 and o["status_grown"] >= 0
+        ref = sv.wait(sv.submit(q["problem"], q["psi"], q["grown"], q["psi_grown"]))
+        assert _rkey(o["base"]) == _rkey(ref["base"]) and _rkey(o["grown"]) == _rkey(ref["grown"])
+    sv.close()
