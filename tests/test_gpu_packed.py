@@ -326,3 +326,23 @@ def test_packed_server_routes_large_requests(cuda):
         ref = sv.wait(sv.submit(q["problem"], q["psi"], q["grown"], q["psi_grown"]))
         assert _rkey(o["base"]) == _rkey(ref["base"]) and _rkey(o["grown"]) == _rkey(ref["grown"])
     sv.close()
+
+
+def test_packed_time_limit_certifies_and_stops(cuda):
+    """A time limit checked between packed launches: the host sets the stop request, the next
+    launch certifies f at the centre with the tight eigen-solve and ends the solve; the status
+    is USBS_NOT_CONVERGED and the reported f(y) is the oracle's (a valid upper bound)."""
+    from paper_2312_11801_amd import Params, Solver, solve_packed
+    prob = si.maxcut_er(200, 0.05, seed=12)
+    psi = si.test_matrix(prob.n, 10, seed=12)
+    s = Solver(prob, Params(rho=0.1, max_iters=100000, time_limit=1e-3, eps_gap=1e-9, eps_infeas=1e-9), psi=psi)
+    out = solve_packed([s], iters_per_launch=1)[0]
+    s.free()
+    _say(f"time limit: iters {out['iters']} status {out['status_code']} f {out['f_scaled']:.6f}")
+    assert out["status_code"] == 1 and not out["converged"]
+    assert 1 <= out["iters"] <= 3
+    sc = orc.scale_problem(prob)
+    y_s = out["y"] / sc.sigma
+    lam1 = orc.jacobi_eigh(sc.C - orc.A_adjoint(prob, y_s))[0][0]
+    f_ref = 2.0 * max(lam1, 0.0) + float(sc.b @ y_s)
+    assert abs(f_ref - out["f_scaled"]) <= 1e-7 * (1 + abs(f_ref))
