@@ -102,6 +102,27 @@ def run_cpu_baseline(seconds: float = 20.0) -> dict:
                       f"(OMP_NUM_THREADS={threads} seen by numpy)"}
 
 
+def measured_copy_peak(stream) -> float:
+    """HBM bandwidth of a plain device-to-device copy (GB/s counting bytes read + written),
+    best of five 1 GiB copies timed with HIP events on the benchmark's stream."""
+    import torch
+    src = torch.ones(128 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = 0.0
+    with torch.cuda.stream(stream):
+        dst.copy_(src)
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            dst.copy_(src)
+            e1.record(stream)
+            e1.synchronize()
+            best = max(best, 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
 def percentile(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
@@ -268,6 +289,7 @@ def main() -> int:
                                      "lanczos_max_restarts": args.lanczos_max_restarts
                                      if args.lanczos_max_restarts is not None else 3}, **res}))
         return 0
+    copy_peak = measured_copy_peak(torch.cuda.current_stream())
     stream = torch.cuda.current_stream().cuda_stream
     if args.workload == "c2":
         n = args.n
@@ -371,6 +393,8 @@ def main() -> int:
             "traffic": measured_traffic() if (args.workload == "c2" and n == 20000 and args.precision == "f32") else None,
             "avg_launch_us": avg_reorth_s * 1e6, "launches": reorth_launches,
             "bytes_per_launch": bytes_per_reorth,
+            "measured_copy_GBs": copy_peak,
+            "frac_of_measured_copy": (achieved / copy_peak) if (achieved and copy_peak) else None,
         },
         "spmm": {"avg_launch_us": avg_spmm_s * 1e6, "achieved_GBs": spmm_gbs, "launches": spmm_launches,
                  "bytes_per_launch": spmm_bytes(n, nnz_off, 8, val_bytes)},
