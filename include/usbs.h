@@ -167,8 +167,10 @@ const char *usbs_last_error(const usbs_handle *h);
  *      handle's own stream is synchronised first; the launches run on 'stream'
  *      (hipStream_t, NULL = default stream).
  *   res[count] (may be NULL), status[count] (may be NULL): per-instance results and
- *      statuses as usbs_solve reports them (y, U and lam are read afterwards with
- *      usbs_solve-free calls such as usbs_step_iterate(h, 0, ...)).
+ *      statuses as usbs_solve reports them.  The final y of a handle is read afterwards
+ *      with usbs_step_iterate(h, 0, y, ...) (scaled units: multiply by sigma from
+ *      usbs_get_scaling for the original ones); the state stays in the handle, so a later
+ *      usbs_solve, usbs_warm_start or usbs_round_maxcut continues from it.
  * Returns USBS_OK when all converged, USBS_NOT_CONVERGED if any stopped at a limit,
  * else the first negative status.  Results do not depend on which other handles
  * share the launch (each workgroup reads only its own instance). */
