@@ -310,6 +310,8 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
                 for (int t = l; t < m; t += 16) s += ws->A[j + 1 + t][j] * x[j + 1 + t];
                 s = b * group16_sum(s);
                 for (int t = l; t < m; t += 16) x[j + 1 + t] -= s * ws->A[j + 1 + t][j];
+                // the next reflector reads entries of x written by other lanes of the group
+                wave_sync();
             }
         }
     }
