@@ -496,15 +496,40 @@ __device__ __forceinline__ double wave_min_eig(int k, double *X, int ldx, Jacobi
 // well gives the paper's eq. delta_S_linear_system2 -- the same direction.
 // ---------------------------------------------------------------------------
 constexpr int kMaxD = kMaxSvec + 1;
+// row stride of the Newton matrix: 7 padding columns take the overrun of the last
+// 8-entry chunk of a row in the Cholesky update
+constexpr int kIpmLd = kMaxD + 8;
+
+// row[l] -= m M_lj for l in [lb, le), with M_lj = col[l * ld] read by every lane of the
+// wavefront (one broadcast address).  Chunks of 8: all loads of a chunk are issued before
+// its stores.  le - lb is a multiple of 8 unless le = D; there the last chunk runs up to 7
+// entries into the row's padding and reads M_lj of row D - 1 for them.
+__device__ __forceinline__ void chol_chunk_update(double *row, double m, const double *col, int ld, int lb, int le,
+                                                  int D) {
+    for (int l = lb; l < le; l += 8) {
+        double x[8], c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int lc = (l + q < D) ? l + q : D - 1;
+            x[q] = row[l + q];
+            c[q] = col[lc * ld];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] -= m * c[q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) row[l + q] = x[q];
+    }
+}
+
 struct IpmShared {
-    double M[kMaxD * (kMaxD + 1)];
+    double M[(kMaxD + 1) * kIpmLd];   // row kMaxD: spare row of the wavefront Cholesky
     double Q11[kMaxSvec * kMaxSvec];   // staged once per solve
     double S[kMaxK * kMaxK], T[kMaxK * kMaxK], Si[kMaxK * kMaxK];
     double LS[kMaxK * kMaxK], LSi[kMaxK * kMaxK], LT[kMaxK * kMaxK], LTi[kMaxK * kMaxK];
     double dS[kMaxK * kMaxK], dT[kMaxK * kMaxK];
     double Y0[16 * 16], X0[16 * 16], Y1[16 * 16], X1[16 * 16];
     double s[kMaxSvec], t[kMaxSvec], F1[kMaxSvec], q12[kMaxSvec], h1[kMaxSvec], svSi[kMaxSvec];
-    double rhs[kMaxD], dt[kMaxSvec], pv[kMaxD];
+    double rhs[kMaxD], dt[kMaxSvec];
     int pi[kMaxSvec], pj[kMaxSvec];
     double red[kWG];
     JacobiWork<64, 16> js0, js1;
@@ -548,7 +573,7 @@ __device__ __forceinline__ double skron_entry(int i, int j, int k, int l, const 
 __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict__ qp, double *state, IpmShared *sh) {
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int k = a.k, d = k * (k + 1) / 2, D = d + 1, ldm = kMaxD + 1;
+    const int k = a.k, d = k * (k + 1) / 2, D = d + 1, ldm = kIpmLd;
     for (int e = tid; e < d * d; e += kWG) sh->Q11[e] = qp[e];
     const double *Q11 = sh->Q11;
     const double r2 = 1.4142135623730951;
@@ -730,13 +755,17 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
         __syncthreads();
         // Cholesky of M (lower, right-looking), one barrier per column: every thread reads
         // the pivot itself and updates with the unscaled column (M_il -= M_ij M_lj / piv);
-        // column j - 1, no longer read, is scaled during step j
+        // column j - 1, no longer read, is scaled during step j.  The trailing columns
+        // l = j+1 .. D-1 are split over the four wavefronts in ranges of a multiple of 8
+        // entries; lane r owns rows j+1+r and j+65+r and updates its row across its
+        // wavefront's range in chunks of 8.  Entries with l > i fall in the strict upper
+        // triangle or the padding, which nothing reads, and lanes past the last row work on
+        // the spare row kMaxD, so the loads and stores carry no predicate.
         {
-            const int tr = tid >> 4, tc = tid & 15;
+            double sp = 1.0;   // square root of the previous pivot
             for (int j = 0; j <= D; ++j) {
                 if (j > 0) {
                     const int jp = j - 1;
-                    const double sp = sqrt(sh->pv[jp]);
                     for (int i = jp + 1 + tid; i < D; i += kWG) sh->M[i * ldm + jp] /= sp;
                     if (tid == 0) sh->M[jp * ldm + jp] = sp;
                 }
@@ -747,11 +776,15 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
                     piv = 1.0;
                 }
                 const double ipiv = 1.0 / piv;
-                for (int i = j + 1 + tr; i < D; i += 16) {
-                    const double mij = sh->M[i * ldm + j] * ipiv;
-                    for (int l = j + 1 + tc; l <= i; l += 16) sh->M[i * ldm + l] -= mij * sh->M[l * ldm + j];
-                }
-                if (tid == 0) sh->pv[j] = piv;
+                const int span = ((D - j - 1 + 31) / 32) * 8;   // columns per wavefront
+                const int lb = j + 1 + wave * span, le = (lb + span < D) ? lb + span : D;
+                if (lb < le)
+                    for (int h = 0; h < 2 && j + 1 + 64 * h < D; ++h) {
+                        const int i = j + 1 + lane + 64 * h;
+                        const double m = (i < D) ? sh->M[i * ldm + j] * ipiv : 0.0;
+                        chol_chunk_update(&sh->M[(i < D ? i : kMaxD) * ldm], m, &sh->M[j], ldm, lb, le, D);
+                    }
+                sp = sqrt(piv);
                 __syncthreads();
             }
             __syncthreads();
