@@ -248,6 +248,9 @@ def main() -> int:
     ap.add_argument("--lanczos-max-restarts", type=int, default=None,
                     help="restart cap of the in-iteration eigen-solve (default: 3 for the MaxCut workloads, "
                          "10 = the paper's for c4)")
+    ap.add_argument("--autotune", type=int, default=1, choices=(0, 1, 2),
+                    help="launch-shape tuner: 0 off, 1 shapes with bitwise-identical results (default), "
+                         "2 also the partition of the matrix-core reductions (changes rounding)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration for HBM traffic)")
     args = ap.parse_args()
@@ -315,7 +318,8 @@ def main() -> int:
     val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[args.precision]
     nnz_off = prob.nnz - n
     maxr = args.lanczos_max_restarts if args.lanczos_max_restarts is not None else (10 if args.workload == "c4" else 3)
-    prm = Params(precision=args.precision, rho=args.rho, max_iters=100000, k_c=kc, k_p=kp, lanczos_max_restarts=maxr)
+    prm = Params(precision=args.precision, rho=args.rho, max_iters=100000, k_c=kc, k_p=kp, lanczos_max_restarts=maxr,
+                 autotune=args.autotune)
 
     # ---- throughput: K timed iterations of Alg. 1 ----
     s = Solver(prob, prm, psi=psi, stream=stream)
@@ -346,7 +350,8 @@ def main() -> int:
     ttg = None
     if not args.no_ttg:
         s2 = Solver(prob, Params(precision=args.precision, rho=args.rho, max_iters=3000, time_limit=120.0,
-                                 k_c=kc, k_p=kp, lanczos_max_restarts=maxr), psi=psi, stream=stream)
+                                 k_c=kc, k_p=kp, lanczos_max_restarts=maxr, autotune=args.autotune),
+                    psi=psi, stream=stream)
         out = s2.solve(want_y=False)
         s2.free()
         ttg = {"seconds": out["seconds"], "iters": out["iters"], "converged": out["converged"],
@@ -384,13 +389,15 @@ def main() -> int:
         "data": "synthetic (seeded random sparse graph standing in for DIMACS10)",
         "config": {"workload": workload,
                    "rho": args.rho, "k_c": kc, "k_p": kp, "lanczos_steps": prm.lanczos_steps,
-                   "lanczos_max_restarts": prm.lanczos_max_restarts, "precision": args.precision},
+                   "lanczos_max_restarts": prm.lanczos_max_restarts, "precision": args.precision,
+                   "autotune": args.autotune},
         "time_to_gap": ttg,
         "roofline": {
             "bound": "hbm", "kernel": "k_tn_mfma<1, UNR, true> (first stage of [Q W]^T W in the Krylov re-orthogonalisation, FP64 MFMA)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": measured_traffic() if (args.workload == "c2" and n == 20000 and args.precision == "f32") else None,
+            "traffic": measured_traffic() if (args.workload == "c2" and n == 20000 and args.precision == "f32"
+                                              and args.autotune != 2) else None,
             "avg_launch_us": avg_reorth_s * 1e6, "launches": reorth_launches,
             "bytes_per_launch": bytes_per_reorth,
             "measured_copy_GBs": copy_peak,
