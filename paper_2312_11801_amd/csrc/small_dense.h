@@ -522,7 +522,7 @@ __device__ __forceinline__ void chol_chunk_update(double *row, double m, const d
 }
 
 struct IpmShared {
-    double M[(kMaxD + 1) * kIpmLd];   // row kMaxD: spare row of the wavefront Cholesky
+    double M[(kMaxD + 1) * kIpmLd];   // row kMaxD: spare row for lanes past the last row in the Cholesky
     double Q11[kMaxSvec * kMaxSvec];   // staged once per solve
     double S[kMaxK * kMaxK], T[kMaxK * kMaxK], Si[kMaxK * kMaxK];
     double LS[kMaxK * kMaxK], LSi[kMaxK * kMaxK], LT[kMaxK * kMaxK], LTi[kMaxK * kMaxK];
