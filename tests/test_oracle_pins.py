@@ -165,6 +165,105 @@ def test_ipm_warm_start_same_solution():
     assert abs(orc.qp_objective(qp2, cold.S, cold.eta) - orc.qp_objective(qp2, warm.S, warm.eta)) < 20 * (k + 2) * 1e-7
 
 
+def _fhat_by_ipm(sc, y, V, Xbar, tau, alpha):
+    """Model value f^_t(y) (eq. model_def over eq. subspace_def) found by the interior point
+    method of App. B.1 instead of the extreme points: maximise <M, eta Xbar/tau + V S V^T>
+    over {eta >= 0, S PSD, eta + tr S <= 1}, i.e. minimise its negative."""
+    M = sc.C - orc.A_adjoint(sc.prob, y)
+    g1 = -orc.svec(V.T @ M @ V)
+    g2 = -float(np.sum(M * Xbar)) / tau if tau > 0 else 0.0
+    val, _, _ = orc.ipm_linear(g1, g2, V.shape[1], tol_mu=1e-12)
+    return alpha * (-val) + float(sc.b @ y)
+
+
+def test_fhat_closed_form_equals_ipm_along_a_run():
+    """At every iteration of a planted run the closed form of f^_t(y~) equals the App. B.1 IPM
+    on the same (V, Xbar, tau, y~).  Early iterations have lambda_max(V^T M V) far below
+    lambda_max(M), so using the latter in the closed form fails here."""
+    prob = si.maxcut_planted_pm1(40, 5.0, seed=1)
+    prm = orc.Params(rho=0.1)
+    sc = orc.scale_problem(prob)
+    Psi = si.test_matrix(prob.n, 10, seed=0).astype(float)
+    st = orc.cold_start(sc, prm, Psi)
+    separated = 0
+    for _ in range(25):
+        V, Xbar, tau = st.V.copy(), st.Xbar.copy(), st.tau
+        rec = orc.usbs_step(sc, prm, st, Psi)
+        y = rec["y_cand"]
+        ref = _fhat_by_ipm(sc, y, V, Xbar, tau, prm.alpha)
+        assert abs(rec["fhat"] - ref) <= 1e-8, (rec["fhat"], ref)
+        M = sc.C - orc.A_adjoint(prob, y)
+        separated += orc.jacobi_eigh(M)[0][0] - orc.jacobi_eigh(V.T @ M @ V)[0][0] > 1e-3
+    assert separated >= 2
+
+
+@pytest.mark.parametrize("case", ["xbar_on_top", "v_misses_top"])
+def test_fhat_closed_form_extreme_cases(case):
+    """Constructed models where each term of the closed form decides the value alone.
+    xbar_on_top: Xbar is a multiple of the top eigenvector's projector and V is orthogonal
+    to it, so <M, Xbar>/tau > lambda_max(V^T M V) (dropping the Xbar term fails).
+    v_misses_top: Xbar = 0 and V misses the top eigenvector, so lambda_max(V^T M V) <
+    lambda_max(M) (using the full spectrum fails)."""
+    prob = si.maxcut_er(30, 0.3, seed=5)
+    sc = orc.scale_problem(prob)
+    rng = np.random.default_rng(9)
+    y = 0.02 * rng.standard_normal(prob.m)
+    M = sc.C - orc.A_adjoint(prob, y)
+    w, Q = orc.jacobi_eigh(M)
+    k = 4
+    V = Q[:, 3:3 + k] if case == "v_misses_top" else Q[:, 5:5 + k]
+    if case == "xbar_on_top":
+        tau = 2.7
+        Xbar = tau * np.outer(Q[:, 0], Q[:, 0])
+        assert float(np.sum(M * Xbar)) / tau > orc.jacobi_eigh(V.T @ M @ V)[0][0] + 1e-3
+    else:
+        tau, Xbar = 0.0, np.zeros_like(M)
+        assert w[0] > orc.jacobi_eigh(V.T @ M @ V)[0][0] + 1e-3
+    cf = orc.fhat_closed_form(sc, y, V, Xbar, tau, 2.0)
+    assert abs(cf - _fhat_by_ipm(sc, y, V, Xbar, tau, 2.0)) <= 1e-8
+
+
+def _psi_t(sc, X, y, w, rho):
+    """psi_t(X, nu) of Sec. 3.2 with w = b - nu, from its definition on a formed X."""
+    AX = orc.A_apply(sc.prob, X)
+    r = w - AX
+    return float(np.sum(sc.C * X)) + float(r @ y) - float(r @ r) / (2.0 * rho)
+
+
+@pytest.mark.parametrize("kind", ["maxcut", "cc"])
+def test_qp_data_is_negated_psi_t(kind):
+    """App. B.2: the master QP is the maximisation of psi_t over the model's set, written in
+    (eta, S) with X = alpha((eta/tau) Xbar + V S V^T).  So the QP objective plus psi_t of that X
+    is the same constant for every (eta, S); with tau != 1 a wrong power of tau in q12, q22 or
+    h2, a dropped term or a wrong sign changes it from one (eta, S) to the next."""
+    prob = si.maxcut_er(24, 0.3, seed=4) if kind == "maxcut" else si.cc_signed(24, avg_degree=4, seed=2)
+    sc = orc.scale_problem(prob)
+    rng = np.random.default_rng(13)
+    n, k, alpha, rho = prob.n, 3, 2.0, 0.05
+    V = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    F = rng.standard_normal((n, 5))
+    Xbar = F @ F.T
+    Xbar *= 3.7 / np.trace(Xbar)
+    tau = float(np.trace(Xbar))
+    y = rng.standard_normal(prob.m)
+    nu = np.where(prob.is_ineq.astype(bool), np.abs(rng.standard_normal(prob.m)), 0.0)
+    w = sc.b - nu
+    qp = orc.qp_data(sc, V, orc.constraint_blocks(prob, V), V.T @ sc.C @ V, y, w,
+                     orc.A_apply(prob, Xbar), float(np.sum(sc.C * Xbar)), tau, alpha, rho)
+    consts = []
+    for _ in range(4):
+        G = rng.standard_normal((k, k))
+        S = G @ G.T
+        s_tr, eta = rng.uniform(0.1, 0.6), rng.uniform(0.05, 0.35)
+        S *= s_tr / np.trace(S)
+        X = alpha * ((eta / tau) * Xbar + V @ S @ V.T)
+        consts.append(orc.qp_objective(qp, S, eta) + _psi_t(sc, X, y, w, rho))
+    scale = max(1.0, max(abs(c) for c in consts))
+    assert max(consts) - min(consts) <= 1e-10 * scale, consts
+    # the constant itself: psi_t at X = 0 is <w, y> - ||w||^2 / (2 rho), the QP objective 0
+    assert abs(consts[0] - (float(w @ y) - float(w @ w) / (2 * rho))) <= 1e-10 * scale
+
+
 # ---------------------------------------------------------------------------
 # Nystrom sketch (Sec. 4, App. C.1)
 # ---------------------------------------------------------------------------
@@ -204,20 +303,22 @@ def test_nystrom_error_bound_fact_c1():
 @pytest.mark.parametrize("kind", ["cc", "overlap"])
 def test_adjoint_identity_and_lowrank(kind):
     """<A X, y> = <X, A^* y>, and A on low-rank factors equals A on the formed matrix; the
-    overlap case has off-diagonal pairs shared by up to eight rows."""
+    overlap case has off-diagonal pairs shared by up to eight rows.  The bounds are absolute:
+    at these sizes (|X_ij| <= 7, |<A X, y>| <= 15) both identities hold to about 1e-15, so
+    nothing is gained by a bound relative to the magnitude."""
     prob = si.cc_signed(30, avg_degree=4, seed=1) if kind == "cc" else si.general_overlap(60, seed=2)
     rng = np.random.default_rng(5)
     F = rng.standard_normal((prob.n, 3))
     lam = rng.random(3)
     X = (F * lam) @ F.T
     y = rng.standard_normal(prob.m)
-    assert abs(orc.A_apply(prob, X) @ y - np.sum(X * orc.A_adjoint(prob, y))) < 1e-10 * (1 + abs(orc.A_apply(prob, X) @ y))
-    assert np.abs(orc.A_lowrank(prob, F, lam) - orc.A_apply(prob, X)).max() < 1e-12 * (1 + np.abs(X).max())
+    assert abs(orc.A_apply(prob, X) @ y - np.sum(X * orc.A_adjoint(prob, y))) < 1e-10
+    assert np.abs(orc.A_lowrank(prob, F, lam) - orc.A_apply(prob, X)).max() < 1e-12
     # a row's value is the sum of its triplets written out entry by entry
     k = prob.n + 3 if kind == "overlap" else prob.n
     sel = prob.a_row == k
     direct = sum(v * X[i, j] for i, j, v in zip(prob.a_i[sel], prob.a_j[sel], prob.a_v[sel]))
-    assert abs(orc.A_apply(prob, X)[k] - direct) < 1e-12 * (1 + abs(direct))
+    assert abs(orc.A_apply(prob, X)[k] - direct) < 1e-12
 
 
 def test_scaling_units():
