@@ -168,8 +168,8 @@ const char *usbs_last_error(const usbs_handle *h);
  *      (hipStream_t, NULL = default stream).
  *   res[count] (may be NULL), status[count] (may be NULL): per-instance results and
  *      statuses as usbs_solve reports them.  The final y of a handle is read afterwards
- *      with usbs_step_iterate(h, 0, y, ...) (scaled units: multiply by sigma from
- *      usbs_get_scaling for the original ones); the state stays in the handle, so a later
+ *      with usbs_get_dual (original units) and X_{t+1} with usbs_get_primal; the state
+ *      stays in the handle, so a later
  *      usbs_solve, usbs_warm_start or usbs_round_maxcut continues from it.
  * Returns USBS_OK when all converged, USBS_NOT_CONVERGED if any stopped at a limit,
  * else the first negative status.  Results do not depend on which other handles
@@ -241,6 +241,29 @@ int usbs_op_nystrom(usbs_handle *h, const double *P_dev, double *U_dev, double *
  * Any output may be NULL. */
 int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *zbar,
                       double *Pbar, double *scal);
+
+/* The current centre y_t of Alg. 1 in original units (y = ||C||_F y_s, App. E):
+ * y_out[m] (host).  Reads the state a usbs_solve_packed run leaves in the handle. */
+int usbs_get_dual(usbs_handle *h, double *y_out);
+
+/* The primal iterate of the last iteration of Alg. 1 (the one the stopping test of
+ * Sec. 5, eq. relative_error_tol, judged), so that another program can re-evaluate
+ * the certificate.  In scaled units (App. E):
+ *     X_{t+1} = alpha ((eta / tau_t) Xbar_t + V_t S V_t^T)        (App. B.2 variables)
+ *   ax_out[m]     A X_{t+1}, the constraint values whose distance to K is the
+ *                 infeasibility;
+ *   cx_out        <C_s, X_{t+1}>, the primal objective of the relative gap;
+ *   V_out[n*k]    the bundle V_t the QP solution refers to (row-major, k = k_c + k_p);
+ *   S_out[k*k]    the master-QP solution S (row-major, symmetric PSD);
+ *   eta_out       its eta;  g_out = alpha eta / tau_t (0 while tau_t = 0).
+ * With zbar (A Xbar_{t+1}), tau and cbar from usbs_step_iterate(h, 0, ...), the model
+ * update of Sec. 3.1 gives A X_{t+1} = zbar + A(V_t (alpha S - K_c) V_t^T), where
+ * K_c = Q_c Lam_c Q_c^T keeps all but the top k_p eigenpairs of alpha S.
+ * Valid after usbs_solve, usbs_step_iterate with t >= 1 or usbs_solve_packed, until the
+ * next usbs_warm_start; before any iteration of the current problem: USBS_E_STATE.
+ * Any output may be NULL. */
+int usbs_get_primal(usbs_handle *h, double *ax_out, double *cx_out, double *V_out, double *S_out,
+                    double *eta_out, double *g_out);
 
 /* Live kernel timing (HIP events on the handle's stream) for one category at a time:
  * flushes the pending events, returns the accumulated milliseconds and launch count of

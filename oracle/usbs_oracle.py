@@ -737,6 +737,50 @@ def certificate(prob, y_scaled: np.ndarray, z_scaled: np.ndarray, cX_scaled: flo
     return {"f": f, "lambda_max": lam_max, "rel_gap": gap, "rel_infeas": inf}
 
 
+def C_quadratic_forms(prob, W: np.ndarray) -> np.ndarray:
+    """diag(W^T C_s W) for an n x q block W (C_s = C / ||C||_F, App. E), with C applied
+    in its sparse form so that it serves at any n."""
+    import scipy.sparse as sp
+    n = prob.n
+    sigma = float(np.linalg.norm(prob.val)) or 1.0
+    rows = np.repeat(np.arange(n), np.diff(prob.rowptr))
+    C = sp.csr_matrix((prob.val / sigma, (rows, prob.col.astype(np.int64))), shape=(n, n))
+    W = np.asarray(W, dtype=np.float64).reshape(n, -1)
+    return np.einsum("iq,iq->q", W, C @ W)
+
+
+def primal_from_model_update(prob, zbar_next: np.ndarray, cbar_next: float, V: np.ndarray, S: np.ndarray,
+                             alpha: float, k_p: int):
+    """A X_{t+1} and <C_s, X_{t+1}> of X_{t+1} = alpha((eta/tau) Xbar_t + V S V^T) from the
+    tracked quantities after the model update (Sec. 3.1, eqs. model_update_eigendecomposition
+    and x_bar_def; App. C tracking).  With alpha S = Q_p Lam_p Q_p^T + Q_c Lam_c Q_c^T (top
+    k_p eigenpairs first) the update sets Xbar_{t+1} = (alpha eta/tau) Xbar_t + (V Q_c) Lam_c
+    (V Q_c)^T, so X_{t+1} = Xbar_{t+1} + (V Q_p) Lam_p (V Q_p)^T."""
+    lam, Q = jacobi_eigh(alpha * np.asarray(S, dtype=np.float64))
+    Wp = np.asarray(V, dtype=np.float64) @ Q[:, :k_p]
+    lp = lam[:k_p]
+    AX = np.asarray(zbar_next, dtype=np.float64) + A_lowrank(prob, Wp, lp)
+    cX = float(cbar_next) + float(np.sum(lp * C_quadratic_forms(prob, Wp)))
+    return AX, cX
+
+
+def sketch_certificate(prob, U: np.ndarray, lam: np.ndarray, units: str = "scaled"):
+    """<C, Xhat> (original units) and the relative infeasibility of Xhat = U diag(lam) U^T,
+    the Nystrom reconstruction handed out in original units (Sec. 4, App. C.1), measured as
+    in eq. relative_error_tol: dist(A Xhat, K) / (1 + ||b||) in the chosen units."""
+    U = np.asarray(U, dtype=np.float64)
+    lam = np.asarray(lam, dtype=np.float64)
+    sigma = float(np.linalg.norm(prob.val)) or 1.0
+    cx = sigma * float(np.sum(lam * C_quadratic_forms(prob, U)))
+    z = A_lowrank(prob, U, lam)
+    if units == "original":
+        inf = dist_K(prob, z, prob.b) / (1.0 + np.linalg.norm(prob.b))
+    else:
+        bs = prob.b / prob.trace
+        inf = dist_K(prob, z / prob.trace, bs) / (1.0 + np.linalg.norm(bs))
+    return cx, inf
+
+
 # --------------------------------------------------------------------------
 # MaxCut helpers (App. E.1)
 # --------------------------------------------------------------------------

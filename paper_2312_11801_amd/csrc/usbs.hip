@@ -93,7 +93,7 @@ struct usbs_handle {
 
     // iteration state
     double *y = nullptr, *yc = nullptr, *nu = nullptr, *dnu = nullptr, *zbar = nullptr, *AX = nullptr,
-           *evec = nullptr;
+           *evec = nullptr, *AXhat = nullptr;
     double *V = nullptr, *Vn = nullptr, *CV = nullptr, *Uritz = nullptr, *P = nullptr;
     // decoupled rows (exact eigenpairs (d_i, e_i)); Ucpl = Ritz vectors of the coupled
     // rows (the Lanczos state; aliases Uritz when there are no decoupled rows)
@@ -123,6 +123,9 @@ struct usbs_handle {
     int recoveries = 0;       // stall re-evaluations of f at the centre
     bool last_conv = false;
     bool ready = false;
+    // value of iters after which AX, Vn (= V_t) and the QP solution in ipm describe
+    // X_{t+1} of that iteration; -1 before the first iteration of the current problem
+    int primal_at = -1;
 
     // live timing of one kernel category with HIP events (bench / roofline)
     int prof_cat = -1;
@@ -448,6 +451,7 @@ void upload(usbs_handle *h) {
     h->dnu = dalloc<double>(m, o, h->stream);
     h->zbar = dalloc<double>(m, o, h->stream);
     h->AX = dalloc<double>(m, o, h->stream);
+    h->AXhat = dalloc<double>(m, o, h->stream);
     h->evec = dalloc<double>(m, o, h->stream);
     h->V = dalloc<double>((size_t)n * 16, o, h->stream);
     h->Vn = dalloc<double>((size_t)n * 16, o, h->stream);
@@ -739,6 +743,7 @@ void iterate(usbs_handle *h) {
     }
     std::swap(h->V, h->Vn);
     h->iters++;
+    h->primal_at = h->iters;
     double desc = 0.0;
     HIPCHK(hipMemcpyAsync(&desc, h->sc + SC_DESC, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1042,10 +1047,11 @@ void fill_result(usbs_handle *h, usbs_result *res, double *y_out, double *U_out,
         std::vector<double> K(r * r, 0.0);
         for (int j = 0; j < r; ++j) K[j * r + j] = lam[j];
         HIPCHK(hipMemcpyAsync(h->Kc, K.data(), r * r * sizeof(double), hipMemcpyHostToDevice, s));
-        lowrank_A(s, h->m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, r, h->Kc, 1.0, nullptr, nullptr, 0.0, h->AX,
+        // A(Xhat) goes to its own buffer: AX keeps A X_{t+1} for usbs_get_primal
+        lowrank_A(s, h->m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, r, h->Kc, 1.0, nullptr, nullptr, 0.0, h->AXhat,
                   0.0);
         std::vector<double> ax(h->m), bs(h->m);
-        HIPCHK(hipMemcpyAsync(ax.data(), h->AX, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(ax.data(), h->AXhat, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipMemcpyAsync(bs.data(), h->b, h->m * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         double d2 = 0.0;
@@ -1255,7 +1261,7 @@ int64_t usbs_footprint_bytes(const usbs_problem *p, const usbs_params *prm) {
     b += 4 * (n + 1) + 4 * nnz + 8 * nnz + 2 * vsz * nnz + 8 * 2 * n + 4 * (n + 1);
     b += 12 * diagt + 16 * 2 * offt + 4 * (m + 1) + 16 * nt + 16 * m + 4 * n * r;
     // iteration state and Lanczos work (see upload)
-    b += 8 * 7 * m;
+    b += 8 * 8 * m;
     b += 8 * n * 16 * 7;                       // V, Vn, CV, Uritz, Ucpl, Ubuf, Zp
     b += 8 * n * std::max<int64_t>(r, 1);     // sketch
     b += 8 * n * kMaxBasis + 8 * n * 8 * 2 + 8 * n * 32;
@@ -1556,6 +1562,53 @@ int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *z
     }
 }
 
+int usbs_get_dual(usbs_handle *h, double *y_out) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!y_out) return USBS_E_INVALID;
+    try {
+        HIPCHK(hipMemcpyAsync(y_out, h->y, (size_t)h->m * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        // App. E: y = ||C||_F y_s
+        for (int q = 0; q < h->m; ++q) y_out[q] *= h->sigma;
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
+int usbs_get_primal(usbs_handle *h, double *ax_out, double *cx_out, double *V_out, double *S_out, double *eta_out,
+                    double *g_out) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (h->primal_at < 0 || h->primal_at != h->iters) {
+        set_err(h, "usbs_get_primal: no iteration has run on the current problem");
+        return USBS_E_STATE;
+    }
+    try {
+        hipStream_t s = h->stream;
+        const int n = h->n, m = h->m, k = h->k;
+        std::vector<double> sc(SC_COUNT), st((size_t)k * k);
+        HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(st.data(), h->ipm, (size_t)k * k * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (ax_out) HIPCHK(hipMemcpyAsync(ax_out, h->AX, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<double> vt;
+        if (V_out) {
+            vt.resize((size_t)n * 16);
+            HIPCHK(hipMemcpyAsync(vt.data(), h->Vn, (size_t)n * 16 * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        if (V_out)
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < k; ++j) V_out[(size_t)i * k + j] = vt[(size_t)i * 16 + j];
+        if (S_out) std::copy(st.begin(), st.end(), S_out);
+        if (cx_out) *cx_out = sc[SC_CX];
+        if (eta_out) *eta_out = sc[SC_ETA];
+        if (g_out) *g_out = sc[SC_G];
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
 int usbs_warm_start(usbs_handle *h, const usbs_problem *grown) { return usbs_pack::warm_prepare(h, grown, true); }
 
 }  // extern "C"
@@ -1598,6 +1651,7 @@ int warm_prepare(usbs_handle *h, const usbs_problem *grown, bool eval_f) {
         // ---- the grown problem ----
         free_problem(h);
         h->ready = false;
+        h->primal_at = -1;
         h->hp = std::move(hp);
         set_geometry(h, h->hp.n);
         upload(h);
@@ -1898,6 +1952,7 @@ int launch(Runner &R, usbs_handle *const *hs, PackState *st, int count, int iter
             st[q] = R.state_host[a];
             if (st[q].swapped) std::swap(h->V, h->Vn);
             st[q].swapped = 0;
+            if (st[q].iters != h->iters) h->primal_at = st[q].iters;
             h->iters = st[q].iters;
             h->null_run = st[q].null_run;
             h->lz_unconverged = st[q].lz_unconverged;

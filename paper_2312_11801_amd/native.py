@@ -30,7 +30,8 @@ EXPORTS = [
     "usbs_op_ipm", "usbs_op_nystrom", "usbs_step_iterate", "usbs_get_scaling", "usbs_profile",
     "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
     "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free", "usbs_round_maxcut",
-    "usbs_get_tuning", "usbs_solve_packed", "usbs_packed_profile",
+    "usbs_get_tuning", "usbs_solve_packed", "usbs_packed_profile", "usbs_get_primal",
+    "usbs_get_dual",
 ]
 PACK_PHASES = ["spmm", "tn", "nn", "ritz", "ipm", "constraints", "small", "shift", "all"]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
@@ -145,6 +146,8 @@ def load_library(path: str | None = None):
         "usbs_get_tuning": (ctypes.c_int, [vp, vp]),
         "usbs_solve_packed": (ctypes.c_int, [vp, i32, i32, vp, ctypes.POINTER(UsbsResult), vp]),
         "usbs_packed_profile": (ctypes.c_int, [vp, i32, vp]),
+        "usbs_get_primal": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
+        "usbs_get_dual": (ctypes.c_int, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -350,6 +353,18 @@ class Solver:
         keys = ["f", "tau", "cbar", "primal", "rel_gap", "rel_infeas", "lambda1", "descents"]
         return {"y": y, "V": V[:, :k], "zbar": zbar, "P": P[:, :self.r], **dict(zip(keys, scal))}
 
+    def primal(self) -> dict:
+        """X_{t+1} of the last iteration (scaled units): A X_{t+1}, <C_s, X_{t+1}>, the
+        bundle V_t, the QP solution (S, eta) and g = alpha eta / tau_t."""
+        k = self.params.k_c + self.params.k_p
+        ax = np.zeros(self.m)
+        V = np.zeros((self.n, k))
+        S = np.zeros((k, k))
+        cx, eta, g = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.usbs_get_primal(self.h, _ptr(ax), ctypes.byref(cx), _ptr(V), _ptr(S),
+                                             ctypes.byref(eta), ctypes.byref(g)))
+        return {"AX": ax, "cX": cx.value, "V": V, "S": S, "eta": eta.value, "g": g.value}
+
     def profile(self, category: str | None, reset: bool = True):
         """Return (ms, launches) timed so far for the current category and start timing
         `category` (None stops timing)."""
@@ -392,9 +407,8 @@ def solve_packed(solvers: list, iters_per_launch: int = 8, stream: int | None = 
     for q, s in enumerate(solvers):
         d = res[q].as_dict()
         y = np.zeros(s.m)
-        s._check(lib.usbs_step_iterate(s.h, 0, _ptr(y), None, None, None, None))
-        sigma, _ = s.scaling()
-        d.update({"y": y * sigma, "converged": int(st[q]) == USBS_OK, "status_code": int(st[q])})
+        s._check(lib.usbs_get_dual(s.h, _ptr(y)))
+        d.update({"y": y, "converged": int(st[q]) == USBS_OK, "status_code": int(st[q])})
         outs.append(d)
     return outs
 

@@ -518,3 +518,61 @@ def test_decoupled_rows_direct_sum():
     cc = si.cc_problem(8, ci, cj, np.array([1.0, 0.0, -1.0]))
     iso = orc.decoupled_rows(cc)
     assert np.array_equal(np.flatnonzero(iso), [6, 7])
+
+
+# ---------------------------------------------------------------------------
+# certificates of results computed elsewhere (Sec. 5, App. C)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,k_p", [("maxcut", 1), ("cc", 0), ("maxcut", 3)])
+def test_primal_from_model_update_equals_dense_X(kind, k_p):
+    """A X_{t+1} and <C_s, X_{t+1}> rebuilt from the state after the model update (the
+    tracked zbar_{t+1}, cbar_{t+1}, the bundle V_t and the QP solution S) equal the same
+    quantities of the dense X_{t+1} = g Xbar_t + alpha V_t S V_t^T along an oracle run.
+    Dropping the top-k_p part, or taking the k_p smallest eigenpairs instead, fails."""
+    prob = si.maxcut_er(50, 0.15, seed=2) if kind == "maxcut" else si.cc_signed(40, avg_degree=6.0, seed=1)
+    k_c = 4 if kind == "cc" else 6
+    prm = orc.Params(rho=0.1, k_c=k_c, k_p=k_p, max_iters=40)
+    sc = orc.scale_problem(prob)
+    Psi = si.test_matrix(prob.n, 10, seed=0).astype(float)
+    st = orc.cold_start(sc, prm, Psi)
+    checked = 0
+    for t in range(12):
+        V, Xbar, tau = st.V.copy(), st.Xbar.copy(), st.tau
+        rec = orc.usbs_step(sc, prm, st, Psi)
+        S, eta = st.ipm.S, st.ipm.eta
+        g = prm.alpha * eta / tau if tau > 0 else 0.0
+        X = g * Xbar + prm.alpha * V @ S @ V.T
+        AX, cX = orc.primal_from_model_update(prob, st.zbar, st.cbar, V, S, prm.alpha, k_p)
+        ref_AX = orc.A_apply(prob, X)
+        assert np.abs(AX - ref_AX).max() <= 1e-12 * (1 + np.abs(ref_AX).max())
+        assert abs(cX - float(np.sum(sc.C * X))) <= 1e-12
+        assert np.abs(AX - rec["AX"]).max() <= 1e-12 and abs(cX - rec["primal"]) <= 1e-12
+        lam = orc.jacobi_eigh(prm.alpha * S)[0]
+        if k_p > 0 and lam[0] > 1e-8 * max(1.0, abs(lam[0])):
+            # the top-k_p part is what separates X_{t+1} from Xbar_{t+1}
+            assert np.abs(orc.A_apply(prob, st.Xbar) - ref_AX).max() > 1e-9
+            checked += 1
+    if k_p > 0:
+        assert checked > 0
+
+
+def test_sketch_certificate_equals_dense_definition():
+    """<C, Xhat> and dist(A Xhat, K) / (1 + ||b||) of Xhat = U diag(lam) U^T match the dense
+    definitions (scaled and original units; equality and inequality rows)."""
+    rng = np.random.default_rng(4)
+    for prob in (si.maxcut_er(60, 0.1, seed=3), si.cc_signed(50, avg_degree=6.0, seed=2)):
+        U = rng.standard_normal((prob.n, 5))
+        lam = rng.random(5) * 3.0
+        X = (U * lam[None, :]) @ U.T
+        C = orc.dense_C(prob)
+        cx, inf_s = orc.sketch_certificate(prob, U, lam, "scaled")
+        _, inf_o = orc.sketch_certificate(prob, U, lam, "original")
+        assert abs(cx - float(np.sum(C * X))) <= 1e-10 * (1 + abs(cx))
+        z = orc.A_apply(prob, X)
+        ineq = prob.is_ineq.astype(bool)
+        e = np.where(ineq, np.maximum(z - prob.b, 0.0), z - prob.b)
+        assert abs(inf_o - np.linalg.norm(e) / (1 + np.linalg.norm(prob.b))) <= 1e-12
+        es = e / prob.trace
+        assert abs(inf_s - np.linalg.norm(es) / (1 + np.linalg.norm(prob.b / prob.trace))) <= 1e-12
+        if ineq.any():
+            assert np.any(e[ineq] == 0.0) or np.all(z[ineq] > prob.b[ineq])
