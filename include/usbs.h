@@ -151,6 +151,8 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
 int usbs_warm_start(usbs_handle *h, const usbs_problem *grown);
 
 void usbs_free(usbs_handle *h); /* NULL-safe */
+/* The message of the handle's last error; with h = NULL, that of the calling thread's
+ * last failed handle-free call (usbs_sketch_update_noalloc), else "NULL handle". */
 const char *usbs_last_error(const usbs_handle *h);
 
 /* Packed solve of several instances in persistent launches (Sec. 3-4, Alg. 1, on
@@ -298,6 +300,34 @@ int usbs_get_scaling(const usbs_handle *h, double *sigma, double *trace);
  * problem and these parameters (used by the server's admission test); < 0 on
  * malformed input. */
 int64_t usbs_footprint_bytes(const usbs_problem *prob, const usbs_params *prm);
+
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP stream capture,
+ * serving loops or harnesses that forbid hipMalloc): the sketch update of
+ * usbs_op_sketch_update without a handle and without any allocation,
+ *     P_dev <- g P_dev + W_dev diag(lam) (W_dev^T psi_dev).
+ *   n        rows, 0 <= n < 2^31 (n = 0 does nothing);
+ *   W_dev    n x q FP64, row-major, leading dimension q, 1 <= q <= USBS_NOALLOC_MAX_Q;
+ *   lam      host array [q];
+ *   psi_dev  n x r FP32 test matrix, row-major, leading dimension r,
+ *            1 <= r <= USBS_NOALLOC_MAX_R;
+ *   P_dev    n x r FP64 sketch, row-major, leading dimension r, updated in place;
+ *   stream   hipStream_t (NULL = the default stream); the call only enqueues work.
+ * The device arrays belong to the caller and live on the current device.  The
+ * temporaries (the reduction partials of W^T psi and the q x r product) go to one fixed
+ * array of USBS_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until the
+ * process ends; its address is looked up on the first call on each device.  All calls on
+ * one GPU share that array.  Each call writes all of it that it reads before reading
+ * it, so nothing carries over between calls; calls that overlap on one GPU (several
+ * host threads, or streams not ordered with each other) race.  The result equals
+ * usbs_op_sketch_update's bit for bit.  Returns USBS_OK, USBS_E_INVALID (size out of
+ * range or NULL pointer) or USBS_E_DEVICE; usbs_last_error(NULL) then gives the calling
+ * thread's message. */
+#define USBS_NOALLOC_MAX_Q 16
+#define USBS_NOALLOC_MAX_R 16
+#define USBS_NOALLOC_SCRATCH_BYTES ((512 * 16 * 16 + 16 * 16) * 8)
+int usbs_sketch_update_noalloc(int64_t n, int32_t q, int32_t r, double g, const double *W_dev,
+                               const double *lam, const float *psi_dev, double *P_dev, void *stream);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching on one GPU.

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["kernels.hip", "steps.hip", "packed.hip", "usbs.hip", "server.hip"]
+SOURCES = ["kernels.hip", "steps.hip", "packed.hip", "usbs.hip", "server.hip", "noalloc.hip"]
 LIB = os.path.join(HERE, "libusbs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -24,6 +24,10 @@
 
 using namespace usbs;
 
+namespace usbs_noalloc {
+const char *last_error();   // noalloc.hip
+}
+
 namespace {
 
 struct DevError : std::runtime_error {
@@ -1242,7 +1246,11 @@ int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_tot
     }
 }
 
-const char *usbs_last_error(const usbs_handle *h) { return h ? h->err.c_str() : "NULL handle"; }
+const char *usbs_last_error(const usbs_handle *h) {
+    if (h) return h->err.c_str();
+    const char *m = usbs_noalloc::last_error();
+    return m ? m : "NULL handle";
+}
 
 int64_t usbs_footprint_bytes(const usbs_problem *p, const usbs_params *prm) {
     if (!p || !prm || p->n < 1 || p->m < 1 || !p->rowptr || (p->n_triplets > 0 && (!p->a_i || !p->a_j)))

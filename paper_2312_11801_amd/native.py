@@ -31,7 +31,7 @@ EXPORTS = [
     "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
     "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free", "usbs_round_maxcut",
     "usbs_get_tuning", "usbs_solve_packed", "usbs_packed_profile", "usbs_get_primal",
-    "usbs_get_dual",
+    "usbs_get_dual", "usbs_sketch_update_noalloc",
 ]
 PACK_PHASES = ["spmm", "tn", "nn", "ritz", "ipm", "constraints", "small", "shift", "all"]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
@@ -148,6 +148,7 @@ def load_library(path: str | None = None):
         "usbs_packed_profile": (ctypes.c_int, [vp, i32, vp]),
         "usbs_get_primal": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "usbs_get_dual": (ctypes.c_int, [vp, vp]),
+        "usbs_sketch_update_noalloc": (ctypes.c_int, [i64, i32, i32, dbl, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -411,6 +412,19 @@ def solve_packed(solvers: list, iters_per_launch: int = 8, stream: int | None = 
         d.update({"y": y, "converged": int(st[q]) == USBS_OK, "status_code": int(st[q])})
         outs.append(d)
     return outs
+
+
+def sketch_update_noalloc(g: float, W_dev, lam, psi_dev, P_dev, stream: int | None = None) -> None:
+    """usbs_sketch_update_noalloc: P <- g P + W diag(lam) (W^T Psi) on device tensors,
+    without a handle and without device allocation (enqueued on `stream`)."""
+    lib = load_library()
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    n, q = W_dev.shape
+    r = P_dev.shape[1]
+    rc = lib.usbs_sketch_update_noalloc(int(n), int(q), int(r), float(g), _ptr(W_dev), _ptr(lam), _ptr(psi_dev),
+                                        _ptr(P_dev), stream)
+    if rc != USBS_OK:
+        raise UsbsError(rc, lib.usbs_last_error(None).decode())
 
 
 def footprint_bytes(prob, params: Params | None = None, psi=None) -> int:
