@@ -91,8 +91,8 @@ typedef struct usbs_params {
     int32_t units;              /* USBS_UNITS_*                            */
     int32_t max_iters;
     double time_limit;          /* seconds, <= 0 for none                  */
-    int32_t lanczos_steps;      /* block steps per restart cycle (block 8; default 4, i.e.
-                                   32 new Krylov vectors per cycle)          */
+    int32_t lanczos_steps;      /* block steps per restart cycle (block 8; default 8, i.e.
+                                   64 new Krylov vectors per cycle)          */
     int32_t lanczos_max_restarts; /* restart cycles of the in-iteration eigen-solve (default 10,
                                      the paper's; the certifying solves use at least 30)     */
     double lanczos_tol;         /* residual / spectral-radius estimate inside the iteration */
@@ -272,10 +272,14 @@ int usbs_get_primal(usbs_handle *h, double *ax_out, double *cx_out, double *V_ou
  * the category being timed (optionally resetting them), then times 'category' from now
  * on (-1 = none).  Used by the benchmark for the roofline of the dominant kernel. */
 #define USBS_PROF_SPMM 0   /* (C - A^* y) X block products                    */
-#define USBS_PROF_REORTH 1 /* first stage of the B^T W reductions of the Krylov block re-orthogonalisation (kernel k_tn_mfma<1, UNR, true>; the finisher is not included) */
+#define USBS_PROF_REORTH 1 /* first stage of the first-pass [Q W]^T W reduction of the Krylov block
+                              re-orthogonalisation (kernel k_tn_mfma<1, UNR, true>; the
+                              finisher is not included)                                      */
 #define USBS_PROF_RITZ 2   /* projected (Rayleigh-Ritz) eigenproblem          */
 #define USBS_PROF_IPM 3    /* master-QP interior point solve                  */
-#define USBS_PROF_COUNT 4
+#define USBS_PROF_UPDATE 4 /* first Gram-Schmidt update of a Krylov block fused with the second
+                              pass's [Q W]^T W reduction (kernel k_nn_tn_mfma)               */
+#define USBS_PROF_COUNT 5
 int usbs_profile(usbs_handle *h, int32_t category, int32_t reset, double *ms_total, int64_t *launches);
 
 /* Rounding of a MaxCut relaxation (App. E.1): the r cuts x_c = sign(U[:, c]) (ties to

@@ -87,6 +87,13 @@ void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const dou
 // follow A's in H (H is (ca + ca2) x cc); C must not alias A or A2
 void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2, int ca2,
                 const double *H, int ldh, int cc, double *C, int ldc);
+// the first Gram-Schmidt update of a Lanczos block fused with the second pass's reduction:
+// C (n x 8, ldc) = [A A2] H (A n x ca, A2 n x 8, H (ca + 8) x 8) and one partial of
+// [A C]^T C ((ca + 8) x 8) per workgroup in rs.partials; returns the workgroup count
+// (reorth_finish sums the partials).  Events, if given, time this dispatch.
+int nn_update2_reorth(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *A2,
+                      int lda2, const double *H, int ldh, double *C, int ldc, hipEvent_t ev_start = nullptr,
+                      hipEvent_t ev_stop = nullptr);
 // same with a float32 destination (sketch storage)
 void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
                  int cc, float *C, int ldc, double alpha, double beta);

@@ -588,6 +588,45 @@ __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict
     wg_nn_mfma(n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, blockIdx.x, gridDim.x, &w);
 }
 
+// pass-0 update of a Lanczos block fused with the pass-1 reduction (wg_nn_tn_mfma)
+template <int NL>
+__global__ __launch_bounds__(kWG) void k_nn_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
+                                                    const double *__restrict__ A2, int lda2,
+                                                    const double *__restrict__ H, int ldh, double *__restrict__ C,
+                                                    int ldc, double *__restrict__ partials) {
+    __shared__ NnTnWork w;
+    wg_nn_tn_mfma<NL>(n, A, lda, ca, A2, lda2, H, ldh, C, ldc, blockIdx.x, gridDim.x,
+                      partials + (size_t)blockIdx.x * (ca + kBlk) * kBlk, &w);
+}
+
+template <int NL>
+static void launch_nn_tn(hipStream_t s, int blocks, hipEvent_t e0, hipEvent_t e1, int n, const double *A, int lda,
+                         int ca, const double *A2, int lda2, const double *H, int ldh, double *C, int ldc,
+                         double *partials) {
+    if (e0 && e1)
+        hipExtLaunchKernelGGL(k_nn_tn_mfma<NL>, dim3(blocks), dim3(kWG), 0, s, e0, e1, 0, n, A, lda, ca, A2, lda2, H,
+                              ldh, C, ldc, partials);
+    else
+        hipLaunchKernelGGL(k_nn_tn_mfma<NL>, dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2, H, ldh, C, ldc,
+                           partials);
+}
+
+int nn_update2_reorth(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *A2,
+                      int lda2, const double *H, int ldh, double *C, int ldc, hipEvent_t ev_start,
+                      hipEvent_t ev_stop) {
+    const int blocks = mfma_blocks(rs, n);
+    const int nl = (16 * (ca + kBlk) + 63) / 64;   // flat loads per lane of one 16-row group
+    if (nl <= 8)
+        launch_nn_tn<8>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
+    else if (nl <= 12)
+        launch_nn_tn<12>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
+    else if (nl <= 16)
+        launch_nn_tn<16>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
+    else
+        launch_nn_tn<kNtMaxLoads>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
+    return blocks;
+}
+
 static bool use_nn_mfma(int n, int cc) { return n > 0 && cc <= 16; }
 static int nn_mfma_blocks(int n) {
     // one row group per wavefront up to the tuned cap (4096 workgroups by default); the
@@ -755,7 +794,6 @@ void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const 
              int do_q11) {
     int blocks = cdiv(m, 2 * kQB);
     if (blocks > rs.max_blocks) blocks = rs.max_blocks;
-    if (blocks > 240) blocks = 240;
     if (blocks < 1) blocks = 1;
     const int d = k * (k + 1) / 2;
     const int nout = (do_q11 ? d * (d + 1) / 2 : 0) + nw * d;

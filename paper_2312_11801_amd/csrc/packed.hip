@@ -30,6 +30,7 @@ struct PackShared {
         IpmShared ipm;
         TnWork tn;
         NnWork nn;
+        NnTnWork nt;
         QpGramWork qg;
         PipWork pip;
         RestartWork rp;
@@ -56,6 +57,9 @@ struct Ctx {
 };
 
 constexpr int kPackUnr = 8;   // row groups in flight per wavefront in the reductions
+// expansion cycles every tight eigen-solve runs before its convergence test counts (as in
+// the per-instance driver)
+constexpr int kCertifyMinCycles = 2;
 
 // adds the device wall-clock time of its scope to one phase (every thread keeps the same
 // counters; thread 0 writes them back)
@@ -227,6 +231,19 @@ __device__ void pk_nn2(Ctx &c, const double *A, int lda, int ca, const double *A
     wg_nn_mfma(uni(c.D)->n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, 0, 1, &g_sh.u.nn);
     sync();
 }
+// Wt = [A A2] H (pass-0 update of a Lanczos block) and Hg = [A Wt]^T Wt (pass-1 reduction)
+// in one sweep over the rows of A (wg_nn_tn_mfma)
+__device__ void pk_nn_tn(Ctx &c, const double *A, int lda, int ca, const double *A2, int lda2, const double *H,
+                         int ldh, double *Wt, int ldw, double *Hg) {
+    PK_TICK(c, PH_NN);
+    const int n = uni(c.D)->n;
+    const int nl = (16 * (ca + kBlk) + 63) / 64;
+    if (nl <= 8) wg_nn_tn_mfma<8>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
+    else if (nl <= 12) wg_nn_tn_mfma<12>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
+    else if (nl <= 16) wg_nn_tn_mfma<16>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
+    else wg_nn_tn_mfma<kNtMaxLoads>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
+    sync();
+}
 __device__ void pk_nn(Ctx &c, const double *A, int lda, int ca, const double *H, int ldh, int cc, double *C, int ldc,
                       double alpha, double beta) {
     pk_nn2(c, A, lda, ca, nullptr, 0, 0, H, ldh, cc, C, ldc, alpha, beta);
@@ -273,7 +290,8 @@ __device__ void pk_small_eig(Ctx &c, int N, const double *A, int lda, double *w,
 // block, Cholesky-QR2 for each new block; Uritz / theta hold the result.
 // Returns the number of restart cycles; c.last_conv tells whether the test passed.
 // ---------------------------------------------------------------------------
-__device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start) {
+__device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start,
+                          int min_cyc) {
     const PackDesc &D = *uni(c.D);
     const int n = D.n, ldb = D.ldb, steps = D.steps;
     if (start != D.Ubuf) pk_copy_cols(n, start, 16, 16, D.Ubuf, 16);
@@ -328,7 +346,7 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
         const int conv = D.flag[0];
         sync();   // every thread has read the flag before it is reused
         c.last_conv = conv != 0;
-        if (conv || cyc == maxr) break;
+        if ((conv && cyc >= min_cyc) || cyc == maxr) break;
         // Krylov expansion from the dominant residual directions
         for (int e = threadIdx.x; e < ldb * ldb; e += kWG) {
             const int a = e / ldb, q = e - a * ldb;
@@ -347,8 +365,8 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
             const bool last = j == steps - 1;
             pk_apply_op(c, D.Bm + c0, ldb, D.W, 8, 8);
             for (int pass = 0; pass < 2; ++pass) {
-                const double *Win = pass == 0 ? D.W : D.Wt;
-                pk_tn_gram(c, D.Bm, ldb, cols, Win, 8, D.Hg);
+                if (pass == 0) pk_tn_gram(c, D.Bm, ldb, cols, D.W, 8, D.Hg);
+                else pk_nn_tn(c, D.Bm, ldb, cols, D.W, 8, D.coef, 8, D.Wt, 8, D.Hg);   // update of pass 0 too
                 {
                     PK_TICK(c, PH_SMALL);
                     wg_pip_chol(D.Hg, cols, pass, D.Rsv, D.Tm + c0, ldb, D.coef,
@@ -356,8 +374,7 @@ __device__ int pk_lanczos(Ctx &c, const double *start, int kc, double tol, doubl
                                 &g_sh.u.pip);
                     sync();
                 }
-                if (pass == 0) pk_nn2(c, D.Bm, ldb, cols, D.W, 8, 8, D.coef, 8, 8, D.Wt, 8, 1.0, 0.0);
-                else if (!last) pk_nn2(c, D.Bm, ldb, cols, D.Wt, 8, 8, D.coef, 8, 8, D.Bm + cols, ldb, 1.0, 0.0);
+                if (pass == 1 && !last) pk_nn2(c, D.Bm, ldb, cols, D.Wt, 8, 8, D.coef, 8, 8, D.Bm + cols, ldb, 1.0, 0.0);
             }
         }
         pk_small_eig(c, ldb, D.Tm, ldb, D.theta, D.Ysm, 16, 16, D.dead);
@@ -441,7 +458,7 @@ __device__ void pk_polish(Ctx &c, int keep_max) {
     pk_copy_cols(D.n, D.Ucpl, 16, 12, D.Ubuf, 16);
     pk_random_block(D.n, 4, D.seed + 1000003ull * (uint64_t)(c.st.iters + 1), D.W, 8);
     pk_copy_cols(D.n, D.W, 8, 4, D.Ubuf + 12, 16);
-    pk_lanczos(c, D.Ubuf, 1, D.tol_final, D.tol_final, 30, true);
+    pk_lanczos(c, D.Ubuf, 1, D.tol_final, D.tol_final, 30, true, kCertifyMinCycles);
     pk_dots(c, D.m, D.b, D.y, nullptr, nullptr, nullptr, nullptr, 1, D.sc + SC_BYT);
     if (threadIdx.x == 0) refresh_f_scalar(D.theta, D.sc, keep_max);
     sync();
@@ -455,7 +472,8 @@ __device__ void pk_cold_start(Ctx &c) {
     if (D.sketch) pk_fill(D.P, (long)D.n * D.r, 0.0);
     pk_random_block(D.n, 16, D.seed, D.Ubuf, 16);
     pk_shift_operator(c, D.y);
-    pk_lanczos(c, D.Ubuf, D.k, D.tol_final, sqrt(D.tol_final), D.max_restarts > 30 ? D.max_restarts : 30, true);
+    pk_lanczos(c, D.Ubuf, D.k, D.tol_final, sqrt(D.tol_final), D.max_restarts > 30 ? D.max_restarts : 30, true,
+               kCertifyMinCycles);
     pk_fill(c.V, (long)D.n * 16, 0.0);
     pk_copy_cols(D.n, D.Uritz, 16, D.k, c.V, 16);
     if (threadIdx.x == 0) D.sc[SC_F] = D.alpha * fmax(D.theta[0], 0.0);
@@ -466,7 +484,8 @@ __device__ void pk_cold_start(Ctx &c) {
 __device__ void pk_warm_f(Ctx &c) {
     const PackDesc &D = *uni(c.D);
     pk_shift_operator(c, D.y);
-    pk_lanczos(c, D.Uritz, D.k, D.tol_final, sqrt(D.tol_final), D.max_restarts > 30 ? D.max_restarts : 30, false);
+    pk_lanczos(c, D.Uritz, D.k, D.tol_final, sqrt(D.tol_final), D.max_restarts > 30 ? D.max_restarts : 30, false,
+               kCertifyMinCycles);
     pk_dots(c, D.m, D.b, D.y, nullptr, nullptr, nullptr, nullptr, 1, D.sc + SC_BYT);
     if (threadIdx.x == 0) refresh_f_scalar(D.theta, D.sc, 0);
     sync();
@@ -532,7 +551,7 @@ __device__ void pk_iterate(Ctx &c) {
     pk_copy_cols(n, D.Ucpl, 16, 14, D.Ubuf, 16);
     pk_random_block(n, 2, D.seed + 7919ull * (uint64_t)(c.st.iters + 1), D.W, 8);
     pk_copy_cols(n, D.W, 8, 2, D.Ubuf + 14, 16);
-    const int cyc = pk_lanczos(c, D.Ubuf, kc, D.tol, D.tol_rest, D.max_restarts, true);
+    const int cyc = pk_lanczos(c, D.Ubuf, kc, D.tol, D.tol_rest, D.max_restarts, true, 0);
     if (cyc >= D.max_restarts && !c.last_conv) c.st.lz_unconverged++;
     if (threadIdx.x == 0) decide_scalar(D.theta, sc);
     sync();

@@ -565,7 +565,8 @@ void cholqr2(usbs_handle *h, const double *src, int lds, int nc, double *tmp, in
 // merged in at the end, and Ucpl keeps the coupled Ritz vectors for the next
 // start.
 // ---------------------------------------------------------------------------
-int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start) {
+int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start,
+            int min_cyc) {
     hipStream_t s = h->stream;
     const int n = h->n, ldb = h->ldb, steps = h->steps;
     if (start != h->Ubuf) copy_cols(s, n, start, 16, 16, h->Ubuf, 16);
@@ -605,7 +606,7 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         HIPCHK(hipMemcpyAsync(&conv, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         h->last_conv = conv != 0;
-        if (conv || cyc == maxr) break;
+        if ((conv && cyc >= min_cyc) || cyc == maxr) break;
         // Krylov expansion from the dominant residual directions
         lanczos_reset_T(s, h->Tm, ldb, ldb, h->theta, h->dead);
         nn_update(s, n, h->Ubuf, 16, 16, h->Zc, 8, 8, h->W, 8, 1.0, 0.0);
@@ -620,20 +621,24 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
             const int c0 = 16 + 8 * j, cols = c0 + 8;
             const bool last = j == steps - 1;
             apply_op(h, h->Bm + c0, ldb, h->W, 8, 8);
-            for (int pass = 0; pass < 2; ++pass) {
-                const double *Win = pass == 0 ? h->W : h->Wt;
-                int g;
-                {
-                    if (h->ev_used + 2 > h->ev_pool.size()) prof_flush(h);
-                    ProfPair pp(h, USBS_PROF_REORTH);
-                    g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, Win, 8, 8, pp.e0, pp.e1);
-                }
-                reorth_finish(s, h->rs, g, cols, 8, h->Hg, 8);
-                pip_chol(s, h->Hg, cols, pass, h->Rsv, h->Tm + c0, ldb, h->coef,
-                         (pass == 1 && !last) ? h->dead + cols : nullptr, pass == 0 ? h->sc + SC_SCALE : nullptr);
-                if (pass == 0) nn_update2(s, n, h->Bm, ldb, cols, h->W, 8, 8, h->coef, 8, 8, h->Wt, 8);
-                else if (!last) nn_update2(s, n, h->Bm, ldb, cols, h->Wt, 8, 8, h->coef, 8, 8, h->Bm + cols, ldb);
+            if (h->ev_used + 4 > h->ev_pool.size()) prof_flush(h);
+            // pass 0: [Q W]^T W, Cholesky of the Pythagorean Gram matrix
+            int g;
+            {
+                ProfPair pp(h, USBS_PROF_REORTH);
+                g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, pp.e0, pp.e1);
             }
+            reorth_finish(s, h->rs, g, cols, 8, h->Hg, 8);
+            pip_chol(s, h->Hg, cols, 0, h->Rsv, h->Tm + c0, ldb, h->coef, nullptr, h->sc + SC_SCALE);
+            // pass-0 update Wt = [Q W] coef fused with pass 1's reduction [Q Wt]^T Wt (the
+            // basis rows are read once for both)
+            {
+                ProfPair pp(h, USBS_PROF_UPDATE);
+                g = nn_update2_reorth(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, h->coef, 8, h->Wt, 8, pp.e0, pp.e1);
+            }
+            reorth_finish(s, h->rs, g, cols, 8, h->Hg, 8);
+            pip_chol(s, h->Hg, cols, 1, h->Rsv, h->Tm + c0, ldb, h->coef, !last ? h->dead + cols : nullptr, nullptr);
+            if (!last) nn_update2(s, n, h->Bm, ldb, cols, h->Wt, 8, 8, h->coef, 8, 8, h->Bm + cols, ldb);
         }
         {
             ProfScope ps(h, USBS_PROF_RITZ);
@@ -654,6 +659,11 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
 // Lanczos restart test and one for the alternating maximisation)
 // ---------------------------------------------------------------------------
 void polish_dual(usbs_handle *h);
+
+// expansion cycles every tight eigen-solve runs before its convergence test counts: a
+// start block that already holds converged eigenvectors of lower eigenvalues would
+// otherwise pass the residual test before the Krylov expansion has found the top one
+constexpr int kCertifyMinCycles = 2;
 
 // consecutive null steps after which f at the centre is re-evaluated with the tight
 // eigen-solve (an inexact eigen-solve can under-estimate f at an accepted centre, after
@@ -723,7 +733,7 @@ void iterate(usbs_handle *h) {
     random_block(s, n, 2, prm.seed + 7919ull * (uint64_t)(h->iters + 1), h->W, 8);
     copy_cols(s, n, h->W, 8, 2, h->Ubuf + 14, 16);
     const double tol_rest = prm.lanczos_tol_rest > 0.0 ? prm.lanczos_tol_rest : std::sqrt(prm.lanczos_tol);
-    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, tol_rest, prm.lanczos_max_restarts, true);
+    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, tol_rest, prm.lanczos_max_restarts, true, 0);
     if (cyc >= prm.lanczos_max_restarts && !h->last_conv) h->lz_unconverged++;
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
@@ -768,7 +778,7 @@ void polish_dual(usbs_handle *h) {
     copy_cols(s, h->n, h->Ucpl, 16, 12, h->Ubuf, 16);
     random_block(s, h->n, 4, h->prm.seed + 1000003ull * (uint64_t)(h->iters + 1), h->W, 8);
     copy_cols(s, h->n, h->W, 8, 4, h->Ubuf + 12, 16);
-    lanczos(h, h->Ubuf, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, true);
+    lanczos(h, h->Ubuf, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, true, kCertifyMinCycles);
     recompute_f(s, h->theta, h->y, h->b, h->m, h->rs, h->sc, 1);
 }
 
@@ -815,7 +825,7 @@ void cold_start(usbs_handle *h) {
     random_block(s, h->n, 16, h->prm.seed, h->Ubuf, 16);
     shift_operator(h, h->y);
     lanczos(h, h->Ubuf, h->k, h->prm.lanczos_tol_final, std::sqrt(h->prm.lanczos_tol_final),
-            std::max(h->prm.lanczos_max_restarts, 30), true);
+            std::max(h->prm.lanczos_max_restarts, 30), true, kCertifyMinCycles);
     HIPCHK(hipMemsetAsync(h->V, 0, (size_t)h->n * 16 * sizeof(double), s));
     copy_cols(s, h->n, h->Uritz, 16, h->k, h->V, 16);
     // f(y0) = alpha [theta_1]_+ (b^T y0 = 0)
@@ -1102,7 +1112,7 @@ int usbs_default_params(usbs_params *p) {
     p->units = USBS_UNITS_SCALED;
     p->max_iters = 1000;
     p->time_limit = 0.0;
-    p->lanczos_steps = 4;   // 32 new Krylov vectors per restart cycle (block 8)
+    p->lanczos_steps = 8;   // 64 new Krylov vectors per restart cycle (block 8)
     p->lanczos_max_restarts = 10;   // the paper's restart limit
     p->lanczos_tol = 1e-4;
     p->lanczos_tol_final = 1e-9;
@@ -1329,7 +1339,7 @@ int usbs_op_eigs(usbs_handle *h, const double *y_dev, int32_t k, const double *s
         if (start_dev) copy_cols(s, h->n, start_dev, 16, 16, h->Ubuf, 16);
         else random_block(s, h->n, 16, h->prm.seed + 7, h->Ubuf, 16);
         const int c = lanczos(h, h->Ubuf, k, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final,
-                              std::max(h->prm.lanczos_max_restarts, 30), true);
+                              std::max(h->prm.lanczos_max_restarts, 30), true, kCertifyMinCycles);
         if (w) HIPCHK(hipMemcpyAsync(w, h->theta, k * sizeof(double), hipMemcpyDeviceToHost, s));
         if (res) HIPCHK(hipMemcpyAsync(res, h->res, k * sizeof(double), hipMemcpyDeviceToHost, s));
         if (U_dev) copy_cols(s, h->n, h->Uritz, 16, 16, U_dev, 16);
@@ -1720,7 +1730,7 @@ int warm_prepare(usbs_handle *h, const usbs_problem *grown, bool eval_f) {
             // f(y0) with a tight tolerance
             shift_operator(h, h->y);
             lanczos(h, h->Uritz, k, h->prm.lanczos_tol_final, std::sqrt(h->prm.lanczos_tol_final),
-                    std::max(h->prm.lanczos_max_restarts, 30), false);
+                    std::max(h->prm.lanczos_max_restarts, 30), false, kCertifyMinCycles);
             recompute_f(s, h->theta, h->y, h->b, m, h->rs, h->sc, 0);
         }
         HIPCHK(hipStreamSynchronize(s));

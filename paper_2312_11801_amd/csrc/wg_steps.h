@@ -260,6 +260,146 @@ __device__ __forceinline__ void wg_nn_mfma(int n, const double *__restrict__ A, 
 }
 
 // ---------------------------------------------------------------------------
+// The first Gram-Schmidt update of a Lanczos block fused with the second pass's
+// reduction: C = [A A2] H (A2 and C of kBlk columns) as in wg_nn_mfma, then over the
+// same 16 rows the partial [A C]^T C ((ca + kBlk) x kBlk, layout as wg_tn_mfma with
+// GRAM): the rows of A are already in the wavefront's LDS tile, so the basis is read
+// from memory once for both.  A wavefront loads its 16 rows of [A A2] as one flat
+// sequence of 16 (ca + kBlk) elements (every lane busy, rows contiguous in memory);
+// H sits in LDS.  Row groups of this workgroup: g = 4 blk + wave + t * 4 nblk.  The four
+// wavefronts are summed in LDS in a fixed order into dst.
+// ---------------------------------------------------------------------------
+constexpr int kNtLd = kMaxBasis + 2 * kBlk + 1;
+constexpr int kNtMaxLoads = (16 * (kMaxBasis + kBlk) + 63) / 64;   // flat loads per lane per group
+struct NnTnWork {
+    union {
+        double tile[4][16][kNtLd];   // [A | A2 | C] of 16 rows per wavefront
+        double sred[3][kMfmaMaxCh + 1][4][64];
+    } u;
+    double sH[kMaxBasis + kBlk][kBlk];
+};
+// orders this wavefront's LDS accesses (a wavefront's LDS operations execute in order):
+// a compiler barrier that, unlike a workgroup-scope fence, does not wait for the
+// wavefront's outstanding global loads and stores
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+template <int NL>   // flat loads per lane per row group: NL >= 16 (ca + kBlk) / 64
+__device__ __forceinline__ void wg_nn_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
+                                              const double *__restrict__ A2, int lda2, const double *__restrict__ H,
+                                              int ldh, double *__restrict__ C, int ldc, int blk, int nblk,
+                                              double *__restrict__ dst, NnTnWork *w) {
+    n = uni(n), lda = uni(lda), ca = uni(ca), lda2 = uni(lda2), ldh = uni(ldh), ldc = uni(ldc);
+    blk = uni(blk), nblk = uni(nblk);
+    A = uni(A), A2 = uni(A2), H = uni(H), C = uni(C), dst = uni(dst);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kk = lane >> 4, j = lane & 15;
+    const int ct = ca + kBlk;        // columns of [A A2]
+    const int nq = (ct + 3) >> 2;
+    const int nch = (ca + 15) >> 4;
+    const int nel = 16 * ct;         // elements of one row group
+    for (int e = tid; e < ct * kBlk; e += kWG) w->sH[e / kBlk][e % kBlk] = H[(e / kBlk) * ldh + e % kBlk];
+    __syncthreads();
+    // element e of a row group is (row e / ct, column e % ct), found with a float reciprocal
+    // and one correction step (e < 16 ct <= 1536, far inside float precision)
+    const float inv = 1.0f / (float)ct;
+    auto split = [&](int e, int &r, int &c) {
+        r = (int)((float)e * inv);
+        c = e - r * ct;
+        if (c >= ct) c -= ct, ++r;
+        if (c < 0) c += ct, --r;
+    };
+    v4d racc[kMfmaMaxCh + 1];
+#pragma unroll
+    for (int q = 0; q <= kMfmaMaxCh; ++q) racc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+    double(*T)[kNtLd] = w->u.tile[wave];
+    const long ngroups = ((long)n + 15) >> 4;
+    const long gstride = (long)nblk * 4;
+    for (long g = (long)blk * 4 + wave; g < ngroups; g += gstride) {
+        const long row0 = 16 * g;
+        const int rows = (int)min(16L, (long)n - row0);
+        // ---- [A A2] rows into the tile: element e = lane + 64 t is (row e / ct, column e % ct);
+        // addresses are clamped to valid rows so that every load is unconditional ----
+        // every load is issued unconditionally from a valid address and masked by a product,
+        // so that no load waits inside a branch (the data are finite)
+        double v[NL];
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int e = lane + 64 * t;
+            int r, c;
+            split(e, r, c);
+            const long rc = row0 + min(r, rows - 1);
+            const double *pa = A + rc * lda + min(c, ca - 1);
+            const double *pb = A2 + rc * lda2 + max(c - ca, 0);
+            const double val = *((c < ca) ? pa : pb);
+            v[t] = val * ((e < nel && r < rows) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int e = lane + 64 * t;
+            int r, c;
+            split(e, r, c);
+            if (e < nel) T[r][c] = v[t];
+        }
+        wave_lds_sync();
+        // ---- C rows: D[m][j] = sum_a T[m][a] H[a][j]; ct is a multiple of 4, so every a < ct ----
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        const double hmask = (j < kBlk) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < kNnMaxQ; ++q)
+            if (q < nq) {
+                const int a = 4 * q + kk;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[m][a], w->sH[a][j & 7] * hmask, acc, 0, 0, 0);
+            }
+        if (j < kBlk) {
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                const int r = kk + 4 * vv;
+                T[r][ct + j] = acc[vv];
+                if (r < rows) C[(row0 + r) * ldc + j] = acc[vv];
+            }
+        }
+        wave_lds_sync();
+        // ---- [A C]^T C over these rows, four rows per product: X = 16 columns of A, Y = C.
+        // Columns 16 q + m >= ca of X read the A2 / C part of the tile: they only feed rows
+        // of the partial that are never written ----
+        const double ymask = (m < kBlk) ? 1.0 : 0.0;
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int row = 4 * s4 + kk;
+            const double y = T[row][ct + (m & 7)] * ymask;
+#pragma unroll
+            for (int q = 0; q < kMfmaMaxCh; ++q)
+                if (q < nch) racc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(T[row][16 * q + m], y, racc[q], 0, 0, 0);
+            racc[kMfmaMaxCh] = __builtin_amdgcn_mfma_f64_16x16x4f64(y, y, racc[kMfmaMaxCh], 0, 0, 0);
+        }
+        wave_lds_sync();   // the tile is rewritten for the next row group
+    }
+    __syncthreads();   // the summation space overlays the tiles
+    if (wave > 0)
+#pragma unroll
+        for (int q = 0; q <= kMfmaMaxCh; ++q)
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) w->u.sred[wave - 1][q][vv][lane] = racc[q][vv];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int q = 0; q <= kMfmaMaxCh; ++q) {
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                const double t = ((racc[q][vv] + w->u.sred[0][q][vv][lane]) + w->u.sred[1][q][vv][lane]) +
+                                 w->u.sred[2][q][vv][lane];
+                const int mm = kk + 4 * vv;
+                const int a = (q < kMfmaMaxCh) ? 16 * q + mm : ca + mm;
+                const bool valid = (q < kMfmaMaxCh) ? (q < nch && a < ca) : (mm < kBlk);
+                if (valid && j < kBlk) dst[(size_t)a * kBlk + j] = t;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // constraint-side bodies (App. B.2 and App. C)
 // ---------------------------------------------------------------------------
 // g_k = svec(V^T A_k V) for one constraint row k into g[0..d) (g may live in LDS)
@@ -285,14 +425,22 @@ __device__ __forceinline__ void svec_constraint(int k, const int *__restrict__ k
     }
 }
 
-// Q11 raw sum and G^T w_j over the constraint rows of this workgroup.  Rows are
-// processed in batches of 64 staged in LDS; each thread owns a fixed set of (P,Q)
-// entries of the upper triangle.  out layout (d = kd(kd+1)/2): if do_q11, the upper
-// triangle of sum_k g_k g_k^T row by row; then G^T w_j, j < nw.
+// Q11 raw sum and G^T w_j over the constraint rows of this workgroup on the FP64 matrix
+// cores.  G' = [G | w_0 .. w_{nw-1}] (row k: g_k = svec(V^T A_k V), then the weights
+// w_j[k]) is built 64 rows at a time in LDS by all threads (four threads per row, each
+// owning the svec columns b = part mod 4); the needed 16 x 16 tiles of G'^T G' (the
+// upper triangle of G^T G when do_q11, and G^T w) are spread over the four wavefronts,
+// each accumulated by V_MFMA_F64_16X16X4F64 over four rows per instruction (operand
+// layout as wg_tn_mfma).  Every output is owned by one lane, so no cross-wave sum.
+// out layout (d = kd(kd+1)/2): if do_q11, the upper triangle of sum_k g_k g_k^T row by
+// row; then G^T w_j, j < nw.
 constexpr int kQB = 64;
+constexpr int kQgCh = (kMaxSvec + 15) / 16;                         // 16-column chunks of G
+constexpr int kQgLd = 16 * (kQgCh + 1) + 1;                         // G chunks, weight chunk, pad
+constexpr int kQgMaxTiles = kQgCh * (kQgCh + 1) / 2 + kQgCh;
+constexpr int kQgPerWave = (kQgMaxTiles + 3) / 4;
 struct QpGramWork {
-    double sg[kQB][kMaxSvec + 1];
-    double sw[4][kQB];
+    double sg[kQB][kQgLd];
 };
 __device__ __forceinline__ void wg_qp_gram(int m, const int *__restrict__ kptr, const int *__restrict__ ti,
                                            const int *__restrict__ tj, const double *__restrict__ tv,
@@ -302,63 +450,101 @@ __device__ __forceinline__ void wg_qp_gram(int m, const int *__restrict__ kptr, 
     m = uni(m), kd = uni(kd), do_q11 = uni(do_q11), nw = uni(nw), blk = uni(blk), nblk = uni(nblk), ldv = uni(ldv);
     kptr = uni(kptr), ti = uni(ti), tj = uni(tj), tv = uni(tv), V = uni(V), out = uni(out);
     w0 = uni(w0), w1 = uni(w1), w2 = uni(w2), w3 = uni(w3);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m16 = lane & 15, kk = lane >> 4;
     const int d = kd * (kd + 1) / 2;
+    const int nch = (d + 15) >> 4;
     const int nupper = do_q11 ? d * (d + 1) / 2 : 0;
-    const int nout = nupper + nw * d;
-    constexpr int kPer = (kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec + kWG - 1) / kWG;
-    double acc[kPer];
-    int pP[kPer], pQ[kPer];
+    const int ntri = do_q11 ? nch * (nch + 1) / 2 : 0;
+    const int ntiles = ntri + (nw > 0 ? nch : 0);
+    int tP[kQgPerWave], tQ[kQgPerWave];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        acc[q] = 0.0;
-        const int o = tid + q * kWG;
-        pP[q] = -1;
-        pQ[q] = -1;
-        if (o < nupper) {
-            // o -> (P, Q) with P <= Q in row-major upper-triangle order
-            int P = 0, rem = o;
-            while (rem >= d - P) {
-                rem -= d - P;
+    for (int u = 0; u < kQgPerWave; ++u) {
+        const int t = wave + 4 * u;
+        tP[u] = -1;
+        tQ[u] = -1;
+        if (t < ntri) {   // (P, Q), P <= Q, in row order of the chunk grid
+            int P = 0, rem = t;
+            while (rem >= nch - P) {
+                rem -= nch - P;
                 ++P;
             }
-            pP[q] = P;
-            pQ[q] = P + rem;
-        } else if (o < nout) {
-            const int j = (o - nupper) / d;
-            pP[q] = -(j + 2);               // weight vector j
-            pQ[q] = (o - nupper) - j * d;   // svec entry
+            tP[u] = P;
+            tQ[u] = P + rem;
+        } else if (t < ntiles) {
+            tP[u] = t - ntri;
+            tQ[u] = kQgCh;   // the weight chunk
         }
     }
+    v4d acc[kQgPerWave];
+#pragma unroll
+    for (int u = 0; u < kQgPerWave; ++u) acc[u] = (v4d){0.0, 0.0, 0.0, 0.0};
     const double *ws[4] = {w0, w1, w2, w3};
+    const double r2 = 1.4142135623730951;
+    const int brow = tid >> 2, part = tid & 3;
     for (long k0 = (long)blk * kQB; k0 < m; k0 += (long)nblk * kQB) {
-        if (tid < kQB) {
-            const long k = k0 + tid;
-            if (k < m) svec_constraint((int)k, kptr, ti, tj, tv, V, ldv, kd, &w->sg[tid][0]);
-            else
-                for (int p = 0; p < d; ++p) w->sg[tid][p] = 0.0;
-            for (int j = 0; j < nw; ++j) w->sw[j][tid] = (k < m) ? ws[j][k] : 0.0;
+        // ---- build 64 rows of G' (this thread: row brow, svec columns b = part mod 4) ----
+        {
+            const long k = k0 + brow;
+            double *g = &w->sg[brow][0];
+            for (int b = part; b < kd; b += 4) {
+                const int off = b * kd - b * (b - 1) / 2;
+                for (int a = b; a < kd; ++a) g[off + a - b] = 0.0;
+            }
+            if (k < m) {
+                for (int t = kptr[k]; t < kptr[k + 1]; ++t) {
+                    const double *vi = V + (size_t)ti[t] * ldv;
+                    const double *vj = V + (size_t)tj[t] * ldv;
+                    const double v = tv[t];
+                    for (int b = part; b < kd; b += 4) {
+                        const int off = b * kd - b * (b - 1) / 2;
+                        const double vib = vi[b], vjb = vj[b];
+                        for (int a = b; a < kd; ++a) {
+                            if (a == b) g[off] += v * vi[a] * vjb;
+                            else g[off + a - b] += v * r2 * 0.5 * (vi[a] * vjb + vib * vj[a]);
+                        }
+                    }
+                }
+            }
+            if (part == 0)
+                for (int j = 0; j < nw; ++j) g[16 * kQgCh + j] = (k < m) ? ws[j][k] : 0.0;
         }
         __syncthreads();
+        // ---- G'^T G' tiles of this wavefront over the 64 rows ----
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int P = pP[q], Q = pQ[q];
-            if (Q < 0) continue;
-            double s = 0.0;
-            if (P >= 0) {
-                for (int r = 0; r < kQB; ++r) s += w->sg[r][P] * w->sg[r][Q];
-            } else {
-                const int j = -P - 2;
-                for (int r = 0; r < kQB; ++r) s += w->sw[j][r] * w->sg[r][Q];
+        for (int u = 0; u < kQgPerWave; ++u) {
+            const int P = tP[u], Q = tQ[u];
+            if (P < 0) continue;
+            const int cx = 16 * P + m16;
+            const bool wq = Q == kQgCh;
+            const int cy = wq ? 16 * kQgCh + m16 : 16 * Q + m16;
+            const bool okx = cx < d, oky = wq ? (m16 < nw) : (cy < d);
+#pragma unroll 4
+            for (int s4 = 0; s4 < kQB / 4; ++s4) {
+                const int row = 4 * s4 + kk;
+                const double x = okx ? w->sg[row][cx] : 0.0;
+                const double y = oky ? w->sg[row][cy] : 0.0;
+                acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[u], 0, 0, 0);
             }
-            acc[q] += s;
         }
         __syncthreads();
     }
+    // ---- lane j + 16 (p % 4), element p / 4 holds D[p][j] of each tile ----
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int o = tid + q * kWG;
-        if (o < nout) out[o] = acc[q];
+    for (int u = 0; u < kQgPerWave; ++u) {
+        const int P = tP[u], Q = tQ[u];
+        if (P < 0) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int p = 16 * P + kk + 4 * v;
+            if (p >= d) continue;
+            if (Q < kQgCh) {
+                const int q = 16 * Q + m16;
+                if (q < d && p <= q) out[p * d - p * (p - 1) / 2 + (q - p)] = acc[u][v];
+            } else if (m16 < nw) {
+                out[nupper + m16 * d + p] = acc[u][v];
+            }
+        }
     }
 }
 
@@ -454,17 +640,17 @@ __device__ __forceinline__ void wg_pip_chol(const double *__restrict__ Hg, int c
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos restart: residual norms, convergence test and the compression of the
-// 16 Ritz residuals to the 8 dominant directions (next block): 8 of the 16
-// residual directions chosen by pivoted Cholesky of the Gram matrix R^T R (greedy:
-// the residual with the largest component orthogonal to those already chosen), each
-// scaled by 1 / ||r_p||; the block is orthonormalised afterwards.  Wavefront 0 does
-// the work, lanes 0..15 own one residual each.
+// Lanczos restart: residual norms, convergence test and the next block.  The next
+// block is spanned by 8 of the 16 Ritz residuals, each scaled by 1 / ||r_p|| (the block
+// is orthonormalised afterwards, with deflation), taken in this order: the wanted pairs
+// (p < kc) that have not met their tolerance, from the top; then the unwanted pairs
+// (p >= kc) from the top; then the converged wanted pairs.  For Ritz vectors of a block
+// Krylov space all residuals lie in the span of the next Krylov block, so this is the
+// thick restart; where the residuals of the kept vectors span more than 8 directions it
+// keeps the ones that improve the pairs still to converge.
 // convergence: residual of Ritz pair 0 <= tol * scale and of pairs 1..kc-1 <= tol_rest * scale
 // ---------------------------------------------------------------------------
 struct RestartWork {
-    double sG[kRitz][kRitz + 1];
-    double sL[kBlk][kRitz];
     int sel[kBlk];
 };
 __device__ __forceinline__ void wg_restart_prep(const double *__restrict__ RtR, const double *__restrict__ theta,
@@ -472,49 +658,35 @@ __device__ __forceinline__ void wg_restart_prep(const double *__restrict__ RtR, 
                                                 int *__restrict__ flag, double *__restrict__ Z,
                                                 const double *__restrict__ scale_est, RestartWork *w) {
     const int tid = threadIdx.x;
+    (void)w;
     if (tid < kRitz) res[tid] = sqrt(fmax(RtR[tid * kRitz + tid], 0.0));
-    if (tid < 64) {
-        for (int e = tid; e < kRitz * kRitz; e += 64) w->sG[e / kRitz][e % kRitz] = RtR[e];
-        for (int e = tid; e < kRitz * kBlk; e += 64) Z[e] = 0.0;
-        wave_sync();
-        const int i = tid & 15;   // every row of 16 lanes holds the same data
-        double d = fmax(w->sG[i][i], 0.0);
-        const double d0 = fmax(row16_max(d), 1e-300);
-        bool taken = false;
-        for (int t = 0; t < kBlk; ++t) {
-            // arg-max of the remaining diagonal (ties: lowest index)
-            const double cand = taken ? -1.0 : d;
-            const double best = row16_max(cand);
-            const double idx = row16_min((cand == best) ? (double)i : 1e9);
-            const int p = (int)idx;
-            if (!(best > 1e-24 * d0)) break;   // the residuals span fewer than t + 1 directions
-            const double piv = sqrt(best);
-            // column t of the pivoted Cholesky factor
-            double l = w->sG[i][p];
-            for (int u = 0; u < t; ++u) l -= w->sL[u][i] * w->sL[u][p];
-            l /= piv;
-            wave_sync();
-            if (tid < kRitz) w->sL[t][i] = l;
-            if (tid == 0) {
-                w->sel[t] = p;
-                Z[p * kBlk + t] = 1.0 / sqrt(fmax(w->sG[p][p], 1e-300));
-            }
-            wave_sync();
-            d = fmax(d - l * l, 0.0);
-            if (i == p) taken = true;
-        }
-        if (tid == 0) {
-            // tolerances are relative to a Gershgorin bound of the current operator
-            double sc = fmax(fabs(theta[0]), fabs(theta[kRitz - 1]));
-            if (scale_est) sc = fmax(sc, *scale_est);
+    if (tid == 0) {
+        // tolerances are relative to a Gershgorin bound of the current operator
+        double sc = fmax(fabs(theta[0]), fabs(theta[kRitz - 1]));
+        if (scale_est) sc = fmax(sc, *scale_est);
+        double r[kRitz], dmax = 0.0;
+        bool conv[kRitz];
+        for (int p = 0; p < kRitz; ++p) {
+            r[p] = sqrt(fmax(RtR[p * kRitz + p], 0.0));
+            dmax = fmax(dmax, r[p]);
             // the top Ritz pair sets f(y): tight tolerance; the others only shape the bundle
-            int ok = sqrt(fmax(RtR[0], 0.0)) <= tol * sc;
-            for (int q = 1; q < kc; ++q) {
-                const double r = sqrt(fmax(RtR[q * kRitz + q], 0.0));
-                if (!(r <= tol_rest * sc)) ok = 0;
-            }
-            *flag = ok;
+            conv[p] = r[p] <= ((p == 0) ? tol : tol_rest) * sc;
         }
+        int ok = 1;
+        for (int p = 0; p < kc && p < kRitz; ++p)
+            if (!conv[p]) ok = 0;
+        int sel[kBlk], ns = 0;
+        for (int p = 0; p < kc && p < kRitz && ns < kBlk; ++p)
+            if (!conv[p]) sel[ns++] = p;
+        for (int p = kc; p < kRitz && ns < kBlk; ++p) sel[ns++] = p;
+        for (int p = 0; p < kc && p < kRitz && ns < kBlk; ++p)
+            if (conv[p]) sel[ns++] = p;
+        for (int e = 0; e < kRitz * kBlk; ++e) Z[e] = 0.0;
+        for (int t = 0; t < ns; ++t) {
+            const int p = sel[t];
+            if (r[p] > 1e-150 * dmax) Z[p * kBlk + t] = 1.0 / r[p];
+        }
+        *flag = ok;
     }
 }
 

@@ -34,7 +34,7 @@ EXPORTS = [
     "usbs_get_dual", "usbs_sketch_update_noalloc",
 ]
 PACK_PHASES = ["spmm", "tn", "nn", "ritz", "ipm", "constraints", "small", "shift", "all"]
-PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3}
+PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3, "update": 4}
 
 
 class UsbsProblem(ctypes.Structure):
@@ -185,7 +185,7 @@ class Params:
     units: str = "scaled"
     max_iters: int = 1000
     time_limit: float = 0.0
-    lanczos_steps: int = 4
+    lanczos_steps: int = 8
     lanczos_max_restarts: int = 10
     lanczos_tol: float = 1e-4
     lanczos_tol_final: float = 1e-9

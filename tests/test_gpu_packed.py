@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import sdp_inputs as si
+from certify import certify
 from oracle import usbs_oracle as orc
 
 pytestmark = pytest.mark.gpu
@@ -23,23 +24,13 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _certify(prob, out, tol=1e-3):
-    """FP64 re-evaluation of the packed result's certificate (scaled units)."""
-    sc = orc.scale_problem(prob)
-    y_s = out["y"] / sc.sigma
-    lam1 = orc.jacobi_eigh(sc.C - orc.A_adjoint(prob, orc.proj_Y(prob, y_s)))[0][0]
-    f_ref = 2.0 * max(lam1, 0.0) + float(sc.b @ orc.proj_Y(prob, y_s))
-    assert abs(f_ref - out["f_scaled"]) <= 1e-7 * (1 + abs(f_ref)), (f_ref, out["f_scaled"])
-    gap = abs(f_ref - out["primal_obj_scaled"]) / (1 + abs(out["primal_obj_scaled"]))
-    assert gap <= tol + 1e-9, gap
-    assert out["rel_infeas"] <= tol
-    return f_ref
-
-
 def _instances():
     """(name, problem, params kwargs, psi): MaxCut with sketch and k_p = 1 (the paper's
-    MaxCut setting at rho = 0.1), a planted +-1 graph in FP32 and a graph with isolated
-    vertices."""
+    MaxCut setting at rho = 0.1), a planted +-1 graph in FP32, a graph with isolated
+    vertices, the +-1 sparse graph of the n = 20,000 workload at n = 150 in FP32, and a
+    correlation-clustering instance of the n = 10,000 workload's shape at n = 97
+    (inequality rows on every edge, k_c = 3, k_p = 0).  The oracle reaches the 1e-3
+    criterion on the last two in 20 and 408 iterations."""
     out = []
     p = si.maxcut_er(120, 0.08, seed=7)
     out.append(("er120", p, dict(rho=0.1, max_iters=600), si.test_matrix(p.n, 10, seed=7)))
@@ -47,6 +38,10 @@ def _instances():
     out.append(("planted203", p, dict(rho=0.1, max_iters=600, precision="f32"), si.test_matrix(p.n, 10, seed=2)))
     p = si.maxcut_er(180, 0.025, seed=4)   # two isolated vertices
     out.append(("iso180", p, dict(rho=0.1, max_iters=600), si.test_matrix(p.n, 10, seed=4)))
+    p = si.maxcut_sparse_pm1(150, 6.0, seed=0)
+    out.append(("sparse150", p, dict(rho=0.1, max_iters=600, precision="f32"), si.test_matrix(p.n, 10, seed=0)))
+    p = si.cc_signed(97, avg_degree=10.0, seed=0)
+    out.append(("cc97", p, dict(rho=0.1, k_c=3, k_p=0, max_iters=800, precision="f32"), None))
     return out
 
 
@@ -74,13 +69,13 @@ def test_packed_certified_by_oracle(cuda):
     _say("packed solve of " + ", ".join(f"{nm} (n={p.n}, m={p.m})" for nm, p, _, _ in items))
     ss = _solvers(items)
     outs = solve_packed(ss, iters_per_launch=8)
-    for s in ss:
-        s.free()
-    for (nm, prob, kw, psi), out in zip(items, outs):
+    for (nm, prob, kw, psi), out, s in zip(items, outs, ss):
         _say(f"{nm}: iters {out['iters']} primal {out['primal_obj']:.6f} dual {out['dual_bound']:.6f} "
              f"gap {out['rel_gap']:.2e} inf {out['rel_infeas']:.2e}")
         assert out["converged"], (nm, out)
-        _certify(prob, out)
+        certify(prob, s, out, say=_say)
+    for s in ss:
+        s.free()
     # objective against the oracle's own solve of the first instance
     nm, prob, kw, psi = items[0]
     ref = orc.usbs_solve(prob, orc.Params(rho=0.1, max_iters=600), Psi=psi, keep_history=False)
@@ -90,31 +85,32 @@ def test_packed_certified_by_oracle(cuda):
 
 def test_packed_cc_planted_closed_form(cuda):
     """Correlation clustering (inequality rows on off-diagonal pairs, refreshed operator
-    values, alternating maximisation) packed with a MaxCut instance: f(y) is certified by
-    the oracle's Jacobi eigenvalues, weak duality f(y) >= p* holds against the closed form,
-    the primal objective is within 1e-2 of p* after 600 iterations (the oracle reaches the
-    same distance on this instance) and y_I >= 0."""
+    values, alternating maximisation) packed with a MaxCut instance: the result reaches the
+    1e-3 criterion and is certified by the oracle, weak duality f(y) >= p* holds against
+    the closed form, the objective is within 1e-3 of p* and y_I >= 0.  The bundle keeps
+    k_c = 6 eigenvectors: at k_c = 3 the method stalls on this instance (the oracle repeats
+    the same null step from about iteration 150 on, at relative gap 1.5e-3)."""
     from paper_2312_11801_amd import Params, Solver, solve_packed
     prob, pstar = _cc_planted()
     mc = _instances()[0]
     _say(f"packed cc (n={prob.n}, m={prob.m}) with {mc[0]}")
-    ss = [Solver(prob, Params(rho=0.1, k_c=3, k_p=0, max_iters=600)), Solver(mc[1], Params(**mc[2]), psi=mc[3])]
+    ss = [Solver(prob, Params(rho=0.1, k_c=6, k_p=0, max_iters=600)), Solver(mc[1], Params(**mc[2]), psi=mc[3])]
     outs = solve_packed(ss, iters_per_launch=10)
-    for x in ss:
-        x.free()
     out = outs[0]
     _say(f"cc: iters {out['iters']} primal {out['primal_obj']:.6f} dual {out['dual_bound']:.6f} p* {pstar:.6f} "
          f"gap {out['rel_gap']:.2e} inf {out['rel_infeas']:.2e}")
-    assert out["status_code"] >= 0
+    assert out["converged"], out
+    cert = certify(prob, ss[0], out, say=_say)
+    assert outs[1]["converged"]
+    certify(mc[1], ss[1], outs[1], say=_say)
+    for x in ss:
+        x.free()
     sc = orc.scale_problem(prob)
     y_s = out["y"] / sc.sigma
     assert np.all(y_s[prob.is_ineq.astype(bool)] >= 0)
-    lam1 = orc.jacobi_eigh(sc.C - orc.A_adjoint(prob, y_s))[0][0]
-    f_ref = 2.0 * max(lam1, 0.0) + float(sc.b @ y_s)
-    assert abs(f_ref - out["f_scaled"]) <= 1e-7 * (1 + abs(f_ref))
-    assert orc.to_original(sc, f_ref) >= pstar - 1e-9 * pstar
-    assert abs(out["primal_obj"] - pstar) / pstar <= 1e-2
-    assert outs[1]["converged"]
+    assert orc.to_original(sc, cert["f"]) >= pstar - 1e-9 * pstar
+    p_s = pstar / (sc.sigma * sc.tau_star)
+    assert abs(out["primal_obj_scaled"] - p_s) / (1 + p_s) <= 1e-3
 
 
 def test_packed_matches_per_instance_solve(cuda):
@@ -220,7 +216,7 @@ def test_packed_server_alone_equals_mix(cuda):
             _say(f"{q['id']} {part}: packed {a['primal_obj']:.6f} ({a['iters']} it, status {a['status']}), "
                  f"streams {b['primal_obj']:.6f} ({b['iters']} it, status {b['status']})")
             if a["status"] == 0 and b["status"] == 0:
-                assert abs(a["primal_obj"] - b["primal_obj"]) / (1 + abs(b["primal_obj"])) <= 2e-3
+                assert abs(a["primal_obj_scaled"] - b["primal_obj_scaled"]) / (1 + abs(b["primal_obj_scaled"])) <= 1e-3
 
 
 def test_packed_graph_replay_equals_eager(cuda):
@@ -256,13 +252,15 @@ def test_packed_bf16_planted_closed_form(cuda):
     psi = si.test_matrix(prob.n, 10, seed=5)
     s = Solver(prob, Params(rho=0.1, max_iters=600, precision="bf16"), psi=psi)
     out = solve_packed([s], iters_per_launch=8)[0]
-    s.free()
     _say(f"bf16 planted: iters {out['iters']} primal {out['primal_obj']:.6f} dual {out['dual_bound']:.6f} "
          f"p* {prob.meta['p_star']}")
     assert out["converged"], out
-    _certify(prob, out)
+    certify(prob, s, out, say=_say)
+    s.free()
     assert out["dual_bound"] >= prob.meta["p_star"] * (1 - 1e-9)
-    assert abs(out["primal_obj"] - prob.meta["p_star"]) / prob.meta["p_star"] <= 2e-3
+    sc = orc.scale_problem(prob)
+    p_s = prob.meta["p_star"] / (sc.sigma * sc.tau_star)
+    assert abs(out["primal_obj_scaled"] - p_s) / (1 + p_s) <= 1e-3
 
 
 def test_packed_server_admission_by_footprint(cuda):
