@@ -1,16 +1,22 @@
 """Benchmark of the USBS hot path on one MI355X.
 
-Workload (default): MaxCut SDP on a random sparse graph, n = 20,000, exactly 60,000 distinct
-uniform random edges (average degree 6), Rademacher +-1 weights, FP32 values in the sparse
-products with FP64 Lanczos re-orthogonalisation / Ritz problems / master QP, Lanczos block
-width 8, sketch rank r = 10; synthetic seeded data (the paper's DIMACS10 graphs are absent).
+Workload (default, the headline): MaxCut SDP on a random 4-regular graph, n = 10^6 vertices
+(pairing model with repair), unit weights, with the paper's FP64 arithmetic everywhere
+(sparse products, Lanczos re-orthogonalisation, Ritz problems, master QP), Lanczos block
+width 8, sketch rank r = 10, X never formed; synthetic seeded data (the paper's DIMACS10
+graphs are absent).  `--precision bf16` gives the mixed-precision form; `--workload c2`
+the n = 20,000 +-1 graph, `c4` correlation clustering, `served` the request loop,
+`sweep` the bundle-size experiment.
 
 A "step" is one iteration of Alg. 1, i.e. one pass over every row of the hot path:
 QP assembly and interior point solve, candidate, shifted operator, block Lanczos on
 C - A^* y~, descent test, model update, sketch update and A(.) on low-rank factors.
 `value` = USBS iterations per second over exactly K timed steps (inputs resident in HBM).
-Also reported: time to the paper's 1e-3 criterion from a cold start, the roofline of the
-dominant kernel measured live with HIP events, and the FP64 CPU oracle on a bounded sample.
+Also reported: the time to the paper's 1e-3 criterion from a cold start in both unit
+systems, the same figures for the BF16 form, the roofline of the dominant kernel measured
+live with HIP events on the solver's stream, and the FP64 CPU oracle on a bounded sample
+of the n = 800 MaxCut workload (the largest the dense oracle runs) beside the GPU's rate on
+that same instance, plus the oracle's certificate evaluator timed on the headline result.
 """
 from __future__ import annotations
 
@@ -40,8 +46,23 @@ def reorth_bytes(n: int, cols: int, nb: int) -> float:
     return n * (cols + nb) * 8
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tn_mfma_reorth_c2_traffic.txt")
-# the roofline kernel: its launcher (kernels.hip) and its body (wg_steps.h)
+def update_bytes(n: int, cols: int, nb: int) -> float:
+    """Algorithmic bytes of one fused Gram-Schmidt update + reduction (k_nn_tn_mfma): the
+    basis slice (n x cols) and the block W (n x nb) read once, the new block (n x nb)
+    written once, all FP64 (the second pass's [Q W']^T W' reads both from LDS)."""
+    return n * (cols + 2 * nb) * 8
+
+
+# roofline kernel per workload: (profile category, bytes per launch given n and the basis
+# width cols of the block step, counter summary file)
+ROOFLINE = {
+    "update": ("k_nn_tn_mfma (first Gram-Schmidt update of a Krylov block fused with the second pass's "
+               "[Q W]^T W reduction, FP64 MFMA)", update_bytes),
+    "reorth": ("k_tn_mfma<1, UNR, true> (first pass's [Q W]^T W reduction of a Krylov block, FP64 MFMA)",
+               reorth_bytes),
+}
+# the roofline kernel's launcher (kernels.hip) and body (wg_steps.h): counter summaries are
+# valid only for the source they were taken on
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2312_11801_amd", "csrc", f) for f in ("kernels.hip", "wg_steps.h")]
 
 
@@ -53,13 +74,13 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def measured_traffic() -> float | None:
-    """HBM bytes per launch of the roofline kernel from the committed counter summary
+def measured_traffic(path: str) -> float | None:
+    """HBM bytes per launch of the roofline kernel from a committed counter summary
     (rocprofv3 FETCH_SIZE / WRITE_SIZE, calibrated on a plain copy), or None when the
     kernel source (launcher and body) has changed since the counters were taken."""
     try:
         kv = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             if ":" in line and not line.startswith("#"):
                 key, val = line.split(":", 1)
                 kv[key.strip()] = val.strip()
@@ -70,36 +91,99 @@ def measured_traffic() -> float | None:
         return None
 
 
-def run_cpu_baseline(seconds: float = 20.0) -> dict:
-    """The FP64 oracle (dense Jacobi eigendecomposition, unreduced IPM Newton systems) on a
-    bounded sample: iterations of Alg. 1 on an instance of the same generator family at
-    n = 400 for about `seconds` seconds; the rate is scaled to n = 20,000 by the oracle's
-    n^3 per-iteration cost (dense eigendecomposition dominates)."""
-    import numpy as np
+def host_info() -> dict:
+    """Host cores this process may use, the CPU model and the BLAS threads numpy uses."""
+    info = {"nproc": len(os.sched_getaffinity(0)), "cpu_model": None, "blas_threads": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        import threadpoolctl
+        pools = threadpoolctl.threadpool_info()
+        info["blas_threads"] = max((p.get("num_threads", 0) for p in pools if p.get("user_api") == "blas"),
+                                   default=None)
+    except Exception:
+        pass
+    return info
+
+
+def c1_problem():
+    """The n = 800 MaxCut workload: G(n = 800, p = 0.02), unit weights, C = L/4, r = 10."""
     import sdp_inputs as si
+    return si.maxcut_er(800, 0.02, seed=0), si.test_matrix(800, 10, seed=0)
+
+
+def run_cpu_baseline(seconds: float = 20.0) -> dict:
+    """The FP64 oracle as it stands (dense Jacobi eigendecompositions, unreduced IPM Newton
+    systems) on a bounded sample: its cold start and then iterations of Alg. 1 on the
+    n = 800 MaxCut workload until about `seconds` seconds have passed.  The headline
+    workload (n = 10^6) cannot be held by a dense oracle at all (X is n x n), so the
+    sample is the largest configuration it runs; the GPU's rate on the same instance is
+    reported beside it."""
+    import numpy as np
     from oracle import usbs_oracle as orc
-    n_s = 400
-    prob = si.maxcut_sparse_pm1(n_s, 6.0, seed=0)
-    psi = si.test_matrix(n_s, 10, seed=0).astype(np.float64)
+    prob, psi = c1_problem()
     prm = orc.Params(rho=0.01)
     sc = orc.scale_problem(prob)
     t0 = time.time()
-    st = orc.cold_start(sc, prm, psi)
+    st = orc.cold_start(sc, prm, psi.astype(np.float64))
     t1 = time.time()
     it = 0
-    while time.time() - t1 < seconds or it < 2:
-        orc.usbs_step(sc, prm, st, psi)
+    while time.time() - t1 < seconds or it < 1:
+        orc.usbs_step(sc, prm, st, psi.astype(np.float64))
         it += 1
     dt = time.time() - t1
-    rate = it / dt
-    scaled = rate * (n_s / 20000.0) ** 3
-    threads = os.environ.get("OMP_NUM_THREADS", "1")
-    return {"value": scaled, "unit": "iterations/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{it} oracle iterations of Alg. 1 on the same generator at n={n_s} "
-                      f"(deg 6, +-1 weights) in {dt:.1f} s = {rate:.3f} it/s; cold start {t1 - t0:.1f} s; "
-                      f"scaled by (n_s/20000)^3 for the dense-Jacobi cost; single-threaded Jacobi "
-                      f"(OMP_NUM_THREADS={threads} seen by numpy)"}
+    hi = host_info()
+    return {"value": it / dt, "unit": "iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle on the n=800 MaxCut workload (G(800, 0.02), unit weights): cold start "
+                      f"{t1 - t0:.1f} s, then {it} iterations of Alg. 1 in {dt:.1f} s; its Jacobi "
+                      f"eigendecompositions run on one core (BLAS steps on up to {hi['blas_threads']} threads); "
+                      f"host: {hi['nproc']} cores available, {hi['cpu_model']}",
+            "host": hi}
+
+
+def gpu_rate_c1(stream, steps: int = 20) -> dict:
+    """The GPU's iterations/s and time to the criterion on the same n = 800 instance, FP64."""
+    import torch
+    from paper_2312_11801_amd import Params, Solver
+    prob, psi = c1_problem()
+    prm = Params(precision="f64", rho=0.01, max_iters=3000, time_limit=20.0, lanczos_max_restarts=3)
+    s = Solver(prob, prm, psi=psi, stream=stream)
+    s.step_iterate(3, 11)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_iterate(steps, 11)
+    torch.cuda.synchronize()
+    rate = steps / (time.perf_counter() - t0)
+    s.free()
+    s = Solver(prob, prm, psi=psi, stream=stream)
+    out = s.solve(want_y=False, want_factors=False)
+    s.free()
+    return {"iterations_per_s": rate, "time_to_gap_s": out["seconds"], "iters": out["iters"],
+            "converged": out["converged"], "rel_gap": out["rel_gap"], "rel_infeas": out["rel_infeas"]}
+
+
+def run_certificate(prob, solver, out, lanczos_steps: int) -> dict:
+    """The oracle's certificate evaluator on a GPU result, timed on the host: f(y) from its
+    Lanczos on the sparse matrix, the relative errors of X_{t+1} from the values the library
+    exports, and <C, Xhat>, A(Xhat) of the Nystrom factors."""
+    import numpy as np
+    from oracle import usbs_oracle as orc
+    t0 = time.time()
+    sigma, _ = solver.scaling()
+    y_s = np.asarray(out["y"]) / sigma
+    pr = solver.primal()
+    lam = orc.lambda_max_sparse(prob, orc.proj_Y(prob, y_s), steps=lanczos_steps)
+    cert = orc.certificate(prob, y_s, pr["AX"], pr["cX"], lam_max=lam, dense=False)
+    cx_hat, inf_hat = orc.sketch_certificate(prob, out["U"], out["lam"]) if out.get("U") is not None else (None, None)
+    dt = time.time() - t0
+    return {"seconds": dt, "lanczos_steps": lanczos_steps, "f_oracle": cert["f"], "f_gpu": out["f_scaled"],
+            "rel_gap": cert["rel_gap"], "rel_infeas": cert["rel_infeas"], "sketch_primal_obj": cx_hat,
+            "sketch_rel_infeas": inf_hat}
 
 
 def measured_copy_peak(stream) -> float:
@@ -198,28 +282,99 @@ def run_served(args) -> dict:
     return out
 
 
-def run_sweep(args) -> dict:
-    """k_c / k_p sweep (the paper's experiment on the bundle size, on the c2 graph): for each
-    (k_c, k_p), a cold solve to the 1e-3 criterion; time, iterations, objective, dual bound and
-    both relative errors, so that objective and infeasibility can be read against time."""
-    import sdp_inputs as si
-    from paper_2312_11801_amd import Params, Solver
-    prob = si.maxcut_sparse_pm1(args.n, 6.0, seed=0)
-    psi = si.test_matrix(args.n, 10, seed=0)
+def trace_solve(prob, psi, prm, kk: int, stream, limit_s: float, max_iters: int) -> dict:
+    """A cold solve one iteration of Alg. 1 at a time (usbs_step_iterate), logging after
+    each the wall time since the start, f(y_t), <C, X_{t+1}> (original units) and both
+    relative errors of Sec. 5 (units as in prm); stops at the criterion (both <= eps),
+    the iteration cap or the time limit.  The solver's own stopping test is not used, so
+    the curve ends at the first iteration that meets the criterion."""
+    import torch
+    from paper_2312_11801_amd import Solver
+    t0 = time.perf_counter()
+    s = Solver(prob, prm, psi=psi, stream=stream)
+    sigma, trace = s.scaling()
     rows = []
-    for kc, kp in [(2, 0), (5, 0), (10, 0), (2, 1), (5, 1), (10, 1), (5, 2), (8, 2)]:
-        prm = Params(precision=args.precision, rho=args.rho, max_iters=3000, time_limit=60.0, k_c=kc, k_p=kp,
-                     lanczos_max_restarts=args.lanczos_max_restarts if args.lanczos_max_restarts is not None else 3)
-        s = Solver(prob, prm, psi=psi)
-        out = s.solve(want_y=False, want_factors=False)
-        s.free()
-        rows.append({"k_c": kc, "k_p": kp, "seconds": out["seconds"], "iters": out["iters"],
-                     "converged": out["converged"], "primal_obj": out["primal_obj"], "dual_bound": out["dual_bound"],
-                     "rel_gap": out["rel_gap"], "rel_infeas": out["rel_infeas"],
-                     "iters_per_s": out["iters"] / max(out["seconds"], 1e-9)})
-        print(f"[sweep] k_c={kc} k_p={kp}: {out['seconds']:.2f} s, {out['iters']} iterations, "
-              f"converged={out['converged']}", file=sys.stderr, flush=True)
-    return {"rows": rows}
+    for it in range(1, max_iters + 1):
+        st = s.step_iterate(1, kk, light=True)
+        el = time.perf_counter() - t0
+        rows.append((round(el, 4), it, sigma * trace * st["f"], sigma * trace * st["primal"], st["rel_gap"],
+                     st["rel_infeas"]))
+        if (st["rel_gap"] <= prm.eps_gap and st["rel_infeas"] <= prm.eps_infeas) or el > limit_s:
+            break
+    s.free()
+    torch.cuda.synchronize()
+    done = rows[-1][4] <= prm.eps_gap and rows[-1][5] <= prm.eps_infeas
+    return {"seconds": rows[-1][0], "iters": rows[-1][1], "converged": bool(done), "rel_gap": rows[-1][4],
+            "rel_infeas": rows[-1][5], "dual_bound": rows[-1][2], "primal_obj": rows[-1][3],
+            "curve": [list(r) for r in rows]}
+
+
+def oracle_trace(prob, psi, kc: int, kp: int, limit_s: float) -> dict:
+    """The same curve from the FP64 oracle (dense X, Jacobi eigendecompositions) on the
+    host: cold start, then iterations until the criterion or the time limit."""
+    import numpy as np
+    from oracle import usbs_oracle as orc
+    prm = orc.Params(rho=0.01, k_c=kc, k_p=kp)
+    sc = orc.scale_problem(prob)
+    t0 = time.perf_counter()
+    st = orc.cold_start(sc, prm, np.asarray(psi, dtype=np.float64))
+    rows = []
+    it = 0
+    while True:
+        it += 1
+        rec = orc.usbs_step(sc, prm, st, np.asarray(psi, dtype=np.float64))
+        el = time.perf_counter() - t0
+        rows.append((round(el, 3), it, orc.to_original(sc, rec["f"]), orc.to_original(sc, rec["primal"]),
+                     rec["rel_gap"], rec["rel_infeas"]))
+        if (rec["rel_gap"] <= 1e-3 and rec["rel_infeas"] <= 1e-3) or el > limit_s:
+            break
+    return {"seconds": rows[-1][0], "iters": it, "converged": rows[-1][4] <= 1e-3 and rows[-1][5] <= 1e-3,
+            "rel_gap": rows[-1][4], "rel_infeas": rows[-1][5], "curve": [list(r) for r in rows]}
+
+
+def run_sweep(args) -> dict:
+    """Bundle-size experiment (the paper's k_c / k_p study, App. F): for each (k_c, k_p) a
+    cold solve logged iteration by iteration, so that the relative gap and infeasibility
+    (and f(y), <C, X>) can be read against time.  Workloads: the n = 2e4 +-1 graph (FP32
+    products), the n = 1e6 4-regular graph (FP64) and the n = 800 ER graph, on which the
+    FP64 CPU oracle runs beside the GPU.  k_c + k_p <= 12 (the device interior point
+    method's limit), so the grid stops there."""
+    import torch
+    import sdp_inputs as si
+    from paper_2312_11801_amd import Params
+    stream = torch.cuda.current_stream().cuda_stream
+    grid = [(2, 0), (4, 0), (8, 0), (10, 0), (8, 1), (8, 2), (8, 4), (10, 1), (10, 2)]
+    out = {"grid": grid, "workloads": {}}
+    wl = [w.strip() for w in args.sweep_workloads.split(",") if w.strip()]
+    for name in wl:
+        if name == "c2":
+            prob, psi, prec = si.maxcut_sparse_pm1(20000, 6.0, seed=0), si.test_matrix(20000, 10, seed=0), "f32"
+        elif name == "c5":
+            prob, psi, prec = si.maxcut_regular(1_000_000, 4, seed=0), si.test_matrix(1_000_000, 10, seed=0), "f64"
+        else:
+            prob, psi, prec = si.maxcut_er(800, 0.02, seed=0), si.test_matrix(800, 10, seed=0), "f64"
+        rows = []
+        for kc, kp in grid:
+            prm = Params(precision=prec, rho=args.rho, max_iters=100000, k_c=kc, k_p=kp,
+                         lanczos_max_restarts=args.lanczos_max_restarts if args.lanczos_max_restarts is not None else 1)
+            r = trace_solve(prob, psi, prm, kc + kp, stream, args.sweep_limit, 100000)
+            r.update({"k_c": kc, "k_p": kp})
+            rows.append(r)
+            print(f"[sweep] {name} k_c={kc} k_p={kp}: {r['seconds']:.2f} s, {r['iters']} iterations, "
+                  f"gap {r['rel_gap']:.2e} infeas {r['rel_infeas']:.2e}, converged={r['converged']}",
+                  file=sys.stderr, flush=True)
+        entry = {"precision": prec, "n": prob.n, "rows": rows}
+        if name == "c1" and not args.no_cpu:
+            orows = []
+            for kc, kp in args.sweep_oracle_grid:
+                r = oracle_trace(prob, psi, kc, kp, args.sweep_oracle_limit)
+                r.update({"k_c": kc, "k_p": kp})
+                orows.append(r)
+                print(f"[sweep] {name} oracle k_c={kc} k_p={kp}: {r['seconds']:.1f} s, {r['iters']} iterations, "
+                      f"gap {r['rel_gap']:.2e} infeas {r['rel_infeas']:.2e}", file=sys.stderr, flush=True)
+            entry["oracle_rows"] = orows
+        out["workloads"][name] = entry
+    return out
 
 
 def main() -> int:
@@ -229,13 +384,23 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=20000)
     ap.add_argument("--rho", type=float, default=0.01)
-    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--precision", default=None, choices=["f64", "f32", "bf16"],
+                    help="arithmetic of the sparse products (default: f64 for c5, f32 for c2 / c4)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttg", action="store_true", help="skip the time-to-gap solve")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "served", "sweep"],
-                    help="c2: MaxCut n=20000 (default line); c4: correlation clustering n=10000; "
-                         "c5: MaxCut on a random 4-regular graph, n=1e6, BF16 products; served: the request loop")
+    ap.add_argument("--no-bf16", action="store_true", help="c5: skip the BF16 form")
+    ap.add_argument("--sweep-workloads", default="c2,c5,c1", help="sweep: workloads (c2, c5, c1)")
+    ap.add_argument("--sweep-limit", type=float, default=20.0, help="sweep: time limit per GPU solve (s)")
+    ap.add_argument("--sweep-oracle-limit", type=float, default=60.0,
+                    help="sweep: time limit per oracle solve on c1 (s)")
+    ap.add_argument("--original-limit", type=float, default=30.0,
+                    help="time limit of the solve judged in original units (seconds)")
+    ap.add_argument("--roofline", default="update", choices=sorted(ROOFLINE),
+                    help="kernel timed live for the roofline figure")
+    ap.add_argument("--workload", default="c5", choices=["c2", "c4", "c5", "served", "sweep"],
+                    help="c5 (default): MaxCut on a random 4-regular graph, n=1e6; c2: MaxCut n=20000 +-1 graph; "
+                         "c4: correlation clustering n=10000; served: the request loop; sweep: bundle sizes")
     ap.add_argument("--requests", type=int, default=256)
     ap.add_argument("--slots", type=int, default=0, help="served: instances at once (0: 256 packed, 4 streams)")
     ap.add_argument("--serve-mode", default="packed", choices=["packed", "streams"])
@@ -246,14 +411,16 @@ def main() -> int:
     ap.add_argument("--served-max-iters", type=int, default=500,
                     help="iteration cap of every served solve (both forms)")
     ap.add_argument("--lanczos-max-restarts", type=int, default=None,
-                    help="restart cap of the in-iteration eigen-solve (default: 3 for the MaxCut workloads, "
-                         "10 = the paper's for c4)")
+                    help="restart cap of the in-iteration eigen-solve (default: 1 for the MaxCut workloads c2 / c5, "
+                         "3 for c4 and the served batch)")
     ap.add_argument("--autotune", type=int, default=1, choices=(0, 1, 2),
                     help="launch-shape tuner: 0 off, 1 shapes with bitwise-identical results (default), "
                          "2 also the partition of the matrix-core reductions (changes rounding)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (counter calibration for HBM traffic)")
     args = ap.parse_args()
+    if args.workload in ("served", "sweep") and args.precision is None:
+        args.precision = "f32"
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is a design "
                                    "note (row partition of C, halo exchange per block product)"}))
@@ -274,11 +441,12 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     if args.workload == "sweep":
+        args.sweep_oracle_grid = [(10, 1), (8, 0), (2, 0)]
         res = run_sweep(args)
-        print(json.dumps({"metric": "k_c / k_p sweep: time to the 1e-3 criterion (MaxCut SDP, c2 graph)",
-                          "unit": "s", "n_gpus": 1, "dtype": args.precision, "data": "synthetic",
-                          "config": {"workload": f"maxcut_sparse_pm1 n={args.n} avg_degree=6 weights=+-1",
-                                     "rho": args.rho}, **res}))
+        print(json.dumps({"metric": "k_c / k_p sweep: relative gap and infeasibility against time (MaxCut SDPs)",
+                          "unit": "s", "n_gpus": 1, "data": "synthetic",
+                          "config": {"workload": args.sweep_workloads, "rho": args.rho,
+                                     "time_limit_s": args.sweep_limit}, **res}))
         return 0
     if args.workload == "served":
         res = run_served(args)
@@ -310,29 +478,52 @@ def main() -> int:
         n = 1_000_000
         prob = si.maxcut_regular(n, 4, seed=0)
         kc, kp = 10, 1
-        if args.precision == "f32":
-            args.precision = "bf16"
         workload = "maxcut_regular n=1000000 degree=4 unit weights, X never formed (n x 10 sketch)"
-        metric = "USBS iterations/sec (MaxCut SDP, n=1e6 random 4-regular graph)"
+        metric = ("USBS iterations/sec (MaxCut SDP, n=1e6 random 4-regular graph); time-to-1e-3 rel gap; "
+                  "roofline of the dominant kernel")
+    precision = args.precision or ("f32" if args.workload in ("c2", "c4") else "f64")
     psi = si.test_matrix(n, 10, seed=0)
-    val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[args.precision]
+    val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[precision]
     nnz_off = prob.nnz - n
-    maxr = args.lanczos_max_restarts if args.lanczos_max_restarts is not None else (10 if args.workload == "c4" else 3)
-    prm = Params(precision=args.precision, rho=args.rho, max_iters=100000, k_c=kc, k_p=kp, lanczos_max_restarts=maxr,
-                 autotune=args.autotune)
+    maxr = args.lanczos_max_restarts if args.lanczos_max_restarts is not None else (3 if args.workload == "c4" else 1)
+
+    def params(prec, **kw):
+        return Params(precision=prec, rho=args.rho, k_c=kc, k_p=kp, lanczos_max_restarts=maxr,
+                      autotune=args.autotune, **kw)
+
+    def throughput(prec, steps, warmup, roof_cat=None):
+        """iterations/s over `steps` timed iterations; the roofline kernel's dispatches are
+        timed live (HIP events attached to each dispatch on the solver's stream)."""
+        s = Solver(prob, params(prec, max_iters=100000), psi=psi, stream=stream)
+        s.step_iterate(warmup, kc + kp)
+        s.profile(roof_cat, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.step_iterate(steps, kc + kp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        roof = s.profile(None, reset=True)
+        return s, st, t1 - t0, roof
+
+    def time_to_gap(prec, units, limit, factors=False):
+        s = Solver(prob, params(prec, max_iters=100000, time_limit=limit, units=units), psi=psi, stream=stream)
+        out = s.solve(want_y=factors, want_factors=factors)
+        res = {"units": units, "seconds": out["seconds"], "iters": out["iters"], "converged": out["converged"],
+               "time_limit_s": limit, "rel_gap": out["rel_gap"], "rel_infeas": out["rel_infeas"],
+               "rel_gap_scaled": out["rel_gap_scaled"], "rel_infeas_scaled": out["rel_infeas_scaled"],
+               "rel_gap_original": out["rel_gap_original"], "rel_infeas_original": out["rel_infeas_original"],
+               "primal_obj": out["primal_obj"], "dual_bound": out["dual_bound"], "descents": out["descents"],
+               "lanczos_matvecs": out["lanczos_matvecs"]}
+        return s, out, res
 
     # ---- throughput: K timed iterations of Alg. 1 ----
-    s = Solver(prob, prm, psi=psi, stream=stream)
-    s.step_iterate(args.warmup, kc + kp)
-    s.profile("reorth", reset=True)       # time the roofline kernel live (HIP events)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = s.step_iterate(args.steps, kc + kp)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    reorth_ms, reorth_launches = s.profile("spmm", reset=True)
+    roof_cat = args.roofline
+    s, st, elapsed, (roof_ms, roof_launches) = throughput(precision, args.steps, args.warmup, roof_cat)
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = args.steps / elapsed
     # two more short stretches for secondary figures: the SpMM and the Ritz eigenproblem
     extra = max(2, args.steps // 4)
+    s.profile("spmm", reset=True)
     s.step_iterate(extra, kc + kp)
     spmm_ms, spmm_launches = s.profile("ritz", reset=True)
     torch.cuda.synchronize()
@@ -341,37 +532,46 @@ def main() -> int:
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     ritz_ms, ritz_launches = s.profile(None, reset=True)
+    steps_per_cycle = Params().lanczos_steps
     s.free()
-    elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = args.steps / elapsed
 
-    # ---- time to the paper's 1e-3 criterion from a cold start ----
+    # ---- time to the paper's 1e-3 criterion from a cold start, both unit systems ----
     ttg = None
+    cert = None
     if not args.no_ttg:
-        s2 = Solver(prob, Params(precision=args.precision, rho=args.rho, max_iters=3000, time_limit=120.0,
-                                 k_c=kc, k_p=kp, lanczos_max_restarts=maxr, autotune=args.autotune),
-                    psi=psi, stream=stream)
-        out = s2.solve(want_y=False)
+        s2, out2, ttg_s = time_to_gap(precision, "scaled", 120.0, factors=True)
+        if not args.no_cpu and args.workload == "c5" and out2["converged"]:
+            cert = run_certificate(prob, s2, out2, lanczos_steps=120)
         s2.free()
-        ttg = {"seconds": out["seconds"], "iters": out["iters"], "converged": out["converged"],
-               "rel_gap": out["rel_gap"], "rel_infeas": out["rel_infeas"], "primal_obj": out["primal_obj"],
-               "dual_bound": out["dual_bound"], "lanczos_matvecs": out["lanczos_matvecs"]}
+        s3, _, ttg_o = time_to_gap(precision, "original", args.original_limit)
+        s3.free()
+        ttg = {"scaled": ttg_s, "original": ttg_o}
 
-    # ---- roofline of the dominant bandwidth kernel (first stage of the re-orthogonalisation
-    # reductions, k_tn_mfma<1, UNR, true>) ----
-    # algorithmic bytes per launch averaged over the basis widths of a restart cycle
-    # (block j of 8 reduces [Q W] with Q the first 16 + 8 (j + 1) columns, j = 0..s-1)
-    widths = [16 + 8 * (j + 1) for j in range(prm.lanczos_steps)]
-    bytes_per_reorth = float(np.mean([reorth_bytes(n, c, 8) for c in widths]))
-    avg_reorth_s = (reorth_ms / 1e3) / max(reorth_launches, 1)
-    achieved = bytes_per_reorth / avg_reorth_s / 1e9 if reorth_launches else None
+    # ---- the BF16 form beside the headline (products in BF16 values, FP32 accumulation) ----
+    bf16 = None
+    if args.workload == "c5" and precision == "f64" and not args.no_bf16:
+        sb, stb, eb, _ = throughput("bf16", args.steps, args.warmup)
+        sb.free()
+        bf16 = {"iterations_per_s": args.steps / eb, "ms_per_step": 1e3 * eb / args.steps}
+        if not args.no_ttg:
+            sb2, _, r = time_to_gap("bf16", "scaled", 120.0)
+            sb2.free()
+            bf16["time_to_gap_scaled"] = r
+
+    # ---- roofline of the dominant kernel ----
+    label, bfun = ROOFLINE[roof_cat]
+    widths = [16 + 8 * (j + 1) for j in range(steps_per_cycle)]
+    bytes_per_launch = float(np.mean([bfun(n, c, 8) for c in widths]))
+    avg_s = (roof_ms / 1e3) / max(roof_launches, 1)
+    achieved = bytes_per_launch / avg_s / 1e9 if roof_launches else None
     avg_spmm_s = (spmm_ms / 1e3) / max(spmm_launches, 1)
     spmm_gbs = spmm_bytes(n, nnz_off, 8, val_bytes) / avg_spmm_s / 1e9 if spmm_launches else None
+    traffic_file = os.path.join(ROOT, "profiles", f"{'k_nn_tn_mfma' if roof_cat == 'update' else 'k_tn_mfma'}"
+                                f"_{args.workload}_{precision}_traffic.txt")
 
     # the Rayleigh-Ritz eigenproblem: Householder tridiagonalisation (4/3 N^3), 16 eigenvectors
     # by inverse iteration and back-transformation (~ 2 * 16 * 2 N^2)
-    nb = 16 + 8 * prm.lanczos_steps
+    nb = 16 + 8 * steps_per_cycle
     ritz_us = 1e3 * ritz_ms / max(ritz_launches, 1)
     ritz_flops = 4.0 / 3.0 * nb ** 3 + 64.0 * nb ** 2
     line = {
@@ -385,28 +585,25 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 SpMM values / f64 Lanczos, Ritz, QP" if args.precision == "f32" else args.precision,
-        "data": "synthetic (seeded random sparse graph standing in for DIMACS10)",
-        "config": {"workload": workload,
-                   "rho": args.rho, "k_c": kc, "k_p": kp, "lanczos_steps": prm.lanczos_steps,
-                   "lanczos_max_restarts": prm.lanczos_max_restarts, "precision": args.precision,
+        "dtype": {"f64": "f64", "f32": "f32 SpMM values / f64 Lanczos, Ritz, QP",
+                  "bf16": "bf16 SpMM values, f32 accumulation / f64 Lanczos, Ritz, QP"}[precision],
+        "data": "synthetic (seeded random graph standing in for DIMACS10)",
+        "config": {"workload": workload, "rho": args.rho, "k_c": kc, "k_p": kp,
+                   "lanczos_steps": steps_per_cycle, "lanczos_max_restarts": maxr, "precision": precision,
                    "autotune": args.autotune},
         "time_to_gap": ttg,
         "roofline": {
-            "bound": "hbm", "kernel": "k_tn_mfma<1, UNR, true> (first stage of [Q W]^T W in the Krylov re-orthogonalisation, FP64 MFMA)",
+            "bound": "hbm", "kernel": label,
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": measured_traffic() if (args.workload == "c2" and n == 20000 and args.precision == "f32"
-                                              and args.autotune != 2) else None,
-            "avg_launch_us": avg_reorth_s * 1e6, "launches": reorth_launches,
-            "bytes_per_launch": bytes_per_reorth,
+            "traffic": measured_traffic(traffic_file) if args.autotune != 2 else None,
+            "avg_launch_us": avg_s * 1e6, "launches": roof_launches,
+            "bytes_per_launch": bytes_per_launch,
             "measured_copy_GBs": copy_peak,
             "frac_of_measured_copy": (achieved / copy_peak) if (achieved and copy_peak) else None,
         },
         "spmm": {"avg_launch_us": avg_spmm_s * 1e6, "achieved_GBs": spmm_gbs, "launches": spmm_launches,
                  "bytes_per_launch": spmm_bytes(n, nnz_off, 8, val_bytes)},
-        # the largest single share of kernel time: the one-workgroup Rayleigh-Ritz eigensolver
-        # (latency-bound: one CU, a few hundred dependent Householder / bisection steps)
         "ritz": {"kernel": f"k_small_eig ({nb} x {nb} projected eigenproblem)", "bound": "latency (one workgroup)",
                  "avg_launch_us": ritz_us, "launches": ritz_launches,
                  "flops_per_launch": ritz_flops, "achieved_GFLOPs": ritz_flops / max(ritz_us, 1e-9) / 1e3,
@@ -414,8 +611,13 @@ def main() -> int:
                  "share_of_step_time": (ritz_ms / 1e3) / max(t3 - t2, 1e-12)},
         "final_state": {"f": st["f"], "rel_gap": st["rel_gap"], "rel_infeas": st["rel_infeas"]},
     }
-    if not args.no_cpu and args.workload == "c2":
+    if bf16 is not None:
+        line["bf16_form"] = bf16
+    if cert is not None:
+        line["oracle_certificate"] = cert
+    if not args.no_cpu:
         line["cpu_baseline"] = run_cpu_baseline(args.cpu_seconds)
+        line["cpu_baseline"]["gpu_same_instance"] = gpu_rate_c1(stream)
     # the paper's own headline figure, quoted with the hardware it states (context only: another
     # baseline solver, another instance, another tolerance)
     line["paper_reference"] = {

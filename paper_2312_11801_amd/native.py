@@ -343,15 +343,19 @@ class Solver:
         self._check(self.lib.usbs_op_nystrom(self.h, _ptr(P_dev), _ptr(U_dev), _ptr(lam)))
         return lam
 
-    def step_iterate(self, t: int, k: int):
+    def step_iterate(self, t: int, k: int, light: bool = False):
+        """t iterations of Alg. 1; returns the scalars and (unless light) y, V, zbar, P."""
+        keys = ["f", "tau", "cbar", "primal", "rel_gap", "rel_infeas", "lambda1", "descents"]
+        scal = np.zeros(8)
+        if light:
+            self._check(self.lib.usbs_step_iterate(self.h, t, None, None, None, None, _ptr(scal)))
+            return dict(zip(keys, scal))
         y = np.zeros(self.m)
         V = np.zeros((self.n, 16))
         zbar = np.zeros(self.m)
         P = np.zeros((self.n, max(self.r, 1)))
-        scal = np.zeros(8)
         self._check(self.lib.usbs_step_iterate(self.h, t, _ptr(y), _ptr(V), _ptr(zbar),
                                                _ptr(P) if self.r else None, _ptr(scal)))
-        keys = ["f", "tau", "cbar", "primal", "rel_gap", "rel_infeas", "lambda1", "descents"]
         return {"y": y, "V": V[:, :k], "zbar": zbar, "P": P[:, :self.r], **dict(zip(keys, scal))}
 
     def primal(self) -> dict:
