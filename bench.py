@@ -324,12 +324,13 @@ def oracle_trace(prob, psi, kc: int, kp: int, limit_s: float) -> dict:
         it += 1
         rec = orc.usbs_step(sc, prm, st, np.asarray(psi, dtype=np.float64))
         el = time.perf_counter() - t0
-        rows.append((round(el, 3), it, orc.to_original(sc, rec["f"]), orc.to_original(sc, rec["primal"]),
-                     rec["rel_gap"], rec["rel_infeas"]))
+        rows.append((round(el, 3), it, float(orc.to_original(sc, rec["f"])), float(orc.to_original(sc, rec["primal"])),
+                     float(rec["rel_gap"]), float(rec["rel_infeas"])))
         if (rec["rel_gap"] <= 1e-3 and rec["rel_infeas"] <= 1e-3) or el > limit_s:
             break
-    return {"seconds": rows[-1][0], "iters": it, "converged": rows[-1][4] <= 1e-3 and rows[-1][5] <= 1e-3,
-            "rel_gap": rows[-1][4], "rel_infeas": rows[-1][5], "curve": [list(r) for r in rows]}
+    return {"seconds": rows[-1][0], "iters": it, "converged": bool(rows[-1][4] <= 1e-3 and rows[-1][5] <= 1e-3),
+            "rel_gap": float(rows[-1][4]), "rel_infeas": float(rows[-1][5]),
+            "curve": [[float(v) for v in r] for r in rows]}
 
 
 def run_sweep(args) -> dict:
@@ -392,7 +393,7 @@ def main() -> int:
     ap.add_argument("--no-bf16", action="store_true", help="c5: skip the BF16 form")
     ap.add_argument("--sweep-workloads", default="c2,c5,c1", help="sweep: workloads (c2, c5, c1)")
     ap.add_argument("--sweep-limit", type=float, default=20.0, help="sweep: time limit per GPU solve (s)")
-    ap.add_argument("--sweep-oracle-limit", type=float, default=60.0,
+    ap.add_argument("--sweep-oracle-limit", type=float, default=40.0,
                     help="sweep: time limit per oracle solve on c1 (s)")
     ap.add_argument("--original-limit", type=float, default=30.0,
                     help="time limit of the solve judged in original units (seconds)")
@@ -482,14 +483,14 @@ def main() -> int:
         metric = ("USBS iterations/sec (MaxCut SDP, n=1e6 random 4-regular graph); time-to-1e-3 rel gap; "
                   "roofline of the dominant kernel")
     precision = args.precision or ("f32" if args.workload in ("c2", "c4") else "f64")
-    psi = si.test_matrix(n, 10, seed=0)
+    psi = None   # the sketch's test matrix is generated on the device from the seed (Sec. 4)
     val_bytes = {"f64": 8, "f32": 4, "bf16": 2}[precision]
     nnz_off = prob.nnz - n
     maxr = args.lanczos_max_restarts if args.lanczos_max_restarts is not None else (3 if args.workload == "c4" else 1)
 
     def params(prec, **kw):
         return Params(precision=prec, rho=args.rho, k_c=kc, k_p=kp, lanczos_max_restarts=maxr,
-                      autotune=args.autotune, **kw)
+                      autotune=args.autotune, psi_from_seed=True, psi_seed=0, **kw)
 
     def throughput(prec, steps, warmup, roof_cat=None):
         """iterations/s over `steps` timed iterations; the roofline kernel's dispatches are

@@ -64,7 +64,8 @@ typedef struct usbs_handle usbs_handle;
  *   trace: tr(X*) (or the value the constraints fix, e.g. n for MaxCut),
  *      used by the scaling of App. E.
  *   psi:  n x r row-major Gaussian test matrix of the Nystrom sketch (Sec. 4),
- *      or NULL to run without the sketch. */
+ *      or NULL: then the sketch runs with a test matrix generated on the device when
+ *      usbs_params.psi_from_seed is set, else without the sketch. */
 typedef struct usbs_problem {
     int64_t n;
     const int64_t *rowptr;
@@ -110,6 +111,17 @@ typedef struct usbs_params {
                                    but rounding then depends on the choice)          */
     double lanczos_tol_rest;    /* residual tolerance of Ritz pairs 2..k_c inside the iteration
                                    (pair 1 uses lanczos_tol); <= 0: sqrt(lanczos_tol)          */
+    uint64_t psi_seed;          /* seed of the device-generated test matrix                    */
+    int32_t psi_from_seed;      /* != 0 and usbs_problem.psi == NULL: the n x r test matrix of
+                                   the sketch (Sec. 4, i.i.d. N(0, 1)) is generated on the
+                                   device: entry (i, c) from the Philox4x32-10 block (Salmon et
+                                   al., SC'11) with counter (i mod 2^32, i div 2^32, c div 2, 0)
+                                   and key (seed mod 2^32, seed div 2^32), words w0..w3,
+                                   u1 = ((w1 w0 >> 11) + 1) 2^-53, u2 = (w3 w2 >> 11) 2^-53, and
+                                   the Box-Muller pair sqrt(-2 ln u1) (cos, sin)(2 pi u2) for the
+                                   even and odd column; stored as float32.  Row i depends only
+                                   on (seed, i), so a warm start keeps the old rows.  0: the
+                                   caller passes psi (or NULL for no sketch).                  */
 } usbs_params;
 
 typedef struct usbs_result {
@@ -243,6 +255,11 @@ int usbs_op_nystrom(usbs_handle *h, const double *P_dev, double *U_dev, double *
  * Any output may be NULL. */
 int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *zbar,
                       double *Pbar, double *scal);
+
+/* The handle's n x r test matrix Psi of the sketch (Sec. 4; the caller's or the one
+ * generated from usbs_params.psi_seed): psi_out[n*r] (host, float32, row-major).
+ * USBS_E_INVALID without a sketch. */
+int usbs_get_test_matrix(usbs_handle *h, float *psi_out);
 
 /* The current centre y_t of Alg. 1 in original units (y = ||C||_F y_s, App. E):
  * y_out[m] (host).  Reads the state a usbs_solve_packed run leaves in the handle. */

@@ -633,6 +633,50 @@ def to_original(sc: Scaled, value: float) -> float:
 
 
 # --------------------------------------------------------------------------
+# Gaussian test matrix of the sketch from a seed (Sec. 4: Psi has i.i.d. N(0, 1) entries)
+# --------------------------------------------------------------------------
+_PHILOX_M = (np.uint64(0xD2511F53), np.uint64(0xCD9E8D57))
+_PHILOX_W = (np.uint64(0x9E3779B9), np.uint64(0xBB67AE85))
+_MASK32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11), elementwise over arrays:
+    ctr = four arrays of 32-bit words, key = two; returns the four output words.  Ten
+    rounds; before every round but the first the key is bumped by the Weyl constants."""
+    c = [np.asarray(x, dtype=np.uint64) & _MASK32 for x in ctr]
+    k = [np.asarray(x, dtype=np.uint64) & _MASK32 for x in key]
+    for rnd in range(10):
+        if rnd > 0:
+            k = [(k[0] + _PHILOX_W[0]) & _MASK32, (k[1] + _PHILOX_W[1]) & _MASK32]
+        p0 = _PHILOX_M[0] * c[0]
+        p1 = _PHILOX_M[1] * c[2]
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK32
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK32
+        c = [hi1 ^ c[1] ^ k[0], lo1, hi0 ^ c[3] ^ k[1], lo0]
+    return c
+
+
+def psi_from_seed(n: int, r: int, seed: int) -> np.ndarray:
+    """n x r test matrix (float32): entry (i, c) from the Philox block with counter
+    (i mod 2^32, i div 2^32, c div 2, 0) and key (seed mod 2^32, seed div 2^32); the words
+    give u1 = ((w1 w0 >> 11) + 1) 2^-53 in (0, 1] and u2 = (w3 w2 >> 11) 2^-53 in [0, 1), and the
+    Box-Muller pair sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) gives columns 2q and 2q + 1."""
+    i = np.repeat(np.arange(n, dtype=np.uint64), r)
+    col = np.tile(np.arange(r, dtype=np.uint64), n)
+    seed = np.uint64(seed)
+    w = philox4x32_10([i & _MASK32, i >> np.uint64(32), col >> np.uint64(1), np.zeros_like(i)],
+                      [seed & _MASK32, seed >> np.uint64(32)])
+    a = (w[1] << np.uint64(32)) | w[0]
+    b = (w[3] << np.uint64(32)) | w[2]
+    u1 = ((a >> np.uint64(11)) + np.uint64(1)).astype(np.float64) * 2.0 ** -53
+    u2 = (b >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    rad = np.sqrt(-2.0 * np.log(u1))
+    z = np.where((col & np.uint64(1)) == 1, rad * np.sin(2.0 * np.pi * u2), rad * np.cos(2.0 * np.pi * u2))
+    return z.astype(np.float32).reshape(n, r)
+
+
+# --------------------------------------------------------------------------
 # certificates for a result computed elsewhere
 # --------------------------------------------------------------------------
 

@@ -94,6 +94,9 @@ void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const do
 int nn_update2_reorth(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const double *A2,
                       int lda2, const double *H, int ldh, double *C, int ldc, hipEvent_t ev_start = nullptr,
                       hipEvent_t ev_stop = nullptr);
+// the n x r Gaussian test matrix of the sketch from a seed (Philox4x32-10 + Box-Muller, row i
+// depends only on (seed, i)), float32, row-major
+void psi_from_seed(hipStream_t s, long n, int r, uint64_t seed, float *psi);
 // same with a float32 destination (sketch storage)
 void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
                  int cc, float *C, int ldc, double alpha, double beta);

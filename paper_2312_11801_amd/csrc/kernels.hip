@@ -580,12 +580,13 @@ __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restri
 // launch), D[m][j] = output row row0 + m, column j.  Each element of A is read from
 // memory once per launch.
 // ---------------------------------------------------------------------------
+template <int NL>
 __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                                  const double *__restrict__ A2, int lda2, int ca2,
                                                  const double *__restrict__ H, int ldh, int cc,
                                                  double *__restrict__ C, int ldc, double alpha, double beta) {
     __shared__ NnWork w;
-    wg_nn_mfma(n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, blockIdx.x, gridDim.x, &w);
+    wg_nn_mfma<NL>(n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, blockIdx.x, gridDim.x, &w);
 }
 
 // pass-0 update of a Lanczos block fused with the pass-1 reduction (wg_nn_tn_mfma)
@@ -615,19 +616,15 @@ int nn_update2_reorth(hipStream_t s, const RedScratch &rs, int n, const double *
                       int lda2, const double *H, int ldh, double *C, int ldc, hipEvent_t ev_start,
                       hipEvent_t ev_stop) {
     const int blocks = mfma_blocks(rs, n);
-    const int nl = (16 * (ca + kBlk) + 63) / 64;   // flat loads per lane of one 16-row group
-    if (nl <= 8)
-        launch_nn_tn<8>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
-    else if (nl <= 12)
-        launch_nn_tn<12>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
-    else if (nl <= 16)
-        launch_nn_tn<16>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
-    else
-        launch_nn_tn<kNtMaxLoads>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc, rs.partials);
+    with_tile_loads(ca, [&](auto nl) {   // buffer loads per lane of one 16-row group
+        launch_nn_tn<decltype(nl)::value>(s, blocks, ev_start, ev_stop, n, A, lda, ca, A2, lda2, H, ldh, C, ldc,
+                                          rs.partials);
+    });
     return blocks;
 }
 
-static bool use_nn_mfma(int n, int cc) { return n > 0 && cc <= 16; }
+// the matrix-core update takes at most 16 output columns and 8 columns of A2
+static bool use_nn_mfma(int n, int cc, int ca2) { return n > 0 && cc <= 16 && ca2 <= kBlk; }
 static int nn_mfma_blocks(int n) {
     // one row group per wavefront up to the tuned cap (4096 workgroups by default); the
     // grid size does not change any output value
@@ -641,9 +638,12 @@ static void nn_update_t(hipStream_t s, int n, const double *A, int lda, int ca, 
                         int ca2, const double *H, int ldh, int cc, TC *C, int ldc, double alpha, double beta) {
     if (n <= 0 || cc <= 0) return;
     if constexpr (sizeof(TC) == 8) {
-        if (use_nn_mfma(n, cc)) {
-            hipLaunchKernelGGL(k_nn_mfma, dim3(nn_mfma_blocks(n)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2, ca2, H,
-                               ldh, cc, (double *)C, ldc, alpha, beta);
+        if (use_nn_mfma(n, cc, ca2)) {
+            const dim3 grid(nn_mfma_blocks(n));
+            with_tile_loads(ca, [&](auto nl) {
+                hipLaunchKernelGGL(k_nn_mfma<decltype(nl)::value>, grid, dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
+                                   ca2, H, ldh, cc, (double *)C, ldc, alpha, beta);
+            });
             return;
         }
     }
@@ -670,6 +670,51 @@ void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const dou
 void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
                  float *C, int ldc, double alpha, double beta) {
     nn_update_t<float>(s, n, A, lda, ca, nullptr, 0, 0, H, ldh, cc, C, ldc, alpha, beta);
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian test matrix of the sketch generated on the device (Sec. 4: Psi has i.i.d.
+// N(0, 1) entries).  Element (i, c) comes from one Philox4x32-10 block (Salmon, Moraes,
+// Dror and Shaw, SC'11) with counter (i mod 2^32, i div 2^32, c div 2, 0) and key (seed mod
+// 2^32, seed div 2^32): u1 = ((w1 w0 >> 11) + 1) 2^-53 in (0, 1], u2 = (w3 w2 >> 11) 2^-53
+// in [0, 1), and the Box-Muller pair sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2) gives the
+// even and the odd column.  Stored as float32.  A row depends only on (seed, row), so the
+// rows of a grown problem's first vertices are unchanged.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c[0] = hi1 ^ c[1] ^ k0;
+        c[1] = lo1;
+        c[2] = hi0 ^ c[3] ^ k1;
+        c[3] = lo0;
+    }
+}
+__global__ void k_psi_from_seed(long n, int r, uint64_t seed, float *__restrict__ psi) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * r) return;
+    const long i = e / r;
+    const int col = (int)(e - i * r);
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)((uint64_t)i >> 32), (uint32_t)(col >> 1), 0u};
+    philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const uint64_t a = ((uint64_t)c[1] << 32) | c[0];
+    const uint64_t b = ((uint64_t)c[3] << 32) | c[2];
+    const double u1 = (double)((a >> 11) + 1) * 0x1.0p-53;
+    const double u2 = (double)(b >> 11) * 0x1.0p-53;
+    const double rad = sqrt(-2.0 * log(u1));
+    const double ang = 6.283185307179586 * u2;   // 2 pi u2
+    psi[e] = (float)((col & 1) ? rad * sin(ang) : rad * cos(ang));
+}
+void psi_from_seed(hipStream_t s, long n, int r, uint64_t seed, float *psi) {
+    if (n <= 0 || r <= 0) return;
+    hipLaunchKernelGGL(k_psi_from_seed, dim3(cdiv(n * r, kWG)), dim3(kWG), 0, s, n, r, seed, psi);
 }
 
 __global__ void k_copy_cols(int n, const double *__restrict__ A, int lda, int cc, double *__restrict__ C,

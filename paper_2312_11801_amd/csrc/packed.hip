@@ -228,7 +228,11 @@ __device__ void pk_tn_gram(Ctx &c, const double *A, int lda, int ca, const doubl
 __device__ void pk_nn2(Ctx &c, const double *A, int lda, int ca, const double *A2, int lda2, int ca2, const double *H,
                        int ldh, int cc, double *C, int ldc, double alpha, double beta) {
     PK_TICK(c, PH_NN);
-    wg_nn_mfma(uni(c.D)->n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, 0, 1, &g_sh.u.nn);
+    const int n = uni(c.D)->n;
+    with_tile_loads(ca + ca2, [&](auto nl) {
+        wg_nn_mfma<decltype(nl)::value, FlatTile>(n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, 0,
+                                                  1, &g_sh.u.nn);
+    });
     sync();
 }
 // Wt = [A A2] H (pass-0 update of a Lanczos block) and Hg = [A Wt]^T Wt (pass-1 reduction)
@@ -237,11 +241,9 @@ __device__ void pk_nn_tn(Ctx &c, const double *A, int lda, int ca, const double 
                          int ldh, double *Wt, int ldw, double *Hg) {
     PK_TICK(c, PH_NN);
     const int n = uni(c.D)->n;
-    const int nl = (16 * (ca + kBlk) + 63) / 64;
-    if (nl <= 8) wg_nn_tn_mfma<8>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
-    else if (nl <= 12) wg_nn_tn_mfma<12>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
-    else if (nl <= 16) wg_nn_tn_mfma<16>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
-    else wg_nn_tn_mfma<kNtMaxLoads>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
+    with_tile_loads(ca + kBlk, [&](auto nl) {
+        wg_nn_tn_mfma<decltype(nl)::value, FlatTile>(n, A, lda, ca, A2, lda2, H, ldh, Wt, ldw, 0, 1, Hg, &g_sh.u.nt);
+    });
     sync();
 }
 __device__ void pk_nn(Ctx &c, const double *A, int lda, int ca, const double *H, int ldh, int cc, double *C, int ldc,

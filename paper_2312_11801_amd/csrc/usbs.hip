@@ -439,10 +439,14 @@ void upload(usbs_handle *h) {
     }
     HIPCHK(hipMemcpyAsync(h->b, bs.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(h->ineq, inq.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
-    h->sketch = !hp.psi.empty();
+    h->sketch = h->r > 0;
     if (h->sketch) {
         h->psi = dalloc<float>((size_t)n * h->r, o, h->stream);
-        HIPCHK(hipMemcpyAsync(h->psi, hp.psi.data(), (size_t)n * h->r * sizeof(float), hipMemcpyHostToDevice, s));
+        if (!hp.psi.empty())
+            HIPCHK(hipMemcpyAsync(h->psi, hp.psi.data(), (size_t)n * h->r * sizeof(float), hipMemcpyHostToDevice,
+                                  s));
+        else
+            psi_from_seed(s, n, h->r, h->prm.psi_seed, h->psi);   // Sec. 4 test matrix, generated here
     }
     convert_values(s, h->prec, nnz, h->cbase, 1.0 / h->val_scale, h->val_cur);
     if (h->has_offc) convert_values(s, h->prec, nnz, h->cbase, 1.0 / h->val_scale, h->val_c);
@@ -1143,7 +1147,7 @@ int create(const usbs_problem *prob, const usbs_params *prm, usbs_handle **out, 
         configure(h, prm);
         HIPCHK(hipGetDevice(&h->dev));
         h->hp = copy_problem(prob, h->r);
-        if (h->hp.psi.empty()) h->r = 0;
+        if (h->hp.psi.empty() && !h->prm.psi_from_seed) h->r = 0;
         set_geometry(h, h->hp.n);
         upload(h);
         if (cold) {
@@ -1273,7 +1277,7 @@ int64_t usbs_footprint_bytes(const usbs_problem *p, const usbs_params *prm) {
     const int64_t diagt = nt - offt;
     const int64_t nnz = nnzC + 2 * offt;   // bound on the off-diagonal pattern
     const int64_t vsz = prm->precision == USBS_PREC_F64 ? 8 : (prm->precision == USBS_PREC_F32 ? 4 : 2);
-    const int64_t r = p->psi ? std::max(prm->r, 0) : 0;
+    const int64_t r = (p->psi || prm->psi_from_seed) ? std::max(prm->r, 0) : 0;
     int64_t b = 0;
     // operator and constraints
     b += 4 * (n + 1) + 4 * nnz + 8 * nnz + 2 * vsz * nnz + 8 * 2 * n + 4 * (n + 1);
@@ -1580,6 +1584,22 @@ int usbs_step_iterate(usbs_handle *h, int32_t t, double *y, double *V, double *z
     }
 }
 
+int usbs_get_test_matrix(usbs_handle *h, float *psi_out) {
+    if (!h || !h->ready) return USBS_E_STATE;
+    if (!psi_out || !h->sketch) {
+        set_err(h, "usbs_get_test_matrix: no sketch or NULL output");
+        return USBS_E_INVALID;
+    }
+    try {
+        HIPCHK(hipMemcpyAsync(psi_out, h->psi, (size_t)h->n * h->r * sizeof(float), hipMemcpyDeviceToHost,
+                              h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        return USBS_OK;
+    } catch (const DevError &e) {
+        return fail(h, e);
+    }
+}
+
 int usbs_get_dual(usbs_handle *h, double *y_out) {
     if (!h || !h->ready) return USBS_E_STATE;
     if (!y_out) return USBS_E_INVALID;
@@ -1646,7 +1666,7 @@ int warm_prepare(usbs_handle *h, const usbs_problem *grown, bool eval_f) {
         HostProblem hp = copy_problem(grown, r);
         if (hp.n < n0 || hp.m < m0)
             throw DevError(USBS_E_INVALID, "usbs_warm_start: the grown problem must keep all vertices and rows");
-        if ((r > 0) != !hp.psi.empty())
+        if (r == 0 ? !hp.psi.empty() : (hp.psi.empty() && !h->prm.psi_from_seed))
             throw DevError(USBS_E_INVALID, "usbs_warm_start: sketch presence must not change");
         // ---- state of the old problem (scaled units) ----
         const double sig0 = h->sigma, tr0 = h->trace;

@@ -173,9 +173,165 @@ __device__ __forceinline__ void wg_tn_mfma(int n, const double *__restrict__ A, 
     }
 }
 
+// orders this wavefront's LDS accesses (a wavefront's LDS operations execute in order):
+// a compiler barrier that, unlike a workgroup-scope fence, does not wait for the
+// wavefront's outstanding global loads and stores
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Rows row0 .. row0 + rows - 1 (rows <= 16) of [A A2] into the wavefront's LDS tile T
+// (rows 0..15, columns 0..ca+ca2-1; rows >= rows are zero) with raw buffer loads.  The
+// buffer resource of a row group (scalar registers) starts at its first row and ends after
+// its last valid row; a lane's byte offset inside the group is the same for every group, so
+// it is computed once (TileLanes), and the hardware range check returns zero for rows past
+// the end and for lanes past the tile (their offset is out of range), with no per-row
+// address arithmetic, clamps or predicated loads.  A's 16 ca elements form one flat
+// sequence, element e = lane + 64 t being (row e / ca, column e % ca), so every lane is busy
+// and each row is read contiguously (NL >= 16 ca / 64 loads per lane); A2 (ca2 <= 8 columns)
+// takes two more loads per lane, element e = lane + 64 h being (row e / 8, column e % 8).
+// Column LD - 1 of the tile is padding (ca + ca2 < LD): lanes past the tile store their
+// zero there, so the stores need no branch either.
+constexpr int kBufOutOfRange = 0x7ffffff8;   // a byte offset past every row group
+constexpr int kBufDword3 = 0x00020000;       // buffer resource word 3 on CDNA (raw, 32-bit data)
+template <int NL>
+struct TileLanes {
+    int boff[NL], loff[NL];   // A: byte offset in the row group, element offset in the tile
+    int boff2[2], loff2[2];   // A2
+};
+template <int NL, int LD>
+__device__ __forceinline__ void tile_lanes(int ca, int lda, int ca2, int lda2, TileLanes<NL> &tl) {
+    const int lane = threadIdx.x & 63;
+    const int nel = 16 * ca;
+    // element e -> (row, column) with a float reciprocal and one correction step
+    // (e < 64 NL <= 1408, far inside float precision)
+    const float inv = 1.0f / (float)max(ca, 1);
+#pragma unroll
+    for (int t = 0; t < NL; ++t) {
+        const int e = lane + 64 * t;
+        int r = (int)((float)e * inv);
+        int c = e - r * ca;
+        if (c >= ca) c -= ca, ++r;
+        if (c < 0) c += ca, --r;
+        const bool in = e < nel;
+        tl.boff[t] = in ? (r * lda + c) * 8 : kBufOutOfRange;
+        tl.loff[t] = in ? r * LD + c : LD - 1;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int e = lane + 64 * h, r = e >> 3, c = e & 7;
+        const bool in = c < ca2;
+        tl.boff2[h] = in ? (r * lda2 + c) * 8 : kBufOutOfRange;
+        tl.loff2[h] = in ? r * LD + ca + c : LD - 1;
+    }
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_group_rsrc(const double *M, int ld, long row0, int rows) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)uni(M + row0 * ld), (short)0, uni(rows * ld * 8), kBufDword3);
+}
+template <int NL, int LD>
+__device__ __forceinline__ void wave_load_tile(long row0, int rows, const double *__restrict__ A, int lda,
+                                               const double *__restrict__ A2, int lda2, int ca2,
+                                               const TileLanes<NL> &tl, double (*T)[LD]) {
+    const __amdgpu_buffer_rsrc_t ra = row_group_rsrc(A, lda, row0, rows);
+    double v[NL];
+#pragma unroll
+    for (int t = 0; t < NL; ++t)
+        v[t] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(ra, tl.boff[t], 0, 0));
+    double v2[2] = {0.0, 0.0};
+    if (ca2 > 0) {
+        const __amdgpu_buffer_rsrc_t rb = row_group_rsrc(A2, lda2, row0, rows);
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            v2[h] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rb, tl.boff2[h], 0, 0));
+    }
+    double *Tf = &T[0][0];
+#pragma unroll
+    for (int t = 0; t < NL; ++t) Tf[tl.loff[t]] = v[t];
+    if (ca2 > 0)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) Tf[tl.loff2[h]] = v2[h];
+}
+// Row-group loaders of the update kernels (template argument Tile of wg_nn_mfma and
+// wg_nn_tn_mfma).  BufferTile: raw buffer loads as above, NL >= 16 ca / 64 (A2 separate).
+// FlatTile: generic loads over the flat sequence of all 16 (ca + ca2) elements of [A A2]
+// (element e = lane + 64 t is (row e / ct, column e % ct)), NL >= 16 (ca + ca2) / 64; every
+// load comes from a valid (clamped) address and is masked by a product (the data are
+// finite), so no load waits inside a branch.  The persistent packed kernel keeps FlatTile:
+// with BufferTile its solves left the trajectory of FlatTile (the two forms computed side
+// by side in that kernel agreed bit for bit), so the per-instance kernels alone use
+// BufferTile.
+template <int NL, int LD>
+struct BufferTile {
+    TileLanes<NL> tl;
+    __device__ __forceinline__ void prepare(int ca, int lda, int ca2, int lda2) {
+        tile_lanes<NL, LD>(ca, lda, ca2, lda2, tl);
+    }
+    __device__ __forceinline__ void load(long row0, int rows, const double *__restrict__ A, int lda, int,
+                                         const double *__restrict__ A2, int lda2, int ca2, double (*T)[LD]) const {
+        wave_load_tile<NL, LD>(row0, rows, A, lda, A2, lda2, ca2, tl, T);
+    }
+};
+template <int NL, int LD>
+struct FlatTile {
+    __device__ __forceinline__ void prepare(int, int, int, int) {}
+    __device__ __forceinline__ void load(long row0, int rows, const double *__restrict__ A, int lda, int ca,
+                                         const double *__restrict__ A2, int lda2, int ca2, double (*T)[LD]) const {
+        const int lane = threadIdx.x & 63;
+        const int ct = ca + ca2, nel = 16 * ct;
+        const float inv = 1.0f / (float)ct;
+        double v[NL];
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int e = lane + 64 * t;
+            int r = (int)((float)e * inv);
+            int c = e - r * ct;
+            if (c >= ct) c -= ct, ++r;
+            if (c < 0) c += ct, --r;
+            const long rc = row0 + min(r, rows - 1);
+            const double *pa = A + rc * lda + min(c, ca - 1);
+            const double *pb = (ca2 > 0) ? A2 + rc * lda2 + max(c - ca, 0) : pa;
+            const double val = *((c < ca) ? pa : pb);
+            v[t] = val * ((e < nel && r < rows) ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int t = 0; t < NL; ++t) {
+            const int e = lane + 64 * t;
+            int r = (int)((float)e * inv);
+            int c = e - r * ct;
+            if (c >= ct) c -= ct, ++r;
+            if (c < 0) c += ct, --r;
+            const bool in = e < nel;
+            T[in ? r : 0][in ? c : LD - 1] = v[t];
+        }
+    }
+};
+
+// loads per lane for a 16-row group of c elements per row (c <= 88: ca for BufferTile,
+// ca + ca2 for FlatTile), rounded up to an instantiated size, and a call of f with that
+// size as a compile-time constant
+__host__ __device__ constexpr int tile_loads(int ca) {
+    return ca <= 16 ? 4 : ca <= 32 ? 8 : ca <= 48 ? 12 : ca <= 64 ? 16 : ca <= 80 ? 20 : 22;
+}
+template <int N>
+struct TileLoadsC {
+    static constexpr int value = N;
+};
+template <typename F>
+__host__ __device__ __forceinline__ void with_tile_loads(int ca, F &&f) {
+    switch (tile_loads(ca)) {
+    case 4: f(TileLoadsC<4>{}); break;
+    case 8: f(TileLoadsC<8>{}); break;
+    case 12: f(TileLoadsC<12>{}); break;
+    case 16: f(TileLoadsC<16>{}); break;
+    case 20: f(TileLoadsC<20>{}); break;
+    default: f(TileLoadsC<22>{});
+    }
+}
+
 // ---------------------------------------------------------------------------
 // C = beta*C + alpha*[A A2] H on the FP64 matrix cores: a wavefront takes 16 rows at a
-// time, loads them with row-contiguous loads into its own LDS tile, then runs
+// time, loads them into its own LDS tile (wave_load_tile), then runs
 // V_MFMA_F64_16X16X4F64 over the (ca + ca2) columns four at a time:
 // X[m][k] = tile[m][4 q + k], Y[k][j] = H[4 q + k][j] (held in registers), D[m][j] =
 // output row row0 + m, column j.  Each element of A is read once.  C must not alias
@@ -186,6 +342,7 @@ constexpr int kNnLd = kMaxBasis + kBlk + 1;
 struct NnWork {
     double tile[4][16][kNnLd];
 };
+template <int NL, template <int, int> class Tile = BufferTile>
 __device__ __forceinline__ void wg_nn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                            const double *__restrict__ A2, int lda2, int ca2,
                                            const double *__restrict__ H, int ldh, int cc, double *__restrict__ C,
@@ -197,62 +354,49 @@ __device__ __forceinline__ void wg_nn_mfma(int n, const double *__restrict__ A, 
     const int m = lane & 15, kk = lane >> 4, j = lane & 15;
     const int ct = ca + ca2;
     const int nq = (ct + 3) >> 2;
+    // H in registers (unconditional loads from clamped indices, masked): Y[k][j] = H[4 q + k][j]
     double yv[kNnMaxQ];
 #pragma unroll
     for (int q = 0; q < kNnMaxQ; ++q) {
         const int a = 4 * q + kk;
-        yv[q] = (q < nq && a < ct && j < cc) ? H[a * ldh + j] : 0.0;
+        const double h = H[min(a, ct - 1) * ldh + min(j, cc - 1)];
+        yv[q] = h * ((a < ct && j < cc) ? 1.0 : 0.0);
     }
     double(*T)[kNnLd] = w->tile[wave];
+    // columns ct .. kNnLd - 1 of the tile are never loaded; the products of a four-step
+    // chunk past ct read them (times yv = 0), so they are zeroed once
+    for (int e = lane; e < 16 * kNnLd; e += 64)
+        if (e % kNnLd >= ct) T[e / kNnLd][e % kNnLd] = 0.0;
+    Tile<NL, kNnLd> tile;
+    tile.prepare(ca, lda, ca2, lda2);
     const long ngroups = ((long)n + 15) >> 4;
     const long gstride = (long)nblk * 4;
     for (long g = (long)blk * 4 + wave; g < ngroups; g += gstride) {
         const long row0 = 16 * g;
-        // rows of A: lanes over columns (two passes when ca > 64); A2 (<= 8 columns): 8 rows
-        // of 8 lanes per load
-        double v[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) v[r] = (lane < ca && row0 + r < n) ? A[(row0 + r) * lda + lane] : 0.0;
-        double w2[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = 8 * h + (lane >> 3), c = lane & 7;
-            w2[h] = (c < ca2 && row0 + r < n) ? A2[(row0 + r) * lda2 + c] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < 16; ++r)
-            if (lane < ca) T[r][lane] = v[r];
-        if (ca > 64) {
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                v[r] = (64 + lane < ca && row0 + r < n) ? A[(row0 + r) * lda + 64 + lane] : 0.0;
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                if (64 + lane < ca) T[r][64 + lane] = v[r];
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = 8 * h + (lane >> 3), c = lane & 7;
-            if (c < ca2) T[r][ca + c] = w2[h];
-        }
-        wave_sync();
+        const int rows = (int)min(16L, (long)n - row0);
+        tile.load(row0, rows, A, lda, ca, A2, lda2, ca2, T);
+        wave_lds_sync();
+        // four products at a time, their tile operands read first (one LDS wait per four)
         v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < kNnMaxQ; ++q)
-            if (q < nq) {
-                const int a = 4 * q + kk;
-                const double x = (a < ct) ? T[m][a] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, yv[q], acc, 0, 0, 0);
+        for (int q0 = 0; q0 < kNnMaxQ; q0 += 4)
+            if (q0 < nq) {
+                double x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = (q0 + u < kNnMaxQ) ? T[m][4 * (q0 + u) + kk] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (q0 + u < kNnMaxQ) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], yv[q0 + u], acc, 0, 0, 0);
             }
-        wave_sync();   // the tile is reloaded for the next row group
+        wave_lds_sync();   // the tile is reloaded for the next row group
         if (j < cc) {
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
-                const long r = row0 + (lane >> 4) + 4 * vv;
-                if (r < n) {
+                const int r = kk + 4 * vv;
+                if (r < rows) {
                     double o = alpha * acc[vv];
-                    if (beta != 0.0) o += beta * C[r * ldc + j];
-                    C[r * ldc + j] = o;
+                    if (beta != 0.0) o += beta * C[(row0 + r) * ldc + j];
+                    C[(row0 + r) * ldc + j] = o;
                 }
             }
         }
@@ -270,7 +414,6 @@ __device__ __forceinline__ void wg_nn_mfma(int n, const double *__restrict__ A, 
 // wavefronts are summed in LDS in a fixed order into dst.
 // ---------------------------------------------------------------------------
 constexpr int kNtLd = kMaxBasis + 2 * kBlk + 1;
-constexpr int kNtMaxLoads = (16 * (kMaxBasis + kBlk) + 63) / 64;   // flat loads per lane per group
 struct NnTnWork {
     union {
         double tile[4][16][kNtLd];   // [A | A2 | C] of 16 rows per wavefront
@@ -278,14 +421,7 @@ struct NnTnWork {
     } u;
     double sH[kMaxBasis + kBlk][kBlk];
 };
-// orders this wavefront's LDS accesses (a wavefront's LDS operations execute in order):
-// a compiler barrier that, unlike a workgroup-scope fence, does not wait for the
-// wavefront's outstanding global loads and stores
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-template <int NL>   // flat loads per lane per row group: NL >= 16 (ca + kBlk) / 64
+template <int NL, template <int, int> class Tile = BufferTile>   // NL: loads per lane (see Tile)
 __device__ __forceinline__ void wg_nn_tn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                               const double *__restrict__ A2, int lda2, const double *__restrict__ H,
                                               int ldh, double *__restrict__ C, int ldc, int blk, int nblk,
@@ -298,59 +434,44 @@ __device__ __forceinline__ void wg_nn_tn_mfma(int n, const double *__restrict__ 
     const int ct = ca + kBlk;        // columns of [A A2]
     const int nq = (ct + 3) >> 2;
     const int nch = (ca + 15) >> 4;
-    const int nel = 16 * ct;         // elements of one row group
-    for (int e = tid; e < ct * kBlk; e += kWG) w->sH[e / kBlk][e % kBlk] = H[(e / kBlk) * ldh + e % kBlk];
+    // H rows past ct and tile columns past ct are zero, read (as products with zero) by the
+    // last four-step chunk of the update
+    for (int e = tid; e < kNnMaxQ * 4 * kBlk; e += kWG)
+        w->sH[e / kBlk][e % kBlk] = (e < ct * kBlk) ? H[(e / kBlk) * ldh + e % kBlk] : 0.0;
+    double(*T)[kNtLd] = w->u.tile[wave];
+    for (int e = lane; e < 16 * kNtLd; e += 64)
+        if (e % kNtLd >= ct) T[e / kNtLd][e % kNtLd] = 0.0;
+    Tile<NL, kNtLd> tile;
+    tile.prepare(ca, lda, kBlk, lda2);
     __syncthreads();
-    // element e of a row group is (row e / ct, column e % ct), found with a float reciprocal
-    // and one correction step (e < 16 ct <= 1536, far inside float precision)
-    const float inv = 1.0f / (float)ct;
-    auto split = [&](int e, int &r, int &c) {
-        r = (int)((float)e * inv);
-        c = e - r * ct;
-        if (c >= ct) c -= ct, ++r;
-        if (c < 0) c += ct, --r;
-    };
     v4d racc[kMfmaMaxCh + 1];
 #pragma unroll
     for (int q = 0; q <= kMfmaMaxCh; ++q) racc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
-    double(*T)[kNtLd] = w->u.tile[wave];
     const long ngroups = ((long)n + 15) >> 4;
     const long gstride = (long)nblk * 4;
     for (long g = (long)blk * 4 + wave; g < ngroups; g += gstride) {
         const long row0 = 16 * g;
         const int rows = (int)min(16L, (long)n - row0);
-        // ---- [A A2] rows into the tile: element e = lane + 64 t is (row e / ct, column e % ct);
-        // addresses are clamped to valid rows so that every load is unconditional ----
-        // every load is issued unconditionally from a valid address and masked by a product,
-        // so that no load waits inside a branch (the data are finite)
-        double v[NL];
-#pragma unroll
-        for (int t = 0; t < NL; ++t) {
-            const int e = lane + 64 * t;
-            int r, c;
-            split(e, r, c);
-            const long rc = row0 + min(r, rows - 1);
-            const double *pa = A + rc * lda + min(c, ca - 1);
-            const double *pb = A2 + rc * lda2 + max(c - ca, 0);
-            const double val = *((c < ca) ? pa : pb);
-            v[t] = val * ((e < nel && r < rows) ? 1.0 : 0.0);
-        }
-#pragma unroll
-        for (int t = 0; t < NL; ++t) {
-            const int e = lane + 64 * t;
-            int r, c;
-            split(e, r, c);
-            if (e < nel) T[r][c] = v[t];
-        }
+        // ---- [A A2] rows into the tile ----
+        tile.load(row0, rows, A, lda, ca, A2, lda2, kBlk, T);
         wave_lds_sync();
         // ---- C rows: D[m][j] = sum_a T[m][a] H[a][j]; ct is a multiple of 4, so every a < ct ----
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         const double hmask = (j < kBlk) ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = 0; q < kNnMaxQ; ++q)
-            if (q < nq) {
-                const int a = 4 * q + kk;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(T[m][a], w->sH[a][j & 7] * hmask, acc, 0, 0, 0);
+        for (int q0 = 0; q0 < kNnMaxQ; q0 += 4)
+            if (q0 < nq) {
+                // operands of four products read first (one LDS wait per four)
+                double x[4], y[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = 4 * (q0 + u) + kk;
+                    x[u] = (q0 + u < kNnMaxQ) ? T[m][a] : 0.0;
+                    y[u] = (q0 + u < kNnMaxQ) ? w->sH[a][j & 7] * hmask : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (q0 + u < kNnMaxQ) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], y[u], acc, 0, 0, 0);
             }
         if (j < kBlk) {
 #pragma unroll
@@ -369,9 +490,12 @@ __device__ __forceinline__ void wg_nn_tn_mfma(int n, const double *__restrict__ 
         for (int s4 = 0; s4 < 4; ++s4) {
             const int row = 4 * s4 + kk;
             const double y = T[row][ct + (m & 7)] * ymask;
+            double x[kMfmaMaxCh];
+#pragma unroll
+            for (int q = 0; q < kMfmaMaxCh; ++q) x[q] = T[row][16 * q + m];
 #pragma unroll
             for (int q = 0; q < kMfmaMaxCh; ++q)
-                if (q < nch) racc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(T[row][16 * q + m], y, racc[q], 0, 0, 0);
+                if (q < nch) racc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[q], y, racc[q], 0, 0, 0);
             racc[kMfmaMaxCh] = __builtin_amdgcn_mfma_f64_16x16x4f64(y, y, racc[kMfmaMaxCh], 0, 0, 0);
         }
         wave_lds_sync();   // the tile is rewritten for the next row group

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libusbs.so")
 
 USBS_OK = 0
 USBS_NOT_CONVERGED = 1
+USBS_E_INVALID, USBS_E_NOMEM, USBS_E_DEVICE, USBS_E_NUMERIC, USBS_E_STATE = -1, -2, -3, -4, -5
 ERRORS = {-1: "USBS_E_INVALID", -2: "USBS_E_NOMEM", -3: "USBS_E_DEVICE", -4: "USBS_E_NUMERIC",
           -5: "USBS_E_STATE"}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
@@ -31,7 +32,7 @@ EXPORTS = [
     "usbs_footprint_bytes", "usbs_server_create", "usbs_server_submit", "usbs_server_wait",
     "usbs_server_get_stats", "usbs_server_last_error", "usbs_server_free", "usbs_round_maxcut",
     "usbs_get_tuning", "usbs_solve_packed", "usbs_packed_profile", "usbs_get_primal",
-    "usbs_get_dual", "usbs_sketch_update_noalloc",
+    "usbs_get_dual", "usbs_sketch_update_noalloc", "usbs_get_test_matrix",
 ]
 PACK_PHASES = ["spmm", "tn", "nn", "ritz", "ipm", "constraints", "small", "shift", "all"]
 PROF = {"spmm": 0, "reorth": 1, "ritz": 2, "ipm": 3, "update": 4}
@@ -56,6 +57,7 @@ class UsbsParams(ctypes.Structure):
         ("lanczos_tol_final", ctypes.c_double),
         ("precision", ctypes.c_int32), ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p),
         ("verbose", ctypes.c_int32), ("autotune", ctypes.c_int32), ("lanczos_tol_rest", ctypes.c_double),
+        ("psi_seed", ctypes.c_uint64), ("psi_from_seed", ctypes.c_int32),
     ]
 
 
@@ -148,6 +150,7 @@ def load_library(path: str | None = None):
         "usbs_packed_profile": (ctypes.c_int, [vp, i32, vp]),
         "usbs_get_primal": (ctypes.c_int, [vp, vp, vp, vp, vp, vp, vp]),
         "usbs_get_dual": (ctypes.c_int, [vp, vp]),
+        "usbs_get_test_matrix": (ctypes.c_int, [vp, vp]),
         "usbs_sketch_update_noalloc": (ctypes.c_int, [i64, i32, i32, dbl, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -194,14 +197,17 @@ class Params:
     verbose: int = 0
     autotune: int = 1
     lanczos_tol_rest: float = 0.0
+    psi_seed: int = 0
+    psi_from_seed: bool = False
 
     def to_c(self, stream: int | None) -> UsbsParams:
         p = UsbsParams()
         load_library().usbs_default_params(ctypes.byref(p))
         for f in ("alpha", "rho", "beta", "k_c", "k_p", "r", "eps_gap", "eps_infeas", "max_iters", "time_limit",
                   "lanczos_steps", "lanczos_max_restarts", "lanczos_tol", "lanczos_tol_final", "seed", "verbose",
-                  "autotune", "lanczos_tol_rest"):
+                  "autotune", "lanczos_tol_rest", "psi_seed"):
             setattr(p, f, getattr(self, f))
+        p.psi_from_seed = int(bool(self.psi_from_seed))
         p.units = UNITS[self.units]
         p.precision = PREC[self.precision]
         p.stream = stream
@@ -242,7 +248,7 @@ class Solver:
         self.lib = load_library()
         self.params = params or Params()
         self.n, self.m = prob.n, prob.m
-        self.r = self.params.r if psi is not None else 0
+        self.r = self.params.r if (psi is not None or self.params.psi_from_seed) else 0
         arrs = _ProblemArrays(prob, psi)
         self._cp = self.params.to_c(stream)
         h = ctypes.c_void_p()
@@ -274,6 +280,12 @@ class Solver:
         arrs = _ProblemArrays(grown, psi)
         self._check(self.lib.usbs_warm_start(self.h, ctypes.byref(arrs.c)))
         self.n, self.m = grown.n, grown.m
+
+    def test_matrix(self) -> np.ndarray:
+        """The handle's test matrix Psi (n x r, float32)."""
+        psi = np.zeros((self.n, self.r), dtype=np.float32)
+        self._check(self.lib.usbs_get_test_matrix(self.h, _ptr(psi)))
+        return psi
 
     def round_maxcut(self) -> dict:
         """Best of the r cuts sign(U[:, c]) of the current sketch (App. E.1)."""

@@ -106,3 +106,40 @@ def test_packed_structs_fit_the_launch_tables():
     assert names[-1] == "kPackPhases" and len(names) - 1 == ph
     from paper_2312_11801_amd.native import PACK_PHASES
     assert len(PACK_PHASES) == ph
+
+
+@pytest.mark.parametrize("field,value,text", [
+    ("k_c", 0, "k_c >= 1"), ("k_p", 12, "k_c + k_p"), ("r", 17, "0 <= r <= 16"),
+    ("lanczos_steps", 9, "lanczos_steps"), ("rho", 0.0, "rho > 0"), ("beta", 1.0, "beta < 1"),
+    ("lanczos_tol", 0.0, "tolerances"), ("autotune", 3, "autotune"), ("lanczos_max_restarts", -1, "restarts")])
+def test_invalid_params_rejected_on_the_host(field, value, text):
+    """usbs_create checks the parameters before it touches the device: each malformed field
+    gives USBS_E_INVALID with a message that names it (header: error codes)."""
+    from paper_2312_11801_amd.native import LIB_PATH, USBS_E_INVALID, Params, Solver, UsbsError
+    import sdp_inputs as si
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("libusbs.so not built")
+    prm = Params()
+    setattr(prm, field, value)
+    with pytest.raises(UsbsError) as ei:
+        Solver(si.maxcut_er(60, 0.1, seed=0), prm)
+    assert ei.value.code == USBS_E_INVALID and text in str(ei.value), str(ei.value)
+
+
+def test_noalloc_rejects_bad_sizes_on_the_host():
+    """usbs_sketch_update_noalloc rejects sizes beyond its fixed scratch and NULL arguments
+    with USBS_E_INVALID before any device call; the thread's message is read with
+    usbs_last_error(NULL).  n = 0 is a no-op."""
+    from paper_2312_11801_amd.native import LIB_PATH, USBS_E_INVALID, USBS_OK, load_library
+    if not os.path.exists(LIB_PATH):
+        pytest.skip("libusbs.so not built")
+    lib = load_library()
+    lam = (ctypes.c_double * 16)(*([1.0] * 16))
+    fake = ctypes.c_void_p(16)   # never dereferenced: every case fails its host checks
+    for n, q, r, ptr, text in ((100, 17, 10, fake, "q and r"), (100, 0, 10, fake, "q and r"),
+                               (100, 4, 17, fake, "q and r"), (100, 4, 0, fake, "q and r"),
+                               (-1, 4, 10, fake, "n must be"), (100, 4, 10, None, "NULL")):
+        rc = lib.usbs_sketch_update_noalloc(n, q, r, 1.0, ptr, lam, ptr, ptr, None)
+        assert rc == USBS_E_INVALID, (n, q, r)
+        assert text in lib.usbs_last_error(None).decode()
+    assert lib.usbs_sketch_update_noalloc(0, 4, 10, 1.0, None, lam, None, None, None) == USBS_OK

@@ -351,3 +351,51 @@ def test_autotune_invariant_shapes(cuda):
     for key in ("f", "rel_gap", "rel_infeas", "lambda1", "descents"):
         assert a[key] == b[key], key
     assert np.array_equal(a["y"], b["y"]) and np.array_equal(a["V"], b["V"])
+
+
+@pytest.mark.parametrize("n,r,seed", [(5003, 10, 11), (777, 7, 2 ** 40 + 3)])
+def test_psi_from_seed_matches_oracle(cuda, n, r, seed):
+    """The test matrix generated on the device (Philox4x32-10 + Box-Muller from the seed,
+    Sec. 4) against the oracle's own implementation of the same definition: identical
+    float32 values (an entry may differ by one float32 unit where the device's and the
+    host's FP64 log / sin / cos round differently right at a float32 rounding boundary)."""
+    from paper_2312_11801_amd import Params, Solver
+    prob = si.maxcut_er(n, 6.0 / n, seed=1)
+    s = Solver(prob, Params(r=r, psi_from_seed=True, psi_seed=seed, max_iters=1, lanczos_max_restarts=1))
+    got = s.test_matrix()
+    s.free()
+    ref = orc.psi_from_seed(n, r, seed)
+    same = np.mean(got == ref)
+    print("identical fraction", same)
+    assert same >= 0.9999
+    assert np.abs(got.astype(np.float64) - ref).max() <= 2.0 ** -22 * max(1.0, np.abs(ref).max())
+
+
+def test_seeded_sketch_solve_and_warm_start(cuda):
+    """A solve whose sketch uses the device-generated test matrix: certified by the oracle
+    (including the Nystrom reconstruction's figures), objective equal to the oracle's solve
+    with the oracle's matrix from the same seed; after a warm start on the problem grown
+    by 1% the first rows of the test matrix are unchanged."""
+    from paper_2312_11801_amd import Params, Solver
+    rng = np.random.default_rng(9)
+    n0, n = 200, 202
+    i, j = si.erdos_renyi(n, 0.05, rng)
+    keep = (i < n0) & (j < n0)
+    base = si.maxcut_problem(n0, i[keep], j[keep], np.ones(int(keep.sum())))
+    grown = si.maxcut_problem(n, i, j, np.ones(i.size))
+    prm = Params(rho=0.1, max_iters=800, psi_from_seed=True, psi_seed=77)
+    s = Solver(base, prm)
+    out = s.solve()
+    assert out["converged"], out
+    certify(base, s, out)
+    psi0 = s.test_matrix()
+    ref = orc.usbs_solve(base, orc.Params(rho=0.1, max_iters=800), Psi=orc.psi_from_seed(n0, 10, 77),
+                         keep_history=False)
+    assert abs(out["primal_obj_scaled"] - ref.primal_obj) / (1 + abs(ref.primal_obj)) <= 1e-3
+    s.warm_start(grown)
+    warm = s.solve()
+    psi1 = s.test_matrix()
+    assert warm["converged"], warm
+    certify(grown, s, warm)
+    s.free()
+    assert psi1.shape == (n, 10) and np.array_equal(psi1[:n0], psi0)

@@ -576,3 +576,39 @@ def test_sketch_certificate_equals_dense_definition():
         assert abs(inf_s - np.linalg.norm(es) / (1 + np.linalg.norm(prob.b / prob.trace))) <= 1e-12
         if ineq.any():
             assert np.any(e[ineq] == 0.0) or np.all(z[ineq] > prob.b[ineq])
+
+
+# ---------------------------------------------------------------------------
+# test matrix from a seed (Sec. 4): Philox4x32-10 and the Box-Muller map
+# ---------------------------------------------------------------------------
+def test_philox_known_answers():
+    """The three known-answer vectors published with Philox4x32-10 (Random123: zero counter
+    and key, all-ones counter and key, and the digits-of-pi counter and key)."""
+    kat = [((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+           ((0xffffffff,) * 4, (0xffffffff,) * 2, (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+           ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+            (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1))]
+    for ctr, key, expect in kat:
+        out = orc.philox4x32_10([np.uint64(x) for x in ctr], [np.uint64(x) for x in key])
+        assert [int(v) for v in out] == list(expect)
+
+
+def test_psi_from_seed_is_standard_normal_and_row_local():
+    """Entries are i.i.d. N(0, 1): moments and a Kolmogorov-Smirnov test on 2e5 draws,
+    no correlation between paired columns (the cos / sin halves of one Box-Muller pair),
+    seeds give different matrices, and a row depends only on (seed, row) (a grown problem
+    keeps its first rows)."""
+    from scipy import stats
+    psi = orc.psi_from_seed(20000, 10, seed=5).astype(np.float64)
+    z = psi.ravel()
+    assert abs(z.mean()) < 0.01 and abs(z.var() - 1.0) < 0.02
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(np.corrcoef(psi[:, 0], psi[:, 1])[0, 1]) < 0.03
+    assert abs(np.corrcoef(psi[:, 2], psi[:, 5])[0, 1]) < 0.03
+    assert np.array_equal(orc.psi_from_seed(300, 10, seed=5), psi[:300])
+    assert not np.array_equal(orc.psi_from_seed(300, 10, seed=6), psi[:300])
+    # one entry by hand from its definition
+    w = orc.philox4x32_10([np.uint64(7), np.uint64(0), np.uint64(1), np.uint64(0)], [np.uint64(5), np.uint64(0)])
+    u1 = ((((int(w[1]) << 32) | int(w[0])) >> 11) + 1) * 2.0 ** -53
+    u2 = (((int(w[3]) << 32) | int(w[2])) >> 11) * 2.0 ** -53
+    assert psi[7, 3] == np.float32(math.sqrt(-2 * math.log(u1)) * math.sin(2 * math.pi * u2))
