@@ -3,6 +3,8 @@
 Inputs come from the seeded generators in sdp_inputs; expected values only from oracle/.
 Sizes span several workgroups/tiles and a ragged tail (n not a multiple of 8, 32 or 256).
 """
+import copy
+
 import numpy as np
 import pytest
 
@@ -399,3 +401,58 @@ def test_seeded_sketch_solve_and_warm_start(cuda):
     certify(grown, s, warm)
     s.free()
     assert psi1.shape == (n, 10) and np.array_equal(psi1[:n0], psi0)
+
+
+def test_malformed_problems_are_rejected(cuda):
+    """usbs_create and usbs_warm_start refuse malformed input with the documented codes and a
+    message (header: error codes): USBS_E_INVALID for structure (rowptr, column range,
+    symmetry, size, a shrinking warm start, a sketch that disappears), USBS_E_NUMERIC for
+    NaN/Inf in C, b or the test matrix.  No kernel runs for any of them."""
+    from paper_2312_11801_amd import Params, Solver, UsbsError
+    from paper_2312_11801_amd.native import USBS_E_INVALID, USBS_E_NUMERIC
+
+    def expect(code, text, prob, psi=None):
+        with pytest.raises(UsbsError) as ei:
+            Solver(prob, Params(max_iters=1), psi=psi)
+        assert ei.value.code == code and text in str(ei.value), str(ei.value)
+
+    base = si.maxcut_er(120, 0.08, seed=3)
+
+    def variant(**kw):
+        p = copy.deepcopy(base)
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    rp = base.rowptr.copy()
+    rp[0] = 1
+    expect(USBS_E_INVALID, "rowptr", variant(rowptr=rp))
+    col = base.col.copy()
+    col[3] = base.n
+    expect(USBS_E_INVALID, "column index", variant(col=col))
+    rows = np.repeat(np.arange(base.n), np.diff(base.rowptr))
+    e = int(np.nonzero(base.col != rows)[0][0])   # the first off-diagonal entry
+    val = base.val.copy()
+    val[e] += 1.0   # (i, j) no longer equals (j, i)
+    expect(USBS_E_INVALID, "symmetric", variant(val=val))
+    val = base.val.copy()
+    val[5] = np.nan
+    expect(USBS_E_NUMERIC, "non-finite value", variant(val=val))
+    b = base.b.copy()
+    b[2] = np.inf
+    expect(USBS_E_NUMERIC, "non-finite b", variant(b=b))
+    psi = si.test_matrix(base.n, 10, seed=3)
+    psi[7, 1] = np.nan
+    expect(USBS_E_NUMERIC, "test matrix", base, psi=psi)
+    expect(USBS_E_INVALID, "block Lanczos basis", si.maxcut_er(30, 0.2, seed=1))
+    # warm start: the grown problem must keep every vertex, and the sketch cannot disappear
+    s = Solver(base, Params(max_iters=1), psi=None)
+    with pytest.raises(UsbsError) as ei:
+        s.warm_start(si.maxcut_er(100, 0.08, seed=3))
+    assert ei.value.code == USBS_E_INVALID and "keep all vertices" in str(ei.value)
+    s.free()
+    s = Solver(base, Params(max_iters=1), psi=si.test_matrix(base.n, 10, seed=3))
+    with pytest.raises(UsbsError) as ei:
+        s.warm_start(si.maxcut_er(122, 0.08, seed=3), psi=None)
+    assert ei.value.code == USBS_E_INVALID and "sketch presence" in str(ei.value)
+    s.free()
