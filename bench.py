@@ -153,10 +153,10 @@ def gpu_rate_c1(stream, steps: int = 20) -> dict:
     prob, psi = c1_problem()
     prm = Params(precision="f64", rho=0.01, max_iters=3000, time_limit=20.0, lanczos_max_restarts=3)
     s = Solver(prob, prm, psi=psi, stream=stream)
-    s.step_iterate(3, 11)
+    s.step_iterate(3, 11, light=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s.step_iterate(steps, 11)
+    s.step_iterate(steps, 11, light=True)
     torch.cuda.synchronize()
     rate = steps / (time.perf_counter() - t0)
     s.free()
@@ -496,11 +496,12 @@ def main() -> int:
         """iterations/s over `steps` timed iterations; the roofline kernel's dispatches are
         timed live (HIP events attached to each dispatch on the solver's stream)."""
         s = Solver(prob, params(prec, max_iters=100000), psi=psi, stream=stream)
-        s.step_iterate(warmup, kc + kp)
+        s.step_iterate(warmup, kc + kp, light=True)
         s.profile(roof_cat, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = s.step_iterate(steps, kc + kp)
+        # the state stays in HBM (light: only the scalars of the last iteration come back)
+        st = s.step_iterate(steps, kc + kp, light=True)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         roof = s.profile(None, reset=True)
@@ -525,11 +526,11 @@ def main() -> int:
     # two more short stretches for secondary figures: the SpMM and the Ritz eigenproblem
     extra = max(2, args.steps // 4)
     s.profile("spmm", reset=True)
-    s.step_iterate(extra, kc + kp)
+    s.step_iterate(extra, kc + kp, light=True)
     spmm_ms, spmm_launches = s.profile("ritz", reset=True)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    s.step_iterate(extra, kc + kp)
+    s.step_iterate(extra, kc + kp, light=True)
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     ritz_ms, ritz_launches = s.profile(None, reset=True)

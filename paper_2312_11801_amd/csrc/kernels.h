@@ -144,6 +144,16 @@ void gather_ritz(hipStream_t s, int n, const double *Uc, const int *plan, double
 void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const int *ti,
              const int *tj, const double *tv, const double *V, int ldv, int k, const double *const *w,
              int nw, double *out, int do_q11);
+// Rayleigh-Ritz update of a Lanczos restart cycle in one sweep: B (ldb) = U Y, R = MU Y -
+// B diag(theta) (R may alias U), RtR (16 x 16) = R^T R; U, MU, R are n x 16 row-major, Y and
+// theta on the device
+void rr_update(hipStream_t s, const RedScratch &rs, int n, const double *U, const double *MU, const double *Y,
+               const double *theta, double *B, int ldb, double *R, double *RtR);
+// G^T w_j (layout of qp_gram's weight part, out[j d + p], nw <= 4) for constraint sets whose
+// every triplet is diagonal: svec(V^T diag(a_j) V), a_j = diag(A^* w_j) from the per-vertex
+// triplet lists (dptr, dk, dv) -- one sweep over the n rows of V instead of the m rows of A
+void wgram(hipStream_t s, const RedScratch &rs, int n, const double *V, int ldv, int k, const int *dptr,
+           const int *dk, const double *dv, const double *const *w, int nw, double *out);
 // z[k] = beta*z[k] + gamma*zb[k] + alpha * sum_t v_t V_i^T K V_j  (K k x k symmetric, device)
 void lowrank_A(hipStream_t s, int m, const int *kptr, const int *ti, const int *tj, const double *tv,
                const double *V, int ldv, int k, const double *K, double alpha, const double *zb,

@@ -848,6 +848,210 @@ void qp_gram(hipStream_t s, const RedScratch &rs, int m, const int *kptr, const 
     red_finish(s, rs.partials, blocks, nout, out, nout, nout, 1.0, 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Rayleigh-Ritz update of a restart cycle in one sweep over the rows (block Lanczos with
+// explicit restarts, App. E): with U (n x 16) the current block, MU = (C_s - A^* y) U and
+// (Y, theta) the eigenpairs of U^T M U,
+//   B = U Y            (the Ritz vectors, into the first 16 columns of the basis)
+//   R = MU Y - B diag(theta)   (their residuals, over U: R may alias U)
+//   R^T R              (per-workgroup partials, summed by red_finish)
+// A wavefront stages 16 rows of U and of MU in LDS (BufferTile), forms both 16 x 16
+// products on the FP64 matrix cores (Y in registers), R from the two accumulators, and
+// R^T R from an LDS copy of R (four rows per product).  Reads 2 x 16 and writes 2 x 16
+// doubles per row: half the traffic of three updates and a reduction.
+// ---------------------------------------------------------------------------
+constexpr int kRrLd = 17;
+struct RrWork {
+    double u[4][16][kRrLd], mu[4][16][kRrLd], r[4][16][kRrLd];
+    double sred[3][4][64];
+};
+__global__ __launch_bounds__(kWG) void k_rr_update(int n, const double *U, const double *__restrict__ MU,
+                                                   const double *__restrict__ Y, const double *__restrict__ theta,
+                                                   double *__restrict__ B, int ldb, double *R,
+                                                   double *__restrict__ partials) {
+    __shared__ RrWork w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int m = lane & 15, kk = lane >> 4, j = lane & 15;
+    double yv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) yv[q] = Y[(4 * q + kk) * 16 + j];
+    const double th = theta[j];
+    double(*Tu)[kRrLd] = w.u[wave];
+    double(*Tm)[kRrLd] = w.mu[wave];
+    double(*Tr)[kRrLd] = w.r[wave];
+    BufferTile<4, kRrLd> tile;
+    tile.prepare(16, 16, 0, 0);
+    v4d racc = {0.0, 0.0, 0.0, 0.0};
+    const long ngroups = ((long)n + 15) >> 4;
+    const long gstride = (long)gridDim.x * 4;
+    for (long g = (long)blockIdx.x * 4 + wave; g < ngroups; g += gstride) {
+        const long row0 = 16 * g;
+        const int rows = (int)min(16L, (long)n - row0);
+        tile.load(row0, rows, U, 16, 16, nullptr, 0, 0, Tu);
+        tile.load(row0, rows, MU, 16, 16, nullptr, 0, 0, Tm);
+        wave_lds_sync();
+        v4d ab = {0.0, 0.0, 0.0, 0.0}, am = {0.0, 0.0, 0.0, 0.0};
+        double xu[4], xm[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            xu[q] = Tu[m][4 * q + kk];
+            xm[q] = Tm[m][4 * q + kk];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ab = __builtin_amdgcn_mfma_f64_16x16x4f64(xu[q], yv[q], ab, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) am = __builtin_amdgcn_mfma_f64_16x16x4f64(xm[q], yv[q], am, 0, 0, 0);
+        wave_lds_sync();   // U's tile is read; R may overwrite U's rows
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+            const int r = kk + 4 * vv;
+            const double b = ab[vv];
+            const double rr = __dsub_rn(am[vv], __dmul_rn(b, th));
+            Tr[r][j] = rr;
+            if (r < rows) {
+                B[(row0 + r) * ldb + j] = b;
+                R[(row0 + r) * 16 + j] = rr;
+            }
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const double x = Tr[4 * s4 + kk][m];
+            racc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, racc, 0, 0, 0);
+        }
+        wave_lds_sync();   // the tiles are reloaded for the next row group
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) w.sred[wave - 1][vv][lane] = racc[vv];
+    __syncthreads();
+    if (wave == 0) {
+        double *dst = partials + (size_t)blockIdx.x * 256;
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+            const double t = ((racc[vv] + w.sred[0][vv][lane]) + w.sred[1][vv][lane]) + w.sred[2][vv][lane];
+            dst[(kk + 4 * vv) * 16 + j] = t;
+        }
+    }
+}
+void rr_update(hipStream_t s, const RedScratch &rs, int n, const double *U, const double *MU, const double *Y,
+               const double *theta, double *B, int ldb, double *R, double *RtR) {
+    const int blocks = mfma_blocks(rs, n);
+    hipLaunchKernelGGL(k_rr_update, dim3(blocks), dim3(kWG), 0, s, n, U, MU, Y, theta, B, ldb, R, rs.partials);
+    red_finish(s, rs.partials, blocks, 256, RtR, 16, 16, 1.0, 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// G^T w_j = svec(V^T A^*(w_j) V) (App. B.2, g_k = svec(V^T A_k V), by linearity) when every
+// constraint triplet is diagonal (the MaxCut SDP of Sec. 5): A^*(w) is then the diagonal
+// matrix with a_i = sum of v w_k over vertex i's triplets (k, i, i, v), and V^T diag(a) V is
+// a weighted Gram matrix of the rows of V.  FP64 MFMA with the operand layout of
+// wg_tn_mfma: a wavefront takes 4 rows per product, X[m][kk] = V[row kk][m] and
+// Y[kk][j] = a_row V[row kk][j] from the same lane, one 16 x 16 accumulator per weight
+// vector (NW <= 4 in one sweep over the rows); a is formed per row from (dptr, dk, dv).
+// Each workgroup writes its NW k x k partials; k_wgram_finish sums them in a fixed order
+// and writes the svec entries.
+// ---------------------------------------------------------------------------
+constexpr int kWgMaxW = 4;
+constexpr int kWgUnr = 4;   // row groups in flight per wavefront
+struct WeightPtrs {
+    const double *w[kWgMaxW];
+};
+template <int NW>
+__global__ __launch_bounds__(kWG) void k_wgram(int n, const double *__restrict__ V, int ldv, int k,
+                                               const int *__restrict__ dptr, const int *__restrict__ dk,
+                                               const double *__restrict__ dv, WeightPtrs ws,
+                                               double *__restrict__ partials) {
+    __shared__ double sred[3][NW][4][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = lane & 15, kk = lane >> 4;
+    v4d acc[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) acc[j] = (v4d){0.0, 0.0, 0.0, 0.0};
+    const long ngroups = ((long)n + 3) >> 2;
+    const long gstride = (long)gridDim.x * 4;
+    for (long g0 = (long)blockIdx.x * 4 + wave; g0 < ngroups; g0 += kWgUnr * gstride) {
+        double x[kWgUnr], a[kWgUnr][NW];
+#pragma unroll
+        for (int u = 0; u < kWgUnr; ++u) {
+            const long row = 4 * (g0 + u * gstride) + kk;
+            const bool ok = row < n;
+            x[u] = (ok && m < k) ? V[row * ldv + m] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NW; ++j) a[u][j] = 0.0;
+            if (ok)
+                for (int e = dptr[row]; e < dptr[row + 1]; ++e) {
+                    const double v = dv[e];
+                    const int kr = dk[e];
+#pragma unroll
+                    for (int j = 0; j < NW; ++j) a[u][j] += v * ws.w[j][kr];
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < kWgUnr; ++u)
+#pragma unroll
+            for (int j = 0; j < NW; ++j) acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], a[u][j] * x[u], acc[j], 0, 0, 0);
+    }
+    if (wave > 0)
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sred[wave - 1][j][v][lane] = acc[j][v];
+    __syncthreads();
+    if (wave == 0) {
+        double *out = partials + (size_t)blockIdx.x * NW * k * k;
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double t = ((acc[j][v] + sred[0][j][v][lane]) + sred[1][j][v][lane]) + sred[2][j][v][lane];
+                const int r = kk + 4 * v, c = m;   // D[r][c]
+                if (r < k && c < k) out[(size_t)j * k * k + r * k + c] = t;
+            }
+    }
+}
+// out[j d + p] = f_p sum over the G partials of entry (j, a, b), p = (a, b) of the
+// column-wise lower triangle (b outer, a = b..k-1), f_p = 1 on the diagonal, sqrt 2 off it.
+// One workgroup per output: thread t sums partials t, t + 256, ... and the 256 sums are
+// added in a fixed tree order.
+__global__ __launch_bounds__(kWG) void k_wgram_finish(const double *__restrict__ part, int G, int k, int nw,
+                                                      double *__restrict__ out) {
+    __shared__ double red[kWG];
+    const int d = k * (k + 1) / 2;
+    const int o = blockIdx.x;
+    const int j = o / d;
+    int p = o - j * d, b = 0;
+    while (p >= k - b) p -= k - b, ++b;
+    const int a = b + p;
+    const size_t src = (size_t)j * k * k + a * k + b, stride = (size_t)nw * k * k;
+    double s = 0.0;
+    for (int g = threadIdx.x; g < G; g += kWG) s += part[g * stride + src];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = kWG / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[o] = (a == b) ? red[0] : 1.4142135623730951 * red[0];
+}
+void wgram(hipStream_t s, const RedScratch &rs, int n, const double *V, int ldv, int k, const int *dptr,
+           const int *dk, const double *dv, const double *const *w, int nw, double *out) {
+    if (nw <= 0) return;
+    int blocks = cdiv(n, 64 * kWgUnr);
+    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    if (blocks < 1) blocks = 1;
+    WeightPtrs ws{};
+    for (int j = 0; j < nw && j < kWgMaxW; ++j) ws.w[j] = w[j];
+    switch (nw) {
+    case 1: hipLaunchKernelGGL(k_wgram<1>, dim3(blocks), dim3(kWG), 0, s, n, V, ldv, k, dptr, dk, dv, ws, rs.partials); break;
+    case 2: hipLaunchKernelGGL(k_wgram<2>, dim3(blocks), dim3(kWG), 0, s, n, V, ldv, k, dptr, dk, dv, ws, rs.partials); break;
+    case 3: hipLaunchKernelGGL(k_wgram<3>, dim3(blocks), dim3(kWG), 0, s, n, V, ldv, k, dptr, dk, dv, ws, rs.partials); break;
+    default: hipLaunchKernelGGL(k_wgram<4>, dim3(blocks), dim3(kWG), 0, s, n, V, ldv, k, dptr, dk, dv, ws, rs.partials);
+    }
+    const int d = k * (k + 1) / 2;
+    hipLaunchKernelGGL(k_wgram_finish, dim3(nw * d), dim3(kWG), 0, s, rs.partials, blocks, k, nw, out);
+}
+
 __global__ __launch_bounds__(kWG) void k_lowrank_A(int m, const int *__restrict__ kptr, const int *__restrict__ ti,
                                                    const int *__restrict__ tj, const double *__restrict__ tv,
                                                    const double *__restrict__ V, int ldv, int kd,

@@ -600,11 +600,8 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         if (cyc == 0 || tol < 1e-7)
             small_eig(s, 16, h->TUU, 16, h->theta, h->Ysm, 16, 16, (cyc == 0 && orth_start) ? h->flag : nullptr);
         else diag_theta(s, h->TUU, 16, h->theta, h->Ysm);
-        nn_update(s, n, h->Ubuf, 16, 16, h->Ysm, 16, 16, h->Bm, ldb, 1.0, 0.0);
-        nn_update(s, n, h->W2, 16, 16, h->Ysm, 16, 16, h->Ubuf, 16, 1.0, 0.0);
-        neg_diag(s, h->theta, 16, h->Hd);
-        nn_update(s, n, h->Bm, ldb, 16, h->Hd, 16, 16, h->Ubuf, 16, 1.0, 1.0);
-        tn_reduce(s, h->rs, n, h->Ubuf, 16, 16, h->Ubuf, 16, 16, h->RtR, 16, 1.0, 0.0);
+        // Ritz vectors B = U Y into the basis, residuals R = M U Y - B Theta over U, R^T R
+        rr_update(s, h->rs, n, h->Ubuf, h->W2, h->Ysm, h->theta, h->Bm, ldb, h->Ubuf, h->RtR);
         lanczos_restart_prep(s, h->RtR, h->theta, kc, tol, tol_rest, h->res, h->flag, h->Zc, h->sc + SC_SCALE);
         int conv = 0;
         HIPCHK(hipMemcpyAsync(&conv, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -674,6 +671,21 @@ constexpr int kCertifyMinCycles = 2;
 // which no candidate passes the descent test)
 constexpr int kStallWindow = 25;
 
+// Master-QP reductions (App. B.2): Q11 = sum_k g_k g_k^T when do_q11, then G^T w_j.  With
+// diagonal constraints only, G^T w goes through the weighted Gram of V (wgram: one sweep over
+// the n rows instead of the m constraint rows, no svec rows formed); otherwise qp_gram forms
+// g_k per constraint row.  Same output layout either way.
+void qp_gram_w(usbs_handle *h, const double *V, int k, const double *const *ws, int nw, double *out, int do_q11) {
+    hipStream_t s = h->stream;
+    const int d = k * (k + 1) / 2;
+    if (!h->has_offc) {
+        if (do_q11) qp_gram(s, h->rs, h->m, h->kptr, h->ti, h->tj, h->tv, V, 16, k, nullptr, 0, out, 1);
+        wgram(s, h->rs, h->n, V, 16, k, h->dptr, h->dk, h->dv, ws, nw, out + (do_q11 ? d * (d + 1) / 2 : 0));
+    } else {
+        qp_gram(s, h->rs, h->m, h->kptr, h->ti, h->tj, h->tv, V, 16, k, ws, nw, out, do_q11);
+    }
+}
+
 void iterate(usbs_handle *h) {
     hipStream_t s = h->stream;
     const int n = h->n, m = h->m, k = h->k, kc = h->kc, kp = h->kp, r = h->r;
@@ -685,7 +697,7 @@ void iterate(usbs_handle *h) {
     // reductions of the master QP: sum g g^T, G^T zbar, G^T y, G^T b
     {
         const double *ws[3] = {h->zbar, h->y, h->b};
-        qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 3, h->raw, 1);
+        qp_gram_w(h, h->V, k, ws, 3, h->raw, 1);
         const double *a[3] = {h->zbar, h->y, h->b}, *bb[3] = {h->zbar, h->zbar, h->zbar};
         dots(s, h->rs, m, a, bb, 3, h->sc + SC_ZZ);
     }
@@ -695,7 +707,7 @@ void iterate(usbs_handle *h) {
     for (int pass = 0; pass < 50; ++pass) {
         if (pass > 0) {
             const double *ws[1] = {h->nu};
-            qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 1, h->Gy, 0);
+            qp_gram_w(h, h->V, k, ws, 1, h->Gy, 0);
             // G^T nu lands after the d*d block of Gy; copy into raw's 4th vector slot
             HIPCHK(hipMemcpyAsync(h->raw + d * (d + 1) / 2 + 3 * d, h->Gy, d * sizeof(double),
                                   hipMemcpyDeviceToDevice, s));
@@ -727,7 +739,7 @@ void iterate(usbs_handle *h) {
         const double *a[3] = {h->b, h->yc, h->evec}, *bb[3] = {h->yc, h->zbar, h->evec};
         dots(s, h->rs, m, a, bb, 3, h->sc + SC_BY);   // SC_BY, SC_YZ, SC_DIST2 are consecutive
         const double *ws[1] = {h->yc};
-        qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, ws, 1, h->Gy, 0);
+        qp_gram_w(h, h->V, k, ws, 1, h->Gy, 0);
         fhat_prep(s, k, h->VCV, h->Gy, h->sc);
     }
     // eigen step at the candidate: the previous Ritz block with its last two columns
@@ -1420,7 +1432,7 @@ int usbs_op_qp_data(usbs_handle *h, const double *V_dev, int32_t k, const double
         apply_C(h, h->Zp, 16, h->CV, 16, k);
         tn_reduce(s, h->rs, n, h->Zp, 16, k, h->CV, 16, k, h->VCV, k, 1.0, 0.0);
         const double *ws[3] = {zbar_dev, y_dev, w_dev};
-        qp_gram(s, h->rs, m, h->kptr, h->ti, h->tj, h->tv, h->Zp, 16, k, ws, 3, h->raw, 1);
+        qp_gram_w(h, h->Zp, k, ws, 3, h->raw, 1);
         const double *a[3] = {zbar_dev, y_dev, w_dev}, *bb[3] = {zbar_dev, zbar_dev, zbar_dev};
         std::vector<double> sc(SC_COUNT, 0.0);
         HIPCHK(hipMemcpyAsync(sc.data(), h->sc, SC_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
