@@ -523,10 +523,25 @@ void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave
                        floor_ref);
 }
 
+// the same reduction with an FP32 B (the sketch's test matrix), widened on load
+__global__ __launch_bounds__(kWG) void k_tn_mfma_f(int n, const double *__restrict__ A, int lda, int ca,
+                                                   const float *__restrict__ B, int ldb, int cb,
+                                                   double *__restrict__ partials) {
+    __shared__ TnWork w;
+    wg_tn_mfma<float, 4, false>(n, A, lda, ca, B, ldb, cb, blockIdx.x, gridDim.x,
+                                partials + (size_t)blockIdx.x * ca * cb, cb, 1.0, 0.0, &w);
+}
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca, const float *B,
                  int ldb, int cb, double *H, int ldh, double alpha) {
-    const int blocks = tn_blocks(rs, n);
-    hipLaunchKernelGGL((k_tn_reduce<float, 0, false>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    int blocks;
+    if (cb <= 16 && ca <= kMaxBasis) {
+        blocks = mfma_blocks(rs, n);
+        hipLaunchKernelGGL(k_tn_mfma_f, dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb, rs.partials);
+    } else {
+        blocks = tn_blocks(rs, n);
+        hipLaunchKernelGGL((k_tn_reduce<float, 0, false>), dim3(blocks), dim3(kWG), 0, s, n, A, lda, ca, B, ldb, cb,
+                           rs.partials);
+    }
     red_finish(s, rs.partials, blocks, ca * cb, H, cb, ldh, alpha, 0.0);
 }
 
@@ -1037,8 +1052,13 @@ __global__ __launch_bounds__(kWG) void k_wgram_finish(const double *__restrict__
 void wgram(hipStream_t s, const RedScratch &rs, int n, const double *V, int ldv, int k, const int *dptr,
            const int *dk, const double *dv, const double *const *w, int nw, double *out) {
     if (nw <= 0) return;
-    int blocks = cdiv(n, 64 * kWgUnr);
-    if (blocks > rs.max_blocks) blocks = rs.max_blocks;
+    // each row costs a chain of dependent loads (triplet range, row index, weight), so the
+    // grid is as large as the partials' space allows (nw k^2 doubles per workgroup), up to
+    // 4096 workgroups, to keep many chains in flight
+    const long room = (long)rs.max_blocks * rs.max_elems / ((long)nw * k * k);
+    int blocks = cdiv(n, 64);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks > room) blocks = (int)room;
     if (blocks < 1) blocks = 1;
     WeightPtrs ws{};
     for (int j = 0; j < nw && j < kWgMaxW; ++j) ws.w[j] = w[j];

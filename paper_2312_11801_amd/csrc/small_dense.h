@@ -11,6 +11,8 @@
 
 namespace usbs {
 
+typedef double dv4 __attribute__((ext_vector_type(4)));   // one lane's FP64 MFMA accumulator
+
 // ---------------------------------------------------------------------------
 // wavefront reductions on DPP lane permutations (VALU, no LDS round trip).
 // Within a row of 16 lanes: quad_perm [1,0,3,2], quad_perm [2,3,0,1],
@@ -65,6 +67,12 @@ __device__ __forceinline__ double wave_allsum(double v) {
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+// orders this wavefront's own LDS accesses (they execute in order) without waiting for its
+// outstanding memory operations
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -367,6 +375,81 @@ __device__ __forceinline__ void wave_tri_inv(int k, const double *L, int ld, dou
     wave_sync();
 }
 
+// For the symmetric positive definite k x k LDS matrix X (k <= kMaxK), on one wavefront:
+// Li = L^{-1} for its lower Cholesky factor L (LDS, ld ldi, k x k) and, if Xi is not null,
+// X^{-1} = Li^T Li (LDS, ld ldxi).  Lane r < k keeps row r of X, then of L, then of L^{-1}
+// in registers and reads other rows' entries with readlane (uniform lane index): neither the
+// factorisation nor the inversion makes an LDS round trip.  X^{-1} is one 16 x 16 x 16 FP64
+// MFMA product.  Returns false if a pivot is not positive (it is replaced by 1; the results
+// are then not to be used).  All 64 lanes must call.
+__device__ __forceinline__ bool wave_chol_inv(int k, const double *X, int ldx, double *Li, int ldi, double *Xi,
+                                              int ldxi) {
+    const int r = threadIdx.x & 63;
+    double a[kMaxK];
+#pragma unroll
+    for (int c = 0; c < kMaxK; ++c) a[c] = (r < k && c < k) ? X[r * ldx + c] : 0.0;
+    bool ok = true;
+    double myd = 1.0;   // L[r][r]
+    // right-looking Cholesky: after step j, a[j] = L[r][j] at lanes r > j
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        if (j < k) {
+            double piv = lane_read(a[j], j);
+            if (!(piv > 0.0)) {
+                ok = false;
+                piv = 1.0;
+            }
+            const double dd = sqrt(piv), inv = 1.0 / dd;
+            const double lj = (r > j) ? a[j] * inv : 0.0;
+            a[j] = lj;
+            if (r == j) myd = dd;
+#pragma unroll
+            for (int c = j + 1; c < kMaxK; ++c)
+                if (c < k) a[c] -= lj * lane_read(lj, c);
+        }
+    }
+    // L^{-1} by rows: z holds e_r - sum_{l < j} L[r][l] Li[l][:]; at step j row j is final
+    // (z_j / L[j][j], read from lane j) and the rows below subtract L[r][j] times it
+    const double myinv = 1.0 / myd;
+    double z[kMaxK];
+#pragma unroll
+    for (int c = 0; c < kMaxK; ++c) z[c] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        if (j < k) {
+            const double lrj = a[j];
+#pragma unroll
+            for (int c = 0; c <= j; ++c) {
+                const double lic = lane_read(z[c] * myinv, j);
+                if (r > j) z[c] -= lrj * lic;
+            }
+        }
+    }
+    if (r < k)
+#pragma unroll
+        for (int c = 0; c < kMaxK; ++c)
+            if (c < k) Li[r * ldi + c] = z[c] * myinv;
+    wave_sync();
+    if (Xi) {
+        // X^{-1}[i][j] = sum_l Li[l][i] Li[l][j]: operand entry (l, i) of both MFMA inputs
+        const int m = r & 15, kq = r >> 4;
+        dv4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int l = 4 * q + kq;
+            const double x = (l < k && m < k) ? Li[l * ldi + m] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = kq + 4 * v;
+            if (i < k && m < k) Xi[i * ldxi + m] = acc[v];
+        }
+        wave_sync();
+    }
+    return ok;
+}
+
 // X = Li D Li^T (D symmetric), via Y = Li D
 __device__ __forceinline__ void wave_congruence(int k, const double *Li, int ldi, const double *D, int ldd,
                                                 double *Y, double *X, int ldx) {
@@ -480,6 +563,118 @@ __device__ __forceinline__ double wave_min_eig(int k, double *X, int ldx, Jacobi
     return lo;
 }
 
+// Lower bound of the smallest eigenvalue of X = Li D Li^T (Li lower triangular, D symmetric,
+// k x k in LDS, k <= kMaxK) on one wavefront, to a relative 1e-8 (the IPM's step length
+// takes 0.95 of the distance to the boundary and needs no more):
+//  * X from two 16 x 16 x 16 FP64 MFMA products: the accumulators of D Li^T are the entries
+//    (Li D)[m][kq + 4v], which is exactly the left operand of (Li D) Li^T; X is staged once
+//    through Xs (16 x 16 LDS) to give lane r its row r;
+//  * Householder reduction to tridiagonal form with row r in lane r's registers and the
+//    entries of v and w read from their lanes by readlane (no LDS round trip);
+//  * 64-section on Sturm counts of the tridiagonal matrix, whose entries every lane holds.
+// All 64 lanes must call.
+__device__ __forceinline__ double wave_congruence_min_eig(int k, const double *Li, int ldi, const double *D, int ldd,
+                                                          double *Xs) {
+    const int lane = threadIdx.x & 63;
+    const int m = lane & 15, kq = lane >> 4;
+    dv4 z = {0.0, 0.0, 0.0, 0.0};
+    double lt[4];   // Li[m][4q + kq]: the right operand of both products
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int c = 4 * q + kq;
+        const double x = (m < k && c < k) ? D[m * ldd + c] : 0.0;
+        lt[q] = (m < k && c < k) ? Li[m * ldi + c] : 0.0;
+        z = __builtin_amdgcn_mfma_f64_16x16x4f64(x, lt[q], z, 0, 0, 0);
+    }
+    dv4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(z[q], lt[q], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Xs[(kq + 4 * v) * 16 + m] = acc[v];
+    wave_lds_order();
+    double a[kMaxK];
+#pragma unroll
+    for (int c = 0; c < kMaxK; ++c) a[c] = (lane < k && c < k) ? Xs[lane * 16 + c] : 0.0;
+    wave_lds_order();   // Xs may be rewritten by the caller
+    double dd[kMaxK], ee[kMaxK];
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        dd[j] = 0.0;
+        ee[j] = 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxK; ++j) {
+        if (j + 2 < k) {
+            const double x = (lane > j) ? a[j] : 0.0;
+            const double nx2 = wave_allsum(x * x);
+            const double xf = lane_read(a[j], j + 1);
+            const double nx = sqrt(nx2);
+            double alpha = (xf >= 0.0) ? -nx : nx;
+            const double vn2 = nx2 - xf * xf + (xf - alpha) * (xf - alpha);
+            const double b = (nx2 > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+            if (b == 0.0) alpha = xf;
+            dd[j] = lane_read(a[j], j);
+            ee[j] = alpha;
+            const double v = (lane == j + 1) ? xf - alpha : ((lane > j + 1) ? a[j] : 0.0);
+            if (b != 0.0) {
+                double p = 0.0;
+#pragma unroll
+                for (int c = j + 1; c < kMaxK; ++c)
+                    if (c < k) p += a[c] * lane_read(v, c);
+                p = (lane > j) ? b * p : 0.0;
+                const double K = 0.5 * b * wave_allsum(p * v);
+                const double w = p - K * v;
+#pragma unroll
+                for (int c = j + 1; c < kMaxK; ++c)
+                    if (c < k) a[c] -= v * lane_read(w, c) + w * lane_read(v, c);
+            }
+        } else if (j + 2 == k) {
+            dd[j] = lane_read(a[j], j);
+            ee[j] = lane_read(a[j], j + 1);
+        } else if (j + 1 == k) {
+            dd[j] = lane_read(a[j], j);
+        }
+    }
+    // Gershgorin interval
+    double lo = 1e300, hi = -1e300;
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i)
+        if (i < k) {
+            const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < k ? fabs(ee[i]) : 0.0);
+            lo = fmin(lo, dd[i] - r);
+            hi = fmax(hi, dd[i] + r);
+        }
+    const double tn = fmax(fmax(fabs(lo), fabs(hi)), 1e-300);
+    lo -= 4e-16 * tn;
+    hi += 4e-16 * tn;
+    const double pivmin = fmax(1e-290, 1e-300 * tn * tn);
+    double e2[kMaxK];
+#pragma unroll
+    for (int i = 0; i < kMaxK; ++i) e2[i] = ee[i] * ee[i];
+    for (int it = 0; it < 12; ++it) {
+        const double x = lo + (hi - lo) * (double)lane * (1.0 / 64.0);
+        int cnt = 0;
+        double q = dd[0] - x;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += (q < 0.0);
+#pragma unroll
+        for (int i = 1; i < kMaxK; ++i)
+            if (i < k) {
+                q = dd[i] - x - e2[i - 1] / q;
+                if (fabs(q) < pivmin) q = -pivmin;
+                cnt += (q < 0.0);
+            }
+        if (lane == 0) cnt = -1;   // lane 0 evaluates lo itself: no information
+        // lambda_min < x  iff  cnt >= 1
+        const double nlo = wave_max((cnt == 0) ? x : -1e308);
+        const double nhi = wave_min((cnt >= 1) ? x : 1e308);
+        if (nlo > -1e308) lo = nlo;
+        if (nhi < 1e308) hi = nhi;
+        if (hi - lo <= 1e-8 * fmax(fabs(lo), fabs(hi)) + 1e-16 * tn) break;
+    }
+    return lo;
+}
+
 // ---------------------------------------------------------------------------
 // Master QP (App. B.2, eq. compressed_subprob_2):
 //   min 1/2 s'Q11 s + eta q12's + 1/2 q22 eta^2 + h1's + h2 eta
@@ -496,40 +691,23 @@ __device__ __forceinline__ double wave_min_eig(int k, double *X, int ldx, Jacobi
 // well gives the paper's eq. delta_S_linear_system2 -- the same direction.
 // ---------------------------------------------------------------------------
 constexpr int kMaxD = kMaxSvec + 1;
-// row stride of the Newton matrix: 7 padding columns take the overrun of the last
-// 8-entry chunk of a row in the Cholesky update
-constexpr int kIpmLd = kMaxD + 8;
-
-// row[l] -= m M_lj for l in [lb, le), with M_lj = col[l * ld] read by every lane of the
-// wavefront (one broadcast address).  Chunks of 8: all loads of a chunk are issued before
-// its stores.  le - lb is a multiple of 8 unless le = D; there the last chunk runs up to 7
-// entries into the row's padding and reads M_lj of row D - 1 for them.
-__device__ __forceinline__ void chol_chunk_update(double *row, double m, const double *col, int ld, int lb, int le,
-                                                  int D) {
-    for (int l = lb; l < le; l += 8) {
-        double x[8], c[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int lc = (l + q < D) ? l + q : D - 1;
-            x[q] = row[l + q];
-            c[q] = col[lc * ld];
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] -= m * c[q];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) row[l + q] = x[q];
-    }
-}
+// the Newton matrix bordered by its right-hand side, (D + 1) x (D + 1), in registers: a 16 x 16
+// thread grid with kIpmR x kIpmR entries per thread
+constexpr int kIpmR = (kMaxD + 1 + 15) / 16;
+// row stride of the Newton matrix and of the factor's rows (odd: lanes reading one column
+// of the factor fall on different banks)
+constexpr int kIpmLd = 16 * kIpmR + 7;
 
 struct IpmShared {
-    double M[(kMaxD + 1) * kIpmLd];   // row kMaxD: spare row for lanes past the last row in the Cholesky
+    double M[kMaxD * kIpmLd];   // the Newton matrix (lower triangle), then the rows of its factor
     double Q11[kMaxSvec * kMaxSvec];   // staged once per solve
     double S[kMaxK * kMaxK], T[kMaxK * kMaxK], Si[kMaxK * kMaxK];
-    double LS[kMaxK * kMaxK], LSi[kMaxK * kMaxK], LT[kMaxK * kMaxK], LTi[kMaxK * kMaxK];
+    double LSi[kMaxK * kMaxK], LTi[kMaxK * kMaxK];
     double dS[kMaxK * kMaxK], dT[kMaxK * kMaxK];
     double Y0[16 * 16], X0[16 * 16], Y1[16 * 16], X1[16 * 16];
     double s[kMaxSvec], t[kMaxSvec], F1[kMaxSvec], q12[kMaxSvec], h1[kMaxSvec], svSi[kMaxSvec];
     double rhs[kMaxD], dt[kMaxSvec];
+    double ldiag[kMaxD];   // diagonal of the factor
     int pi[kMaxSvec], pj[kMaxSvec];
     double red[kWG];
     JacobiWork<64, 16> js0, js1;
@@ -679,32 +857,13 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
             else if (it >= a.max_iter && !(sh->mu < a.tol_mu && sh->maxres < a.tol_res)) status = 1;
             break;
         }
-        // S^{-1} (wave 0), L_T (wave 1)
+        // L_S^{-1} and S^{-1} (wave 0), L_T^{-1} (wave 1)
         if (wave == 0) {
-            for (int e = lane; e < k * k; e += 64) {
-                const int i = e / k, j = e - i * k;
-                sh->LS[i * kMaxK + j] = sh->S[i * kMaxK + j];
-            }
-            wave_sync();
-            const bool ok = wave_chol(k, sh->LS, kMaxK);
+            const bool ok = wave_chol_inv(k, sh->S, kMaxK, sh->LSi, kMaxK, sh->Si, kMaxK);
             if (lane == 0) sh->okS = ok;
-            wave_tri_inv(k, sh->LS, kMaxK, sh->LSi, kMaxK);
-            for (int e = lane; e < k * k; e += 64) {
-                const int i = e / k, j = e - i * k;
-                double v = 0.0;
-                const int lo = i > j ? i : j;
-                for (int l = lo; l < k; ++l) v += sh->LSi[l * kMaxK + i] * sh->LSi[l * kMaxK + j];
-                sh->Si[i * kMaxK + j] = v;
-            }
         } else if (wave == 1) {
-            for (int e = lane; e < k * k; e += 64) {
-                const int i = e / k, j = e - i * k;
-                sh->LT[i * kMaxK + j] = sh->T[i * kMaxK + j];
-            }
-            wave_sync();
-            const bool ok = wave_chol(k, sh->LT, kMaxK);
+            const bool ok = wave_chol_inv(k, sh->T, kMaxK, sh->LTi, kMaxK, nullptr, 0);
             if (lane == 0) sh->okT = ok;
-            wave_tri_inv(k, sh->LT, kMaxK, sh->LTi, kMaxK);
         }
         __syncthreads();
         if (!sh->okS || !sh->okT) {
@@ -753,67 +912,85 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
         }
         if (tid == 0) sh->okM = 1;
         __syncthreads();
-        // Cholesky of M (lower, right-looking), one barrier per column: every thread reads
-        // the pivot itself and updates with the unscaled column (M_il -= M_ij M_lj / piv);
-        // column j - 1, no longer read, is scaled during step j.  The trailing columns
-        // l = j+1 .. D-1 are split over the four wavefronts in ranges of a multiple of 8
-        // entries; lane r owns rows j+1+r and j+65+r and updates its row across its
-        // wavefront's range in chunks of 8.  Entries with l > i fall in the strict upper
-        // triangle or the padding, which nothing reads, and lanes past the last row work on
-        // the spare row kMaxD, so the loads and stores carry no predicate.
+        // Cholesky of the bordered matrix [M rhs; rhs^T 0] = L L^T, right-looking, column by
+        // column: its last row is y = L_M^{-1} rhs, so the forward solve comes with the
+        // factorisation.  Thread (tr, tc) = (tid >> 4, tid & 15) keeps entries
+        // [tr + 16 i][tc + 16 q] of the full symmetric matrix in registers.  Row j (= column
+        // j) lives in the 16 lanes of row group j & 15: they scale it by the pivot's square
+        // root into row j of the factor's storage (column j of L, zero at indices <= j);
+        // after one barrier every thread subtracts the outer product of that column from its
+        // entries (entries in finished rows or columns meet a zero factor).  One workgroup
+        // barrier per column, no matrix traffic through LDS.
         {
-            double sp = 1.0;   // square root of the previous pivot
-            for (int j = 0; j <= D; ++j) {
-                if (j > 0) {
-                    const int jp = j - 1;
-                    for (int i = jp + 1 + tid; i < D; i += kWG) sh->M[i * ldm + jp] /= sp;
-                    if (tid == 0) sh->M[jp * ldm + jp] = sp;
+            const int tr = tid >> 4, tc = tid & 15, D1 = D + 1;
+            double am[kIpmR][kIpmR];
+#pragma unroll
+            for (int i = 0; i < kIpmR; ++i)
+#pragma unroll
+                for (int q = 0; q < kIpmR; ++q) {
+                    const int r = tr + 16 * i, c = tc + 16 * q;
+                    double v = 0.0;
+                    if (r < D && c < D) v = (r >= c) ? sh->M[r * ldm + c] : sh->M[c * ldm + r];
+                    else if (r == D && c < D) v = sh->rhs[c];
+                    else if (c == D && r < D) v = sh->rhs[r];
+                    am[i][q] = v;
                 }
-                if (j == D) break;
-                double piv = sh->M[j * ldm + j];
-                if (!(piv > 0.0)) {
-                    if (tid == 0) sh->okM = 0;
-                    piv = 1.0;
-                }
-                const double ipiv = 1.0 / piv;
-                const int span = ((D - j - 1 + 31) / 32) * 8;   // columns per wavefront
-                const int lb = j + 1 + wave * span, le = (lb + span < D) ? lb + span : D;
-                if (lb < le)
-                    for (int h = 0; h < 2 && j + 1 + 64 * h < D; ++h) {
-                        const int i = j + 1 + lane + 64 * h;
-                        const double m = (i < D) ? sh->M[i * ldm + j] * ipiv : 0.0;
-                        chol_chunk_update(&sh->M[(i < D ? i : kMaxD) * ldm], m, &sh->M[j], ldm, lb, le, D);
+            __syncthreads();   // sh->M now receives the factor's columns as rows
+#pragma unroll
+            for (int jb = 0; jb < kIpmR; ++jb) {
+                for (int jj = 0; jj < 16; ++jj) {
+                    const int j = 16 * jb + jj;
+                    if (j >= D) break;
+                    if (tr == jj) {
+                        double piv = row16_sum((tc == jj) ? am[jb][jb] : 0.0);   // one nonzero term
+                        if (!(piv > 0.0)) {
+                            if (tc == 0) sh->okM = 0;
+                            piv = 1.0;
+                        }
+                        const double dd = sqrt(piv), inv = 1.0 / dd;
+#pragma unroll
+                        for (int q = 0; q < kIpmR; ++q) {
+                            const int c = tc + 16 * q;
+                            sh->M[j * ldm + c] = (c > j && c < D1) ? am[jb][q] * inv : 0.0;
+                        }
+                        if (tc == 0) sh->ldiag[j] = dd;
                     }
-                sp = sqrt(piv);
-                __syncthreads();
+                    __syncthreads();
+                    double lr[kIpmR], lc[kIpmR];
+#pragma unroll
+                    for (int i = 0; i < kIpmR; ++i) {
+                        lr[i] = sh->M[j * ldm + tr + 16 * i];
+                        lc[i] = sh->M[j * ldm + tc + 16 * i];
+                    }
+#pragma unroll
+                    for (int i = 0; i < kIpmR; ++i)
+#pragma unroll
+                        for (int q = 0; q < kIpmR; ++q) am[i][q] -= lr[i] * lc[q];
+                }
             }
-            __syncthreads();
         }
+        __syncthreads();
         if (!sh->okM) {
             status = 2;
             break;
         }
-        // solves L L^T x = rhs on wavefront 0: lane l keeps rows l and l + 64 of the right-hand
-        // side in registers; each solved component is broadcast from its lane (no LDS round
-        // trip or divide on the dependent chain: the pivots' reciprocals are formed first)
+        // back substitution L^T x = y on wavefront 0: lane l keeps rows l and l + 64 in
+        // registers; each solved component is broadcast from its lane and the pivots'
+        // reciprocals are formed first (no LDS round trip or divide on the dependent chain).
+        // L[j][i] (i < j) is entry j of the factor's row i; y_i is its entry D.
         if (wave == 0) {
             const int i0 = lane, i1 = lane + 64;
-            double r0 = (i0 < D) ? sh->rhs[i0] : 0.0, r1 = (i1 < D) ? sh->rhs[i1] : 0.0;
-            const double v0 = (i0 < D) ? 1.0 / sh->M[i0 * ldm + i0] : 0.0;
-            const double v1 = (i1 < D) ? 1.0 / sh->M[i1 * ldm + i1] : 0.0;
-            for (int j = 0; j < D; ++j) {   // forward: L y = rhs
+            double r0 = (i0 < D) ? sh->M[i0 * ldm + D] : 0.0, r1 = (i1 < D) ? sh->M[i1 * ldm + D] : 0.0;
+            const double v0 = (i0 < D) ? 1.0 / sh->ldiag[i0] : 0.0;
+            const double v1 = (i1 < D) ? 1.0 / sh->ldiag[i1] : 0.0;
+            // the factor's entries for step j - 1 are loaded during step j
+            double n0 = (i0 < D - 1) ? sh->M[i0 * ldm + D - 1] : 0.0;
+            double n1 = (i1 < D - 1) ? sh->M[i1 * ldm + D - 1] : 0.0;
+            for (int j = D - 1; j >= 0; --j) {
+                const double m0 = n0, m1 = n1;
+                n0 = (i0 < j - 1) ? sh->M[i0 * ldm + j - 1] : 0.0;
+                n1 = (i1 < j - 1) ? sh->M[i1 * ldm + j - 1] : 0.0;
                 const double xj = (j < 64) ? lane_read(r0, j) * lane_read(v0, j) : lane_read(r1, j - 64) * lane_read(v1, j - 64);
-                const double m0 = (i0 > j && i0 < D) ? sh->M[i0 * ldm + j] : 0.0;
-                const double m1 = (i1 > j && i1 < D) ? sh->M[i1 * ldm + j] : 0.0;
-                if (i0 == j) r0 = xj;
-                if (i1 == j) r1 = xj;
-                r0 -= m0 * xj;
-                r1 -= m1 * xj;
-            }
-            for (int j = D - 1; j >= 0; --j) {   // backward: L^T x = y
-                const double xj = (j < 64) ? lane_read(r0, j) * lane_read(v0, j) : lane_read(r1, j - 64) * lane_read(v1, j - 64);
-                const double m0 = (i0 < j) ? sh->M[j * ldm + i0] : 0.0;
-                const double m1 = (i1 < j) ? sh->M[j * ldm + i1] : 0.0;
                 if (i0 == j) r0 = xj;
                 if (i1 == j) r1 = xj;
                 r0 -= m0 * xj;
@@ -871,12 +1048,10 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
         __syncthreads();
         // step lengths: lambda_min(L_S^{-1} dS L_S^{-T}) on wave 0, same for T on wave 1
         if (wave == 0) {
-            wave_congruence(k, sh->LSi, kMaxK, sh->dS, kMaxK, sh->Y0, sh->X0, 16);
-            const double lm = wave_min_eig(k, sh->X0, 16, &sh->js0);
+            const double lm = wave_congruence_min_eig(k, sh->LSi, kMaxK, sh->dS, kMaxK, sh->X0);
             if (lane == 0) sh->dmaxS = (lm < 0.0) ? -1.0 / lm : 1e300;
         } else if (wave == 1) {
-            wave_congruence(k, sh->LTi, kMaxK, sh->dT, kMaxK, sh->Y1, sh->X1, 16);
-            const double lm = wave_min_eig(k, sh->X1, 16, &sh->js1);
+            const double lm = wave_congruence_min_eig(k, sh->LTi, kMaxK, sh->dT, kMaxK, sh->X1);
             if (lane == 0) sh->dmaxT = (lm < 0.0) ? -1.0 / lm : 1e300;
         }
         __syncthreads();

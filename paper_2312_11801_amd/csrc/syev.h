@@ -3,8 +3,9 @@
 // Lanczos solver and the other small eigenproblems of the iteration
 // (eigen-split of S, lambda_max(V^T M V), the Nystrom core).
 //
-//   1. Householder reduction to tridiagonal form, A = Q T Q^T, the reflectors
-//      kept in the strictly lower part of A (four barriers per column);
+//   1. Householder reduction to tridiagonal form, A = Q T Q^T, with the matrix
+//      in registers (a 16 x 16 thread grid, 5 x 5 entries per thread) and the
+//      reflectors stored as the rows of ws->A (two barriers per column);
 //   2. eigenvalues of T by 16-section: 16 lanes share one eigenvalue and
 //      evaluate Sturm counts at 15 interior points of its bracket, which
 //      shrinks 16x per step (16 steps from the Gershgorin interval);
@@ -12,7 +13,8 @@
 //      Gaussian elimination with partial pivoting on T - lambda I);
 //   4. Cholesky-QR twice on the eigenvectors (vectors of a cluster become an
 //      orthonormal basis of its invariant subspace);
-//   5. back-transformation by the reflectors (16 lanes per vector, shuffles).
+//   5. back-transformation by the reflectors (16 lanes per vector, the vector in
+//      registers, sums across the lanes by DPP).
 #pragma once
 #include <hip/hip_runtime.h>
 #include "kernels.h"
@@ -22,12 +24,14 @@ namespace usbs {
 
 constexpr int kSyevMaxN = kMaxBasis;
 constexpr int kSyevMaxV = 16;
+constexpr int kSyR = kSyevMaxN / 16;   // entries per thread and dimension in the register grid
+static_assert(kSyevMaxN % 16 == 0, "the register grid tiles the matrix by 16");
 
 struct SyevWork {
     double A[kSyevMaxN][kSyevMaxN + 1];
     double d[kSyevMaxN], e[kSyevMaxN], e2[kSyevMaxN], beta[kSyevMaxN];
-    double p[kSyevMaxN];
-    double vw[4][kSyevMaxN];   // per-wave copy of the current Householder vector
+    double p[2][kSyevMaxN];   // p = b A v of the current column (two buffers: columns alternate)
+    double vp[2][4];          // per-wavefront shares of v^T p
     double lam[kSyevMaxV];
     double X[kSyevMaxV][kSyevMaxN + 1];
     double U0[kSyevMaxV][kSyevMaxN], U1[kSyevMaxV][kSyevMaxN], U2[kSyevMaxV][kSyevMaxN];
@@ -59,93 +63,128 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     // ---- 1. tridiagonalisation ----
-    // Column j: every wave forms the reflector from column j itself (identical
-    // arithmetic, so all waves hold the same v) into its own LDS row vw[wave]; the
-    // rows of p = b A22 v are split over the workgroup; after one barrier every wave
-    // forms K = (b/2) p^T v and updates its rows of A22 -= v w^T + w v^T with
-    // w = p - K v.  Two barriers per column.
-    for (int j = 0; j + 2 < N; ++j) {
-        const int m = N - j - 1;
-        double *vv = ws->vw[wave];
-        const double x0 = (lane < m) ? ws->A[j + 1 + lane][j] : 0.0;
-        const double x1 = (lane + 64 < m) ? ws->A[j + 1 + lane + 64][j] : 0.0;
-        const double nx2 = wave_allsum(x0 * x0 + x1 * x1);
-        const double xf = ws->A[j + 1][j];
-        const double nx = sqrt(nx2);
-        double alpha = (xf >= 0.0) ? -nx : nx;
-        const double vn2 = nx2 - xf * xf + (xf - alpha) * (xf - alpha);
-        const double b = (nx2 > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
-        if (b == 0.0) alpha = xf;
-        if (lane < m) vv[lane] = (lane == 0) ? xf - alpha : x0;
-        if (lane + 64 < m) vv[lane + 64] = x1;
-        wave_sync();
-        if (b != 0.0) {
-            // p = b A22 v: 4 lanes per row, each over a quarter of the columns
-            {
-                const int q4 = tid & 3;
-                for (int r = tid >> 2; r < ((m + 63) & ~63); r += kWG / 4) {
-                    double s = 0.0;
-                    if (r < m) {
-                        const double *row = &ws->A[j + 1 + r][j + 1];
-#pragma unroll 4
-                        for (int q = q4; q < m; q += 4) s += row[q] * vv[q];
+    // Thread (tr, tc) = (tid >> 4, tid & 15) keeps A[tr + 16 i][tc + 16 q], i, q < kSyR, in
+    // registers.  Row j (= column j) lives in the 16 lanes of row group j & 15, one DPP row of
+    // one wavefront: they form the reflector H = I - b v v^T that zeroes A[j + 2:, j] from
+    // their own registers and store v (zero at indices <= j and >= N) as row j of ws->A.
+    // After a barrier every thread forms its share of p = b A v over its columns and sums it
+    // across its row group; five lanes of each group publish p at the group's rows, and every
+    // wavefront its share of v^T p.  After a second barrier every thread applies
+    // A -= v w^T + w v^T, w = p - (b/2)(p^T v) v, to its registers.  Rows and columns <= j
+    // are left alone (v and p vanish there).
+    {
+        const int tr = tid >> 4, tc = tid & 15;
+        double a[kSyR][kSyR];
+#pragma unroll
+        for (int i = 0; i < kSyR; ++i)
+#pragma unroll
+            for (int q = 0; q < kSyR; ++q) {
+                const int r = tr + 16 * i, c = tc + 16 * q;
+                a[i][q] = (r < N && c < N) ? ws->A[r][c] : 0.0;
+            }
+        __syncthreads();   // ws->A now receives the reflectors
+#pragma unroll
+        for (int jb = 0; jb < kSyR; ++jb) {
+            for (int jj = 0; jj < 16; ++jj) {
+                const int j = 16 * jb + jj;
+                if (j + 2 >= N) break;
+                const int par = j & 1;
+                if (tr == jj) {
+                    // row j: a[jb][q] = A[j][tc + 16 q]
+                    double nx2 = 0.0, xf = 0.0;
+#pragma unroll
+                    for (int q = 0; q < kSyR; ++q) {
+                        const int c = tc + 16 * q;
+                        const double x = a[jb][q];
+                        nx2 += (c > j) ? x * x : 0.0;
+                        xf += (c == j + 1) ? x : 0.0;
                     }
-                    s = quad_sum(s);
-                    if (r < m && q4 == 0) ws->p[r] = b * s;
+                    nx2 = row16_sum(nx2);
+                    xf = row16_sum(xf);   // one nonzero term: exact
+                    const double nx = sqrt(nx2);
+                    double alpha = (xf >= 0.0) ? -nx : nx;
+                    const double vn2 = nx2 - xf * xf + (xf - alpha) * (xf - alpha);
+                    const double b = (nx2 > 0.0 && vn2 > 0.0) ? 2.0 / vn2 : 0.0;
+                    if (b == 0.0) alpha = xf;
+#pragma unroll
+                    for (int q = 0; q < kSyR; ++q) {
+                        const int c = tc + 16 * q;
+                        ws->A[j][c] = (c == j + 1) ? xf - alpha : ((c > j + 1 && c < N) ? a[jb][q] : 0.0);
+                    }
+                    if (tc == 0) {
+                        ws->beta[j] = b;
+                        ws->e[j] = alpha;
+                    }
+                    if (tc == jj) ws->d[j] = a[jb][jb];
                 }
-            }
-            __syncthreads();
-            double pv = 0.0;
-            for (int t = lane; t < m; t += 64) pv += ws->p[t] * vv[t];
-            const double K = 0.5 * b * wave_allsum(pv);
-            // A22 -= v w^T + w v^T on a 16 x 16 thread grid; the thread's columns of v and
-            // w are held in registers
-            const int tr = tid >> 4, tc = tid & 15;
-            double vc[kSyevMaxN / 16], wc[kSyevMaxN / 16];
+                __syncthreads();
+                const double b = ws->beta[j];
+                if (b == 0.0) continue;   // uniform: no reflection, nothing to update
+                double vr[kSyR], vc[kSyR], pr[kSyR];
 #pragma unroll
-            for (int q = 0; q < kSyevMaxN / 16; ++q) {
-                const int c = tc + 16 * q;
-                vc[q] = (c < m) ? vv[c] : 0.0;
-                wc[q] = (c < m) ? ws->p[c] - K * vc[q] : 0.0;
-            }
-            for (int r = tr; r < m; r += 16) {
-                const double vr = vv[r], wr = ws->p[r] - K * vv[r];
-                double *row = &ws->A[j + 1 + r][j + 1];
+                for (int i = 0; i < kSyR; ++i) {
+                    vr[i] = ws->A[j][tr + 16 * i];
+                    vc[i] = ws->A[j][tc + 16 * i];
+                }
+                double vp = 0.0;
 #pragma unroll
-                for (int q = 0; q < kSyevMaxN / 16; ++q) {
-                    const int c = tc + 16 * q;
-                    if (c < m) row[c] -= vr * wc[q] + wr * vc[q];
+                for (int i = 0; i < kSyR; ++i) {
+                    double sdot = 0.0;
+#pragma unroll
+                    for (int q = 0; q < kSyR; ++q) sdot += a[i][q] * vc[q];
+                    sdot = row16_sum(sdot);
+                    const int r = tr + 16 * i;
+                    pr[i] = (r > j && r < N) ? b * sdot : 0.0;
+                    if (tc == i) {
+                        ws->p[par][r] = pr[i];
+                        vp = vr[i] * pr[i];
+                    }
+                }
+                vp = wave_allsum(vp);
+                if (lane == 0) ws->vp[par][wave] = vp;
+                __syncthreads();
+                const double K = 0.5 * b * ((ws->vp[par][0] + ws->vp[par][1]) + (ws->vp[par][2] + ws->vp[par][3]));
+                double wc[kSyR];
+#pragma unroll
+                for (int q = 0; q < kSyR; ++q) wc[q] = ws->p[par][tc + 16 * q] - K * vc[q];
+#pragma unroll
+                for (int i = 0; i < kSyR; ++i) {
+                    const double wr = pr[i] - K * vr[i];
+#pragma unroll
+                    for (int q = 0; q < kSyR; ++q) a[i][q] -= vr[i] * wc[q] + wr * vc[q];
                 }
             }
         }
-        // column j has been read by every wave (before the barrier above, or it is zero)
-        if (tid == 0) {
-            ws->A[j + 1][j] = vv[0];   // v_0; the rest of v is the column itself
-            ws->beta[j] = b;
-            ws->e[j] = alpha;
-            ws->d[j] = ws->A[j][j];
-        }
-        __syncthreads();
+        // the last two diagonal entries and the last off-diagonal one
+#pragma unroll
+        for (int i = 0; i < kSyR; ++i)
+#pragma unroll
+            for (int q = 0; q < kSyR; ++q) {
+                const int r = tr + 16 * i, c = tc + 16 * q;
+                if (r == c && r >= N - 2 && r < N) ws->d[r] = a[i][q];
+                if (r == N - 1 && c == N - 2) ws->e[N - 2] = a[i][q];
+            }
+        if (tid == 0 && N >= 3) ws->beta[N - 2] = 0.0;
     }
-    if (tid == 0) {
-        if (N >= 2) {
-            ws->d[N - 2] = ws->A[N - 2][N - 2];
-            ws->e[N - 2] = ws->A[N - 1][N - 2];
-            if (N >= 3) ws->beta[N - 2] = 0.0;
-        }
-        ws->d[N - 1] = ws->A[N - 1][N - 1];
-        double gl = 1e300, gh = -1e300, tn = 0.0;
-        for (int i = 0; i < N; ++i) {
+    __syncthreads();
+    // Gershgorin bracket of T on wavefront 0
+    if (wave == 0) {
+        double gl = 1e300, gh = -1e300;
+        for (int i = lane; i < N; i += 64) {
             const double r = (i > 0 ? fabs(ws->e[i - 1]) : 0.0) + (i + 1 < N ? fabs(ws->e[i]) : 0.0);
             gl = fmin(gl, ws->d[i] - r);
             gh = fmax(gh, ws->d[i] + r);
             if (i + 1 < N) ws->e2[i] = ws->e[i] * ws->e[i];
         }
-        tn = fmax(fabs(gl), fabs(gh));
-        // widen slightly so that the bracket certainly contains every eigenvalue
-        ws->gl = gl - 4e-16 * tn - 1e-300;
-        ws->gh = gh + 4e-16 * tn + 1e-300;
-        ws->red[0] = tn;
+        gl = wave_min(gl);
+        gh = wave_max(gh);
+        if (lane == 0) {
+            const double tn = fmax(fabs(gl), fabs(gh));
+            // widen slightly so that the bracket certainly contains every eigenvalue
+            ws->gl = gl - 4e-16 * tn - 1e-300;
+            ws->gh = gh + 4e-16 * tn + 1e-300;
+            ws->red[0] = tn;
+        }
     }
     __syncthreads();
     // ---- 2. eigenvalues by 16-section ----
@@ -298,21 +337,27 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
         __syncthreads();
     }
     // ---- 5. back-transformation x <- H_0 ... H_{N-3} x, 16 lanes per vector ----
+    // Lane l of the group keeps x[l + 16 t], t < kSyR; reflector j is row j of ws->A
+    // (zero outside j + 1 .. N - 1), so no index masks are needed.
     {
         const int c = tid >> 4, l = tid & 15;
         if (c < ny) {
-            double *x = ws->X[c];
+            double xr[kSyR];
+#pragma unroll
+            for (int t = 0; t < kSyR; ++t) xr[t] = (l + 16 * t < N) ? ws->X[c][l + 16 * t] : 0.0;
             for (int j = N - 3; j >= 0; --j) {
                 const double b = ws->beta[j];
                 if (b == 0.0) continue;
-                const int m = N - j - 1;
-                double s = 0.0;
-                for (int t = l; t < m; t += 16) s += ws->A[j + 1 + t][j] * x[j + 1 + t];
-                s = b * group16_sum(s);
-                for (int t = l; t < m; t += 16) x[j + 1 + t] -= s * ws->A[j + 1 + t][j];
-                // the next reflector reads entries of x written by other lanes of the group
-                wave_sync();
+                double sdot = 0.0;
+#pragma unroll
+                for (int t = 0; t < kSyR; ++t) sdot += ws->A[j][l + 16 * t] * xr[t];
+                sdot = b * group16_sum(sdot);
+#pragma unroll
+                for (int t = 0; t < kSyR; ++t) xr[t] -= sdot * ws->A[j][l + 16 * t];
             }
+#pragma unroll
+            for (int t = 0; t < kSyR; ++t)
+                if (l + 16 * t < N) ws->X[c][l + 16 * t] = xr[t];
         }
     }
     __syncthreads();
