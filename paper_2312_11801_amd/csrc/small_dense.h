@@ -260,62 +260,81 @@ __device__ __forceinline__ void wg_sort_store(int N, const double *sA, const dou
 }
 
 // ---------------------------------------------------------------------------
-// Cholesky-QR factor (one thread-team = wavefront 0 of the calling workgroup).
-// G (nc x nc, LDS, ld) = W^T W.  Lower Cholesky with semidefinite deflation:
-// a pivot below max(1e-24 * max diag, floor2) marks the column dead and
-// zeroes it.  Writes R^{-1} = L^{-T} to H (global, ldh), dead columns zero.
+// Cholesky with semidefinite deflation of the nc x nc LDS matrix G (nc <= 16) on one
+// wavefront, in registers: lane r keeps row r of G, then of L, then of L^{-1}, and reads
+// other rows' entries by readlane (uniform lane index).  A pivot at or below thr marks its
+// column dead: the pivot counts as 1 and the column of L below it as zero.  On return
+// a[c] = L[r][c] (c < r), myd = L[r][r], li[c] = L^{-1}[r][c] with the rows of dead pivots
+// zero; the result is the mask of dead pivots (the same in every lane).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void wave_cholqr(int nc, double *G, int ld, double *H, int ldh, int *flags,
-                                            double floor2) {
-    const int lane = threadIdx.x & 63;
-    __shared__ int sdead[16];
-    __shared__ double sLi[16 * 17];
-    double md = 0.0;
-    for (int i = 0; i < nc; ++i) md = fmax(md, G[i * ld + i]);
-    const double thr = fmax(1e-24 * md, floor2);
-    if (lane < 16) sdead[lane] = 0;
-    wave_sync();
-    for (int j = 0; j < nc; ++j) {
-        if (lane == 0) {
-            const double piv = G[j * ld + j];
-            if (!(piv > thr)) {
-                sdead[j] = 1;
-                G[j * ld + j] = 1.0;
-            } else {
-                G[j * ld + j] = sqrt(piv);
+__device__ __forceinline__ unsigned wave_chol_rows(int nc, const double *G, int ld, double thr, double (&a)[16],
+                                                   double (&li)[16], double &myd) {
+    const int r = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = (r < nc && c < nc) ? G[r * ld + c] : 0.0;
+    unsigned dead = 0;
+    myd = 1.0;
+    // right-looking: after step j, a[j] = L[r][j] at lanes r > j
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j < nc) {
+            const double piv = lane_read(a[j], j);
+            const bool dj = !(piv > thr);
+            if (dj) dead |= 1u << j;
+            const double dd = dj ? 1.0 : sqrt(piv), inv = 1.0 / dd;
+            const double lj = (r > j && !dj) ? a[j] * inv : 0.0;
+            a[j] = lj;
+            if (r == j) myd = dd;
+#pragma unroll
+            for (int c = j + 1; c < 16; ++c)
+                if (c < nc) a[c] -= lj * lane_read(lj, c);
+        }
+    }
+    // L^{-1} by rows: li holds e_r - sum_{l < j} L[r][l] Li[l][:]; at step j row j is final
+    // (li_j / L[j][j], read from lane j) and the rows below subtract L[r][j] times it
+    const double myinv = 1.0 / myd;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) li[c] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j < nc) {
+            const double lrj = a[j];
+#pragma unroll
+            for (int c = 0; c <= j; ++c) {
+                const double lic = lane_read(li[c] * myinv, j);
+                if (r > j) li[c] -= lrj * lic;
             }
         }
-        wave_sync();
-        const double ljj = G[j * ld + j];
-        const int dj = sdead[j];
-        for (int i = j + 1 + lane; i < nc; i += 64) G[i * ld + j] = dj ? 0.0 : G[i * ld + j] / ljj;
-        wave_sync();
-        const int m = nc - j - 1;
-        for (int e = lane; e < m * m; e += 64) {
-            const int i = j + 1 + e / m, l = j + 1 + e % m;
-            if (l <= i) G[i * ld + l] -= G[i * ld + j] * G[l * ld + j];
-        }
-        wave_sync();
     }
-    // L^{-1}: lane c solves L x = e_c
-    if (lane < nc) {
-        const int c = lane;
-        double x[16];
-        for (int i = 0; i < 16; ++i) x[i] = 0.0;
-        for (int i = c; i < nc; ++i) {
-            double v = (i == c) ? 1.0 : 0.0;
-            for (int l = c; l < i; ++l) v -= G[i * ld + l] * x[l];
-            x[i] = v / G[i * ld + i];
-        }
-        for (int i = 0; i < nc; ++i) sLi[i * 17 + c] = x[i];   // sLi[i][c] = L^{-1}[i][c]
+    const bool dr = r < 16 && ((dead >> r) & 1u);
+#pragma unroll
+    for (int c = 0; c < 16; ++c) li[c] = dr ? 0.0 : li[c] * myinv;
+    return dead;
+}
+
+// Cholesky-QR factor (one thread-team = wavefront 0 of the calling workgroup).
+// G (nc x nc, LDS, ld, nc <= 16) = W^T W.  A pivot at or below max(1e-24 * max diag,
+// floor2) marks the column dead and zeroes it.  Writes the factor L back into G's lower
+// triangle and R^{-1} = L^{-T} to H (ldh), dead columns zero.
+__device__ __forceinline__ void wave_cholqr(int nc, double *G, int ld, double *H, int ldh, int *flags,
+                                            double floor2) {
+    const int r = threadIdx.x & 63;
+    double md = 0.0;
+    for (int i = 0; i < nc; ++i) md = fmax(md, G[i * ld + i]);
+    double a[16], li[16], myd;
+    const unsigned dead = wave_chol_rows(nc, G, ld, fmax(1e-24 * md, floor2), a, li, myd);
+    wave_sync();   // every lane has read G
+    if (r < nc) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < nc) {
+                if (c < r) G[r * ld + c] = a[c];
+                if (c == r) G[r * ld + c] = myd;
+                H[c * ldh + r] = li[c];   // R^{-1}[c][r] = L^{-1}[r][c]
+            }
+        if (flags && ((dead >> r) & 1u)) flags[r] = 1;
     }
     wave_sync();
-    // H[a][c] = R^{-1}[a][c] = L^{-1}[c][a]; dead columns of R^{-1} are zero
-    for (int e = lane; e < nc * nc; e += 64) {
-        const int a = e / nc, c = e - a * nc;
-        H[a * ldh + c] = sdead[c] ? 0.0 : sLi[c * 17 + a];
-    }
-    if (flags && lane < nc && sdead[lane]) flags[lane] = 1;
 }
 
 // ---------------------------------------------------------------------------

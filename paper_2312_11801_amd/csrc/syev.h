@@ -12,7 +12,8 @@
 //   3. eigenvectors of T by inverse iteration (one lane per eigenvector,
 //      Gaussian elimination with partial pivoting on T - lambda I);
 //   4. Cholesky-QR twice on the eigenvectors (vectors of a cluster become an
-//      orthonormal basis of its invariant subspace);
+//      orthonormal basis of its invariant subspace), the Gram matrix and the
+//      triangular solve on the FP64 matrix cores;
 //   5. back-transformation by the reflectors (16 lanes per vector, the vector in
 //      registers, sums across the lanes by DPP).
 #pragma once
@@ -34,6 +35,8 @@ struct SyevWork {
     double vp[2][4];          // per-wavefront shares of v^T p
     double lam[kSyevMaxV];
     double X[kSyevMaxV][kSyevMaxN + 1];
+    double G[kSyevMaxV][kSyevMaxV + 1];    // Gram matrix of the eigenvectors (Cholesky-QR)
+    double Li[kSyevMaxV][kSyevMaxV + 1];   // inverse of its Cholesky factor
     double U0[kSyevMaxV][kSyevMaxN], U1[kSyevMaxV][kSyevMaxN], U2[kSyevMaxV][kSyevMaxN];
     double red[8];
     double gl, gh;
@@ -291,47 +294,44 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
         }
     }
     __syncthreads();
-    // ---- 4. orthonormalise the ny vectors: Cholesky-QR twice on all threads ----
-    // G = X X^T (ny x ny), G = L L^T, X <- L^{-1} X by forward substitution along each
-    // position i (one thread per position, in place)
+    // ---- 4. orthonormalise the ny vectors: Cholesky-QR twice ----
+    // Wavefront 0 forms G = X X^T on the FP64 matrix cores (both operands are entry
+    // (m, 4q + kq) of X) and its Cholesky factor in registers; a pivot at or below 1e-28
+    // zeroes its vector.  Then X <- L^{-1} X on the matrix cores, 16 positions per tile,
+    // the tiles spread over the four wavefronts.
     for (int pass = 0; pass < 2 && ny > 1; ++pass) {
-        __shared__ double G[kSyevMaxV][kSyevMaxV + 1];
-        {
-            const int b2 = tid >> 4, c = tid & 15;
-            if (b2 < ny && c < ny && c <= b2) {
-                double s = 0.0;
-                for (int i = 0; i < N; ++i) s += ws->X[b2][i] * ws->X[c][i];
-                G[b2][c] = s;
-                G[c][b2] = s;
-            }
-        }
-        __syncthreads();
+        const int m = lane & 15, kq = lane >> 4;
         if (wave == 0) {
-            // lower Cholesky of G on lanes; a vanishing pivot zeroes that vector
-            for (int jj = 0; jj < ny; ++jj) {
-                if (lane == 0) {
-                    const double piv = G[jj][jj];
-                    G[jj][jj] = (piv > 1e-28) ? sqrt(piv) : 0.0;
-                }
-                wave_sync();
-                const double ljj = G[jj][jj];
-                for (int i = jj + 1 + lane; i < ny; i += 64) G[i][jj] = (ljj > 0.0) ? G[i][jj] / ljj : 0.0;
-                wave_sync();
-                const int mm = ny - jj - 1;
-                for (int e = lane; e < mm * mm; e += 64) {
-                    const int i = jj + 1 + e / mm, l = jj + 1 + e % mm;
-                    if (l <= i) G[i][l] -= G[i][jj] * G[l][jj];
-                }
-                wave_sync();
+            dv4 g = {0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; 4 * q < N; ++q) {
+                const int i = 4 * q + kq;
+                const double x = (m < ny && i < N) ? ws->X[m][i] : 0.0;
+                g = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, g, 0, 0, 0);
             }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ws->G[kq + 4 * v][m] = g[v];
+            wave_lds_order();
+            double a[16], li[16], myd;
+            wave_chol_rows(ny, &ws->G[0][0], kSyevMaxV + 1, 1e-28, a, li, myd);
+            if (lane < 16)
+#pragma unroll
+                for (int c = 0; c < 16; ++c) ws->Li[lane][c] = li[c];
         }
         __syncthreads();
-        if (tid < N) {
-            for (int b2 = 0; b2 < ny; ++b2) {
-                double v = ws->X[b2][tid];
-                for (int l = 0; l < b2; ++l) v -= G[b2][l] * ws->X[l][tid];
-                const double g = G[b2][b2];
-                ws->X[b2][tid] = (g > 0.0) ? v / g : 0.0;
+        for (int t = wave; 16 * t < N; t += 4) {
+            const int pos = 16 * t + m;
+            dv4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int l = 4 * q + kq;
+                const double x = ws->Li[m][l];
+                const double y = (l < ny && pos < N) ? ws->X[l][pos] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int b2 = kq + 4 * v;
+                if (b2 < ny && pos < N) ws->X[b2][pos] = acc[v];
             }
         }
         __syncthreads();

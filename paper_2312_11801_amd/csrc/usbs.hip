@@ -608,14 +608,21 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         HIPCHK(hipStreamSynchronize(s));
         h->last_conv = conv != 0;
         if ((conv && cyc >= min_cyc) || cyc == maxr) break;
-        // Krylov expansion from the dominant residual directions
+        // Krylov expansion from the dominant residual directions W = U Zc, orthonormalised
+        // against the 16 Ritz vectors by the two Pythagorean Gram-Schmidt passes of the block
+        // steps below (three sweeps over [B W]).  Their projections land in T[0:16, 16:24],
+        // which block step 0 overwrites with the projections of M q_0.
         lanczos_reset_T(s, h->Tm, ldb, ldb, h->theta, h->dead);
         nn_update(s, n, h->Ubuf, 16, 16, h->Zc, 8, 8, h->W, 8, 1.0, 0.0);
-        for (int pass = 0; pass < 2; ++pass) {
-            tn_reduce(s, h->rs, n, h->Bm, ldb, 16, h->W, 8, 8, h->Hred, 8, 1.0, 0.0);
-            nn_update(s, n, h->Bm, ldb, 16, h->Hred, 8, 8, h->W, 8, -1.0, 1.0);
+        {
+            int g = reorth_partials(s, h->rs, n, h->Bm, ldb, 16, h->W, 8, 8);
+            reorth_finish(s, h->rs, g, 16, 8, h->Hg, 8);
+            pip_chol(s, h->Hg, 16, 0, h->Rsv, h->Tm + 16, ldb, h->coef, h->dead + 16, h->sc + SC_SCALE);
+            g = nn_update2_reorth(s, h->rs, n, h->Bm, ldb, 16, h->W, 8, h->coef, 8, h->Wt, 8);
+            reorth_finish(s, h->rs, g, 16, 8, h->Hg, 8);
+            pip_chol(s, h->Hg, 16, 1, h->Rsv, h->Tm + 16, ldb, h->coef, h->dead + 16, nullptr);
+            nn_update2(s, n, h->Bm, ldb, 16, h->Wt, 8, 8, h->coef, 8, 8, h->Bm + 16, ldb);
         }
-        cholqr2(h, h->W, 8, 8, h->Wt, 8, h->Bm + 16, ldb, h->dead + 16);
         // block steps: W = M q_j, then two passes of block Gram-Schmidt with Pythagorean
         // inner products against the whole basis (one reduction [Q W]^T W per pass)
         for (int j = 0; j < steps; ++j) {

@@ -720,11 +720,14 @@ __device__ __forceinline__ void wg_pip_chol(const double *__restrict__ Hg, int c
     for (int e = tid; e < cols * kBlk; e += kWG) w->sH[e / kBlk][e % kBlk] = Hg[e];
     if (tid < kBlk * kBlk) w->sR[tid / kBlk][tid % kBlk] = (pass == 1) ? Rsave[tid] : 0.0;
     __syncthreads();
-    if (tid < kBlk * kBlk) {
-        const int i = tid / kBlk, j = tid % kBlk;
+    {
+        // Omega = G - H^T H: four lanes (one DPP quad) per entry
+        static_assert(kBlk * kBlk * 4 == kWG, "one quad of lanes per entry of Omega");
+        const int e = tid >> 2, q4 = tid & 3, i = e / kBlk, j = e % kBlk;
         double sacc = 0.0;
-        for (int a = 0; a < cols; ++a) sacc += w->sH[a][i] * w->sH[a][j];
-        w->sOm[i * 17 + j] = Hg[(cols + i) * kBlk + j] - sacc;
+        for (int a = q4; a < cols; a += 4) sacc += w->sH[a][i] * w->sH[a][j];
+        sacc = quad_sum(sacc);
+        if (q4 == 0) w->sOm[i * 17 + j] = Hg[(cols + i) * kBlk + j] - sacc;
     }
     // projections of the original block into T
     for (int e = tid; e < cols * kBlk; e += kWG) {
