@@ -105,6 +105,8 @@ void copy_cols(hipStream_t s, int n, const double *A, int lda, int cc, double *C
 void fill(hipStream_t s, size_t count, double v, double *p);
 // deterministic pseudo-random start block (counter hash, uniform in [-1, 1])
 void random_block(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ldc);
+// the same columns with C[:, cc..ldc) = 0 (the whole n x ldc block is written)
+void random_block_pad(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ldc);
 
 // ---- small dense problems (one workgroup) --------------------------------
 // top eigenpairs of the symmetric N x N matrix A (upper triangle read, ld lda, N <= kMaxBasis):

@@ -765,6 +765,18 @@ void random_block(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ld
     if (n <= 0 || cc <= 0) return;
     hipLaunchKernelGGL(k_random_block, dim3(cdiv((long)n * cc, kWG)), dim3(kWG), 0, s, n, cc, seed, C, ldc);
 }
+// the same cc random columns (the same values) with columns cc..ldc-1 set to zero
+__global__ void k_random_block_pad(int n, int cc, int ldc, uint64_t seed, double *C) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n * ldc) return;
+    const long i = e / ldc;
+    const int c = (int)(e - i * ldc);
+    C[e] = (c < cc) ? hash_uniform(seed, (uint64_t)(i * cc + c)) : 0.0;
+}
+void random_block_pad(hipStream_t s, int n, int cc, uint64_t seed, double *C, int ldc) {
+    if (n <= 0 || ldc <= 0) return;
+    hipLaunchKernelGGL(k_random_block_pad, dim3(cdiv((long)n * ldc, kWG)), dim3(kWG), 0, s, n, cc, ldc, seed, C);
+}
 
 // ---------------------------------------------------------------------------
 // small symmetric eigenproblem on one workgroup (parallel cyclic Jacobi)

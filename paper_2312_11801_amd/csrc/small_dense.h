@@ -65,6 +65,16 @@ __device__ __forceinline__ double wave_allsum(double v) {
     return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
+// 1/q to double precision without the IEEE division sequence, for dependent chains: the
+// hardware reciprocal approximation refined by two Newton steps (each squares the
+// relative error), as the compiler's fast double division does
+__device__ __forceinline__ double rcp_nr(double q) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = __builtin_fma(r, __builtin_fma(-q, r, 1.0), r);
+    r = __builtin_fma(r, __builtin_fma(-q, r, 1.0), r);
+    return r;
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -679,7 +689,7 @@ __device__ __forceinline__ double wave_congruence_min_eig(int k, const double *L
 #pragma unroll
         for (int i = 1; i < kMaxK; ++i)
             if (i < k) {
-                q = dd[i] - x - e2[i - 1] / q;
+                q = __builtin_fma(-e2[i - 1], rcp_nr(q), dd[i] - x);
                 if (fabs(q) < pivmin) q = -pivmin;
                 cnt += (q < 0.0);
             }

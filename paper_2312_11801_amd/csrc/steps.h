@@ -60,6 +60,8 @@ void model_update(hipStream_t s, int k, int kp, int r, const double *st, const d
 void fix_dead(hipStream_t s, int n, const int *flags, int kc, int kp, const double *U, int ldu, double *Vn,
               int ldv);
 void add_small(hipStream_t s, int rows, int cols, const double *H, int ldh, double *T, int ldt);
+// P (rows x ldp) = H (rows x cols, ld ldh) with columns cols..ldp-1 zero
+void pad_small(hipStream_t s, int rows, int cols, const double *H, int ldh, double *P, int ldp);
 void set_int(hipStream_t s, int *p, int count, int v);
 void nystrom_core(hipStream_t s, int n, int r, const double *Gm, double *H, double *lam, int *status);
 void interleave(hipStream_t s, int n, int r, const double *P, const float *Psi, double *out);

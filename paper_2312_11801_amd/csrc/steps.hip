@@ -142,6 +142,16 @@ __global__ void k_add_small(int rows, int cols, const double *__restrict__ H, in
     const int a = e / cols, c = e - a * cols;
     T[a * ldt + c] += H[a * ldh + c];
 }
+__global__ void k_pad_small(int rows, int cols, const double *__restrict__ H, int ldh, double *__restrict__ P,
+                            int ldp) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= rows * ldp) return;
+    const int a = e / ldp, c = e - a * ldp;
+    P[e] = (c < cols) ? H[a * ldh + c] : 0.0;
+}
+void pad_small(hipStream_t s, int rows, int cols, const double *H, int ldh, double *P, int ldp) {
+    hipLaunchKernelGGL(k_pad_small, dim3(cdiv_(rows * ldp, kWG)), dim3(kWG), 0, s, rows, cols, H, ldh, P, ldp);
+}
 void add_small(hipStream_t s, int rows, int cols, const double *H, int ldh, double *T, int ldt) {
     hipLaunchKernelGGL(k_add_small, dim3(cdiv_(rows * cols, kWG)), dim3(kWG), 0, s, rows, cols, H, ldh, T, ldt);
 }

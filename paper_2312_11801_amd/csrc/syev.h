@@ -52,7 +52,7 @@ __device__ __forceinline__ int sturm_count(int N, const double *d, const double 
     c += (q < 0.0);
 #pragma unroll 8
     for (int i = 1; i < N; ++i) {
-        q = d[i] - x - e2[i - 1] / q;
+        q = __builtin_fma(-e2[i - 1], rcp_nr(q), d[i] - x);
         if (fabs(q) < pivmin) q = -pivmin;
         c += (q < 0.0);
     }
@@ -250,7 +250,7 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
                     const double an = dn - lam;
                     const bool keep = fabs(c0) >= fabs(ei);
                     const double piv = (c0 == 0.0) ? tiny : c0;
-                    const double mlt = keep ? ei / piv : c0 / ei;
+                    const double mlt = keep ? ei * rcp_nr(piv) : c0 * rcp_nr(ei);
                     ws->U0[c][i] = keep ? piv : ei;
                     ws->U1[c][i] = keep ? c1 : an;
                     ws->U2[c][i] = keep ? 0.0 : en;
@@ -276,7 +276,7 @@ __device__ __forceinline__ void wg_syev_top(int N, int nv, int ny, SyevWork *ws,
                     if (i + 2 < N) v -= ws->U2[c][i] * x2;
                     const double u = ws->U0[c][i];
                     const double u0 = (fabs(u) < tiny) ? (u < 0.0 ? -tiny : tiny) : u;
-                    const double xi = v / u0;
+                    const double xi = v * rcp_nr(u0);   // the reciprocal is off the chain through x
                     x[i] = xi;
                     mx = fmax(mx, fabs(xi));
                     x2 = x1;

@@ -109,11 +109,12 @@ struct usbs_handle {
     double *Tm = nullptr, *theta = nullptr, *Ysm = nullptr, *TUU = nullptr, *RtR = nullptr, *Zc = nullptr,
            *Hred = nullptr, *Rinv = nullptr, *res = nullptr, *Hd = nullptr;
     double *Hg = nullptr, *coef = nullptr, *Rsv = nullptr;   // block Gram-Schmidt (Pythagorean) work
+    double *Tscr = nullptr;                                   // projections of a fresh block (16 x 8, unused)
     int *dead = nullptr, *flag = nullptr;
     // QP / model
     double *raw = nullptr, *qp = nullptr, *ipm = nullptr, *VCV = nullptr, *Gy = nullptr, *Kc = nullptr,
            *Qp = nullptr, *Hsk = nullptr, *VtPsi = nullptr, *sc = nullptr, *small = nullptr, *Zp = nullptr,
-           *hz = nullptr, *Rz = nullptr;
+           *hz = nullptr, *Rz = nullptr, *Qp8 = nullptr;
     int *zdead = nullptr;
     RedScratch rs{};
 
@@ -492,11 +493,12 @@ void upload(usbs_handle *h) {
     h->Hg = dalloc<double>((size_t)(ldb + 8) * 8, o, h->stream);
     h->coef = dalloc<double>((size_t)(ldb + 8) * 8, o, h->stream);
     h->Rsv = dalloc<double>(64, o, h->stream);
+    h->Tscr = dalloc<double>(16 * 8, o, h->stream);
     h->Rinv = dalloc<double>(256, o, h->stream);
     h->res = dalloc<double>(16, o, h->stream);
     h->Hd = dalloc<double>(256, o, h->stream);
     h->dead = dalloc<int>(ldb, o, h->stream);
-    h->flag = dalloc<int>(16, o, h->stream);
+    h->flag = dalloc<int>(24, o, h->stream);   // 16 start-block flags + 8 for a fresh block at column 16
     h->zdead = dalloc<int>(16, o, h->stream);
     const int d = kMaxSvec;
     h->raw = dalloc<double>(d * d + 4 * d, o, h->stream);
@@ -506,6 +508,7 @@ void upload(usbs_handle *h) {
     h->Gy = dalloc<double>(d * d + 4 * d, o, h->stream);
     h->Kc = dalloc<double>(256, o, h->stream);
     h->Qp = dalloc<double>(256, o, h->stream);
+    h->Qp8 = dalloc<double>(16 * 8, o, h->stream);
     h->Hsk = dalloc<double>(16 * 32, o, h->stream);
     h->VtPsi = dalloc<double>(16 * 32, o, h->stream);
     h->hz = dalloc<double>(256, o, h->stream);
@@ -558,6 +561,26 @@ void cholqr2(usbs_handle *h, const double *src, int lds, int nc, double *tmp, in
     nn_update(s, h->n, tmp, ldt, nc, h->Rinv, nc, nc, dst, ldd, 1.0, 0.0);
 }
 
+// Orthonormalise the fresh block W (n x 8, ld 8; zero beyond its used columns) against the
+// orthonormal columns Q (n x nq, ld ldq) by two passes of block Gram-Schmidt with Pythagorean
+// inner products, as in the Krylov block steps, and write its first cc columns to dst (ld ldd,
+// disjoint from Q's columns).  Three sweeps over [Q W]: the reduction [Q W]^T W, the first
+// update fused with the second pass's reduction, the second update.  Deflated columns are
+// zero and flagged in flags[0..8) (zero padding columns always are); the projections go to T
+// (nq x 8, ld ldt).  Uses W, Wt, Hg, coef and Rsv.
+void orth_fresh(usbs_handle *h, const double *Q, int ldq, int nq, double *dst, int ldd, int cc, int *flags,
+                double *T, int ldt) {
+    hipStream_t s = h->stream;
+    const int n = h->n;
+    int g = reorth_partials(s, h->rs, n, Q, ldq, nq, h->W, 8, 8);
+    reorth_finish(s, h->rs, g, nq, 8, h->Hg, 8);
+    pip_chol(s, h->Hg, nq, 0, h->Rsv, T, ldt, h->coef, flags, h->sc + SC_SCALE);
+    g = nn_update2_reorth(s, h->rs, n, Q, ldq, nq, h->W, 8, h->coef, 8, h->Wt, 8);
+    reorth_finish(s, h->rs, g, nq, 8, h->Hg, 8);
+    pip_chol(s, h->Hg, nq, 1, h->Rsv, T, ldt, h->coef, flags, nullptr);
+    nn_update2(s, n, Q, ldq, nq, h->Wt, 8, 8, h->coef, 8, cc, dst, ldd);
+}
+
 // ---------------------------------------------------------------------------
 // block Lanczos with Rayleigh-Ritz restarts (the eigen step behind f(y),
 // Sec. 3 and App. E): start block of 16 vectors, block width 8, 'steps'
@@ -569,13 +592,18 @@ void cholqr2(usbs_handle *h, const double *src, int lds, int nc, double *tmp, in
 // merged in at the end, and Ucpl keeps the coupled Ritz vectors for the next
 // start.
 // ---------------------------------------------------------------------------
+// keep < 16: the first keep (>= 8) columns of the start block are orthonormal (coupled Ritz
+// vectors of an earlier solve) and h->W holds 16 - keep fresh directions, zero-padded to 8
+// columns; with orth_start they are orthonormalised against the kept ones into the block's
+// last columns (three sweeps instead of a Cholesky-QR2 of all 16).
 int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start,
-            int min_cyc) {
+            int min_cyc, int keep = 16) {
     hipStream_t s = h->stream;
     const int n = h->n, ldb = h->ldb, steps = h->steps;
     if (start != h->Ubuf) copy_cols(s, n, start, 16, 16, h->Ubuf, 16);
     if (h->n_iso > 0) {
         mask_rows(s, h->n_iso, h->iso_idx, h->Ubuf, 16, 16);
+        if (keep < 16) mask_rows(s, h->n_iso, h->iso_idx, h->W, 8, 8);
         orth_start = true;
         if (h->n_iso == n) {   // a diagonal operator: every eigenpair is exact
             iso_merge(s, h->n_iso, h->iso_idx, h->dshift, 0, h->theta, h->res, h->plan);
@@ -585,8 +613,10 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         }
     }
     if (orth_start) {
-        set_int(s, h->flag, 16, 0);
-        cholqr2(h, h->Ubuf, 16, 16, h->W2, 16, h->Ubuf, 16, h->flag);
+        set_int(s, h->flag, 24, 0);
+        if (keep >= 8 && keep < 16)
+            orth_fresh(h, h->Ubuf, 16, keep, h->Ubuf + keep, 16, 16 - keep, h->flag + keep, h->Tscr, 8);
+        else cholqr2(h, h->Ubuf, 16, 16, h->W2, 16, h->Ubuf, 16, h->flag);
     }
     int cyc = 0;
     for (cyc = 0; cyc <= maxr; ++cyc) {
@@ -614,15 +644,7 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         // which block step 0 overwrites with the projections of M q_0.
         lanczos_reset_T(s, h->Tm, ldb, ldb, h->theta, h->dead);
         nn_update(s, n, h->Ubuf, 16, 16, h->Zc, 8, 8, h->W, 8, 1.0, 0.0);
-        {
-            int g = reorth_partials(s, h->rs, n, h->Bm, ldb, 16, h->W, 8, 8);
-            reorth_finish(s, h->rs, g, 16, 8, h->Hg, 8);
-            pip_chol(s, h->Hg, 16, 0, h->Rsv, h->Tm + 16, ldb, h->coef, h->dead + 16, h->sc + SC_SCALE);
-            g = nn_update2_reorth(s, h->rs, n, h->Bm, ldb, 16, h->W, 8, h->coef, 8, h->Wt, 8);
-            reorth_finish(s, h->rs, g, 16, 8, h->Hg, 8);
-            pip_chol(s, h->Hg, 16, 1, h->Rsv, h->Tm + 16, ldb, h->coef, h->dead + 16, nullptr);
-            nn_update2(s, n, h->Bm, ldb, 16, h->Wt, 8, 8, h->coef, 8, 8, h->Bm + 16, ldb);
-        }
+        orth_fresh(h, h->Bm, ldb, 16, h->Bm + 16, ldb, 8, h->dead + 16, h->Tm + 16, ldb);
         // block steps: W = M q_j, then two passes of block Gram-Schmidt with Pythagorean
         // inner products against the whole basis (one reduction [Q W]^T W per pass)
         for (int j = 0; j < steps; ++j) {
@@ -753,10 +775,9 @@ void iterate(usbs_handle *h) {
     // replaced by fresh random directions (the new top eigenvector need not lie in it)
     shift_operator(h, h->yc);
     copy_cols(s, n, h->Ucpl, 16, 14, h->Ubuf, 16);
-    random_block(s, n, 2, prm.seed + 7919ull * (uint64_t)(h->iters + 1), h->W, 8);
-    copy_cols(s, n, h->W, 8, 2, h->Ubuf + 14, 16);
+    random_block_pad(s, n, 2, prm.seed + 7919ull * (uint64_t)(h->iters + 1), h->W, 8);
     const double tol_rest = prm.lanczos_tol_rest > 0.0 ? prm.lanczos_tol_rest : std::sqrt(prm.lanczos_tol);
-    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, tol_rest, prm.lanczos_max_restarts, true, 0);
+    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, tol_rest, prm.lanczos_max_restarts, true, 0, 14);
     if (cyc >= prm.lanczos_max_restarts && !h->last_conv) h->lz_unconverged++;
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
@@ -768,7 +789,14 @@ void iterate(usbs_handle *h) {
     if (h->sketch) nn_update_dev_beta(h, h->V, 16, k, h->Hsk, r, r, h->P, r);
     // V_{t+1} = orth([V Q_p, v_1..v_kc]) (eq. v_next_def)
     copy_cols(s, n, h->Uritz, 16, kc, h->Vn, 16);
-    if (kp > 0) {
+    if (kp > 0 && kp <= 8) {
+        // V Q_p (zero-padded to 8 columns) orthonormalised against the kc Ritz vectors
+        pad_small(s, k, kp, h->Qp, kp, h->Qp8, 8);
+        nn_update(s, n, h->V, 16, k, h->Qp8, 8, 8, h->W, 8, 1.0, 0.0);
+        set_int(s, h->zdead, 16, 0);
+        orth_fresh(h, h->Uritz, 16, kc, h->Vn + kc, 16, kp, h->zdead, h->Tscr, 8);
+        fix_dead(s, n, h->zdead, kc, kp, h->Uritz, 16, h->Vn, 16);
+    } else if (kp > 0) {
         nn_update(s, n, h->V, 16, k, h->Qp, kp, kp, h->Zp, 16, 1.0, 0.0);
         for (int pass = 0; pass < 2; ++pass) {
             tn_reduce(s, h->rs, n, h->Uritz, 16, kc, h->Zp, 16, kp, h->hz, kp, 1.0, 0.0);
@@ -799,9 +827,8 @@ void polish_dual(usbs_handle *h) {
     shift_operator(h, h->y);
     // start: the 12 leading Ritz vectors of the last candidate plus 4 random directions
     copy_cols(s, h->n, h->Ucpl, 16, 12, h->Ubuf, 16);
-    random_block(s, h->n, 4, h->prm.seed + 1000003ull * (uint64_t)(h->iters + 1), h->W, 8);
-    copy_cols(s, h->n, h->W, 8, 4, h->Ubuf + 12, 16);
-    lanczos(h, h->Ubuf, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, true, kCertifyMinCycles);
+    random_block_pad(s, h->n, 4, h->prm.seed + 1000003ull * (uint64_t)(h->iters + 1), h->W, 8);
+    lanczos(h, h->Ubuf, 1, h->prm.lanczos_tol_final, h->prm.lanczos_tol_final, 30, true, kCertifyMinCycles, 12);
     recompute_f(s, h->theta, h->y, h->b, h->m, h->rs, h->sc, 1);
 }
 
