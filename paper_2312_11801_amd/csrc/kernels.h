@@ -23,6 +23,7 @@ struct RedScratch {
     double *partials;   // kRedMaxBlocks * max_elems
     int max_blocks;
     int max_elems;      // doubles per partial
+    unsigned *counter;  // zero between launches: workgroups of a fused finish count in here
 };
 
 // Launch-shape choices made by the autotuner (usbs.hip).  spmm8 / spmm16: 0 = one column
@@ -76,6 +77,10 @@ void reorth_finish(hipStream_t s, const RedScratch &rs, int blocks, int ca, int 
 // null); pass 0 writes T (cols x 8, ldt) = H and saves R; pass 1 adds H * R_saved to T.
 void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave, double *T, int ldt,
               double *coef, int *flags, const double *floor_ref);
+// reorth_finish and pip_chol in one launch: the workgroups of the finish sum their outputs
+// into Hg, and the last one to finish (rs.counter) runs the pass's Cholesky step on Hg
+void finish_pip(hipStream_t s, const RedScratch &rs, int blocks, int cols, double *Hg, int pass, double *Rsave,
+                double *T, int ldt, double *coef, int *flags, const double *floor_ref);
 // out[o] = sum over g < G of part[g * nout + o] (fixed order), o < nout
 void sum_partials(hipStream_t s, const double *part, int G, int nout, double *out);
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,

@@ -517,6 +517,50 @@ __global__ __launch_bounds__(kWG) void k_pip_chol(const double *__restrict__ Hg,
     __shared__ PipWork w;
     wg_pip_chol(Hg, cols, pass, Rsave, T, ldt, coef, flags, floor_ref, &w);
 }
+// k_red_finish's sums (alpha 1, beta 0, contiguous output) into Hg, then the pass's pip_chol on
+// the last workgroup to finish.  Each workgroup's stores are released at device scope before
+// it counts itself in; the last one acquires them before reading Hg and resets the counter
+// for the next launch on the stream.  No workgroup waits for another.
+__global__ __launch_bounds__(kWG) void k_finish_pip(const double *__restrict__ part, int G, int cols, double *Hg,
+                                                    unsigned *counter, int pass, double *Rsave, double *T, int ldt,
+                                                    double *coef, int *flags, const double *floor_ref) {
+    __shared__ PipWork w;
+    __shared__ double s4[4][64];
+    __shared__ unsigned arrived;
+    const int nout = (cols + kBlk) * kBlk;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + lane;
+    const int per = (G + 3) / 4;
+    const int b0 = wv * per, b1 = min(G, b0 + per);
+    double sum = 0.0;
+    if (o < nout) {
+        for (int bb = b0; bb < b1; bb += 16) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = (bb + q < b1) ? part[(size_t)(bb + q) * nout + o] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sum += v[q];
+        }
+    }
+    s4[wv][lane] = sum;
+    __syncthreads();
+    if (wv == 0 && o < nout) Hg[o] = ((s4[0][lane] + s4[1][lane]) + s4[2][lane]) + s4[3][lane];
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) arrived = atomicAdd(counter, 1u);
+    __syncthreads();
+    if (arrived != gridDim.x - 1) return;
+    __threadfence();
+    if (threadIdx.x == 0) *counter = 0u;
+    wg_pip_chol(Hg, cols, pass, Rsave, T, ldt, coef, flags, floor_ref, &w);
+}
+void finish_pip(hipStream_t s, const RedScratch &rs, int blocks, int cols, double *Hg, int pass, double *Rsave,
+                double *T, int ldt, double *coef, int *flags, const double *floor_ref) {
+    const int nout = (cols + kBlk) * kBlk;
+    hipLaunchKernelGGL(k_finish_pip, dim3(cdiv(nout, 64)), dim3(kWG), 0, s, rs.partials, blocks, cols, Hg, rs.counter,
+                       pass, Rsave, T, ldt, coef, flags, floor_ref);
+}
+
 void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave, double *T, int ldt,
               double *coef, int *flags, const double *floor_ref) {
     hipLaunchKernelGGL(k_pip_chol, dim3(1), dim3(kWG), 0, s, Hg, cols, pass, Rsave, T, ldt, coef, flags,

@@ -519,6 +519,8 @@ void upload(usbs_handle *h) {
     h->rs.max_elems = kMaxSvec * (kMaxSvec + 1) / 2 + 4 * kMaxSvec;
     if (h->rs.max_elems < kMaxBasis * 16) h->rs.max_elems = kMaxBasis * 16;
     h->rs.partials = dalloc<double>((size_t)h->rs.max_blocks * h->rs.max_elems, o, h->stream);
+    h->rs.counter = dalloc<unsigned>(4, o, h->stream);
+    HIPCHK(hipMemsetAsync(h->rs.counter, 0, 4 * sizeof(unsigned), s));
     HIPCHK(hipMemsetAsync(h->V, 0, (size_t)n * 16 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(h->Vn, 0, (size_t)n * 16 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(h->CV, 0, (size_t)n * 16 * sizeof(double), s));
@@ -573,11 +575,9 @@ void orth_fresh(usbs_handle *h, const double *Q, int ldq, int nq, double *dst, i
     hipStream_t s = h->stream;
     const int n = h->n;
     int g = reorth_partials(s, h->rs, n, Q, ldq, nq, h->W, 8, 8);
-    reorth_finish(s, h->rs, g, nq, 8, h->Hg, 8);
-    pip_chol(s, h->Hg, nq, 0, h->Rsv, T, ldt, h->coef, flags, h->sc + SC_SCALE);
+    finish_pip(s, h->rs, g, nq, h->Hg, 0, h->Rsv, T, ldt, h->coef, flags, h->sc + SC_SCALE);
     g = nn_update2_reorth(s, h->rs, n, Q, ldq, nq, h->W, 8, h->coef, 8, h->Wt, 8);
-    reorth_finish(s, h->rs, g, nq, 8, h->Hg, 8);
-    pip_chol(s, h->Hg, nq, 1, h->Rsv, T, ldt, h->coef, flags, nullptr);
+    finish_pip(s, h->rs, g, nq, h->Hg, 1, h->Rsv, T, ldt, h->coef, flags, nullptr);
     nn_update2(s, n, Q, ldq, nq, h->Wt, 8, 8, h->coef, 8, cc, dst, ldd);
 }
 
@@ -658,16 +658,15 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
                 ProfPair pp(h, USBS_PROF_REORTH);
                 g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, pp.e0, pp.e1);
             }
-            reorth_finish(s, h->rs, g, cols, 8, h->Hg, 8);
-            pip_chol(s, h->Hg, cols, 0, h->Rsv, h->Tm + c0, ldb, h->coef, nullptr, h->sc + SC_SCALE);
+            finish_pip(s, h->rs, g, cols, h->Hg, 0, h->Rsv, h->Tm + c0, ldb, h->coef, nullptr, h->sc + SC_SCALE);
             // pass-0 update Wt = [Q W] coef fused with pass 1's reduction [Q Wt]^T Wt (the
             // basis rows are read once for both)
             {
                 ProfPair pp(h, USBS_PROF_UPDATE);
                 g = nn_update2_reorth(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, h->coef, 8, h->Wt, 8, pp.e0, pp.e1);
             }
-            reorth_finish(s, h->rs, g, cols, 8, h->Hg, 8);
-            pip_chol(s, h->Hg, cols, 1, h->Rsv, h->Tm + c0, ldb, h->coef, !last ? h->dead + cols : nullptr, nullptr);
+            finish_pip(s, h->rs, g, cols, h->Hg, 1, h->Rsv, h->Tm + c0, ldb, h->coef, !last ? h->dead + cols : nullptr,
+                       nullptr);
             if (!last) nn_update2(s, n, h->Bm, ldb, cols, h->Wt, 8, 8, h->coef, 8, 8, h->Bm + cols, ldb);
         }
         {
