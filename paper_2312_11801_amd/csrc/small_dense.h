@@ -75,6 +75,16 @@ __device__ __forceinline__ double rcp_nr(double q) {
     return r;
 }
 
+// 1/sqrt(x) to double precision for dependent chains: the hardware approximation refined by
+// two Newton steps y <- y (3 - x y^2) / 2 (x > 0)
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    y = y * __builtin_fma(-h * y, y, 1.5);
+    return y;
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
@@ -291,7 +301,7 @@ __device__ __forceinline__ unsigned wave_chol_rows(int nc, const double *G, int 
             const double piv = lane_read(a[j], j);
             const bool dj = !(piv > thr);
             if (dj) dead |= 1u << j;
-            const double dd = dj ? 1.0 : sqrt(piv), inv = 1.0 / dd;
+            const double inv = dj ? 1.0 : rsq_nr(piv), dd = dj ? 1.0 : piv * inv;
             const double lj = (r > j && !dj) ? a[j] * inv : 0.0;
             a[j] = lj;
             if (r == j) myd = dd;
@@ -428,7 +438,7 @@ __device__ __forceinline__ bool wave_chol_inv(int k, const double *X, int ldx, d
                 ok = false;
                 piv = 1.0;
             }
-            const double dd = sqrt(piv), inv = 1.0 / dd;
+            const double inv = rsq_nr(piv), dd = piv * inv;
             const double lj = (r > j) ? a[j] * inv : 0.0;
             a[j] = lj;
             if (r == j) myd = dd;
@@ -976,7 +986,7 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
                             if (tc == 0) sh->okM = 0;
                             piv = 1.0;
                         }
-                        const double dd = sqrt(piv), inv = 1.0 / dd;
+                        const double inv = rsq_nr(piv), dd = piv * inv;
 #pragma unroll
                         for (int q = 0; q < kIpmR; ++q) {
                             const int c = tc + 16 * q;
@@ -1012,18 +1022,27 @@ __device__ __forceinline__ void wg_ipm(const IpmArgs a, const double *__restrict
             double r0 = (i0 < D) ? sh->M[i0 * ldm + D] : 0.0, r1 = (i1 < D) ? sh->M[i1 * ldm + D] : 0.0;
             const double v0 = (i0 < D) ? 1.0 / sh->ldiag[i0] : 0.0;
             const double v1 = (i1 < D) ? 1.0 / sh->ldiag[i1] : 0.0;
-            // the factor's entries for step j - 1 are loaded during step j
-            double n0 = (i0 < D - 1) ? sh->M[i0 * ldm + D - 1] : 0.0;
-            double n1 = (i1 < D - 1) ? sh->M[i1 * ldm + D - 1] : 0.0;
-            for (int j = D - 1; j >= 0; --j) {
-                const double m0 = n0, m1 = n1;
-                n0 = (i0 < j - 1) ? sh->M[i0 * ldm + j - 1] : 0.0;
-                n1 = (i1 < j - 1) ? sh->M[i1 * ldm + j - 1] : 0.0;
-                const double xj = (j < 64) ? lane_read(r0, j) * lane_read(v0, j) : lane_read(r1, j - 64) * lane_read(v1, j - 64);
-                if (i0 == j) r0 = xj;
-                if (i1 == j) r1 = xj;
-                r0 -= m0 * xj;
-                r1 -= m1 * xj;
+            // columns in blocks of 16, from the last: a block's factor entries are loaded
+            // together (sixteen loads in flight) before its sixteen dependent steps
+            for (int jb = (D - 1) >> 4; jb >= 0; --jb) {
+                double m0[16], m1[16];
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const int j = 16 * jb + t;
+                    m0[t] = (i0 < j && j < D) ? sh->M[i0 * ldm + j] : 0.0;
+                    m1[t] = (i1 < j && j < D) ? sh->M[i1 * ldm + j] : 0.0;
+                }
+#pragma unroll
+                for (int t = 15; t >= 0; --t) {
+                    const int j = 16 * jb + t;
+                    if (j < D) {
+                        const double xj = (j < 64) ? lane_read(r0 * v0, j) : lane_read(r1 * v1, j - 64);
+                        if (i0 == j) r0 = xj;
+                        if (i1 == j) r1 = xj;
+                        r0 -= m0[t] * xj;
+                        r1 -= m1[t] * xj;
+                    }
+                }
             }
             if (i0 < D) sh->rhs[i0] = r0;
             if (i1 < D) sh->rhs[i1] = r1;
