@@ -127,6 +127,8 @@ struct usbs_handle {
     int null_run = 0;         // consecutive null steps
     int recoveries = 0;       // stall re-evaluations of f at the centre
     bool last_conv = false;
+    bool conv_pending = false;   // last_conv is still on its way into conv_host
+    int *conv_host = nullptr;    // pinned
     bool ready = false;
     // value of iters after which AX, Vn (= V_t) and the QP solution in ipm describe
     // X_{t+1} of that iteration; -1 before the first iteration of the current problem
@@ -596,8 +598,11 @@ void orth_fresh(usbs_handle *h, const double *Q, int ldq, int nq, double *dst, i
 // vectors of an earlier solve) and h->W holds 16 - keep fresh directions, zero-padded to 8
 // columns; with orth_start they are orthonormalised against the kept ones into the block's
 // last columns (three sweeps instead of a Cholesky-QR2 of all 16).
+// defer_last: the last allowed cycle ends the solve whatever its residual test says, so its
+// flag is copied into h->conv_host for the caller to read at its next synchronisation
+// (h->conv_pending) instead of the host waiting for the device here.
 int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_rest, int maxr, bool orth_start,
-            int min_cyc, int keep = 16) {
+            int min_cyc, int keep = 16, bool defer_last = false) {
     hipStream_t s = h->stream;
     const int n = h->n, ldb = h->ldb, steps = h->steps;
     if (start != h->Ubuf) copy_cols(s, n, start, 16, 16, h->Ubuf, 16);
@@ -633,6 +638,12 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
         // Ritz vectors B = U Y into the basis, residuals R = M U Y - B Theta over U, R^T R
         rr_update(s, h->rs, n, h->Ubuf, h->W2, h->Ysm, h->theta, h->Bm, ldb, h->Ubuf, h->RtR);
         lanczos_restart_prep(s, h->RtR, h->theta, kc, tol, tol_rest, h->res, h->flag, h->Zc, h->sc + SC_SCALE);
+        if (cyc == maxr && defer_last) {
+            if (!h->conv_host) HIPCHK(hipHostMalloc((void **)&h->conv_host, sizeof(int), hipHostMallocDefault));
+            HIPCHK(hipMemcpyAsync(h->conv_host, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+            h->conv_pending = true;
+            break;
+        }
         int conv = 0;
         HIPCHK(hipMemcpyAsync(&conv, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -776,8 +787,8 @@ void iterate(usbs_handle *h) {
     copy_cols(s, n, h->Ucpl, 16, 14, h->Ubuf, 16);
     random_block_pad(s, n, 2, prm.seed + 7919ull * (uint64_t)(h->iters + 1), h->W, 8);
     const double tol_rest = prm.lanczos_tol_rest > 0.0 ? prm.lanczos_tol_rest : std::sqrt(prm.lanczos_tol);
-    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, tol_rest, prm.lanczos_max_restarts, true, 0, 14);
-    if (cyc >= prm.lanczos_max_restarts && !h->last_conv) h->lz_unconverged++;
+    const int cyc = lanczos(h, h->Ubuf, kc, prm.lanczos_tol, tol_rest, prm.lanczos_max_restarts, true, 0, 14, true);
+    const bool at_cap = cyc >= prm.lanczos_max_restarts;
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
     // model update
@@ -811,6 +822,11 @@ void iterate(usbs_handle *h) {
     double desc = 0.0;
     HIPCHK(hipMemcpyAsync(&desc, h->sc + SC_DESC, sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    if (h->conv_pending) {
+        h->last_conv = *h->conv_host != 0;
+        h->conv_pending = false;
+    }
+    if (at_cap && !h->last_conv) h->lz_unconverged++;
     h->null_run = desc != 0.0 ? 0 : h->null_run + 1;
     if (h->null_run >= kStallWindow) {
         polish_dual(h);
@@ -1276,6 +1292,7 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
 void usbs_free(usbs_handle *h) {
     if (!h) return;
     free_problem(h);
+    if (h->conv_host) (void)hipHostFree(h->conv_host);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
 }
