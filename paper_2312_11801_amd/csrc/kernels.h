@@ -79,8 +79,9 @@ void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave
               double *coef, int *flags, const double *floor_ref);
 // reorth_finish and pip_chol in one launch: the workgroups of the finish sum their outputs
 // into Hg, and the last one to finish (rs.counter) runs the pass's Cholesky step on Hg
+// (pass 0 with skip: *skip = 1 when the second pass may be left out, see kPass2Skip)
 void finish_pip(hipStream_t s, const RedScratch &rs, int blocks, int cols, double *Hg, int pass, double *Rsave,
-                double *T, int ldt, double *coef, int *flags, const double *floor_ref);
+                double *T, int ldt, double *coef, int *flags, const double *floor_ref, int *skip = nullptr);
 // out[o] = sum over g < G of part[g * nout + o] (fixed order), o < nout
 void sum_partials(hipStream_t s, const double *part, int G, int nout, double *out);
 void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, int lda, int ca,
@@ -89,9 +90,11 @@ void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, in
 void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
                int cc, double *C, int ldc, double alpha, double beta);
 // C (n x cc, ldc) = [A A2] H with a second source A2 (n x ca2, ca2 <= 8) whose rows
-// follow A's in H (H is (ca + ca2) x cc); C must not alias A or A2
+// follow A's in H (H is (ca + ca2) x cc).  C must not overlap A; it may be A2 itself (every
+// row group is read into LDS before its outputs are written).  Nothing is done when skip is
+// given and *skip is set.
 void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2, int ca2,
-                const double *H, int ldh, int cc, double *C, int ldc);
+                const double *H, int ldh, int cc, double *C, int ldc, const int *skip = nullptr);
 // the first Gram-Schmidt update of a Lanczos block fused with the second pass's reduction:
 // C (n x 8, ldc) = [A A2] H (A n x ca, A2 n x 8, H (ca + 8) x 8) and one partial of
 // [A C]^T C ((ca + 8) x 8) per workgroup in rs.partials; returns the workgroup count

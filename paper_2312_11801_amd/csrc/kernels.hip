@@ -523,7 +523,7 @@ __global__ __launch_bounds__(kWG) void k_pip_chol(const double *__restrict__ Hg,
 // for the next launch on the stream.  No workgroup waits for another.
 __global__ __launch_bounds__(kWG) void k_finish_pip(const double *__restrict__ part, int G, int cols, double *Hg,
                                                     unsigned *counter, int pass, double *Rsave, double *T, int ldt,
-                                                    double *coef, int *flags, const double *floor_ref) {
+                                                    double *coef, int *flags, const double *floor_ref, int *skip) {
     __shared__ PipWork w;
     __shared__ double s4[4][64];
     __shared__ unsigned arrived;
@@ -552,13 +552,13 @@ __global__ __launch_bounds__(kWG) void k_finish_pip(const double *__restrict__ p
     if (arrived != gridDim.x - 1) return;
     __threadfence();
     if (threadIdx.x == 0) *counter = 0u;
-    wg_pip_chol(Hg, cols, pass, Rsave, T, ldt, coef, flags, floor_ref, &w);
+    wg_pip_chol(Hg, cols, pass, Rsave, T, ldt, coef, flags, floor_ref, &w, skip);
 }
 void finish_pip(hipStream_t s, const RedScratch &rs, int blocks, int cols, double *Hg, int pass, double *Rsave,
-                double *T, int ldt, double *coef, int *flags, const double *floor_ref) {
+                double *T, int ldt, double *coef, int *flags, const double *floor_ref, int *skip) {
     const int nout = (cols + kBlk) * kBlk;
     hipLaunchKernelGGL(k_finish_pip, dim3(cdiv(nout, 64)), dim3(kWG), 0, s, rs.partials, blocks, cols, Hg, rs.counter,
-                       pass, Rsave, T, ldt, coef, flags, floor_ref);
+                       pass, Rsave, T, ldt, coef, flags, floor_ref, skip);
 }
 
 void pip_chol(hipStream_t s, const double *Hg, int cols, int pass, double *Rsave, double *T, int ldt,
@@ -599,8 +599,10 @@ template <typename TC, int L>
 __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restrict__ A, int lda, int ca,
                                                    const double *__restrict__ A2, int lda2, int ca2,
                                                    const double *__restrict__ H, int ldh, int cc,
-                                                   TC *__restrict__ C, int ldc, double alpha, double beta) {
+                                                   TC *__restrict__ C, int ldc, double alpha, double beta,
+                                                   const int *skip) {
     constexpr int R = kWG / L;  // rows per workgroup
+    if (skip && *skip) return;
     __shared__ double sH[(kMaxBasis + kBlk) * 16];
     __shared__ double sA[R][kMaxBasis + kBlk + 1];
     const int tid = threadIdx.x;
@@ -643,8 +645,10 @@ template <int NL>
 __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict__ A, int lda, int ca,
                                                  const double *__restrict__ A2, int lda2, int ca2,
                                                  const double *__restrict__ H, int ldh, int cc,
-                                                 double *__restrict__ C, int ldc, double alpha, double beta) {
+                                                 double *__restrict__ C, int ldc, double alpha, double beta,
+                                                 const int *skip) {
     __shared__ NnWork w;
+    if (skip && *skip) return;
     wg_nn_mfma<NL>(n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, blockIdx.x, gridDim.x, &w);
 }
 
@@ -694,32 +698,33 @@ static int nn_mfma_blocks(int n) {
 
 template <typename TC>
 static void nn_update_t(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2,
-                        int ca2, const double *H, int ldh, int cc, TC *C, int ldc, double alpha, double beta) {
+                        int ca2, const double *H, int ldh, int cc, TC *C, int ldc, double alpha, double beta,
+                        const int *skip = nullptr) {
     if (n <= 0 || cc <= 0) return;
     if constexpr (sizeof(TC) == 8) {
         if (use_nn_mfma(n, cc, ca2)) {
             const dim3 grid(nn_mfma_blocks(n));
             with_tile_loads(ca, [&](auto nl) {
                 hipLaunchKernelGGL(k_nn_mfma<decltype(nl)::value>, grid, dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
-                                   ca2, H, ldh, cc, (double *)C, ldc, alpha, beta);
+                                   ca2, H, ldh, cc, (double *)C, ldc, alpha, beta, skip);
             });
             return;
         }
     }
     if (cc <= 4)
         hipLaunchKernelGGL((k_nn_update<TC, 4>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
-                           ca2, H, ldh, cc, C, ldc, alpha, beta);
+                           ca2, H, ldh, cc, C, ldc, alpha, beta, skip);
     else if (cc <= 8)
         hipLaunchKernelGGL((k_nn_update<TC, 8>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
-                           ca2, H, ldh, cc, C, ldc, alpha, beta);
+                           ca2, H, ldh, cc, C, ldc, alpha, beta, skip);
     else
         hipLaunchKernelGGL((k_nn_update<TC, 16>), dim3(cdiv(n, kWG / 16)), dim3(kWG), 0, s, n, A, lda, ca, A2,
-                           lda2, ca2, H, ldh, cc, C, ldc, alpha, beta);
+                           lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, skip);
 }
 
 void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2, int ca2,
-                const double *H, int ldh, int cc, double *C, int ldc) {
-    nn_update_t<double>(s, n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, 1.0, 0.0);
+                const double *H, int ldh, int cc, double *C, int ldc, const int *skip) {
+    nn_update_t<double>(s, n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, 1.0, 0.0, skip);
 }
 
 void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,

@@ -335,9 +335,10 @@ __device__ __forceinline__ unsigned wave_chol_rows(int nc, const double *G, int 
 // Cholesky-QR factor (one thread-team = wavefront 0 of the calling workgroup).
 // G (nc x nc, LDS, ld, nc <= 16) = W^T W.  A pivot at or below max(1e-24 * max diag,
 // floor2) marks the column dead and zeroes it.  Writes the factor L back into G's lower
-// triangle and R^{-1} = L^{-T} to H (ldh), dead columns zero.
-__device__ __forceinline__ void wave_cholqr(int nc, double *G, int ld, double *H, int ldh, int *flags,
-                                            double floor2) {
+// triangle and R^{-1} = L^{-T} to H (ldh), dead columns zero.  Returns the mask of dead
+// columns.
+__device__ __forceinline__ unsigned wave_cholqr(int nc, double *G, int ld, double *H, int ldh, int *flags,
+                                                double floor2) {
     const int r = threadIdx.x & 63;
     double md = 0.0;
     for (int i = 0; i < nc; ++i) md = fmax(md, G[i * ld + i]);
@@ -355,6 +356,7 @@ __device__ __forceinline__ void wave_cholqr(int nc, double *G, int ld, double *H
         if (flags && ((dead >> r) & 1u)) flags[r] = 1;
     }
     wave_sync();
+    return dead;
 }
 
 // ---------------------------------------------------------------------------

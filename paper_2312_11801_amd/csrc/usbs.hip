@@ -110,6 +110,7 @@ struct usbs_handle {
            *Hred = nullptr, *Rinv = nullptr, *res = nullptr, *Hd = nullptr;
     double *Hg = nullptr, *coef = nullptr, *Rsv = nullptr;   // block Gram-Schmidt (Pythagorean) work
     double *Tscr = nullptr;                                   // projections of a fresh block (16 x 8, unused)
+    int *skip2 = nullptr;                                     // the block step's second pass is left out
     int *dead = nullptr, *flag = nullptr;
     // QP / model
     double *raw = nullptr, *qp = nullptr, *ipm = nullptr, *VCV = nullptr, *Gy = nullptr, *Kc = nullptr,
@@ -496,6 +497,7 @@ void upload(usbs_handle *h) {
     h->coef = dalloc<double>((size_t)(ldb + 8) * 8, o, h->stream);
     h->Rsv = dalloc<double>(64, o, h->stream);
     h->Tscr = dalloc<double>(16 * 8, o, h->stream);
+    h->skip2 = dalloc<int>(1, o, h->stream);
     h->Rinv = dalloc<double>(256, o, h->stream);
     h->res = dalloc<double>(16, o, h->stream);
     h->Hd = dalloc<double>(256, o, h->stream);
@@ -669,16 +671,21 @@ int lanczos(usbs_handle *h, const double *start, int kc, double tol, double tol_
                 ProfPair pp(h, USBS_PROF_REORTH);
                 g = reorth_partials(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, 8, pp.e0, pp.e1);
             }
-            finish_pip(s, h->rs, g, cols, h->Hg, 0, h->Rsv, h->Tm + c0, ldb, h->coef, nullptr, h->sc + SC_SCALE);
+            finish_pip(s, h->rs, g, cols, h->Hg, 0, h->Rsv, h->Tm + c0, ldb, h->coef, nullptr, h->sc + SC_SCALE,
+                       last ? nullptr : h->skip2);
             // pass-0 update Wt = [Q W] coef fused with pass 1's reduction [Q Wt]^T Wt (the
             // basis rows are read once for both)
             {
                 ProfPair pp(h, USBS_PROF_UPDATE);
-                g = nn_update2_reorth(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, h->coef, 8, h->Wt, 8, pp.e0, pp.e1);
+                // the pass-0 block goes straight into its basis slot (the next block): when pass 0
+                // lost little it stays as it is, otherwise pass 1 corrects it in place
+                g = nn_update2_reorth(s, h->rs, n, h->Bm, ldb, cols, h->W, 8, h->coef, 8, last ? h->Wt : h->Bm + cols,
+                                      last ? 8 : ldb, pp.e0, pp.e1);
             }
             finish_pip(s, h->rs, g, cols, h->Hg, 1, h->Rsv, h->Tm + c0, ldb, h->coef, !last ? h->dead + cols : nullptr,
                        nullptr);
-            if (!last) nn_update2(s, n, h->Bm, ldb, cols, h->Wt, 8, 8, h->coef, 8, 8, h->Bm + cols, ldb);
+            if (!last)
+                nn_update2(s, n, h->Bm, ldb, cols, h->Bm + cols, ldb, 8, h->coef, 8, 8, h->Bm + cols, ldb, h->skip2);
         }
         {
             ProfScope ps(h, USBS_PROF_RITZ);

@@ -712,10 +712,16 @@ struct PipWork {
     double sRi[kBlk * kBlk];
     double sR[kBlk][kBlk];
 };
+// A second pass adds nothing when the first lost little: with Pythagorean inner products the
+// block after pass 0 is orthogonal to Q, and orthonormal, to about eps / p, where p is the
+// smallest ratio L_cc^2 / ||W_c||^2 of the pass's Cholesky pivots to the column norms.
+// With p >= kPass2Skip (error below 100 eps) and no deflated column, pass 0 sets *skip and
+// the caller may take the pass-0 block as it stands (the pass-1 update is then skipped).
+constexpr double kPass2Skip = 1e-2;
 __device__ __forceinline__ void wg_pip_chol(const double *__restrict__ Hg, int cols, int pass,
                                             double *__restrict__ Rsave, double *__restrict__ T, int ldt,
                                             double *__restrict__ coef, int *flags,
-                                            const double *__restrict__ floor_ref, PipWork *w) {
+                                            const double *__restrict__ floor_ref, PipWork *w, int *skip = nullptr) {
     const int tid = threadIdx.x;
     for (int e = tid; e < cols * kBlk; e += kWG) w->sH[e / kBlk][e % kBlk] = Hg[e];
     if (tid < kBlk * kBlk) w->sR[tid / kBlk][tid % kBlk] = (pass == 1) ? Rsave[tid] : 0.0;
@@ -746,7 +752,17 @@ __device__ __forceinline__ void wg_pip_chol(const double *__restrict__ Hg, int c
         const double rf = 1e-10 * (*floor_ref);
         f2 = rf * rf;
     }
-    if (tid < 64) wave_cholqr(kBlk, w->sOm, 17, w->sRi, kBlk, flags, f2);
+    if (tid < 64) {
+        const unsigned dead = wave_cholqr(kBlk, w->sOm, 17, w->sRi, kBlk, flags, f2);
+        if (skip && pass == 0 && tid == 0) {
+            bool ok = dead == 0;
+            for (int c = 0; c < kBlk; ++c) {
+                const double l = w->sOm[c * 17 + c];
+                ok = ok && l * l >= kPass2Skip * Hg[(cols + c) * kBlk + c];
+            }
+            *skip = ok ? 1 : 0;
+        }
+    }
     __syncthreads();
     // R = L^T (upper) of this pass, kept for the correction of the next pass
     if (pass == 0 && tid < kBlk * kBlk) {
