@@ -573,16 +573,21 @@ void cholqr2(usbs_handle *h, const double *src, int lds, int nc, double *tmp, in
 // disjoint from Q's columns).  Three sweeps over [Q W]: the reduction [Q W]^T W, the first
 // update fused with the second pass's reduction, the second update.  Deflated columns are
 // zero and flagged in flags[0..8) (zero padding columns always are); the projections go to T
-// (nq x 8, ld ldt).  Uses W, Wt, Hg, coef and Rsv.
+// (nq x 8, ld ldt).  Uses W, Wt, Hg, coef and Rsv.  With cc == 8 the pass-0 block goes
+// straight to dst and the second update runs only when pass 0 lost too much (kPass2Skip).
 void orth_fresh(usbs_handle *h, const double *Q, int ldq, int nq, double *dst, int ldd, int cc, int *flags,
                 double *T, int ldt) {
     hipStream_t s = h->stream;
     const int n = h->n;
+    const bool direct = cc == 8;
+    double *mid = direct ? dst : h->Wt;
+    const int ldm = direct ? ldd : 8;
     int g = reorth_partials(s, h->rs, n, Q, ldq, nq, h->W, 8, 8);
-    finish_pip(s, h->rs, g, nq, h->Hg, 0, h->Rsv, T, ldt, h->coef, flags, h->sc + SC_SCALE);
-    g = nn_update2_reorth(s, h->rs, n, Q, ldq, nq, h->W, 8, h->coef, 8, h->Wt, 8);
+    finish_pip(s, h->rs, g, nq, h->Hg, 0, h->Rsv, T, ldt, h->coef, flags, h->sc + SC_SCALE,
+               direct ? h->skip2 : nullptr);
+    g = nn_update2_reorth(s, h->rs, n, Q, ldq, nq, h->W, 8, h->coef, 8, mid, ldm);
     finish_pip(s, h->rs, g, nq, h->Hg, 1, h->Rsv, T, ldt, h->coef, flags, nullptr);
-    nn_update2(s, n, Q, ldq, nq, h->Wt, 8, 8, h->coef, 8, cc, dst, ldd);
+    nn_update2(s, n, Q, ldq, nq, mid, ldm, 8, h->coef, 8, cc, dst, ldd, direct ? h->skip2 : nullptr);
 }
 
 // ---------------------------------------------------------------------------
