@@ -89,6 +89,9 @@ void tn_reduce_f(hipStream_t s, const RedScratch &rs, int n, const double *A, in
 // C[i*ldc + c] = beta*C + alpha * sum_a A[i*lda + a] * H[a*ldh + c]   (c < cc <= 16, ca <= 80)
 void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh,
                int cc, double *C, int ldc, double alpha, double beta);
+// the same with alpha = 1 and beta read from device memory (*beta_dev) by the kernel
+void nn_update_beta_dev(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
+                        double *C, int ldc, const double *beta_dev);
 // C (n x cc, ldc) = [A A2] H with a second source A2 (n x ca2, ca2 <= 8) whose rows
 // follow A's in H (H is (ca + ca2) x cc).  C must not overlap A; it may be A2 itself (every
 // row group is read into LDS before its outputs are written).  Nothing is done when skip is

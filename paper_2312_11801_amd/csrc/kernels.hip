@@ -600,9 +600,10 @@ __global__ __launch_bounds__(kWG) void k_nn_update(int n, const double *__restri
                                                    const double *__restrict__ A2, int lda2, int ca2,
                                                    const double *__restrict__ H, int ldh, int cc,
                                                    TC *__restrict__ C, int ldc, double alpha, double beta,
-                                                   const int *skip) {
+                                                   const int *skip, const double *beta_dev) {
     constexpr int R = kWG / L;  // rows per workgroup
     if (skip && *skip) return;
+    if (beta_dev) beta = *beta_dev;
     __shared__ double sH[(kMaxBasis + kBlk) * 16];
     __shared__ double sA[R][kMaxBasis + kBlk + 1];
     const int tid = threadIdx.x;
@@ -646,9 +647,10 @@ __global__ __launch_bounds__(kWG) void k_nn_mfma(int n, const double *__restrict
                                                  const double *__restrict__ A2, int lda2, int ca2,
                                                  const double *__restrict__ H, int ldh, int cc,
                                                  double *__restrict__ C, int ldc, double alpha, double beta,
-                                                 const int *skip) {
+                                                 const int *skip, const double *beta_dev) {
     __shared__ NnWork w;
     if (skip && *skip) return;
+    if (beta_dev) beta = *beta_dev;
     wg_nn_mfma<NL>(n, A, lda, ca, A2, lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, blockIdx.x, gridDim.x, &w);
 }
 
@@ -699,27 +701,27 @@ static int nn_mfma_blocks(int n) {
 template <typename TC>
 static void nn_update_t(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2,
                         int ca2, const double *H, int ldh, int cc, TC *C, int ldc, double alpha, double beta,
-                        const int *skip = nullptr) {
+                        const int *skip = nullptr, const double *beta_dev = nullptr) {
     if (n <= 0 || cc <= 0) return;
     if constexpr (sizeof(TC) == 8) {
         if (use_nn_mfma(n, cc, ca2)) {
             const dim3 grid(nn_mfma_blocks(n));
             with_tile_loads(ca, [&](auto nl) {
                 hipLaunchKernelGGL(k_nn_mfma<decltype(nl)::value>, grid, dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
-                                   ca2, H, ldh, cc, (double *)C, ldc, alpha, beta, skip);
+                                   ca2, H, ldh, cc, (double *)C, ldc, alpha, beta, skip, beta_dev);
             });
             return;
         }
     }
     if (cc <= 4)
         hipLaunchKernelGGL((k_nn_update<TC, 4>), dim3(cdiv(n, kWG / 4)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
-                           ca2, H, ldh, cc, C, ldc, alpha, beta, skip);
+                           ca2, H, ldh, cc, C, ldc, alpha, beta, skip, beta_dev);
     else if (cc <= 8)
         hipLaunchKernelGGL((k_nn_update<TC, 8>), dim3(cdiv(n, kWG / 8)), dim3(kWG), 0, s, n, A, lda, ca, A2, lda2,
-                           ca2, H, ldh, cc, C, ldc, alpha, beta, skip);
+                           ca2, H, ldh, cc, C, ldc, alpha, beta, skip, beta_dev);
     else
         hipLaunchKernelGGL((k_nn_update<TC, 16>), dim3(cdiv(n, kWG / 16)), dim3(kWG), 0, s, n, A, lda, ca, A2,
-                           lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, skip);
+                           lda2, ca2, H, ldh, cc, C, ldc, alpha, beta, skip, beta_dev);
 }
 
 void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const double *A2, int lda2, int ca2,
@@ -730,6 +732,10 @@ void nn_update2(hipStream_t s, int n, const double *A, int lda, int ca, const do
 void nn_update(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
                double *C, int ldc, double alpha, double beta) {
     nn_update_t<double>(s, n, A, lda, ca, nullptr, 0, 0, H, ldh, cc, C, ldc, alpha, beta);
+}
+void nn_update_beta_dev(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
+                        double *C, int ldc, const double *beta_dev) {
+    nn_update_t<double>(s, n, A, lda, ca, nullptr, 0, 0, H, ldh, cc, C, ldc, 1.0, 1.0, nullptr, beta_dev);
 }
 void nn_update_f(hipStream_t s, int n, const double *A, int lda, int ca, const double *H, int ldh, int cc,
                  float *C, int ldc, double alpha, double beta) {

@@ -862,19 +862,10 @@ void polish_dual(usbs_handle *h) {
 }  // namespace
 
 // nn_update with beta read from the device scalar g (sketch update of Sec. 4:
-// P <- g P + V (Kc V^T Psi)); implemented as scale-then-accumulate.
-namespace {
-__global__ void k_scale_dev(long count, const double *g, double *p) {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < count) p[e] *= *g;
-}
-}  // namespace
+// P <- g P + V (Kc V^T Psi)), one sweep over P (C = P has exactly cc = ldc columns)
 void nn_update_dev_beta(usbs_handle *h, const double *A, int lda, int ca, const double *H, int ldh, int cc, double *C,
                         int ldc) {
-    const long count = (long)h->n * ldc;
-    hipLaunchKernelGGL(k_scale_dev, dim3((unsigned)((count + kWG - 1) / kWG)), dim3(kWG), 0, h->stream, count,
-                       h->sc + SC_G, C);
-    nn_update(h->stream, h->n, A, lda, ca, H, ldh, cc, C, ldc, 1.0, 1.0);
+    nn_update_beta_dev(h->stream, h->n, A, lda, ca, H, ldh, cc, C, ldc, h->sc + SC_G);
 }
 
 namespace {
