@@ -30,28 +30,38 @@ static inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 // (deterministic): 4 waves split the partials, LDS combines them in fixed order.
 //   out[(o / cb) * ldo + (o % cb)] = alpha * sum_b part[b][o] (+ beta * old)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_red_finish(const double *__restrict__ part, int G, int nout,
-                                                    double *out, int cb, int ldo, double alpha, double beta) {
-    __shared__ double s4[4][64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int o = blockIdx.x * 64 + lane;
-    const int per = (G + 3) / 4;
-    const int b0 = w * per, b1 = min(G, b0 + per);
-    double s = 0.0;
+// 16 outputs per workgroup: lane o % 16 of each 16-lane group, the G partials split over the
+// sixteen groups (sixteen independent loads in flight per lane), then the group sums added in
+// a fixed order (deterministic)
+__device__ __forceinline__ double finish16(const double *__restrict__ part, int G, int nout, int o,
+                                           double (*s16)[16]) {
+    const int l16 = threadIdx.x & 15, sl = threadIdx.x >> 4;
+    const int per = (G + 15) / 16;
+    const int b0 = sl * per, b1 = min(G, b0 + per);
+    double sum = 0.0;
     if (o < nout) {
-        // sixteen independent loads in flight per lane
         for (int bb = b0; bb < b1; bb += 16) {
             double v[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) v[q] = (bb + q < b1) ? part[(size_t)(bb + q) * nout + o] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) s += v[q];
+            for (int q = 0; q < 16; ++q) sum += v[q];
         }
     }
-    s4[w][lane] = s;
+    s16[sl][l16] = sum;
     __syncthreads();
-    if (w == 0 && o < nout) {
-        const double t = alpha * (((s4[0][lane] + s4[1][lane]) + s4[2][lane]) + s4[3][lane]);
+    double t = 0.0;
+    if (threadIdx.x < 16)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += s16[q][threadIdx.x];
+    return t;   // meaningful in threads 0..15
+}
+__global__ __launch_bounds__(kWG) void k_red_finish(const double *__restrict__ part, int G, int nout,
+                                                    double *out, int cb, int ldo, double alpha, double beta) {
+    __shared__ double s16[16][16];
+    const int o = blockIdx.x * 16 + (threadIdx.x & 15);
+    const double t = alpha * finish16(part, G, nout, o, s16);
+    if (threadIdx.x < 16 && o < nout) {
         const int r = o / cb, c = o - r * cb;
         double *dst = out + (size_t)r * ldo + c;
         *dst = (beta != 0.0) ? t + beta * (*dst) : t;
@@ -60,7 +70,7 @@ __global__ __launch_bounds__(kWG) void k_red_finish(const double *__restrict__ p
 
 static void red_finish(hipStream_t s, const double *part, int G, int nout, double *out, int cb, int ldo,
                        double alpha, double beta) {
-    hipLaunchKernelGGL(k_red_finish, dim3(cdiv(nout, 64)), dim3(kWG), 0, s, part, G, nout, out, cb, ldo, alpha,
+    hipLaunchKernelGGL(k_red_finish, dim3(cdiv(nout, 16)), dim3(kWG), 0, s, part, G, nout, out, cb, ldo, alpha,
                        beta);
 }
 
@@ -525,26 +535,12 @@ __global__ __launch_bounds__(kWG) void k_finish_pip(const double *__restrict__ p
                                                     unsigned *counter, int pass, double *Rsave, double *T, int ldt,
                                                     double *coef, int *flags, const double *floor_ref, int *skip) {
     __shared__ PipWork w;
-    __shared__ double s4[4][64];
+    __shared__ double s16[16][16];
     __shared__ unsigned arrived;
     const int nout = (cols + kBlk) * kBlk;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int o = blockIdx.x * 64 + lane;
-    const int per = (G + 3) / 4;
-    const int b0 = wv * per, b1 = min(G, b0 + per);
-    double sum = 0.0;
-    if (o < nout) {
-        for (int bb = b0; bb < b1; bb += 16) {
-            double v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = (bb + q < b1) ? part[(size_t)(bb + q) * nout + o] : 0.0;
-#pragma unroll
-            for (int q = 0; q < 16; ++q) sum += v[q];
-        }
-    }
-    s4[wv][lane] = sum;
-    __syncthreads();
-    if (wv == 0 && o < nout) Hg[o] = ((s4[0][lane] + s4[1][lane]) + s4[2][lane]) + s4[3][lane];
+    const int o = blockIdx.x * 16 + (threadIdx.x & 15);
+    const double t = finish16(part, G, nout, o, s16);
+    if (threadIdx.x < 16 && o < nout) Hg[o] = t;
     __threadfence();
     __syncthreads();
     if (threadIdx.x == 0) arrived = atomicAdd(counter, 1u);
@@ -557,7 +553,7 @@ __global__ __launch_bounds__(kWG) void k_finish_pip(const double *__restrict__ p
 void finish_pip(hipStream_t s, const RedScratch &rs, int blocks, int cols, double *Hg, int pass, double *Rsave,
                 double *T, int ldt, double *coef, int *flags, const double *floor_ref, int *skip) {
     const int nout = (cols + kBlk) * kBlk;
-    hipLaunchKernelGGL(k_finish_pip, dim3(cdiv(nout, 64)), dim3(kWG), 0, s, rs.partials, blocks, cols, Hg, rs.counter,
+    hipLaunchKernelGGL(k_finish_pip, dim3(cdiv(nout, 16)), dim3(kWG), 0, s, rs.partials, blocks, cols, Hg, rs.counter,
                        pass, Rsave, T, ldt, coef, flags, floor_ref, skip);
 }
 
