@@ -118,6 +118,11 @@ struct usbs_handle {
            *hz = nullptr, *Rz = nullptr, *Qp8 = nullptr;
     int *zdead = nullptr;
     RedScratch rs{};
+    // side stream (default priority) for V^T Psi, which runs beside the one-workgroup master-QP
+    // solve; its own reduction scratch
+    hipStream_t side = nullptr;
+    hipEvent_t ev_side0 = nullptr, ev_side1 = nullptr;
+    RedScratch rs_side{};
 
     Tuning tune;   // launch shapes (autotuner)
 
@@ -524,6 +529,9 @@ void upload(usbs_handle *h) {
     if (h->rs.max_elems < kMaxBasis * 16) h->rs.max_elems = kMaxBasis * 16;
     h->rs.partials = dalloc<double>((size_t)h->rs.max_blocks * h->rs.max_elems, o, h->stream);
     h->rs.counter = dalloc<unsigned>(4, o, h->stream);
+    h->rs_side.max_blocks = kRedMaxBlocks;
+    h->rs_side.max_elems = 16 * kMaxRank;
+    h->rs_side.partials = dalloc<double>((size_t)h->rs_side.max_blocks * h->rs_side.max_elems, o, h->stream);
     HIPCHK(hipMemsetAsync(h->rs.counter, 0, 4 * sizeof(unsigned), s));
     HIPCHK(hipMemsetAsync(h->V, 0, (size_t)n * 16 * sizeof(double), s));
     HIPCHK(hipMemsetAsync(h->Vn, 0, (size_t)n * 16 * sizeof(double), s));
@@ -752,6 +760,19 @@ void iterate(usbs_handle *h) {
         const double *a[3] = {h->zbar, h->y, h->b}, *bb[3] = {h->zbar, h->zbar, h->zbar};
         dots(s, h->rs, m, a, bb, 3, h->sc + SC_ZZ);
     }
+    // V^T Psi of the sketch update needs V only: it runs on the side stream while the master
+    // QP is solved on one workgroup (the model update waits for it)
+    if (h->sketch) {
+        if (!h->side) {
+            HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&h->ev_side0, hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->ev_side1, hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(h->ev_side0, s));
+        HIPCHK(hipStreamWaitEvent(h->side, h->ev_side0, 0));
+        tn_reduce_f(h->side, h->rs_side, n, h->V, 16, k, h->psi, r, r, h->VtPsi, r, 1.0);
+        HIPCHK(hipEventRecord(h->ev_side1, h->side));
+    }
     // alternating maximisation over (X, nu) (eqs. small_quad_sdp, dual_slack_update)
     fill(s, m, 0.0, h->nu);
     IpmArgs ia{k, 1e-7, 1e-7, 100, 0};
@@ -804,7 +825,7 @@ void iterate(usbs_handle *h) {
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
     // model update
-    if (h->sketch) tn_reduce_f(s, h->rs, n, h->V, 16, k, h->psi, r, r, h->VtPsi, r, 1.0);
+    if (h->sketch) HIPCHK(hipStreamWaitEvent(s, h->ev_side1, 0));
     model_update(s, k, kp, r, h->ipm, h->VCV, h->VtPsi, h->sc, h->Kc, h->Qp, h->sketch ? h->Hsk : nullptr);
     lowrank_A(s, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, h->Kc, 1.0, h->zbar, h->sc + SC_G, 0.0, h->zbar,
               0.0);
@@ -1294,7 +1315,11 @@ int usbs_solve(usbs_handle *h, usbs_result *res, double *y_out, double *U_out, d
 
 void usbs_free(usbs_handle *h) {
     if (!h) return;
+    if (h->side) (void)hipStreamSynchronize(h->side);
     free_problem(h);
+    if (h->ev_side0) (void)hipEventDestroy(h->ev_side0);
+    if (h->ev_side1) (void)hipEventDestroy(h->ev_side1);
+    if (h->side) (void)hipStreamDestroy(h->side);
     if (h->conv_host) (void)hipHostFree(h->conv_host);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     delete h;
