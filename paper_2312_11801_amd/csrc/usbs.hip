@@ -121,7 +121,7 @@ struct usbs_handle {
     // side stream (default priority) for V^T Psi, which runs beside the one-workgroup master-QP
     // solve; its own reduction scratch
     hipStream_t side = nullptr;
-    hipEvent_t ev_side0 = nullptr, ev_side1 = nullptr;
+    hipEvent_t ev_side0 = nullptr, ev_side1 = nullptr, ev_side2 = nullptr;
     RedScratch rs_side{};
 
     Tuning tune;   // launch shapes (autotuner)
@@ -530,7 +530,7 @@ void upload(usbs_handle *h) {
     h->rs.partials = dalloc<double>((size_t)h->rs.max_blocks * h->rs.max_elems, o, h->stream);
     h->rs.counter = dalloc<unsigned>(4, o, h->stream);
     h->rs_side.max_blocks = kRedMaxBlocks;
-    h->rs_side.max_elems = 16 * kMaxRank;
+    h->rs_side.max_elems = h->rs.max_elems;
     h->rs_side.partials = dalloc<double>((size_t)h->rs_side.max_blocks * h->rs_side.max_elems, o, h->stream);
     HIPCHK(hipMemsetAsync(h->rs.counter, 0, 4 * sizeof(unsigned), s));
     HIPCHK(hipMemsetAsync(h->V, 0, (size_t)n * 16 * sizeof(double), s));
@@ -734,15 +734,27 @@ constexpr int kStallWindow = 25;
 // diagonal constraints only, G^T w goes through the weighted Gram of V (wgram: one sweep over
 // the n rows instead of the m constraint rows, no svec rows formed); otherwise qp_gram forms
 // g_k per constraint row.  Same output layout either way.
-void qp_gram_w(usbs_handle *h, const double *V, int k, const double *const *ws, int nw, double *out, int do_q11) {
-    hipStream_t s = h->stream;
+void qp_gram_w(usbs_handle *h, const double *V, int k, const double *const *ws, int nw, double *out, int do_q11,
+               hipStream_t s, const RedScratch &rs) {
     const int d = k * (k + 1) / 2;
     if (!h->has_offc) {
-        if (do_q11) qp_gram(s, h->rs, h->m, h->kptr, h->ti, h->tj, h->tv, V, 16, k, nullptr, 0, out, 1);
-        wgram(s, h->rs, h->n, V, 16, k, h->dptr, h->dk, h->dv, ws, nw, out + (do_q11 ? d * (d + 1) / 2 : 0));
+        if (do_q11) qp_gram(s, rs, h->m, h->kptr, h->ti, h->tj, h->tv, V, 16, k, nullptr, 0, out, 1);
+        wgram(s, rs, h->n, V, 16, k, h->dptr, h->dk, h->dv, ws, nw, out + (do_q11 ? d * (d + 1) / 2 : 0));
     } else {
-        qp_gram(s, h->rs, h->m, h->kptr, h->ti, h->tj, h->tv, V, 16, k, ws, nw, out, do_q11);
+        qp_gram(s, rs, h->m, h->kptr, h->ti, h->tj, h->tv, V, 16, k, ws, nw, out, do_q11);
     }
+}
+void qp_gram_w(usbs_handle *h, const double *V, int k, const double *const *ws, int nw, double *out, int do_q11) {
+    qp_gram_w(h, V, k, ws, nw, out, do_q11, h->stream, h->rs);
+}
+
+// the side stream and its events, created on first use
+void ensure_side(usbs_handle *h) {
+    if (h->side) return;
+    HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_side0, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_side1, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->ev_side2, hipEventDisableTiming));
 }
 
 void iterate(usbs_handle *h) {
@@ -750,29 +762,28 @@ void iterate(usbs_handle *h) {
     const int n = h->n, m = h->m, k = h->k, kc = h->kc, kp = h->kp, r = h->r;
     const int d = k * (k + 1) / 2;
     const usbs_params &prm = h->prm;
+    // The reductions of the master QP (sum g g^T, G^T zbar, G^T y, G^T b; matrix-core and LDS
+    // bound) run on the side stream beside V^T C V (HBM bound) on the handle's stream; then
+    // V^T Psi of the sketch update, which needs V only, runs there while the master QP is
+    // solved on one workgroup (the model update waits for it).
+    ensure_side(h);
+    HIPCHK(hipEventRecord(h->ev_side0, s));
+    HIPCHK(hipStreamWaitEvent(h->side, h->ev_side0, 0));
+    {
+        const double *ws[3] = {h->zbar, h->y, h->b};
+        qp_gram_w(h, h->V, k, ws, 3, h->raw, 1, h->side, h->rs_side);
+        HIPCHK(hipEventRecord(h->ev_side2, h->side));
+        if (h->sketch) tn_reduce_f(h->side, h->rs_side, n, h->V, 16, k, h->psi, r, r, h->VtPsi, r, 1.0);
+        HIPCHK(hipEventRecord(h->ev_side1, h->side));
+    }
     // V^T C V
     apply_C(h, h->V, 16, h->CV, 16, 16);
     tn_reduce(s, h->rs, n, h->V, 16, k, h->CV, 16, k, h->VCV, k, 1.0, 0.0);
-    // reductions of the master QP: sum g g^T, G^T zbar, G^T y, G^T b
     {
-        const double *ws[3] = {h->zbar, h->y, h->b};
-        qp_gram_w(h, h->V, k, ws, 3, h->raw, 1);
         const double *a[3] = {h->zbar, h->y, h->b}, *bb[3] = {h->zbar, h->zbar, h->zbar};
         dots(s, h->rs, m, a, bb, 3, h->sc + SC_ZZ);
     }
-    // V^T Psi of the sketch update needs V only: it runs on the side stream while the master
-    // QP is solved on one workgroup (the model update waits for it)
-    if (h->sketch) {
-        if (!h->side) {
-            HIPCHK(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&h->ev_side0, hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&h->ev_side1, hipEventDisableTiming));
-        }
-        HIPCHK(hipEventRecord(h->ev_side0, s));
-        HIPCHK(hipStreamWaitEvent(h->side, h->ev_side0, 0));
-        tn_reduce_f(h->side, h->rs_side, n, h->V, 16, k, h->psi, r, r, h->VtPsi, r, 1.0);
-        HIPCHK(hipEventRecord(h->ev_side1, h->side));
-    }
+    HIPCHK(hipStreamWaitEvent(s, h->ev_side2, 0));
     // alternating maximisation over (X, nu) (eqs. small_quad_sdp, dual_slack_update)
     fill(s, m, 0.0, h->nu);
     IpmArgs ia{k, 1e-7, 1e-7, 100, 0};
@@ -825,7 +836,7 @@ void iterate(usbs_handle *h) {
     decide(s, h->theta, h->sc);
     cond_copy(s, m, h->sc + SC_DESC, h->yc, h->y);
     // model update
-    if (h->sketch) HIPCHK(hipStreamWaitEvent(s, h->ev_side1, 0));
+    HIPCHK(hipStreamWaitEvent(s, h->ev_side1, 0));
     model_update(s, k, kp, r, h->ipm, h->VCV, h->VtPsi, h->sc, h->Kc, h->Qp, h->sketch ? h->Hsk : nullptr);
     lowrank_A(s, m, h->kptr, h->ti, h->tj, h->tv, h->V, 16, k, h->Kc, 1.0, h->zbar, h->sc + SC_G, 0.0, h->zbar,
               0.0);
@@ -1319,6 +1330,7 @@ void usbs_free(usbs_handle *h) {
     free_problem(h);
     if (h->ev_side0) (void)hipEventDestroy(h->ev_side0);
     if (h->ev_side1) (void)hipEventDestroy(h->ev_side1);
+    if (h->ev_side2) (void)hipEventDestroy(h->ev_side2);
     if (h->side) (void)hipStreamDestroy(h->side);
     if (h->conv_host) (void)hipHostFree(h->conv_host);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
